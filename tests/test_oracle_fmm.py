@@ -1,0 +1,131 @@
+"""Pins for the oracle's direct sum and serial FMM: momentum conservation of the
+pure short-range sum (Sec. 2), the Plummer closed form, theta = 0 as direct
+summation (Sec. 2), the leaf <- cell asymmetry of Sec. 4 against the mutual
+walk of Sec. 7, the KDK centre-of-mass identity, and the direct-sum adjoint."""
+import numpy as np
+import pytest
+
+from paper_2502_01496_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def c1(orc):
+    x, m, h = W.plummer(4096, 1)
+    return x, m, h, orc.direct(x, m, h)
+
+
+def eta(a, ref):
+    return np.sqrt(((a - ref) ** 2).sum() / (ref ** 2).sum())
+
+
+def test_direct_conserves_momentum(orc, c1):
+    x, m, h, a = c1
+    st = orc.stats(x, None, m, a)
+    assert st["ratio"] <= 1e-14
+
+
+def test_direct_newtonian_pair_and_sign(orc):
+    x = np.array([[0.0, 0, 0], [3.0, 0, 0]])
+    a = orc.direct(x, np.array([2.0, 5.0]), np.array([0.1, 0.2]), G=1.5)
+    assert a[0, 0] == pytest.approx(1.5 * 5.0 / 9.0, rel=1e-15)   # pulled towards +x
+    assert a[1, 0] == pytest.approx(-1.5 * 2.0 / 9.0, rel=1e-15)
+
+
+def test_plummer_closed_form(orc, c1):
+    # E[a(x)] = -G M (N-1)/N x / (|x|^2 + a^2)^{3/2} for a Plummer sphere
+    x, m, h, a = c1
+    n = len(m)
+    r = np.linalg.norm(x, axis=1)
+    ar = (a * x).sum(1) / r
+    model = -(n - 1) / n * r / (r * r + 1.0) ** 1.5
+    sel = (r > 5 * h[0]) & (r < 10.0)
+    edges = np.quantile(r[sel], np.linspace(0, 1, 17))
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        b = sel & (r >= lo) & (r <= hi)
+        d = ar[b] - model[b]
+        se = d.std(ddof=1) / np.sqrt(b.sum())
+        assert abs(d.mean()) < 4 * se + 1e-3 * abs(model[b]).mean()
+
+
+def test_theta_zero_is_direct(orc, c1):
+    x, m, h, a = c1
+    r = orc.fmm(x, m, h, theta=0.0)
+    assert len(r.lists.far_src) == 0
+    assert eta(r.a, a) <= 1e-13
+
+
+def test_single_leaf_is_direct(orc):
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((8, 3))
+    m = rng.random(8) + 0.1
+    h = rng.random(8) * 0.5 + 0.1
+    r = orc.fmm(x, m, h, leaf_size=8)
+    assert r.tree.nnodes == 1
+    np.testing.assert_allclose(r.a, orc.direct(x, m, h), rtol=1e-14)
+
+
+def test_error_trend_and_asymmetry(orc):
+    x, m, h = W.polytrope_binary(4096, 2, cache=False)
+    a = orc.direct(x, m, h)
+    errs = []
+    for th in (0.3, 0.5, 0.7):
+        r = orc.fmm(x, m, h, theta=th)
+        errs.append(eta(r.a, a))
+        ratio = orc.stats(x, None, m, r.a)["ratio"]
+        assert 1e-8 < ratio < 1e-3          # leaf <- cell pairing leaves a net force
+    assert errs[0] < errs[1] < errs[2] < 5e-3
+    rm = orc.fmm(x, m, h, theta=0.5, policy=orc.MUTUAL)
+    assert orc.stats(x, None, m, rm.a)["ratio"] <= 1e-13   # mutual pairs cancel
+    assert eta(rm.a, a) < 5e-3
+
+
+def test_kdk_centre_of_mass_identity(orc):
+    x, m, h = W.plummer(512, 2)
+    v = np.zeros_like(x)
+    dt = 1e-3
+    force = lambda xx: orc.fmm(xx, m, h, theta=0.5).a
+    _, _, _, hist = orc.kdk(x, v, m, h, dt, 6, force)
+    M = m.sum()
+    X = hist[0]["xcom"] * M / M
+    V = hist[0]["P"] / M
+    for k in range(6):
+        F0, F1 = hist[k]["sumF"], hist[k + 1]["sumF"]
+        Xn = hist[k]["xcom"] + dt * hist[k]["P"] / M + dt * dt / (2 * M) * F0
+        Vn = hist[k]["P"] / M + dt / (2 * M) * (F0 + F1)
+        np.testing.assert_allclose(hist[k + 1]["xcom"], Xn, atol=1e-15)
+        np.testing.assert_allclose(hist[k + 1]["P"] / M, Vn, atol=1e-16)
+    assert np.linalg.norm(hist[-1]["xcom"] - hist[0]["xcom"]) > 0
+
+
+def test_direct_adjoint_matches_finite_differences(orc):
+    rng = np.random.default_rng(4)
+    n = 40
+    x = rng.standard_normal((n, 3)) * 0.3
+    m = rng.random(n) + 0.5
+    h = rng.random(n) * 0.2 + 0.1   # many softened pairs
+    ab = rng.standard_normal((n, 3))
+    xb, mb = orc.direct_vjp(x, m, h, ab)
+    eps = 1e-6
+    for _ in range(6):
+        e = rng.standard_normal((n, 3))
+        e /= np.linalg.norm(e)
+        fd = ((orc.direct(x + eps * e, m, h) - orc.direct(x - eps * e, m, h)) * ab).sum() / (2 * eps)
+        assert (xb * e).sum() == pytest.approx(fd, rel=1e-6)
+        em = rng.standard_normal(n)
+        em /= np.linalg.norm(em)
+        fd = ((orc.direct(x, m + eps * em, h) - orc.direct(x, m - eps * em, h)) * ab).sum() / (2 * eps)
+        assert (mb * em).sum() == pytest.approx(fd, rel=1e-7)
+
+
+def test_direct_adjoint_momentum_identity(orc):
+    # sum_i m_i a_i = 0 for every x, m: with abar_i = m_i e, xbar = 0 and mbar_j = -e.a_j
+    rng = np.random.default_rng(6)
+    n = 30
+    x = rng.standard_normal((n, 3))
+    m = rng.random(n) + 0.5
+    h = np.full(n, 0.3)
+    e = np.array([0.3, -1.2, 0.7])
+    xb, mb = orc.direct_vjp(x, m, h, m[:, None] * e[None, :])
+    a = orc.direct(x, m, h)
+    assert np.abs(xb).max() < 1e-13 * np.abs(a).max() * m.max()
+    np.testing.assert_allclose(mb, -(a @ e), rtol=1e-12, atol=1e-14 * np.abs(a).max())
