@@ -1,0 +1,197 @@
+/*
+ * fmm_mi355.h -- C ABI of the MI355X (gfx950) kd-tree FMM gravity library.
+ *
+ * The library evaluates self-gravity accelerations of N particles the way the
+ * paper analyses it (Potashov & Yudin, arXiv:2502.01496, Sec. 2):
+ *
+ *     a_grav = a_short + a_long                                   eq. (3)
+ *
+ * Particles are grouped in a kd-tree; for every sink leaf cell the tree is
+ * walked with the opening criterion eq. (4) and the smoothing-sphere overlap
+ * criterion eq. (5).  Opened leaf cells are summed directly with the softened
+ * pair kernel (Sec. 3, eqs. (12)-(15)); accepted cells act through their mass
+ * and quadrupole (eq. (7)), the field eq. (6) and its Taylor evaluation at each
+ * particle, eq. (8).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers (HIP device memory), contiguous, in
+ *     the caller's particle order: positions and accelerations are row-major
+ *     [n][3], masses and smoothing lengths [n].  Exceptions say "host".
+ *   - The caller owns its inputs and outputs; they must stay valid until the
+ *     work enqueued on `stream` has completed.  The library owns the tree and
+ *     its workspace until fmm_tree_free.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on it, except where a call says it synchronises.
+ *   - Arguments are validated on the host before any launch; a bad argument
+ *     returns FMM_ERR_INVALID and enqueues nothing.  Data-dependent errors
+ *     (non-finite coordinates, non-positive masses or smoothing lengths) are
+ *     detected on the device and reported by the next call that synchronises
+ *     (fmm_forces), which then returns FMM_ERR_INVALID.
+ *   - A HIP runtime failure returns FMM_ERR_HIP.  fmm_last_error() returns the
+ *     message of the last failure on the calling thread.
+ *   - A tree is not thread-safe; distinct trees may be used concurrently on
+ *     distinct streams.
+ */
+#ifndef FMM_MI355_H
+#define FMM_MI355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fmm_status {
+    FMM_OK = 0,
+    FMM_ERR_INVALID = -1,  /* bad argument or bad input data */
+    FMM_ERR_ALLOC = -2,    /* device allocation failed */
+    FMM_ERR_CAPACITY = -3, /* a size limit of the library was exceeded */
+    FMM_ERR_HIP = -4,      /* HIP runtime error */
+    FMM_ERR_STATE = -5     /* call out of order or unknown handle */
+} fmm_status;
+
+/* Arithmetic of the far and near field (M2L, L2P, P2P).  FMM_FP32 keeps the
+ * tree build, the moments, the walk and the momentum reductions in FP64 and
+ * runs M2L/L2P/P2P in FP32 with FP32 accumulation on leaf-relative offsets;
+ * the output accelerations are then float[n][3]. */
+enum { FMM_FP64 = 0, FMM_FP32 = 1 };
+
+/* Interaction-list policy.
+ * FMM_WALK_PHANTOM: partners are sought for leaf cells only, each with the
+ *   one-sided criterion (4) (Sec. 4); pairs "leaf <- super-cell" are never
+ *   formed in reverse.
+ * FMM_WALK_MUTUAL: symmetric dual-tree walk (the remedy of Sec. 7): every
+ *   accepted cell pair acts in both directions, cells of any level may be
+ *   sinks, and local expansions are passed down the tree (L2L). */
+enum { FMM_WALK_PHANTOM = 0, FMM_WALK_MUTUAL = 1 };
+
+/* fmm_forces flags */
+enum { FMM_REWALK = 1 /* rebuild the interaction lists even if present */ };
+
+typedef struct fmm_params {
+    double theta;      /* opening parameter of eq. (4), 0 <= theta <= 1 (default 0.5) */
+    double r_kern;     /* kernel support radius in units of h, eq. (5); M4: 2 (default) */
+    double G;          /* gravitational constant; G = 1 in the units of eq. (1) (default) */
+    int32_t leaf_size; /* a cell with at most this many particles is a leaf; 1..64 (default 8) */
+    int32_t walk;      /* FMM_WALK_* (default PHANTOM) */
+    int32_t precision; /* FMM_FP64 or FMM_FP32 (default FP64) */
+    int32_t reserved;  /* must be 0 */
+} fmm_params;
+
+/* Momentum diagnostics of Secs. 5-6, accumulated in FP64.
+ * F_i = m_i a_i.  ratio = |sumF| / sumAbsF. */
+typedef struct fmm_stats {
+    double sumF[3];
+    double sumAbsF;
+    double ratio;
+    double mass;
+    double xcom[3];
+    double P[3]; /* sum m v (0 if v == NULL) */
+    double L[3]; /* sum m x cross v (0 if v == NULL) */
+    double pad;
+} fmm_stats;
+
+typedef struct fmm_tree fmm_tree; /* opaque, library-owned */
+
+/* Fill *p with the defaults listed in fmm_params. */
+void fmm_default_params(fmm_params *p);
+
+/* Build the kd-tree of x (Sec. 2: cells are cut along their longest axis until
+ * a cell holds at most leaf_size particles).  Reading of the cut: the longest
+ * axis of the cell's particle bounding box (ties -> lowest axis) is split at
+ * the count median; the left child takes the ceil(n/2) particles that come
+ * first in the order (coordinate, Morton rank), where the Morton rank orders
+ * the particles by a 63-bit Morton key of their position quantised to 2^21
+ * per axis in the global bounding box (ties by caller index).  Both children
+ * keep ascending Morton rank.
+ *   x      device, double[n][3]; read during the call's stream work only.
+ *   n      1 <= n <= 2^31 - 1.
+ *   p      host; copied.
+ *   *tree  NULL: a new tree is allocated and returned; otherwise the given
+ *          tree (built earlier with the same n and leaf_size) is rebuilt in
+ *          place, reusing its memory.  Rebuilding invalidates the moments and
+ *          the interaction lists.
+ * Errors: FMM_ERR_INVALID (n, p out of range, NULL pointers, n/leaf_size
+ * differing from the reused tree's), FMM_ERR_ALLOC, FMM_ERR_HIP. */
+fmm_status fmm_build_tree(const double *x, int64_t n, const fmm_params *p, void *stream,
+                          fmm_tree **tree);
+
+/* Cell properties for the current tree membership (Sec. 2): mass M, centre of
+ * mass c, size s (radius of the smallest sphere about c that holds all the
+ * cell's particles), the largest smoothing length h_max, and the quadrupole
+ * of eq. (7) about c; leaves from their particles, parents by exact shifts of
+ * their children (the dipole about a centre of mass vanishes).
+ *   x, m, h  device, double[n][3], double[n], double[n]; m > 0, h > 0.
+ * The positions may differ from those the tree was built on (the tree
+ * membership is then held fixed).  The interaction lists are kept: the next
+ * fmm_forces reuses them unless it is given FMM_REWALK (this is how forces
+ * with a frozen tree and frozen lists are evaluated); fmm_build_tree discards
+ * them. */
+fmm_status fmm_moments(fmm_tree *tree, const double *x, const double *m, const double *h,
+                       void *stream);
+
+/* Accelerations a_grav = a_short + a_long (eq. (3)) for every particle.
+ * Walks the tree (building the interaction lists) when there are none or
+ * flags & FMM_REWALK, then evaluates M2L (eq. (6)), L2L (mutual walk only),
+ * L2P (eq. (8)) and the softened near field, and writes
+ *   a  device, double[n][3] (FMM_FP64) or float[n][3] (FMM_FP32), caller order.
+ * Synchronises `stream` once to size the interaction lists when it walks.
+ * Errors: FMM_ERR_STATE (no moments), FMM_ERR_INVALID (bad input data found
+ * on the device), FMM_ERR_ALLOC, FMM_ERR_HIP. */
+fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream);
+
+/* Vector-Jacobian product of the accelerations of the last fmm_forces call
+ * with respect to the positions and masses, with the tree membership and the
+ * interaction lists held fixed (the moments do depend on x and m):
+ *   a_bar  device, [n][3] cotangent of a (double or float per precision);
+ *   x_bar  device, [n][3] output, same precision;
+ *   m_bar  device, [n] output, same precision.
+ * Errors: FMM_ERR_STATE (no prior fmm_forces on this tree state). */
+fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *m_bar,
+                          void *stream);
+
+/* Momentum diagnostics (Secs. 5-6) in FP64 with a fixed reduction order
+ * (bitwise reproducible run to run):
+ *   x  device double[n][3];  v  device double[n][3] or NULL;  m  device double[n];
+ *   a  device [n][3], double if a_precision == FMM_FP64, float if FMM_FP32;
+ *   out  HOST pointer, written before the call returns (synchronises stream). */
+fmm_status fmm_momentum_stats(const double *x, const double *v, const double *m, const void *a,
+                              int32_t a_precision, int64_t n, fmm_stats *out, void *stream);
+
+/* Release a tree and its device memory (synchronises the device first).
+ * NULL is a no-op. */
+void fmm_tree_free(fmm_tree *tree);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *fmm_last_error(void);
+
+/* Sizes of a tree, host int64_t[8]: n, nodes, leaves, depth, far entries,
+ * near entries, list sinks, has_lists. */
+fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info);
+
+/* Copy the tree, cell records and interaction lists to HOST buffers (test and
+ * bring-up aid; synchronises).  Any pointer may be NULL to skip it.
+ *   perm      int32[n]      tree position -> caller index
+ *   first, count, left, right, axis   int32[nodes] (left = right = -1, axis = -1 for leaves)
+ *   rec       double[nodes][12]: M, cx, cy, cz, s, h_max, Qxx, Qxy, Qxz, Qyy, Qyz, Qzz
+ *   far_off   int64[nodes+1], far_src int32[far entries]  (CSR over sink node ids)
+ *   near_off  int64[nodes+1], near_src int32[near entries]
+ *   local     double[nodes][19]: local expansions L1(3), L2(6), L3(10) of the
+ *             last fmm_forces (zero where a node has no far field) */
+fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first, int32_t *count,
+                            int32_t *left, int32_t *right, int32_t *axis, double *rec,
+                            int64_t *far_off, int32_t *far_src, int64_t *near_off,
+                            int32_t *near_src, double *local);
+
+/* Per-stage device times of the last build/moments/forces calls in
+ * milliseconds, host double[8]: build, moments, walk, m2l+l2l, p2p+l2p, vjp,
+ * stats, total.  Timing is recorded only when enabled with
+ * fmm_set_timing(tree, 1) (it adds event synchronisation). */
+fmm_status fmm_set_timing(fmm_tree *tree, int32_t on);
+fmm_status fmm_stage_times(const fmm_tree *tree, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_MI355_H */

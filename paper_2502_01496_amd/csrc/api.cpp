@@ -1,0 +1,624 @@
+// Host side of the C ABI declared in include/fmm_mi355.h: argument checks,
+// the data-independent tree shape, device memory, and the order of launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+static constexpr uint32_t TREE_MAGIC = 0x464d4d33u;
+static thread_local std::string g_err;
+
+static fmm_status fail(fmm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? FMM_ERR_ALLOC : FMM_ERR_HIP, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                     \
+    } while (0)
+
+void build_topology(int64_t n, int leaf_size, Topology &T)
+{
+    T = Topology();
+    T.n = n;
+    T.leaf_size = leaf_size;
+    struct E {
+        int64_t f, c;
+        int32_t parent;
+        int32_t side;
+        int32_t lvl;
+    };
+    std::vector<E> st;
+    st.push_back({0, n, -1, 0, 0});
+    int64_t est = 2 * (n / std::max(1, leaf_size)) + 16;
+    T.first.reserve(est);
+    T.count.reserve(est);
+    T.left.reserve(est);
+    T.right.reserve(est);
+    T.parent.reserve(est);
+    T.level.reserve(est);
+    while (!st.empty()) {
+        E e = st.back();
+        st.pop_back();
+        int32_t id = (int32_t)T.first.size();
+        T.first.push_back((int32_t)e.f);
+        T.count.push_back((int32_t)e.c);
+        T.left.push_back(-1);
+        T.right.push_back(-1);
+        T.parent.push_back(e.parent);
+        T.level.push_back(e.lvl);
+        if (e.parent >= 0)
+            (e.side == 0 ? T.left : T.right)[e.parent] = id;
+        if (e.c > leaf_size) {
+            int64_t nl = (e.c + 1) / 2;
+            st.push_back({e.f + nl, e.c - nl, id, 1, e.lvl + 1});
+            st.push_back({e.f, nl, id, 0, e.lvl + 1});
+        }
+    }
+    T.nnodes = (int)T.first.size();
+    T.node_leaf.assign(T.nnodes, -1);
+    int maxlvl = 0;
+    for (int v = 0; v < T.nnodes; ++v) {
+        maxlvl = std::max(maxlvl, T.level[v]);
+        if (T.left[v] < 0) {
+            T.node_leaf[v] = (int32_t)T.leaf_node.size();
+            T.leaf_node.push_back(v);
+        }
+    }
+    T.nleaves = (int)T.leaf_node.size();
+    T.depth = maxlvl + 1;
+    // level-synchronous part: nodes larger than SUBTREE_MAX, left to right per level
+    std::vector<std::vector<int32_t>> up(T.depth);
+    for (int v = 0; v < T.nnodes; ++v)
+        if (T.count[v] > SUBTREE_MAX)
+            up[T.level[v]].push_back(v);
+    T.lvl_blk_off.push_back(0);
+    for (int l = 0; l < T.depth && !up[l].empty(); ++l) {
+        int nb = 0;
+        for (int v : up[l]) {
+            int bf = nb;
+            for (int64_t s = T.first[v]; s < (int64_t)T.first[v] + T.count[v]; s += LVL_CHUNK) {
+                T.blk_node.push_back(v);
+                T.blk_start.push_back((int32_t)s);
+                T.blk_end.push_back((int32_t)std::min<int64_t>(s + LVL_CHUNK,
+                                                               (int64_t)T.first[v] + T.count[v]));
+                T.blk_first.push_back(bf);
+                ++nb;
+            }
+        }
+        T.lvl_blk_off.push_back((int32_t)T.blk_node.size());
+        T.max_lvl_blocks = std::max(T.max_lvl_blocks, nb);
+        ++T.nlevels_up;
+    }
+    for (int v = 0; v < T.nnodes; ++v)
+        if (T.count[v] <= SUBTREE_MAX && (T.parent[v] < 0 || T.count[T.parent[v]] > SUBTREE_MAX))
+            T.sub_root.push_back(v);
+}
+
+template <typename P>
+static hipError_t dalloc(Tree &t, P **out, size_t elems)
+{
+    void *p = nullptr;
+    size_t bytes = std::max<size_t>(elems * sizeof(P), 256);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+        return e;
+    t.owned.push_back({p, bytes});
+    *out = (P *)p;
+    return hipSuccess;
+}
+
+template <typename P>
+static hipError_t upload(Tree &t, P **out, const std::vector<P> &v)
+{
+    hipError_t e = dalloc(t, out, v.size());
+    if (e != hipSuccess || v.empty())
+        return e;
+    return hipMemcpy(*out, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice);
+}
+
+static void release(Tree *t)
+{
+    (void)hipDeviceSynchronize();
+    for (auto &b : t->owned)
+        (void)hipFree(b.p);
+    t->owned.clear();
+    if (t->far_buf.p)
+        (void)hipFree(t->far_buf.p);
+    if (t->near_buf.p)
+        (void)hipFree(t->near_buf.p);
+    if (t->h_totals)
+        (void)hipHostFree(t->h_totals);
+    if (t->h_red)
+        (void)hipHostFree(t->h_red);
+    for (auto &e : t->ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    t->magic = 0;
+    delete t;
+}
+
+static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
+{
+    Tree *t = new Tree();
+    t->magic = TREE_MAGIC;
+    t->p = p;
+    build_topology(n, p.leaf_size, t->topo);
+    const Topology &T = t->topo;
+    const int64_t nn = T.nnodes;
+    const int64_t nblk = (n + RS_TILE - 1) / RS_TILE;
+    hipError_t e = hipSuccess;
+#define A(expr)                \
+    if (e == hipSuccess)       \
+        e = (expr);
+    A(upload(*t, &t->first, T.first));
+    A(upload(*t, &t->count, T.count));
+    A(upload(*t, &t->left, T.left));
+    A(upload(*t, &t->right, T.right));
+    A(upload(*t, &t->parent, T.parent));
+    A(upload(*t, &t->level, T.level));
+    A(upload(*t, &t->leaf_node, T.leaf_node));
+    A(upload(*t, &t->node_leaf, T.node_leaf));
+    A(upload(*t, &t->blk_node, T.blk_node));
+    A(upload(*t, &t->blk_start, T.blk_start));
+    A(upload(*t, &t->blk_end, T.blk_end));
+    A(upload(*t, &t->blk_first, T.blk_first));
+    A(upload(*t, &t->sub_root, T.sub_root));
+    A(dalloc(*t, &t->axis, nn));
+    A(dalloc(*t, &t->keys0, 3 * n));
+    A(dalloc(*t, &t->keys1, 3 * n));
+    A(dalloc(*t, &t->vals0, 3 * n));
+    A(dalloc(*t, &t->vals1, 3 * n));
+    A(dalloc(*t, &t->rs_hist, 3 * 256 * nblk));
+    A(dalloc(*t, &t->rs_tot, (size_t)RS_PASSES * 3 * 256));
+    A(dalloc(*t, &t->r2o, n));
+    A(dalloc(*t, &t->xr, 3 * n));
+    A(dalloc(*t, &t->lists, 8 * n));
+    A(dalloc(*t, &t->flag, n));
+    A(dalloc(*t, &t->lvl_cnt, 4 * (size_t)std::max(1, T.max_lvl_blocks)));
+    A(dalloc(*t, &t->lvl_pre, 4 * (size_t)std::max(1, T.max_lvl_blocks)));
+    A(dalloc(*t, &t->bbox, 8));
+    A(dalloc(*t, &t->err, 4));
+    A(dalloc(*t, &t->perm, n));
+    A(dalloc(*t, &t->pm, n));
+    A(dalloc(*t, &t->hs, n));
+    A(dalloc(*t, &t->ph, n));
+    A(dalloc(*t, &t->pf, n));
+    A(dalloc(*t, &t->pfh, n));
+    A(dalloc(*t, &t->recA, NREC * nn));
+    A(dalloc(*t, &t->recQ, NREC * nn));
+    A(dalloc(*t, &t->recF, NREC * nn));
+    A(dalloc(*t, &t->s2bits, nn));
+    A(dalloc(*t, &t->upcnt, nn));
+    A(dalloc(*t, &t->far_cnt, nn));
+    A(dalloc(*t, &t->near_cnt, nn));
+    A(dalloc(*t, &t->far_off, nn + 1));
+    A(dalloc(*t, &t->near_off, nn + 1));
+    A(dalloc(*t, &t->scan_tmp, 2 * (nn / 4096 + 2)));
+    A(dalloc(*t, &t->totals, 4));
+    A(dalloc(*t, &t->L, NLOC * nn));
+    A(dalloc(*t, &t->Lf, NLOC * nn));
+    A(dalloc(*t, &t->red, 16 + 16 * 512));
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&t->h_totals, 4 * sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&t->h_red, 16 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipEventCreate(&t->ev[0]);
+    if (e == hipSuccess)
+        e = hipEventCreate(&t->ev[1]);
+#undef A
+    if (e != hipSuccess) {
+        fmm_status st = fail(e == hipErrorOutOfMemory ? FMM_ERR_ALLOC : FMM_ERR_HIP,
+                             "tree allocation failed: %s", hipGetErrorString(e));
+        release(t);
+        return st;
+    }
+    *out = t;
+    return FMM_OK;
+}
+
+static bool tree_ok(const fmm_tree *h)
+{
+    return h && reinterpret_cast<const Tree *>(h)->magic == TREE_MAGIC;
+}
+
+static fmm_status check_params(const fmm_params *p)
+{
+    if (!p)
+        return fail(FMM_ERR_INVALID, "params is NULL");
+    if (!(p->theta >= 0.0 && p->theta <= 1.0))
+        return fail(FMM_ERR_INVALID, "theta must lie in [0, 1] (got %g)", p->theta);
+    if (!(p->r_kern > 0.0 && std::isfinite(p->r_kern)))
+        return fail(FMM_ERR_INVALID, "r_kern must be positive and finite");
+    if (!std::isfinite(p->G))
+        return fail(FMM_ERR_INVALID, "G must be finite");
+    if (p->leaf_size < 1 || p->leaf_size > MAX_LEAF)
+        return fail(FMM_ERR_INVALID, "leaf_size must lie in [1, %d]", MAX_LEAF);
+    if (p->walk != FMM_WALK_PHANTOM && p->walk != FMM_WALK_MUTUAL)
+        return fail(FMM_ERR_INVALID, "unknown walk policy %d", p->walk);
+    if (p->walk == FMM_WALK_MUTUAL)
+        return fail(FMM_ERR_INVALID, "the mutual walk is not available in this library build");
+    if (p->precision != FMM_FP64 && p->precision != FMM_FP32)
+        return fail(FMM_ERR_INVALID, "unknown precision %d", p->precision);
+    if (p->reserved != 0)
+        return fail(FMM_ERR_INVALID, "reserved must be 0");
+    return FMM_OK;
+}
+
+// stage timing (only when enabled)
+struct StageTimer {
+    Tree &t;
+    hipStream_t s;
+    int slot;
+    StageTimer(Tree &tt, hipStream_t ss, int sl) : t(tt), s(ss), slot(sl)
+    {
+        if (t.timing)
+            (void)hipEventRecord(t.ev[0], s);
+    }
+    void done()
+    {
+        if (!t.timing)
+            return;
+        (void)hipEventRecord(t.ev[1], s);
+        (void)hipEventSynchronize(t.ev[1]);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t.ev[0], t.ev[1]);
+        t.times[slot] = ms;
+    }
+};
+
+static fmm_status ensure_capacity(Tree &t, DevBuf &b, int32_t **ptr, int64_t &cap, int64_t need)
+{
+    if (need <= cap && b.p)
+        return FMM_OK;
+    int64_t nc = std::max<int64_t>(need + need / 4, 1024);
+    if (b.p) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(b.p));
+        b.p = nullptr;
+    }
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, (size_t)nc * sizeof(int32_t)));
+    b.p = p;
+    b.bytes = (size_t)nc * sizeof(int32_t);
+    *ptr = (int32_t *)p;
+    cap = nc;
+    return FMM_OK;
+}
+
+static std::mutex g_scratch_mu;
+static std::map<int, std::pair<double *, double *>> g_scratch;
+
+static fmm_status stats_scratch(double **dev, double **host)
+{
+    int d = 0;
+    HIP_TRY(hipGetDevice(&d));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(d);
+    if (it == g_scratch.end()) {
+        double *dp = nullptr, *hp = nullptr;
+        HIP_TRY(hipMalloc((void **)&dp, (16 + 16 * 512) * sizeof(double)));
+        HIP_TRY(hipHostMalloc((void **)&hp, 16 * sizeof(double), hipHostMallocDefault));
+        it = g_scratch.emplace(d, std::make_pair(dp, hp)).first;
+    }
+    *dev = it->second.first;
+    *host = it->second.second;
+    return FMM_OK;
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+extern "C" {
+
+void fmm_default_params(fmm_params *p)
+{
+    if (!p)
+        return;
+    p->theta = 0.5;
+    p->r_kern = 2.0;
+    p->G = 1.0;
+    p->leaf_size = 8;
+    p->walk = FMM_WALK_PHANTOM;
+    p->precision = FMM_FP64;
+    p->reserved = 0;
+}
+
+const char *fmm_last_error(void) { return g_err.c_str(); }
+
+fmm_status fmm_build_tree(const double *x, int64_t n, const fmm_params *p, void *stream,
+                          fmm_tree **tree)
+{
+    if (!x || !tree)
+        return fail(FMM_ERR_INVALID, "x and tree must not be NULL");
+    if (n < 1 || n > (int64_t)INT32_MAX)
+        return fail(FMM_ERR_INVALID, "n must lie in [1, 2^31-1] (got %lld)", (long long)n);
+    fmm_status st = check_params(p);
+    if (st != FMM_OK)
+        return st;
+    Tree *t = nullptr;
+    if (*tree) {
+        if (!tree_ok(*tree))
+            return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+        t = reinterpret_cast<Tree *>(*tree);
+        if (t->topo.n != n || t->topo.leaf_size != p->leaf_size)
+            return fail(FMM_ERR_INVALID, "a reused tree must keep n and leaf_size");
+        t->p = *p;
+    } else {
+        st = create_tree(n, *p, &t);
+        if (st != FMM_OK)
+            return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    StageTimer tm(*t, s, 0);
+    hipError_t e = launch_build(*t, x, s);
+    if (e != hipSuccess) {
+        if (!*tree)
+            release(t);
+        return fail(FMM_ERR_HIP, "tree build launch failed: %s", hipGetErrorString(e));
+    }
+    tm.done();
+    t->has_tree = true;
+    t->has_moments = t->has_lists = t->has_forces = false;
+    *tree = reinterpret_cast<fmm_tree *>(t);
+    return FMM_OK;
+}
+
+fmm_status fmm_moments(fmm_tree *tree, const double *x, const double *m, const double *h,
+                       void *stream)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!x || !m || !h)
+        return fail(FMM_ERR_INVALID, "x, m and h must not be NULL");
+    Tree &t = *reinterpret_cast<Tree *>(tree);
+    if (!t.has_tree)
+        return fail(FMM_ERR_STATE, "the tree has not been built");
+    hipStream_t s = (hipStream_t)stream;
+    StageTimer tm(t, s, 1);
+    hipError_t e = launch_moments(t, x, m, h, s);
+    if (e != hipSuccess)
+        return fail(FMM_ERR_HIP, "moments launch failed: %s", hipGetErrorString(e));
+    tm.done();
+    t.has_moments = true;
+    t.has_forces = false;
+    return FMM_OK;
+}
+
+fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!a)
+        return fail(FMM_ERR_INVALID, "a must not be NULL");
+    Tree &t = *reinterpret_cast<Tree *>(tree);
+    if (!t.has_moments)
+        return fail(FMM_ERR_STATE, "fmm_moments must run before fmm_forces");
+    hipStream_t s = (hipStream_t)stream;
+    if (!t.has_lists || (flags & FMM_REWALK) || t.lists_policy != t.p.walk) {
+        StageTimer tm(t, s, 2);
+        HIP_TRY(launch_walk_count(t, s));
+        HIP_TRY(hipMemcpyAsync(t.h_totals, t.totals, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(t.h_totals + 2, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        uint32_t errbits = (uint32_t)(t.h_totals[2] & 0xffffffffu);
+        if (errbits) {
+            t.has_lists = false;
+            return fail(FMM_ERR_INVALID, "bad input data:%s%s%s",
+                        (errbits & 1) ? " non-finite positions" : "",
+                        (errbits & 2) ? " masses not positive and finite" : "",
+                        (errbits & 4) ? " smoothing lengths not positive and finite" : "");
+        }
+        t.n_far = t.h_totals[0];
+        t.n_near = t.h_totals[1];
+        fmm_status st = ensure_capacity(t, t.far_buf, &t.far_src, t.cap_far, t.n_far);
+        if (st != FMM_OK)
+            return st;
+        st = ensure_capacity(t, t.near_buf, &t.near_src, t.cap_near, t.n_near);
+        if (st != FMM_OK)
+            return st;
+        HIP_TRY(launch_walk_fill(t, s));
+        tm.done();
+        t.has_lists = true;
+        t.lists_policy = t.p.walk;
+        t.nsinks = t.topo.nleaves;
+    }
+    {
+        StageTimer tm(t, s, 3);
+        HIP_TRY(launch_far(t, s));
+        tm.done();
+    }
+    {
+        StageTimer tm(t, s, 4);
+        HIP_TRY(launch_near(t, a, s));
+        tm.done();
+    }
+    t.has_forces = true;
+    return FMM_OK;
+}
+
+fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *m_bar,
+                          void *stream)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!a_bar || !x_bar || !m_bar)
+        return fail(FMM_ERR_INVALID, "a_bar, x_bar and m_bar must not be NULL");
+    Tree &t = *reinterpret_cast<Tree *>(tree);
+    if (!t.has_forces)
+        return fail(FMM_ERR_STATE, "fmm_forces must run on this tree state before the VJP");
+    hipStream_t s = (hipStream_t)stream;
+    StageTimer tm(t, s, 5);
+    hipError_t e = launch_vjp(t, a_bar, x_bar, m_bar, s);
+    if (e != hipSuccess)
+        return fail(FMM_ERR_HIP, "vjp launch failed: %s", hipGetErrorString(e));
+    tm.done();
+    return FMM_OK;
+}
+
+fmm_status fmm_momentum_stats(const double *x, const double *v, const double *m, const void *a,
+                              int32_t a_precision, int64_t n, fmm_stats *out, void *stream)
+{
+    if (!x || !m || !a || !out)
+        return fail(FMM_ERR_INVALID, "x, m, a and out must not be NULL");
+    if (n < 1)
+        return fail(FMM_ERR_INVALID, "n must be positive");
+    if (a_precision != FMM_FP64 && a_precision != FMM_FP32)
+        return fail(FMM_ERR_INVALID, "unknown precision %d", a_precision);
+    double *dev = nullptr, *host = nullptr;
+    fmm_status st = stats_scratch(&dev, &host);
+    if (st != FMM_OK)
+        return st;
+    HIP_TRY(launch_stats(x, v, m, a, a_precision == FMM_FP32, n, dev, host, (hipStream_t)stream));
+    static_assert(sizeof(fmm_stats) == 16 * sizeof(double), "fmm_stats layout");
+    std::memcpy(out, host, sizeof(fmm_stats));
+    return FMM_OK;
+}
+
+void fmm_tree_free(fmm_tree *tree)
+{
+    if (!tree_ok(tree))
+        return;
+    release(reinterpret_cast<Tree *>(tree));
+}
+
+fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!info)
+        return fail(FMM_ERR_INVALID, "info must not be NULL");
+    const Tree &t = *reinterpret_cast<const Tree *>(tree);
+    info[0] = t.topo.n;
+    info[1] = t.topo.nnodes;
+    info[2] = t.topo.nleaves;
+    info[3] = t.topo.depth;
+    info[4] = t.has_lists ? t.n_far : 0;
+    info[5] = t.has_lists ? t.n_near : 0;
+    info[6] = t.has_lists ? t.nsinks : 0;
+    info[7] = t.has_lists ? 1 : 0;
+    return FMM_OK;
+}
+
+fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first, int32_t *count,
+                            int32_t *left, int32_t *right, int32_t *axis, double *rec,
+                            int64_t *far_off, int32_t *far_src, int64_t *near_off,
+                            int32_t *near_src, double *local)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    const Tree &t = *reinterpret_cast<const Tree *>(tree);
+    const Topology &T = t.topo;
+    const int64_t nn = T.nnodes;
+    HIP_TRY(hipDeviceSynchronize());
+    if (perm)
+        HIP_TRY(hipMemcpy(perm, t.perm, T.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (first)
+        std::memcpy(first, T.first.data(), nn * sizeof(int32_t));
+    if (count)
+        std::memcpy(count, T.count.data(), nn * sizeof(int32_t));
+    if (left)
+        std::memcpy(left, T.left.data(), nn * sizeof(int32_t));
+    if (right)
+        std::memcpy(right, T.right.data(), nn * sizeof(int32_t));
+    if (axis) {
+        HIP_TRY(hipMemcpy(axis, t.axis, nn * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t v = 0; v < nn; ++v)
+            if (T.left[v] < 0)
+                axis[v] = -1;
+    }
+    if (rec) {
+        std::vector<double> a(NREC * nn), q(NREC * nn);
+        HIP_TRY(hipMemcpy(a.data(), t.recA, a.size() * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(q.data(), t.recQ, q.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int64_t v = 0; v < nn; ++v) {
+            double *r = rec + 12 * v;
+            r[0] = a[NREC * v + 3];
+            r[1] = a[NREC * v + 0];
+            r[2] = a[NREC * v + 1];
+            r[3] = a[NREC * v + 2];
+            r[4] = a[NREC * v + 4];
+            r[5] = a[NREC * v + 5];
+            for (int k = 0; k < 6; ++k)
+                r[6 + k] = q[NREC * v + k];
+        }
+    }
+    if (far_off || far_src || near_off || near_src) {
+        if (!t.has_lists)
+            return fail(FMM_ERR_STATE, "no interaction lists to export");
+        int ns = t.nsinks;
+        std::vector<int64_t> fo(ns + 1), no(ns + 1);
+        HIP_TRY(hipMemcpy(fo.data(), t.far_off, (ns + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(no.data(), t.near_off, (ns + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+        // sinks are leaves (indexed by leaf) -> node-indexed CSR, same entry order
+        auto to_nodes = [&](const std::vector<int64_t> &o, int64_t *out) {
+            out[0] = 0;
+            for (int64_t v = 0; v < nn; ++v) {
+                int lf = T.node_leaf[v];
+                out[v + 1] = out[v] + (lf >= 0 ? o[lf + 1] - o[lf] : 0);
+            }
+        };
+        if (far_off)
+            to_nodes(fo, far_off);
+        if (near_off)
+            to_nodes(no, near_off);
+        if (far_src && t.n_far)
+            HIP_TRY(hipMemcpy(far_src, t.far_src, t.n_far * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (near_src && t.n_near)
+            HIP_TRY(hipMemcpy(near_src, t.near_src, t.n_near * sizeof(int32_t),
+                              hipMemcpyDeviceToHost));
+    }
+    if (local) {
+        std::vector<double> Lh(NLOC * nn);
+        HIP_TRY(hipMemcpy(Lh.data(), t.L, Lh.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int64_t v = 0; v < nn; ++v)
+            for (int k = 0; k < 19; ++k)
+                local[19 * v + k] = (t.has_forces && T.left[v] < 0) ? Lh[NLOC * v + k] : 0.0;
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_set_timing(fmm_tree *tree, int32_t on)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    reinterpret_cast<Tree *>(tree)->timing = on != 0;
+    return FMM_OK;
+}
+
+fmm_status fmm_stage_times(const fmm_tree *tree, double *ms)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!ms)
+        return fail(FMM_ERR_INVALID, "ms must not be NULL");
+    const Tree &t = *reinterpret_cast<const Tree *>(tree);
+    double tot = 0.0;
+    for (int k = 0; k < 7; ++k) {
+        ms[k] = t.times[k];
+        tot += t.times[k];
+    }
+    ms[7] = tot;
+    return FMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,682 @@
+// kd-tree build on gfx950.
+//
+// The paper's tree (Sec. 2) cuts every cell along its longest axis until a
+// cell holds at most a few particles.  The cut used here is the count median
+// of the longest axis of the cell's particle bounding box, ties broken by
+// (coordinate, Morton rank); both halves keep ascending Morton rank.
+//
+// Steps (all on the caller's stream):
+//   1. global bounding box (ordered-bit atomics, order-free);
+//   2. 63-bit Morton keys of positions quantised to 2^21 per axis;
+//   3. stable LSD radix sort by key -> Morton rank order;
+//   4. three stable radix sorts by ordered coordinate bits, from rank order,
+//      giving per axis the particles sorted by (x_d, rank);
+//   5. for cells larger than SUBTREE_MAX, one level at a time: the median of
+//      the longest axis is the middle entry of that axis's sorted segment, so
+//      the split is a stable partition of the four lists (three axis lists +
+//      the rank list) by a per-particle side flag;
+//   6. every cell of at most SUBTREE_MAX particles is finished by one
+//      workgroup in LDS (all levels below it), which writes the final order.
+//
+// Compiled with -ffp-contract=off: the quantisation and the split-axis test
+// are single IEEE operations in the same order as the definition.
+#include "fmm_internal.h"
+
+namespace fmm {
+
+// ---------------------------------------------------------------- bbox / keys
+__global__ void k_bbox_init(uint64_t *bbox, uint32_t *err)
+{
+    int t = threadIdx.x;
+    if (t < 3) {
+        bbox[t] = ~0ull;
+        bbox[3 + t] = 0ull;
+    }
+    if (t == 0)
+        err[0] = 0u;
+}
+
+__global__ void k_bbox(const double *__restrict__ x, int64_t n, uint64_t *bbox, uint32_t *err)
+{
+    uint64_t mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v = x[3 * i + d];
+            bad |= !isfinite(v);
+            uint64_t k = ordbits(v);
+            mn[d] = k < mn[d] ? k : mn[d];
+            mx[d] = k > mx[d] ? k : mx[d];
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            uint64_t a = __shfl_xor(mn[d], off);
+            uint64_t b = __shfl_xor(mx[d], off);
+            mn[d] = a < mn[d] ? a : mn[d];
+            mx[d] = b > mx[d] ? b : mx[d];
+        }
+    uint64_t anybad = __ballot(bad);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            atomicMin((unsigned long long *)&bbox[d], (unsigned long long)mn[d]);
+            atomicMax((unsigned long long *)&bbox[3 + d], (unsigned long long)mx[d]);
+        }
+        if (anybad)
+            atomicOr(err, 1u);
+    }
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_morton(const double *__restrict__ x, int64_t n, const uint64_t *bbox,
+                         uint64_t *keys, uint32_t *vals)
+{
+    double lo[3], ext = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = from_ordbits(bbox[d]);
+        double e = from_ordbits(bbox[3 + d]) - lo[d];
+        if (e > ext)
+            ext = e;
+    }
+    if (ext == 0.0)
+        ext = 1.0;
+    double scale = 2097152.0 / ext;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t k = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double t = floor((x[3 * i + d] - lo[d]) * scale);
+            uint64_t q = t >= 2097151.0 ? 2097151ull : (t >= 0.0 ? (uint64_t)t : 0ull);
+            k |= spread3(q) << d;
+        }
+        keys[i] = k;
+        vals[i] = (uint32_t)i;
+    }
+}
+
+// Coordinates in Morton-rank order, and the three axis keys (ordered bits,
+// value = rank) for the per-axis sorts; the rank list starts as the identity.
+__global__ void k_rank_gather(const double *__restrict__ x, int64_t n, const uint32_t *order,
+                              int32_t *r2o, double *xr, uint64_t *keys, uint32_t *vals,
+                              uint32_t *ranklist)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = order[r];
+        r2o[r] = (int32_t)i;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v = x[3 * i + d];
+            xr[d * n + r] = v;
+            keys[d * n + r] = ordbits(v);
+            vals[d * n + r] = (uint32_t)r;
+        }
+        ranklist[r] = (uint32_t)r;
+    }
+}
+
+// ---------------------------------------------------------------- radix sort
+// Stable LSD radix sort of B independent (key u64, value u32) arrays of
+// length n laid out back to back.  Per 8-bit pass: per-tile digit histograms,
+// a scan per (digit, array) over the tiles, then a stable scatter.  Inside a
+// tile the four waves take consecutive quarters; a wave ranks its 64 keys of a
+// round with ballot-based digit matching, so rank order = input order.
+__global__ void k_rs_zero(uint32_t *p, int64_t cnt)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restrict__ keys,
+                                                        int64_t n, int shift, uint32_t *hist,
+                                                        uint32_t *tot, int nblk)
+{
+    __shared__ uint32_t h[256];
+    int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
+    h[t] = 0u;
+    __syncthreads();
+    const uint64_t *k = keys + (int64_t)b * n;
+    int64_t base = (int64_t)blk * RS_TILE;
+#pragma unroll 4
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        int64_t i = base + r * RS_THREADS + t;
+        if (i < n)
+            atomicAdd(&h[(uint32_t)(k[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    uint32_t c = h[t];
+    hist[((int64_t)b * 256 + t) * nblk + blk] = c;
+    if (c)
+        atomicAdd(&tot[b * 256 + t], c);
+}
+
+// Exclusive scan across one block of up to 256 threads (values <= 2^32).
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    int t = threadIdx.x, lane = lane_id(), w = t >> 6, nw = blockDim.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(inc, off);
+        if (lane >= off)
+            inc += o;
+    }
+    if (lane == 63)
+        sh[w] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        uint32_t s = sh[i];
+        wbase += i < w ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return wbase + inc - v;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scan(uint32_t *hist, const uint32_t *tot,
+                                                        int nblk)
+{
+    __shared__ uint32_t sh[8];
+    int d = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    uint32_t mine = t < d ? tot[b * 256 + t] : 0u;
+    uint32_t base;
+    block_excl_scan_u32(mine, sh, base);
+    uint32_t *row = hist + ((int64_t)b * 256 + d) * nblk;
+    uint32_t run = base;
+    for (int c0 = 0; c0 < nblk; c0 += RS_THREADS) {
+        int i = c0 + t;
+        uint32_t v = i < nblk ? row[i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_excl_scan_u32(v, sh, total);
+        if (i < nblk)
+            row[i] = run + ex;
+        run += total;
+    }
+}
+
+__device__ __forceinline__ uint64_t match_u8(uint32_t d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        bool on = (d >> bit) & 1u;
+        uint64_t bb = __ballot(valid && on);
+        m &= on ? bb : ~bb;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
+    uint32_t *vout, int64_t n, int shift, const uint32_t *__restrict__ hist, int nblk)
+{
+    __shared__ uint32_t wrun[4][256];
+    __shared__ uint32_t gofs[256];
+    int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        wrun[i][t] = 0u;
+    __syncthreads();
+    const uint64_t *k = kin + (int64_t)b * n;
+    const uint32_t *v = vin + (int64_t)b * n;
+    int64_t wbase = (int64_t)blk * RS_TILE + (int64_t)w * (RS_TILE / 4);
+    uint32_t rank[RS_ROUNDS];
+    uint32_t dig[RS_ROUNDS];
+    uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        int64_t i = wbase + r * 64 + lane;
+        bool valid = i < n;
+        uint32_t d = valid ? (uint32_t)(k[i] >> shift) & 255u : 0u;
+        uint64_t peers = match_u8(d, valid);
+        uint32_t cur = wrun[w][d];
+        rank[r] = cur + (uint32_t)__popcll(peers & lt);
+        dig[r] = d;
+        bool leader = valid && ((peers & lt) == 0ull);
+        if (leader)
+            wrun[w][d] = cur + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t c = wrun[i][t];
+            wrun[i][t] = s;
+            s += c;
+        }
+        gofs[t] = hist[((int64_t)b * 256 + t) * nblk + blk];
+    }
+    __syncthreads();
+    uint64_t *ko = kout + (int64_t)b * n;
+    uint32_t *vo = vout + (int64_t)b * n;
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        int64_t i = wbase + r * 64 + lane;
+        if (i < n) {
+            uint32_t d = dig[r];
+            int64_t pos = (int64_t)gofs[d] + wrun[w][d] + rank[r];
+            ko[pos] = k[i];
+            vo[pos] = v[i];
+        }
+    }
+}
+
+// Sort B arrays; the result ends in (k0, v0) after an even number of passes.
+static hipError_t radix_sort(Tree &t, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                             int64_t n, int B, hipStream_t s)
+{
+    int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
+    k_rs_zero<<<64, 256, 0, s>>>(t.rs_tot, (int64_t)RS_PASSES * B * 256);
+    for (int pass = 0; pass < RS_PASSES; ++pass) {
+        int shift = 8 * pass;
+        uint64_t *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
+        uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
+        uint32_t *tot = t.rs_tot + (int64_t)pass * B * 256;
+        dim3 g(nblk, B);
+        k_rs_hist<<<g, RS_THREADS, 0, s>>>(ki, n, shift, t.rs_hist, tot, nblk);
+        k_rs_scan<<<dim3(256, B), RS_THREADS, 0, s>>>(t.rs_hist, tot, nblk);
+        k_rs_scatter<<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, t.rs_hist, nblk);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- level kernels
+// Longest axis of a node from its three sorted lists (first = min, last = max).
+__device__ __forceinline__ int node_axis(const uint32_t *L, int64_t n, const double *xr,
+                                         int64_t f, int64_t c)
+{
+    int ax = 0;
+    double best = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double lo = xr[d * n + L[d * n + f]];
+        double hi = xr[d * n + L[d * n + f + c - 1]];
+        double e = hi - lo;
+        if (d == 0 || e > best) {
+            best = e;
+            ax = d;
+        }
+    }
+    return ax;
+}
+
+__global__ __launch_bounds__(LVL_THREADS) void k_lvl_flags(
+    const uint32_t *__restrict__ L, int64_t n, const double *__restrict__ xr,
+    const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
+    const int32_t *first, const int32_t *count, uint8_t *flag, int32_t *axis_out)
+{
+    int b = blockIdx.x;
+    int v = blk_node[b];
+    int64_t f = first[v], c = count[v], nl = (c + 1) / 2;
+    int ax = node_axis(L, n, xr, f, c);
+    if (threadIdx.x == 0 && blk_start[b] == f)
+        axis_out[v] = ax;
+    const uint32_t *La = L + ax * n;
+    for (int64_t p = blk_start[b] + threadIdx.x; p < blk_end[b]; p += LVL_THREADS)
+        flag[La[p]] = (uint8_t)(p - f < nl);
+}
+
+__global__ __launch_bounds__(LVL_THREADS) void k_lvl_count(
+    const uint32_t *__restrict__ L, int64_t n, const int32_t *blk_start, const int32_t *blk_end,
+    const uint8_t *__restrict__ flag, int32_t *cnt, int stride)
+{
+    __shared__ uint32_t sh[8];
+    int b = blockIdx.x, d = blockIdx.y;
+    const uint32_t *Ld = L + d * n;
+    uint32_t c = 0;
+    for (int64_t p = blk_start[b] + threadIdx.x; p < blk_end[b]; p += LVL_THREADS)
+        c += flag[Ld[p]];
+    uint32_t total;
+    block_excl_scan_u32(c, sh, total);
+    if (threadIdx.x == 0)
+        cnt[d * stride + b] = (int32_t)total;
+}
+
+__global__ __launch_bounds__(1024) void k_lvl_scan(const int32_t *cnt, int32_t *pre, int nb,
+                                                   int stride)
+{
+    __shared__ uint32_t sh[16];
+    int d = blockIdx.x;
+    uint32_t run = 0;
+    for (int c0 = 0; c0 < nb; c0 += 1024) {
+        int i = c0 + threadIdx.x;
+        uint32_t v = i < nb ? (uint32_t)cnt[d * stride + i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_excl_scan_u32(v, sh, total);
+        if (i < nb)
+            pre[d * stride + i] = (int32_t)(run + ex);
+        run += total;
+    }
+}
+
+__global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
+    const uint32_t *__restrict__ Lsrc, uint32_t *Ldst, int64_t n, const int32_t *blk_node,
+    const int32_t *blk_start, const int32_t *blk_end, const int32_t *blk_first,
+    const int32_t *first, const int32_t *count, const uint8_t *__restrict__ flag,
+    const int32_t *pre, int stride)
+{
+    constexpr int PER = LVL_CHUNK / LVL_THREADS;
+    __shared__ uint32_t sh[8];
+    int b = blockIdx.x, d = blockIdx.y;
+    int v = blk_node[b];
+    int64_t f = first[v], c = count[v], nl = (c + 1) / 2;
+    int64_t s = blk_start[b], e = blk_end[b];
+    const uint32_t *Ls = Lsrc + d * n;
+    uint32_t *Ld = Ldst + d * n;
+    uint32_t r[PER];
+    uint32_t fl[PER];
+    uint32_t mine = 0;
+    int64_t p0 = s + (int64_t)threadIdx.x * PER;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int64_t p = p0 + k;
+        r[k] = p < e ? Ls[p] : 0u;
+        fl[k] = p < e ? flag[r[k]] : 0u;
+        mine += fl[k];
+    }
+    uint32_t total;
+    uint32_t ex = block_excl_scan_u32(mine, sh, total);
+    int64_t nb = (int64_t)(pre[d * stride + b] - pre[d * stride + blk_first[b]]) + ex;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int64_t p = p0 + k;
+        if (p < e) {
+            int64_t pos;
+            if (fl[k]) {
+                pos = f + nb;
+                ++nb;
+            } else {
+                pos = f + nl + (p - f - nb);
+            }
+            Ld[pos] = r[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- LDS subtrees
+// Exclusive scan of 64-bit packed counters across the block.
+__device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh)
+{
+    int t = threadIdx.x, lane = lane_id(), w = t >> 6, nw = blockDim.x >> 6;
+    uint64_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t o = __shfl_up(inc, off);
+        if (lane >= off)
+            inc += o;
+    }
+    if (lane == 63)
+        sh[w] = inc;
+    __syncthreads();
+    uint64_t wb = 0;
+    for (int i = 0; i < nw; ++i)
+        wb += i < w ? sh[i] : 0ull;
+    __syncthreads();
+    return wb + inc - v;
+}
+
+__device__ __forceinline__ int find_seg(const int16_t *sf, const int16_t *sn, int nseg, int p)
+{
+    int lo = 0, hi = nseg - 1, k = -1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        if (sf[mid] <= p) {
+            k = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (k >= 0 && p < sf[k] + sn[k])
+        return k;
+    return -1;
+}
+
+__global__ __launch_bounds__(SUBTREE_THREADS) void k_subtree(
+    const uint32_t *__restrict__ Lall, int64_t n, const double *__restrict__ xr,
+    const int32_t *__restrict__ r2o, const int32_t *__restrict__ sub_root,
+    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+    const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+    const int32_t *__restrict__ level, int leaf_size, int32_t *perm, int32_t *axis_out)
+{
+    constexpr int PER = SUBTREE_MAX / SUBTREE_THREADS;  // 4 positions per thread
+    __shared__ uint32_t rk[SUBTREE_MAX];
+    __shared__ uint16_t lst[2][3][SUBTREE_MAX];
+    __shared__ uint8_t flg[SUBTREE_MAX];
+    __shared__ int16_t sf[2][SUBTREE_MAXSEG], sn[2][SUBTREE_MAXSEG];
+    __shared__ int32_t snode[2][SUBTREE_MAXSEG];
+    __shared__ uint8_t sax[SUBTREE_MAXSEG];
+    __shared__ uint64_t segE[SUBTREE_MAXSEG];
+    __shared__ uint32_t emit_ofs[SUBTREE_MAXSEG];
+    __shared__ uint64_t shs[16];
+    __shared__ int nseg_sh[2];
+
+    const int t = threadIdx.x;
+    const int root = sub_root[blockIdx.x];
+    const int64_t f0 = first[root];
+    const int n0 = count[root];
+    const uint32_t *L = Lall + (int64_t)(level[root] & 1) * 4 * n;
+
+    for (int p = t; p < n0; p += SUBTREE_THREADS)
+        rk[p] = L[3 * n + f0 + p];
+    __syncthreads();
+    for (int d = 0; d < 3; ++d)
+        for (int p = t; p < n0; p += SUBTREE_THREADS) {
+            uint32_t r = L[d * n + f0 + p];
+            int lo = 0, hi = n0;  // lower_bound in the ascending rank list
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (rk[mid] < r)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            lst[0][d][p] = (uint16_t)lo;
+        }
+    if (t == 0) {
+        sf[0][0] = 0;
+        sn[0][0] = (int16_t)n0;
+        snode[0][0] = root;
+        nseg_sh[0] = n0 > leaf_size ? 1 : 0;
+    }
+    __syncthreads();
+
+    int cur = 0;
+    int nseg = nseg_sh[0];
+    while (nseg > 0) {
+        const int nxt = cur ^ 1;
+        // A. split axis per segment and the number of children that split again
+        uint32_t my_emit[2] = {0u, 0u};
+        for (int q = 0; q < 2; ++q) {
+            int k = t * 2 + q;
+            if (k < nseg) {
+                int fk = sf[cur][k], nk = sn[cur][k];
+                int ax = 0;
+                double best = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    double lo = xr[d * n + rk[lst[cur][d][fk]]];
+                    double hi = xr[d * n + rk[lst[cur][d][fk + nk - 1]]];
+                    double e = hi - lo;
+                    if (d == 0 || e > best) {
+                        best = e;
+                        ax = d;
+                    }
+                }
+                sax[k] = (uint8_t)ax;
+                axis_out[snode[cur][k]] = ax;
+                int nl = (nk + 1) >> 1;
+                my_emit[q] = (uint32_t)(nl > leaf_size) + (uint32_t)(nk - nl > leaf_size);
+            }
+        }
+        {
+            uint32_t tot2;
+            uint32_t ex = block_excl_scan_u32(my_emit[0] + my_emit[1], (uint32_t *)shs, tot2);
+            if (t * 2 < nseg)
+                emit_ofs[t * 2] = ex;
+            if (t * 2 + 1 < nseg)
+                emit_ofs[t * 2 + 1] = ex + my_emit[0];
+            if (t == 0)
+                nseg_sh[nxt] = (int)tot2;
+        }
+        __syncthreads();
+        // B. side flags, by local id, from the split axis's list
+        for (int p = t; p < n0; p += SUBTREE_THREADS) {
+            int k = find_seg(sf[cur], sn[cur], nseg, p);
+            if (k >= 0) {
+                int fk = sf[cur][k], nk = sn[cur][k];
+                flg[lst[cur][sax[k]][p]] = (uint8_t)(p - fk < ((nk + 1) >> 1));
+            }
+        }
+        __syncthreads();
+        // C. packed exclusive scan of the flags of the three lists
+        int segk[PER];
+        uint64_t pk[PER];
+        uint64_t mine = 0;
+        const int pbase = t * PER;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int p = pbase + j;
+            segk[j] = p < n0 ? find_seg(sf[cur], sn[cur], nseg, p) : -1;
+            uint64_t v = 0;
+            if (segk[j] >= 0) {
+                v = (uint64_t)flg[lst[cur][0][p]] | ((uint64_t)flg[lst[cur][1][p]] << 21) |
+                    ((uint64_t)flg[lst[cur][2][p]] << 42);
+            }
+            pk[j] = v;
+            mine += v;
+        }
+        uint64_t ex = block_excl_scan_u64(mine, shs);
+        uint64_t E[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            E[j] = ex;
+            ex += pk[j];
+            int p = pbase + j;
+            if (segk[j] >= 0 && p == sf[cur][segk[j]])
+                segE[segk[j]] = E[j];
+        }
+        __syncthreads();
+        // D. stable partition into the other buffer; unsplit positions copy through
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int p = pbase + j;
+            if (p >= n0)
+                continue;
+            int k = segk[j];
+            if (k < 0) {
+                for (int d = 0; d < 3; ++d)
+                    lst[nxt][d][p] = lst[cur][d][p];
+                continue;
+            }
+            int fk = sf[cur][k], nk = sn[cur][k], nl = (nk + 1) >> 1;
+            uint64_t rel = E[j] - segE[k];
+            for (int d = 0; d < 3; ++d) {
+                int nb = (int)((rel >> (21 * d)) & 0x1fffffull);
+                int fl = (int)((pk[j] >> (21 * d)) & 1ull);
+                int pos = fl ? fk + nb : fk + nl + (p - fk - nb);
+                lst[nxt][d][pos] = lst[cur][d][p];
+            }
+        }
+        // next segments, in position order
+        for (int k = t; k < nseg; k += SUBTREE_THREADS) {
+            int fk = sf[cur][k], nk = sn[cur][k], nl = (nk + 1) >> 1;
+            int node = snode[cur][k];
+            uint32_t o = emit_ofs[k];
+            if (nl > leaf_size) {
+                sf[nxt][o] = (int16_t)fk;
+                sn[nxt][o] = (int16_t)nl;
+                snode[nxt][o] = left[node];
+                ++o;
+            }
+            if (nk - nl > leaf_size) {
+                sf[nxt][o] = (int16_t)(fk + nl);
+                sn[nxt][o] = (int16_t)(nk - nl);
+                snode[nxt][o] = right[node];
+            }
+        }
+        __syncthreads();
+        cur = nxt;
+        nseg = nseg_sh[cur];
+    }
+
+    // leaves: members in ascending local id (= ascending Morton rank)
+    for (int p = t; p < n0; p += SUBTREE_THREADS) {
+        int v = root;
+        while (left[v] >= 0) {
+            int l = left[v];
+            v = (f0 + p < first[l] + count[l]) ? l : right[v];
+        }
+        int lf = (int)(first[v] - f0), ln = count[v];
+        uint16_t me = lst[cur][0][p];
+        int rank = 0;
+        for (int q = 0; q < ln; ++q)
+            rank += lst[cur][0][lf + q] < me;
+        perm[f0 + lf + rank] = r2o[rk[me]];
+    }
+}
+
+// ---------------------------------------------------------------- driver
+hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const int64_t n = T.n;
+    const int gs = (int)std::min<int64_t>((n + 255) / 256, 2048);
+    k_bbox_init<<<1, 64, 0, s>>>(t.bbox, t.err);
+    k_bbox<<<gs, 256, 0, s>>>(x, n, t.bbox, t.err);
+    k_morton<<<gs, 256, 0, s>>>(x, n, t.bbox, t.keys0, t.vals0);
+    hipError_t e = radix_sort(t, t.keys0, t.vals0, t.keys1, t.vals1, n, 1, s);
+    if (e != hipSuccess)
+        return e;
+    // lists buffer 0: axis lists 0..2 and the rank list 3
+    uint32_t *L0 = t.lists, *L1 = t.lists + 4 * n;
+    k_rank_gather<<<gs, 256, 0, s>>>(x, n, t.vals0, t.r2o, t.xr, t.keys1, t.vals1, L0 + 3 * n);
+    // sort the three axis arrays (keys1, vals1) -> result in keys1/vals1 after 8 passes;
+    // the values are the Morton ranks, copied into list buffer 0.
+    e = radix_sort(t, t.keys1, t.vals1, t.keys0, t.vals0, n, 3, s);
+    if (e != hipSuccess)
+        return e;
+    e = hipMemcpyAsync(L0, t.vals1, sizeof(uint32_t) * 3 * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+        return e;
+    for (int l = 0; l < T.nlevels_up; ++l) {
+        int b0 = T.lvl_blk_off[l], nb = T.lvl_blk_off[l + 1] - b0;
+        const uint32_t *Ls = (l & 1) ? L1 : L0;
+        uint32_t *Ld = (l & 1) ? L0 : L1;
+        k_lvl_flags<<<nb, LVL_THREADS, 0, s>>>(Ls, n, t.xr, t.blk_node + b0, t.blk_start + b0,
+                                              t.blk_end + b0, t.first, t.count, t.flag, t.axis);
+        k_lvl_count<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(Ls, n, t.blk_start + b0, t.blk_end + b0,
+                                                       t.flag, t.lvl_cnt, T.max_lvl_blocks);
+        k_lvl_scan<<<4, 1024, 0, s>>>(t.lvl_cnt, t.lvl_pre, nb, T.max_lvl_blocks);
+        k_lvl_scatter<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
+            Ls, Ld, n, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.blk_first + b0,
+            t.first, t.count, t.flag, t.lvl_pre, T.max_lvl_blocks);
+    }
+    int nsub = (int)T.sub_root.size();
+    k_subtree<<<nsub, SUBTREE_THREADS, 0, s>>>(t.lists, n, t.xr, t.r2o, t.sub_root, t.first,
+                                               t.count, t.left, t.right, t.level, T.leaf_size,
+                                               t.perm, t.axis);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

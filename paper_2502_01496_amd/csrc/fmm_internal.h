@@ -1,0 +1,150 @@
+// Internal declarations of the gfx950 kd-tree FMM library: the tree object,
+// device helpers shared by the kernel files, and the host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fmm_mi355.h"
+
+namespace fmm {
+
+// Nodes with at most SUBTREE_MAX particles are split entirely inside one
+// workgroup's LDS (all their descendants in one launch).
+constexpr int SUBTREE_MAX = 2048;
+constexpr int SUBTREE_MAXSEG = SUBTREE_MAX / 2;
+constexpr int SUBTREE_THREADS = 512;
+// Positions handled by one workgroup in the per-level partition kernels.
+constexpr int LVL_CHUNK = 2048;
+constexpr int LVL_THREADS = 256;
+// Radix sort: 4 waves x 16 rounds x 64 lanes = 4096 keys per tile, 8-bit digits.
+constexpr int RS_THREADS = 256;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
+constexpr int RS_PASSES = 8;
+constexpr int MAX_LEAF = 64;
+constexpr int NREC = 8;   // doubles per node record (geometry / quadrupole)
+constexpr int NLOC = 20;  // doubles per local expansion (19 used)
+
+// ------------------------------------------------------------------ device
+__device__ __forceinline__ uint64_t ordbits(double v)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double from_ordbits(uint64_t k)
+{
+    uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// ------------------------------------------------------------------ host
+// Data-independent shape of the median-split tree: with ceil(n/2) / floor(n/2)
+// children, node sizes (and so first/count/left/right) depend on n and the
+// leaf size only.  Computed once per (n, leaf_size) on the host.
+struct Topology {
+    int64_t n = 0;
+    int leaf_size = 0;
+    int nnodes = 0, nleaves = 0, depth = 0;
+    std::vector<int32_t> first, count, left, right, parent, level, leaf_node, node_leaf;
+    // level-synchronous partition of the nodes larger than SUBTREE_MAX
+    int nlevels_up = 0;
+    int max_lvl_blocks = 0;
+    std::vector<int32_t> lvl_blk_off;  // nlevels_up + 1
+    std::vector<int32_t> blk_node, blk_start, blk_end, blk_first;
+    std::vector<int32_t> sub_root;     // roots of the LDS subtrees
+};
+
+void build_topology(int64_t n, int leaf_size, Topology &t);
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Tree {
+    uint32_t magic = 0;
+    fmm_params p{};
+    Topology topo;
+    std::vector<DevBuf> owned;
+
+    // topology on the device
+    int32_t *first = nullptr, *count = nullptr, *left = nullptr, *right = nullptr;
+    int32_t *parent = nullptr, *level = nullptr, *leaf_node = nullptr, *node_leaf = nullptr;
+    int32_t *blk_node = nullptr, *blk_start = nullptr, *blk_end = nullptr, *blk_first = nullptr;
+    int32_t *sub_root = nullptr, *axis = nullptr;
+
+    // build workspace
+    uint64_t *keys0 = nullptr, *keys1 = nullptr;  // 3n each (batched sorts)
+    uint32_t *vals0 = nullptr, *vals1 = nullptr;
+    uint32_t *rs_hist = nullptr, *rs_tot = nullptr;
+    int32_t *r2o = nullptr;       // Morton rank -> caller index
+    double *xr = nullptr;         // coordinates by Morton rank, 3 x n SoA
+    uint32_t *lists = nullptr;    // 2 buffers x 4 lists x n
+    uint8_t *flag = nullptr;      // by Morton rank
+    int32_t *lvl_cnt = nullptr, *lvl_pre = nullptr;
+    uint64_t *bbox = nullptr;     // ordered bits: min xyz, max xyz
+    uint32_t *err = nullptr;      // device error flags (bit 0 x, bit 1 m, bit 2 h)
+    int32_t *perm = nullptr;      // tree position -> caller index
+
+    // particles in tree order
+    double4 *pm = nullptr;        // x, y, z, m
+    double *hs = nullptr;         // h
+    double2 *ph = nullptr;        // 1/h, 1/h^3
+    float4 *pf = nullptr;         // FP32 form: offset from the leaf centre of mass, m
+    float2 *pfh = nullptr;        // FP32 form: 1/h, 1/h^3
+
+    // nodes
+    double *recA = nullptr;       // per node: cx, cy, cz, M, s, hmax, 0, 0
+    double *recQ = nullptr;       // per node: Qxx, Qxy, Qxz, Qyy, Qyz, Qzz, 0, 0
+    float *recF = nullptr;        // per node FP32 mirror: M, Q[6], 0
+    uint64_t *s2bits = nullptr;
+    int32_t *upcnt = nullptr;
+
+    // interaction lists (CSR over sinks: leaves for PHANTOM, nodes for MUTUAL)
+    int64_t *far_off = nullptr, *near_off = nullptr;
+    int32_t *far_src = nullptr, *near_src = nullptr;
+    int64_t cap_far = 0, cap_near = 0;
+    DevBuf far_buf, near_buf;
+    int32_t *far_cnt = nullptr, *near_cnt = nullptr;
+    int64_t *scan_tmp = nullptr;
+    int64_t *totals = nullptr;    // device: far, near totals
+    int64_t *h_totals = nullptr;  // pinned host mirror
+    int nsinks = 0;
+    int64_t n_far = 0, n_near = 0;
+    double *L = nullptr;          // local expansions, NLOC per node
+    float *Lf = nullptr;          // FP32 form, NLOC per node
+
+    // reductions
+    double *red = nullptr;
+    double *h_red = nullptr;
+
+    bool has_tree = false, has_moments = false, has_lists = false, has_forces = false;
+    int lists_policy = -1;
+
+    bool timing = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    double times[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+// launchers (return hipError_t of the last launch / runtime call)
+hipError_t launch_build(Tree &t, const double *x, hipStream_t s);
+hipError_t launch_moments(Tree &t, const double *x, const double *m, const double *h,
+                          hipStream_t s);
+hipError_t launch_walk_count(Tree &t, hipStream_t s);
+hipError_t launch_walk_fill(Tree &t, hipStream_t s);
+hipError_t launch_far(Tree &t, hipStream_t s);
+hipError_t launch_near(Tree &t, void *a, hipStream_t s);
+hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,
+                        int a_fp32, int64_t n, double *red, double *h_out, hipStream_t s);
+hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s);
+
+}  // namespace fmm

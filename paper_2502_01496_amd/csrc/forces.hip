@@ -1,0 +1,280 @@
+// Far and near field on gfx950.
+//
+// M2L (eq. (6) of the paper and its first two r-derivatives): for a sink cell
+// and a source cell with mass M, quadrupole Q about its centre of mass, and
+// r = c_sink - c_source, the local expansion is L = (a, grad a, grad grad a)
+// at c_sink.  With g_n = (-1)^n (2n-1)!! r^-(2n+1) (so d/dr_i g_n = g_{n+1} r_i),
+// q = Q r, qq = r.q and
+//   a0 = M g1 + g3 qq / 6,  a1 = M g2 + g4 qq / 6,  a2 = M g3 + g5 qq / 6,
+//   b2 = g2 / 3, b3 = g3 / 3, b4 = g4 / 3:
+//   L1_i   = a0 r_i + b2 q_i                                   (= eq. (6))
+//   L2_ij  = a1 r_i r_j + a0 d_ij + b3 (r_i q_j + q_i r_j) + b2 Q_ij
+//   L3_ijk = a2 r_i r_j r_k + a1 (d_ij r_k + d_ik r_j + d_jk r_i)
+//            + b4 (r_i r_j q_k + r_i r_k q_j + r_j r_k q_i)
+//            + b3 (d_ij q_k + d_ik q_j + d_jk q_i) + b3 (r_i Q_jk + r_j Q_ik + r_k Q_ij)
+// L2P (eq. (8)): a(y) = L1 + L2 y + 1/2 L3 : y y, y = x - c_sink.
+// Near field (Sec. 3, eqs. (12)-(15), M4 kernel, R_kern = 2): particle i gets
+//   -m_j * 1/2 [g(r, h_i) + g(r, h_j)] * (x_i - x_j) from every j != i of its
+// near cells, with g = phi'/r:
+//   q < 1:      h^-3 (4/3 - 6/5 q^2 + 1/2 q^3)
+//   1 <= q < 2: h^-3 (8/3 - 3 q + 6/5 q^2 - 1/6 q^3) - 1/(15 r^3)
+//   q >= 2:     1/r^3.
+//
+// Storage: symmetric rank-2 (xx,xy,xz,yy,yz,zz); rank-3
+// (xxx,xxy,xxz,xyy,xyz,xzz,yyy,yyz,yzz,zzz).
+#include "fmm_internal.h"
+
+namespace fmm {
+
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T x);
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double x) { return rsqrt(x); }
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x) { return rsqrtf(x); }
+
+// One source -> sink M2L, accumulated into L[19].
+template <typename T>
+__device__ __forceinline__ void m2l_acc(T rx, T ry, T rz, T M, const T *Q, T *L)
+{
+    const T r2 = rx * rx + ry * ry + rz * rz;
+    const T u = rsqrt_t<T>(r2);
+    const T u2 = u * u;
+    const T g1 = -u * u2;
+    const T g2 = T(-3) * g1 * u2;
+    const T g3 = T(-5) * g2 * u2;
+    const T g4 = T(-7) * g3 * u2;
+    const T g5 = T(-9) * g4 * u2;
+    const T Qxx = Q[0], Qxy = Q[1], Qxz = Q[2], Qyy = Q[3], Qyz = Q[4], Qzz = Q[5];
+    const T qx = Qxx * rx + Qxy * ry + Qxz * rz;
+    const T qy = Qxy * rx + Qyy * ry + Qyz * rz;
+    const T qz = Qxz * rx + Qyz * ry + Qzz * rz;
+    const T qq = qx * rx + qy * ry + qz * rz;
+    const T sixth = T(1) / T(6), third = T(1) / T(3);
+    const T a0 = M * g1 + g3 * qq * sixth;
+    const T a1 = M * g2 + g4 * qq * sixth;
+    const T a2 = M * g3 + g5 * qq * sixth;
+    const T b2 = g2 * third, b3 = g3 * third, b4 = g4 * third;
+    // L1
+    L[0] += a0 * rx + b2 * qx;
+    L[1] += a0 * ry + b2 * qy;
+    L[2] += a0 * rz + b2 * qz;
+    // L2
+    L[3] += a1 * rx * rx + a0 + b3 * (T(2) * rx * qx) + b2 * Qxx;
+    L[4] += a1 * rx * ry + b3 * (rx * qy + qx * ry) + b2 * Qxy;
+    L[5] += a1 * rx * rz + b3 * (rx * qz + qx * rz) + b2 * Qxz;
+    L[6] += a1 * ry * ry + a0 + b3 * (T(2) * ry * qy) + b2 * Qyy;
+    L[7] += a1 * ry * rz + b3 * (ry * qz + qy * rz) + b2 * Qyz;
+    L[8] += a1 * rz * rz + a0 + b3 * (T(2) * rz * qz) + b2 * Qzz;
+    // L3: the delta terms are folded per component
+    const T a2x = a2 * rx, a2y = a2 * ry, a2z = a2 * rz;
+    // xxx: rrr = x^3; dr = 3x; rrq = 3 x^2 qx; dq = 3 qx; rQ = 3 x Qxx
+    L[9] += a2x * rx * rx + a1 * T(3) * rx + b4 * (T(3) * rx * rx * qx) + b3 * (T(3) * qx) +
+            b3 * (T(3) * rx * Qxx);
+    // xxy: dr = y; rrq = x^2 qy + 2 x y qx; dq = qy; rQ = 2 x Qxy + y Qxx
+    L[10] += a2x * rx * ry + a1 * ry + b4 * (rx * rx * qy + T(2) * rx * ry * qx) + b3 * qy +
+             b3 * (T(2) * rx * Qxy + ry * Qxx);
+    // xxz
+    L[11] += a2x * rx * rz + a1 * rz + b4 * (rx * rx * qz + T(2) * rx * rz * qx) + b3 * qz +
+             b3 * (T(2) * rx * Qxz + rz * Qxx);
+    // xyy: dr = x; rrq = y^2 qx + 2 x y qy; dq = qx; rQ = x Qyy + 2 y Qxy
+    L[12] += a2x * ry * ry + a1 * rx + b4 * (ry * ry * qx + T(2) * rx * ry * qy) + b3 * qx +
+             b3 * (rx * Qyy + T(2) * ry * Qxy);
+    // xyz: dr = 0; rrq = xy qz + xz qy + yz qx; dq = 0; rQ = x Qyz + y Qxz + z Qxy
+    L[13] += a2x * ry * rz + b4 * (rx * ry * qz + rx * rz * qy + ry * rz * qx) +
+             b3 * (rx * Qyz + ry * Qxz + rz * Qxy);
+    // xzz
+    L[14] += a2x * rz * rz + a1 * rx + b4 * (rz * rz * qx + T(2) * rx * rz * qz) + b3 * qx +
+             b3 * (rx * Qzz + T(2) * rz * Qxz);
+    // yyy
+    L[15] += a2y * ry * ry + a1 * T(3) * ry + b4 * (T(3) * ry * ry * qy) + b3 * (T(3) * qy) +
+             b3 * (T(3) * ry * Qyy);
+    // yyz
+    L[16] += a2y * ry * rz + a1 * rz + b4 * (ry * ry * qz + T(2) * ry * rz * qy) + b3 * qz +
+             b3 * (T(2) * ry * Qyz + rz * Qyy);
+    // yzz
+    L[17] += a2y * rz * rz + a1 * ry + b4 * (rz * rz * qy + T(2) * ry * rz * qz) + b3 * qy +
+             b3 * (ry * Qzz + T(2) * rz * Qyz);
+    // zzz
+    L[18] += a2z * rz * rz + a1 * T(3) * rz + b4 * (T(3) * rz * rz * qz) + b3 * (T(3) * qz) +
+             b3 * (T(3) * rz * Qzz);
+}
+
+// L2P, eq. (8)
+template <typename T>
+__device__ __forceinline__ void l2p(const T *L, T y0, T y1, T y2, T &a0, T &a1, T &a2)
+{
+    const T h = T(0.5);
+    a0 = L[0] + L[3] * y0 + L[4] * y1 + L[5] * y2 +
+         h * (L[9] * y0 * y0 + L[12] * y1 * y1 + L[14] * y2 * y2) +
+         (L[10] * y0 * y1 + L[11] * y0 * y2 + L[13] * y1 * y2);
+    a1 = L[1] + L[4] * y0 + L[6] * y1 + L[7] * y2 +
+         h * (L[10] * y0 * y0 + L[15] * y1 * y1 + L[17] * y2 * y2) +
+         (L[12] * y0 * y1 + L[13] * y0 * y2 + L[16] * y1 * y2);
+    a2 = L[2] + L[5] * y0 + L[7] * y1 + L[8] * y2 +
+         h * (L[11] * y0 * y0 + L[16] * y1 * y1 + L[18] * y2 * y2) +
+         (L[13] * y0 * y1 + L[14] * y0 * y2 + L[17] * y1 * y2);
+}
+
+// ---------------------------------------------------------------- M2L, FP64
+// 16 lanes per sink leaf, 4 sinks per wave; lanes stride the far list, then a
+// butterfly sum over the 16 lanes (fixed order: deterministic).
+__global__ __launch_bounds__(256) void k_m2l_leaf_f64(
+    const double *__restrict__ recA, const double *__restrict__ recQ,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int64_t *__restrict__ far_off,
+    const int32_t *__restrict__ far_src, double *Lout)
+{
+    const int g = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    const bool valid = g < nleaves;
+    const int v = valid ? leaf_node[g] : 0;
+    const double *rv = recA + (int64_t)NREC * v;
+    const double c0 = rv[0], c1 = rv[1], c2 = rv[2];
+    double L[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        L[k] = 0.0;
+    const int64_t k0 = valid ? far_off[g] : 0, k1 = valid ? far_off[g + 1] : 0;
+    for (int64_t k = k0 + sub; k < k1; k += 16) {
+        const int b = far_src[k];
+        const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
+        const double *qb = recQ + (int64_t)NREC * b;
+        const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
+                      q45 = *(const double2 *)(qb + 4);
+        const double Q[6] = {q01.x, q01.y, q23.x, q23.y, q45.x, q45.y};
+        m2l_acc<double>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            L[k] += __shfl_xor(L[k], off);
+    if (valid && sub == 0) {
+        double *o = Lout + (int64_t)NLOC * v;
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            o[k] = L[k];
+        o[19] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- P2P + L2P, FP64
+__device__ __forceinline__ double m4g_f64(double q, double hinv3, double u3)
+{
+    const double p1 = hinv3 * (4.0 / 3.0 + q * q * (-1.2 + 0.5 * q));
+    const double p2 = hinv3 * (8.0 / 3.0 + q * (-3.0 + q * (1.2 - q * (1.0 / 6.0)))) -
+                      u3 * (1.0 / 15.0);
+    return q < 1.0 ? p1 : (q < 2.0 ? p2 : u3);
+}
+
+// One wavefront per sink leaf: lane = 8 * s + t takes sink s of the leaf and
+// source slot t of each near leaf, so a near leaf of 8 particles is one
+// 8 x 8 tile per wave step.  Larger leaves loop over 8-wide chunks.  The 8
+// partial sums of a sink are reduced with xor-shuffles; the t = 0 lane adds
+// L2P and writes G * a to the caller's slot of the particle.
+__global__ __launch_bounds__(256) void k_p2p_leaf_f64(
+    const double4 *__restrict__ pm, const double2 *__restrict__ ph,
+    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int64_t *__restrict__ near_off,
+    const int32_t *__restrict__ near_src, const double *__restrict__ Lloc,
+    const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, int have_far,
+    double *aout)
+{
+    const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (leaf >= nleaves)
+        return;
+    const int lane = lane_id();
+    const int s = lane >> 3, tt = lane & 7;
+    const int v = leaf_node[leaf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const int64_t k0 = near_off[leaf], k1 = near_off[leaf + 1];
+    for (int sb = 0; sb < c; sb += 8) {
+        const bool vi = sb + s < c;
+        const int64_t i = f + sb + s;
+        double4 xi = make_double4(0, 0, 0, 0);
+        double2 hi = make_double2(1, 1);
+        if (vi) {
+            xi = pm[i];
+            hi = ph[i];
+        }
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int64_t k = k0; k < k1; ++k) {
+            const int bn = __builtin_amdgcn_readfirstlane(near_src[k]);
+            const int64_t fb = first[bn];
+            const int cb = count[bn];
+            for (int tb = 0; tb < cb; tb += 8) {
+                const bool vj = tb + tt < cb;
+                const int64_t j = fb + tb + tt;
+                double4 xj = make_double4(0, 0, 0, 0);
+                double2 hj = make_double2(1, 1);
+                if (vj) {
+                    xj = pm[j];
+                    hj = ph[j];
+                }
+                const double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double u = r2 > 0.0 ? rsqrt(r2) : 0.0;
+                const double r = r2 * u;
+                const double u3 = u * u * u;
+                const double gi = m4g_f64(r * hi.x, hi.y, u3);
+                const double gj = m4g_f64(r * hj.x, hj.y, u3);
+                const double fm = (vi && vj) ? xj.w * 0.5 * (gi + gj) : 0.0;
+                ax -= fm * dx;
+                ay -= fm * dy;
+                az -= fm * dz;
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            ax += __shfl_xor(ax, off);
+            ay += __shfl_xor(ay, off);
+            az += __shfl_xor(az, off);
+        }
+        if (vi && tt == 0) {
+            double fx = 0.0, fy = 0.0, fz = 0.0;
+            if (have_far) {
+                const double *rv = recA + (int64_t)NREC * v;
+                const double *L = Lloc + (int64_t)NLOC * v;
+                double Lr[19];
+#pragma unroll
+                for (int k = 0; k < 19; ++k)
+                    Lr[k] = L[k];
+                l2p<double>(Lr, xi.x - rv[0], xi.y - rv[1], xi.z - rv[2], fx, fy, fz);
+            }
+            const int64_t o = 3 * (int64_t)perm[i];
+            aout[o] = G * (fx + ax);
+            aout[o + 1] = G * (fy + ay);
+            aout[o + 2] = G * (fz + az);
+        }
+    }
+}
+
+hipError_t launch_far(Tree &t, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    int nl = T.nleaves;
+    if (t.p.precision == FMM_FP64) {
+        k_m2l_leaf_f64<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
+                                                             t.far_off, t.far_src, t.L);
+    } else {
+        return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_near(Tree &t, void *a, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    int nl = T.nleaves;
+    if (t.p.precision == FMM_FP64) {
+        k_p2p_leaf_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node,
+                                                    nl, t.near_off, t.near_src, t.L, t.recA,
+                                                    t.perm, t.p.G, 1, (double *)a);
+    } else {
+        return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fmm

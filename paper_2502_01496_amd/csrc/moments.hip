@@ -1,0 +1,240 @@
+// Cell properties on gfx950 (Sec. 2 of the paper: mass, centre of mass, size
+// s, h_max; quadrupole eq. (7)).
+//
+//   k_gather     caller-order x, m, h -> tree-order SoA (x, y, z, m) and
+//                (1/h, 1/h^3); flags bad inputs; clears the per-node counters.
+//   k_leaf_up    one thread per leaf: M, sum(m x) left to right, c = S / M,
+//                h_max and the quadrupole about c; then the thread climbs:
+//                the second child to arrive at a parent (arrival counter)
+//                combines both children -- M = M_L + M_R,
+//                c = (M_L c_L + M_R c_R) / M, Q by the parallel-axis shift.
+//                The parent result does not depend on which child came last.
+//   k_node_s2    s^2 = max over the node's particles of |x - c|^2, exactly:
+//                one thread per particle walks root -> leaf; lanes on the same
+//                node reduce with a segmented wave max, then one u64 atomicMax
+//                on the bit pattern (order-free for non-negative doubles).
+//   k_node_final s = sqrt(s^2) and the FP32 mirrors.
+//
+// Compiled with -ffp-contract=off: M, c, s and h_max are bit-identical to the
+// serial definition (same operations, same order).
+#include "fmm_internal.h"
+
+namespace fmm {
+
+__global__ void k_gather(const double *__restrict__ x, const double *__restrict__ m,
+                         const double *__restrict__ h, int64_t n, const int32_t *__restrict__ perm,
+                         double4 *pm, double *hs, double2 *ph, uint32_t *err, int nnodes,
+                         uint64_t *s2bits, int32_t *upcnt, int want_fp32, float2 *pfh)
+{
+    int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t bad = 0;
+    for (int64_t p = gid; p < n; p += stride) {
+        int64_t i = perm[p];
+        double xx = x[3 * i], yy = x[3 * i + 1], zz = x[3 * i + 2], mm = m[i], hh = h[i];
+        if (!(isfinite(xx) && isfinite(yy) && isfinite(zz)))
+            bad |= 1u;
+        if (!(mm > 0.0 && isfinite(mm)))
+            bad |= 2u;
+        if (!(hh > 0.0 && isfinite(hh)))
+            bad |= 4u;
+        pm[p] = make_double4(xx, yy, zz, mm);
+        hs[p] = hh;
+        double hi = 1.0 / hh;
+        ph[p] = make_double2(hi, hi * hi * hi);
+        if (want_fp32)
+            pfh[p] = make_float2((float)hi, (float)(hi * hi * hi));
+    }
+    for (int64_t v = gid; v < nnodes; v += stride) {
+        s2bits[v] = 0ull;
+        upcnt[v] = 0;
+    }
+    // OR-reduce the error bits over the wave, one atomic per wave
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        bad |= (uint32_t)__shfl_xor((int)bad, off);
+    if (lane_id() == 0 && bad)
+        atomicOr(err, bad);
+}
+
+__device__ __forceinline__ double ld_acq(const double *p)
+{
+    uint64_t b = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ void quad_add(double *Q, double w, double y0, double y1, double y2)
+{
+    double yy = y0 * y0 + y1 * y1 + y2 * y2;
+    Q[0] += w * (3.0 * y0 * y0 - yy);
+    Q[1] += w * (3.0 * y0 * y1);
+    Q[2] += w * (3.0 * y0 * y2);
+    Q[3] += w * (3.0 * y1 * y1 - yy);
+    Q[4] += w * (3.0 * y1 * y2);
+    Q[5] += w * (3.0 * y2 * y2 - yy);
+}
+
+__global__ __launch_bounds__(256) void k_leaf_up(
+    const double4 *__restrict__ pm, const double *__restrict__ hs,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ first,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ left,
+    const int32_t *__restrict__ right, const int32_t *__restrict__ parent, double *recA,
+    double *recQ, int32_t *upcnt, int want_fp32, float4 *pf)
+{
+    int lf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves)
+        return;
+    int v = leaf_node[lf];
+    int64_t f = first[v];
+    int c = count[v];
+    double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hm = 0.0;
+    for (int k = 0; k < c; ++k) {
+        double4 q = pm[f + k];
+        M += q.w;
+        S0 += q.w * q.x;
+        S1 += q.w * q.y;
+        S2 += q.w * q.z;
+        double hh = hs[f + k];
+        hm = hh > hm ? hh : hm;
+    }
+    double c0 = S0 / M, c1 = S1 / M, c2 = S2 / M;
+    double Q[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < c; ++k) {
+        double4 q = pm[f + k];
+        double y0 = q.x - c0, y1 = q.y - c1, y2 = q.z - c2;
+        quad_add(Q, q.w, y0, y1, y2);
+        if (want_fp32)
+            pf[f + k] = make_float4((float)y0, (float)y1, (float)y2, (float)q.w);
+    }
+    double *ra = recA + (int64_t)NREC * v;
+    ra[0] = c0;
+    ra[1] = c1;
+    ra[2] = c2;
+    ra[3] = M;
+    ra[5] = hm;
+    double *rq = recQ + (int64_t)NREC * v;
+    for (int k = 0; k < 6; ++k)
+        rq[k] = Q[k];
+    // climb: the second child to arrive combines
+    while (v != 0) {
+        __threadfence();
+        int p = parent[v];
+        int old = atomicAdd(&upcnt[p], 1);
+        if (old == 0)
+            return;
+        __threadfence();
+        int l = left[p], r = right[p];
+        const double *al = recA + (int64_t)NREC * l, *ar = recA + (int64_t)NREC * r;
+        const double *ql = recQ + (int64_t)NREC * l, *qr = recQ + (int64_t)NREC * r;
+        double Ml = ld_acq(al + 3), Mr = ld_acq(ar + 3);
+        double cl[3] = {ld_acq(al), ld_acq(al + 1), ld_acq(al + 2)};
+        double cr[3] = {ld_acq(ar), ld_acq(ar + 1), ld_acq(ar + 2)};
+        double Mp = Ml + Mr;
+        double cp[3];
+        for (int d = 0; d < 3; ++d)
+            cp[d] = (Ml * cl[d] + Mr * cr[d]) / Mp;
+        double Qp[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < 6; ++k)
+            Qp[k] += ld_acq(ql + k);
+        quad_add(Qp, Ml, cl[0] - cp[0], cl[1] - cp[1], cl[2] - cp[2]);
+        for (int k = 0; k < 6; ++k)
+            Qp[k] += ld_acq(qr + k);
+        quad_add(Qp, Mr, cr[0] - cp[0], cr[1] - cp[1], cr[2] - cp[2]);
+        double hl = ld_acq(al + 5), hr = ld_acq(ar + 5);
+        double *pa = recA + (int64_t)NREC * p;
+        pa[0] = cp[0];
+        pa[1] = cp[1];
+        pa[2] = cp[2];
+        pa[3] = Mp;
+        pa[5] = hl > hr ? hl : hr;
+        double *pq = recQ + (int64_t)NREC * p;
+        for (int k = 0; k < 6; ++k)
+            pq[k] = Qp[k];
+        v = p;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm, int64_t n,
+                                                 const double *__restrict__ recA,
+                                                 const int32_t *__restrict__ first,
+                                                 const int32_t *__restrict__ count,
+                                                 const int32_t *__restrict__ left,
+                                                 const int32_t *__restrict__ right,
+                                                 uint64_t *s2bits)
+{
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    bool done = p >= n;
+    double4 xp = done ? make_double4(0, 0, 0, 0) : pm[p];
+    int v = 0;
+    while (__ballot(!done) != 0ull) {
+        int key = done ? -1 : v;
+        uint64_t val = 0ull;
+        if (!done) {
+            const double *ra = recA + (int64_t)NREC * v;
+            double dx = xp.x - ra[0], dy = xp.y - ra[1], dz = xp.z - ra[2];
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            val = (uint64_t)__double_as_longlong(d2);
+        }
+        // segmented inclusive max over runs of equal key (runs are contiguous)
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            uint64_t ov = __shfl_up(val, off);
+            int ok = __shfl_up(key, off);
+            if (lane >= off && ok == key)
+                val = ov > val ? ov : val;
+        }
+        int nk = __shfl_down(key, 1);
+        bool tail = (lane == 63) || (nk != key);
+        if (!done && tail)
+            atomicMax((unsigned long long *)&s2bits[v], (unsigned long long)val);
+        if (!done) {
+            int l = left[v];
+            if (l < 0)
+                done = true;
+            else
+                v = (p < (int64_t)first[l] + count[l]) ? l : right[v];
+        }
+    }
+}
+
+__global__ void k_node_final(int nnodes, const uint64_t *__restrict__ s2bits, double *recA,
+                             const double *__restrict__ recQ, int want_fp32, float *recF)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nnodes; v += gridDim.x * blockDim.x) {
+        double s2 = __longlong_as_double((long long)s2bits[v]);
+        recA[(int64_t)NREC * v + 4] = sqrt(s2);
+        recA[(int64_t)NREC * v + 6] = 0.0;
+        recA[(int64_t)NREC * v + 7] = 0.0;
+        if (want_fp32) {
+            float *rf = recF + (int64_t)NREC * v;
+            rf[0] = (float)recA[(int64_t)NREC * v + 3];
+            for (int k = 0; k < 6; ++k)
+                rf[1 + k] = (float)recQ[(int64_t)NREC * v + k];
+            rf[7] = 0.0f;
+        }
+    }
+}
+
+hipError_t launch_moments(Tree &t, const double *x, const double *m, const double *h,
+                          hipStream_t s)
+{
+    const Topology &T = t.topo;
+    int64_t n = T.n;
+    int64_t work = n > T.nnodes ? n : T.nnodes;
+    int gs = (int)std::min<int64_t>((work + 255) / 256, 4096);
+    int want32 = t.p.precision == FMM_FP32;
+    k_gather<<<gs, 256, 0, s>>>(x, m, h, n, t.perm, t.pm, t.hs, t.ph, t.err, T.nnodes, t.s2bits,
+                                t.upcnt, want32, t.pfh);
+    k_leaf_up<<<(T.nleaves + 255) / 256, 256, 0, s>>>(t.pm, t.hs, t.leaf_node, T.nleaves,
+                                                      t.first, t.count, t.left, t.right,
+                                                      t.parent, t.recA, t.recQ, t.upcnt, want32,
+                                                      t.pf);
+    k_node_s2<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, t.first, t.count, t.left,
+                                                     t.right, t.s2bits);
+    k_node_final<<<(T.nnodes + 255) / 256, 256, 0, s>>>(T.nnodes, t.s2bits, t.recA, t.recQ,
+                                                       want32, t.recF);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

@@ -1,0 +1,46 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI and run
+the oracle on the same seeded inputs."""
+import numpy as np
+
+from paper_2502_01496_amd import fmm as F
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def to_dev(*arrs):
+    import torch
+
+    return [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in arrs]
+
+
+def gpu_run(x, m, h, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, export=True, local=False):
+    """build -> moments -> forces on the GPU; returns (a, export dict, info)."""
+    import torch
+
+    X, Mt, H = to_dev(x, m, h)
+    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision)
+    t = F.fmm_build_tree(X, p)
+    try:
+        F.fmm_moments(t, X, Mt, H)
+        dt = torch.float32 if precision == F.FMM_FP32 else torch.float64
+        A = torch.empty((len(m), 3), dtype=dt, device="cuda")
+        F.fmm_forces(t, A)
+        torch.cuda.synchronize()
+        ex = F.fmm_debug_export(t, lists=True, local=local) if export else None
+        info = F.fmm_tree_info(t)
+    finally:
+        F.fmm_tree_free(t)
+    return A.cpu().numpy().astype(np.float64), ex, info
+
+
+def force_err(a, ref):
+    """max_i |a_i - ref_i| / max(|ref_i|, 1e-3 rms|ref|)."""
+    nr = np.linalg.norm(ref, axis=1)
+    floor = max(1e-3 * np.sqrt((nr ** 2).mean()), 1e-300)
+    return (np.linalg.norm(a - ref, axis=1) / np.maximum(nr, floor)).max()
+
+
+def eta(a, ref):
+    return float(np.sqrt(((a - ref) ** 2).sum() / (ref ** 2).sum()))

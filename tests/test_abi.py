@@ -1,0 +1,83 @@
+"""The C ABI library loads and exports every function the public header
+declares; host-side argument checks fail before any device work (these calls
+never touch a GPU, so they run on the CPU)."""
+import ctypes as C
+
+import pytest
+
+from paper_2502_01496_amd import fmm as F
+
+
+def test_library_exports_header_functions():
+    L = F.lib()
+    names = F.header_functions()
+    assert len(names) >= 12
+    for n in ("fmm_build_tree", "fmm_moments", "fmm_forces", "fmm_forces_vjp",
+              "fmm_momentum_stats"):
+        assert n in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert missing == []
+
+
+def test_default_params():
+    p = F.default_params()
+    assert (p.theta, p.r_kern, p.G, p.leaf_size, p.walk, p.precision, p.reserved) == (
+        0.5, 2.0, 1.0, 8, F.FMM_WALK_PHANTOM, F.FMM_FP64, 0)
+    assert C.sizeof(F.fmm_stats) == 16 * 8
+
+
+def _build(p, n=10, x=C.c_void_p(16), tree=None):
+    h = C.c_void_p(tree)
+    return F.lib().fmm_build_tree(x, n, C.byref(p), None, C.byref(h)), h.value
+
+
+@pytest.mark.parametrize("field,value", [
+    ("theta", -0.1), ("theta", 1.5), ("theta", float("nan")), ("r_kern", 0.0),
+    ("r_kern", float("inf")), ("G", float("nan")), ("leaf_size", 0), ("leaf_size", 65),
+    ("walk", 7), ("precision", 2), ("reserved", 1)])
+def test_bad_params_rejected_on_host(field, value):
+    p = F.default_params()
+    setattr(p, field, value)
+    st, h = _build(p)
+    assert st == F.FMM_ERR_INVALID and h is None
+    assert F.fmm_last_error() != ""
+
+
+def test_bad_sizes_and_pointers_rejected():
+    p = F.default_params()
+    assert _build(p, n=0)[0] == F.FMM_ERR_INVALID
+    assert _build(p, n=-5)[0] == F.FMM_ERR_INVALID
+    assert _build(p, n=2 ** 31)[0] == F.FMM_ERR_INVALID
+    assert _build(p, x=None)[0] == F.FMM_ERR_INVALID
+    L = F.lib()
+    h = C.c_void_p(None)
+    assert L.fmm_build_tree(C.c_void_p(16), 10, None, None, C.byref(h)) == F.FMM_ERR_INVALID
+    assert L.fmm_build_tree(C.c_void_p(16), 10, C.byref(p), None, None) == F.FMM_ERR_INVALID
+
+
+def test_unknown_handles_rejected():
+    L = F.lib()
+    bogus = C.c_void_p(None)
+    assert L.fmm_moments(bogus, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == F.FMM_ERR_STATE
+    assert L.fmm_forces(bogus, C.c_void_p(8), 0, None) == F.FMM_ERR_STATE
+    assert L.fmm_forces_vjp(bogus, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == F.FMM_ERR_STATE
+    info = (C.c_int64 * 8)()
+    assert L.fmm_tree_info(bogus, info) == F.FMM_ERR_STATE
+    L.fmm_tree_free(bogus)  # no-op
+
+
+def test_stats_argument_checks():
+    L = F.lib()
+    out = F.fmm_stats()
+    v = C.c_void_p(8)
+    assert L.fmm_momentum_stats(None, None, v, v, 0, 10, C.byref(out), None) == F.FMM_ERR_INVALID
+    assert L.fmm_momentum_stats(v, None, v, v, 0, 0, C.byref(out), None) == F.FMM_ERR_INVALID
+    assert L.fmm_momentum_stats(v, None, v, v, 5, 10, C.byref(out), None) == F.FMM_ERR_INVALID
+    assert L.fmm_momentum_stats(v, None, v, v, 0, 10, None, None) == F.FMM_ERR_INVALID
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+
+    with pytest.raises((TypeError, RuntimeError)):
+        F.fmm_build_tree(torch.zeros(4, 3, dtype=torch.float64), F.default_params())
