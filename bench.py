@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Throughput of the gfx950 kd-tree FMM gravity path on one MI355X.
+
+A step is one kick-drift-kick leapfrog step of the whole hot path on the
+synthetic workload: drift, tree build (Morton sort + median splits), moments,
+walk (interaction lists), M2L, P2P + L2P, closing kick, and the FP64 momentum
+diagnostics.  The default workload is the binary of two n=1 polytropes with
+2 x 2^18 particles, 58-neighbour smoothing lengths, theta = 0.5, leaf size 8,
+dt = 1e-3.  value = N * steps / elapsed (particle-forces per second).
+
+The P2P and M2L kernel durations come from HIP events the library records
+around each launch on the stream it launches on, during the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-forces/s (FP32 vs FP64 FMM) at rel err ≤1e-3; |ΣF|/Σ|F|"
+PEAK_FP64 = 78.6e12      # MI355X vector FP64, FLOP/s (FMA = 2)
+PEAK_FP32 = 157.3e12     # MI355X vector FP32 (packed), FLOP/s
+HBM_PEAK = 8.0e12        # B/s
+# Algorithmic flops (FMA = 2, reciprocal square root = 1):
+FLOP_PAIR_NEWTON = 20    # d (3), r^2 (5), 1/r (1), 1/r^3 (2), m 1/r^3 (1), a -= f d (6), + 2 select
+FLOP_PAIR_SOFT = 40      # + r, two q's, two spline polynomials with h^-3, the mean
+FLOP_M2L = 250           # one cell-cell interaction, 19 coefficients
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="binary_2x2^18")
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--accuracy-sinks", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-census", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def direct_reference(x, m, h, sinks, G=1.0, chunk=64):
+    """FP64 softened direct sum at sampled sinks (plain torch on the GPU): the
+    accuracy reference for the 'rel err' of the metric."""
+    import torch
+
+    out = torch.empty((len(sinks), 3), dtype=torch.float64, device=x.device)
+    for s0 in range(0, len(sinks), chunk):
+        idx = sinks[s0:s0 + chunk]
+        d = x[idx][:, None, :] - x[None, :, :]
+        r = torch.sqrt((d * d).sum(-1))
+
+        def g(hh):
+            q = r / hh
+            h3 = hh ** 3
+            p1 = (4.0 / 3.0 - 1.2 * q * q + 0.5 * q ** 3) / h3
+            p2 = (8.0 / 3.0 - 3.0 * q + 1.2 * q * q - q ** 3 / 6.0) / h3 - 1.0 / (15.0 * r ** 3)
+            return torch.where(q < 1, p1, torch.where(q < 2, p2, 1.0 / r ** 3))
+
+        gij = 0.5 * (g(h[idx][:, None]) + g(h[None, :]))
+        w = m[None, :] * gij
+        w[torch.arange(len(idx)), idx] = 0.0
+        out[s0:s0 + chunk] = -G * (w[:, :, None] * d).sum(1)
+    return out
+
+
+def pair_census(x, h, ex, leaf_size):
+    """Count near-field particle pairs (self pairs excluded) and how many lie
+    within the softening support 2 max(h_i, h_j), from the exported lists."""
+    import numpy as np
+    import torch
+
+    dev = x.device
+    perm = torch.from_numpy(ex["perm"].astype(np.int64)).to(dev)
+    xs, hs = x[perm], h[perm]
+    first = torch.from_numpy(ex["first"].astype(np.int64)).to(dev)
+    count = torch.from_numpy(ex["count"].astype(np.int64)).to(dev)
+    off = torch.from_numpy(ex["near_off"]).to(dev)
+    src = torch.from_numpy(ex["near_src"].astype(np.int64)).to(dev)
+    sink = torch.repeat_interleave(torch.arange(len(first), device=dev), off[1:] - off[:-1])
+    total = soft = 0
+    ar = torch.arange(leaf_size, device=dev)
+    for c0 in range(0, len(src), 1 << 20):
+        a, b = sink[c0:c0 + (1 << 20)], src[c0:c0 + (1 << 20)]
+        ia = first[a][:, None] + ar[None, :]
+        ib = first[b][:, None] + ar[None, :]
+        va = ar[None, :] < count[a][:, None]
+        vb = ar[None, :] < count[b][:, None]
+        ia = torch.where(va, ia, 0)
+        ib = torch.where(vb, ib, 0)
+        d = xs[ia][:, :, None, :] - xs[ib][:, None, :, :]
+        r2 = (d * d).sum(-1)
+        hm = torch.maximum(hs[ia][:, :, None], hs[ib][:, None, :])
+        valid = va[:, :, None] & vb[:, None, :] & (ia[:, :, None] != ib[:, None, :])
+        total += int(valid.sum())
+        soft += int((valid & (r2 < (2.0 * hm) ** 2)).sum())
+    return total, soft
+
+
+def profile_traffic(kernel_tag):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter runs, valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel_tag)
+    except Exception:
+        return None
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2502_01496_amd", "csrc", rec["source"])
+    digest = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    if digest != rec.get("source_sha1"):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(x, m, h, theta):
+    """The oracle (serial C, FP64) on one full force evaluation of the workload."""
+    from oracle import oracle as O
+
+    O.lib()
+    t0 = time.perf_counter()
+    O.fmm(x, m, h, theta=theta)
+    dt = time.perf_counter() - t0
+    return {"value": len(m) / dt, "unit": "particle-forces/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full force evaluation (build, moments, walk, M2L, P2P+L2P) of the "
+                      f"same {len(m)}-particle workload, serial FP64 C oracle, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the multi-GPU sharding of this path is a design (see DESIGN.md), not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2502_01496_amd import fmm as F
+    from paper_2502_01496_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    x_np, m_np, h_np, _ = W.config(args.workload)
+    n = len(m_np)
+    log(f"[bench] workload {args.workload}: n={n}, setup {time.perf_counter() - t0:.1f}s")
+    dev = "cuda"
+    x = torch.from_numpy(x_np).to(dev)
+    m = torch.from_numpy(m_np).to(dev)
+    h = torch.from_numpy(h_np).to(dev)
+    v = torch.zeros_like(x)
+    prec = F.FMM_FP32 if args.precision == "fp32" else F.FMM_FP64
+    adt = torch.float32 if prec == F.FMM_FP32 else torch.float64
+    g = F.GravityFMM(theta=args.theta, precision=prec)
+    a = torch.empty((n, 3), dtype=adt, device=dev)
+    dt = args.dt
+
+    def forces():
+        g.build(x)
+        F.fmm_moments(g.tree, x, m, h)
+        F.fmm_forces(g.tree, a, F.FMM_REWALK)
+
+    def step():
+        F.fmm_kick_drift(x, v, a, 0.5 * dt, dt)
+        forces()
+        F.fmm_kick_drift(x, v, a, 0.5 * dt, 0.0)
+        return F.fmm_momentum_stats(x, v, m, a)
+
+    forces()
+    st0 = F.fmm_momentum_stats(x, v, m, a)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    F.fmm_set_timing(g.tree, True)
+    ratios = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+        ratios.append(st["ratio"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    stages = F.fmm_stage_times(g.tree)
+    F.fmm_set_timing(g.tree, False)
+    ms_step = 1e3 * elapsed / args.steps
+    value = n * args.steps / elapsed
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s -> {ms_step:.3f} ms/step, "
+        f"{value:.4e} particle-forces/s; stages (ms/call) {stages}")
+
+    info = F.fmm_tree_info(g.tree)
+    ex = F.fmm_debug_export(g.tree, lists=True)
+    # accuracy at the final state, against the FP64 direct sum on sampled sinks
+    rng = np.random.default_rng(123)
+    sinks = torch.from_numpy(rng.choice(n, size=min(args.accuracy_sinks, n), replace=False)).to(dev)
+    ref = direct_reference(x, m, h, sinks)
+    got = a[sinks].double()
+    rel = (torch.linalg.norm(got - ref, dim=1) / torch.linalg.norm(ref, dim=1)).cpu().numpy()
+    eta = float(torch.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum()))
+    log(f"[bench] accuracy on {len(sinks)} sinks: median {np.median(rel):.3e} "
+        f"p99 {np.percentile(rel, 99):.3e} eta {eta:.3e}")
+
+    # roofline of the dominant kernel
+    peak = PEAK_FP32 if prec == F.FMM_FP32 else PEAK_FP64
+    if args.no_census:
+        pairs = soft = None
+        p2p_flops = None
+    else:
+        pairs, soft = pair_census(x, h, ex, g.leaf_size)
+        p2p_flops = FLOP_PAIR_NEWTON * (pairs - soft) + FLOP_PAIR_SOFT * soft
+    m2l_flops = FLOP_M2L * info["n_far"]
+    kern = {}
+    if p2p_flops is not None and stages["near"] > 0:
+        kern["p2p"] = (p2p_flops / (stages["near"] * 1e-3), stages["near"])
+    if stages["far"] > 0:
+        kern["m2l"] = (m2l_flops / (stages["far"] * 1e-3), stages["far"])
+    dom = max(kern, key=lambda k: kern[k][1]) if kern else None
+    roof = None
+    if dom:
+        achieved = kern[dom][0] / 1e12
+        tag = {"p2p": "k_p2p_leaf", "m2l": "k_m2l_leaf"}[dom] + ("_f32" if prec else "_f64")
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
+                "traffic": profile_traffic(tag), "kernel": tag,
+                "kernel_ms": round(kern[dom][1], 4)}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-forces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == F.FMM_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: n={n}, theta={args.theta}, leaf 8, "
+                               f"KDK dt={dt}, walk=leaf<-cell", "n": n, "theta": args.theta,
+                   "precision": args.precision},
+        "rel_err": {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
+                    "eta": eta, "sinks": int(len(sinks)), "reference": "FP64 direct sum"},
+        "sumF_ratio": {"first": st0["ratio"], "mean": float(np.mean(ratios)),
+                       "last": ratios[-1]},
+        "stages_ms": {k: round(v_, 4) for k, v_ in stages.items()},
+        "lists": {"far": info["n_far"], "near_leaf_pairs": info["n_near"],
+                  "p2p_pairs": pairs, "p2p_softened": soft},
+        "roofline": roof,
+    }
+    g.free()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host (cpu_baseline)")
+        out["cpu_baseline"] = cpu_baseline(x_np, m_np, h_np, args.theta)
+        import multiprocessing
+
+        out["cpu_baseline"]["host_cpus"] = multiprocessing.cpu_count()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

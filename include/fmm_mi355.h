@@ -159,6 +159,15 @@ fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *
 fmm_status fmm_momentum_stats(const double *x, const double *v, const double *m, const void *a,
                               int32_t a_precision, int64_t n, fmm_stats *out, void *stream);
 
+/* Leapfrog update for kick-drift-kick time stepping with fixed dt:
+ *   v += kick * a;  then  x += drift * v      (elementwise, FP64 state)
+ * A KDK step is fmm_kick_drift(kick = dt/2, drift = dt), new forces, then
+ * fmm_kick_drift(kick = dt/2, drift = 0); consecutive half kicks may be merged.
+ *   x, v  device double[n][3], updated in place;
+ *   a     device [n][3], double if a_precision == FMM_FP64, float if FMM_FP32. */
+fmm_status fmm_kick_drift(double *x, double *v, const void *a, int32_t a_precision, int64_t n,
+                          double kick, double drift, void *stream);
+
 /* Release a tree and its device memory (synchronises the device first).
  * NULL is a no-op. */
 void fmm_tree_free(fmm_tree *tree);
@@ -184,10 +193,14 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
                             int64_t *far_off, int32_t *far_src, int64_t *near_off,
                             int32_t *near_src, double *local);
 
-/* Per-stage device times of the last build/moments/forces calls in
- * milliseconds, host double[8]: build, moments, walk, m2l+l2l, p2p+l2p, vjp,
- * stats, total.  Timing is recorded only when enabled with
- * fmm_set_timing(tree, 1) (it adds event synchronisation). */
+/* Stage timing.  fmm_set_timing(tree, 1) starts recording a pair of HIP
+ * events around each stage on the caller's stream (no added synchronisation;
+ * it also clears the accumulated times); fmm_stage_times (synchronises on the
+ * last events) returns the MEAN device time per call since then, in
+ * milliseconds, host double[8]: build, moments, walk (count + scan + fill),
+ * far field (M2L, L2L), near field (P2P + L2P), vjp, stats (unused), and the
+ * sum of the first seven.  The far and near stages are one kernel launch
+ * each, so their means are per-launch kernel durations. */
 fmm_status fmm_set_timing(fmm_tree *tree, int32_t on);
 fmm_status fmm_stage_times(const fmm_tree *tree, double *ms);
 

@@ -148,9 +148,10 @@ static void release(Tree *t)
         (void)hipHostFree(t->h_totals);
     if (t->h_red)
         (void)hipHostFree(t->h_red);
-    for (auto &e : t->ev)
-        if (e)
-            (void)hipEventDestroy(e);
+    for (auto &pr : t->sev)
+        for (auto &e : pr)
+            if (e)
+                (void)hipEventDestroy(e);
     t->magic = 0;
     delete t;
 }
@@ -220,10 +221,9 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
         e = hipHostMalloc((void **)&t->h_totals, 4 * sizeof(int64_t), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&t->h_red, 16 * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipEventCreate(&t->ev[0]);
-    if (e == hipSuccess)
-        e = hipEventCreate(&t->ev[1]);
+    for (int k = 0; k < 8 && e == hipSuccess; ++k)
+        for (int j = 0; j < 2 && e == hipSuccess; ++j)
+            e = hipEventCreate(&t->sev[k][j]);
 #undef A
     if (e != hipSuccess) {
         fmm_status st = fail(e == hipErrorOutOfMemory ? FMM_ERR_ALLOC : FMM_ERR_HIP,
@@ -263,25 +263,40 @@ static fmm_status check_params(const fmm_params *p)
     return FMM_OK;
 }
 
-// stage timing (only when enabled)
+// Stage timing (only when enabled): a start/stop event pair per stage on the
+// caller's stream.  The previous pair of a stage is read when the stage runs
+// again (by then it has normally completed) or by fmm_stage_times, so timing
+// adds no synchronisation to the steady state.
+static void harvest(Tree &t, int slot)
+{
+    if (!t.pending[slot])
+        return;
+    (void)hipEventSynchronize(t.sev[slot][1]);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.sev[slot][0], t.sev[slot][1]) == hipSuccess) {
+        t.acc_ms[slot] += ms;
+        t.acc_n[slot] += 1;
+    }
+    t.pending[slot] = false;
+}
+
 struct StageTimer {
     Tree &t;
     hipStream_t s;
     int slot;
     StageTimer(Tree &tt, hipStream_t ss, int sl) : t(tt), s(ss), slot(sl)
     {
-        if (t.timing)
-            (void)hipEventRecord(t.ev[0], s);
+        if (t.timing) {
+            harvest(t, slot);
+            (void)hipEventRecord(t.sev[slot][0], s);
+        }
     }
     void done()
     {
         if (!t.timing)
             return;
-        (void)hipEventRecord(t.ev[1], s);
-        (void)hipEventSynchronize(t.ev[1]);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, t.ev[0], t.ev[1]);
-        t.times[slot] = ms;
+        (void)hipEventRecord(t.sev[slot][1], s);
+        t.pending[slot] = true;
     }
 };
 
@@ -494,6 +509,22 @@ fmm_status fmm_momentum_stats(const double *x, const double *v, const double *m,
     return FMM_OK;
 }
 
+fmm_status fmm_kick_drift(double *x, double *v, const void *a, int32_t a_precision, int64_t n,
+                          double kick, double drift, void *stream)
+{
+    if (!x || !v || !a)
+        return fail(FMM_ERR_INVALID, "x, v and a must not be NULL");
+    if (n < 1)
+        return fail(FMM_ERR_INVALID, "n must be positive");
+    if (a_precision != FMM_FP64 && a_precision != FMM_FP32)
+        return fail(FMM_ERR_INVALID, "unknown precision %d", a_precision);
+    if (!std::isfinite(kick) || !std::isfinite(drift))
+        return fail(FMM_ERR_INVALID, "kick and drift must be finite");
+    HIP_TRY(launch_kick_drift(x, v, a, a_precision == FMM_FP32, n, kick, drift,
+                              (hipStream_t)stream));
+    return FMM_OK;
+}
+
 void fmm_tree_free(fmm_tree *tree)
 {
     if (!tree_ok(tree))
@@ -601,7 +632,13 @@ fmm_status fmm_set_timing(fmm_tree *tree, int32_t on)
 {
     if (!tree_ok(tree))
         return fail(FMM_ERR_STATE, "unknown or freed tree handle");
-    reinterpret_cast<Tree *>(tree)->timing = on != 0;
+    Tree &t = *reinterpret_cast<Tree *>(tree);
+    for (int k = 0; k < 8; ++k) {
+        harvest(t, k);
+        t.acc_ms[k] = 0.0;
+        t.acc_n[k] = 0;
+    }
+    t.timing = on != 0;
     return FMM_OK;
 }
 
@@ -611,11 +648,12 @@ fmm_status fmm_stage_times(const fmm_tree *tree, double *ms)
         return fail(FMM_ERR_STATE, "unknown or freed tree handle");
     if (!ms)
         return fail(FMM_ERR_INVALID, "ms must not be NULL");
-    const Tree &t = *reinterpret_cast<const Tree *>(tree);
+    Tree &t = *const_cast<Tree *>(reinterpret_cast<const Tree *>(tree));
     double tot = 0.0;
     for (int k = 0; k < 7; ++k) {
-        ms[k] = t.times[k];
-        tot += t.times[k];
+        harvest(t, k);
+        ms[k] = t.acc_n[k] ? t.acc_ms[k] / (double)t.acc_n[k] : 0.0;
+        tot += ms[k];
     }
     ms[7] = tot;
     return FMM_OK;

@@ -130,9 +130,12 @@ struct Tree {
     bool has_tree = false, has_moments = false, has_lists = false, has_forces = false;
     int lists_policy = -1;
 
+    // stage timers: an event pair per stage, harvested lazily (no added syncs)
     bool timing = false;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    double times[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hipEvent_t sev[8][2] = {};
+    bool pending[8] = {};
+    double acc_ms[8] = {};
+    int64_t acc_n[8] = {};
 };
 
 // launchers (return hipError_t of the last launch / runtime call)
@@ -146,5 +149,7 @@ hipError_t launch_near(Tree &t, void *a, hipStream_t s);
 hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,
                         int a_fp32, int64_t n, double *red, double *h_out, hipStream_t s);
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s);
+hipError_t launch_kick_drift(double *x, double *v, const void *a, int a_fp32, int64_t n,
+                             double kick, double drift, hipStream_t s);
 
 }  // namespace fmm

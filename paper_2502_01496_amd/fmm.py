@@ -76,6 +76,9 @@ def lib() -> C.CDLL:
     L.fmm_momentum_stats.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_int64,
                                      C.POINTER(fmm_stats), _vp]
     L.fmm_momentum_stats.restype = st
+    L.fmm_kick_drift.argtypes = [_vp, _vp, _vp, C.c_int32, C.c_int64, C.c_double, C.c_double,
+                                 _vp]
+    L.fmm_kick_drift.restype = st
     L.fmm_tree_free.argtypes = [_vp]
     L.fmm_tree_free.restype = None
     L.fmm_tree_info.argtypes = [_vp, _vp]
@@ -185,6 +188,17 @@ def fmm_momentum_stats(x, v, m, a, stream=None) -> dict:
     return {"sumF": np.array(out.sumF), "sumAbsF": out.sumAbsF, "ratio": out.ratio,
             "mass": out.mass, "xcom": np.array(out.xcom), "P": np.array(out.P),
             "L": np.array(out.L)}
+
+
+def fmm_kick_drift(x, v, a, kick: float, drift: float, stream=None):
+    """v += kick * a; x += drift * v (in place, on the GPU)."""
+    import torch
+
+    n = x.shape[0]
+    prec = FMM_FP32 if a.dtype == torch.float32 else FMM_FP64
+    _check(lib().fmm_kick_drift(_ptr(x, torch.float64, (n, 3), "x"),
+                                _ptr(v, torch.float64, (n, 3), "v"), _ptr(a, a.dtype, (n, 3), "a"),
+                                prec, n, float(kick), float(drift), _stream(stream)))
 
 
 def fmm_tree_free(tree):
