@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -110,6 +111,18 @@ void build_topology(int64_t n, int leaf_size, Topology &T)
     for (int v = 0; v < T.nnodes; ++v)
         if (T.count[v] <= SUBTREE_MAX && (T.parent[v] < 0 || T.count[T.parent[v]] > SUBTREE_MAX))
             T.sub_root.push_back(v);
+    std::vector<std::vector<int32_t>> byl(T.depth);
+    for (int v = 0; v < T.nnodes; ++v)
+        if (T.left[v] >= 0)
+            byl[T.level[v]].push_back(v);
+    for (int v = 0; v < T.nnodes; ++v)
+        if (T.count[v] >= 64)
+            T.big_nodes.push_back(v);
+    T.lvl_int_off.assign(1, 0);
+    for (int l = 0; l < T.depth; ++l) {
+        T.int_nodes.insert(T.int_nodes.end(), byl[l].begin(), byl[l].end());
+        T.lvl_int_off.push_back((int32_t)T.int_nodes.size());
+    }
 }
 
 template <typename P>
@@ -144,8 +157,8 @@ static void release(Tree *t)
         (void)hipFree(t->far_buf.p);
     if (t->near_buf.p)
         (void)hipFree(t->near_buf.p);
-    if (t->h_totals)
-        (void)hipHostFree(t->h_totals);
+    if (t->h_flags)
+        (void)hipHostFree(t->h_flags);
     if (t->h_red)
         (void)hipHostFree(t->h_red);
     for (auto &pr : t->sev)
@@ -161,6 +174,10 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     Tree *t = new Tree();
     t->magic = TREE_MAGIC;
     t->p = p;
+    // Test hook: a smaller stack for the wide walk sends more leaves through
+    // the exact narrow-stack walk.
+    if (const char *e = std::getenv("FMM_MI355_WIDE_STACK"))
+        t->wide_stack_limit = std::atoi(e);
     build_topology(n, p.leaf_size, t->topo);
     const Topology &T = t->topo;
     const int64_t nn = T.nnodes;
@@ -182,6 +199,7 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(upload(*t, &t->blk_end, T.blk_end));
     A(upload(*t, &t->blk_first, T.blk_first));
     A(upload(*t, &t->sub_root, T.sub_root));
+    A(upload(*t, &t->int_nodes, T.int_nodes));
     A(dalloc(*t, &t->axis, nn));
     A(dalloc(*t, &t->keys0, 3 * n));
     A(dalloc(*t, &t->keys1, 3 * n));
@@ -207,18 +225,17 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->recQ, NREC * nn));
     A(dalloc(*t, &t->recF, NREC * nn));
     A(dalloc(*t, &t->s2bits, nn));
+    A(dalloc(*t, &t->s2part, (size_t)T.depth * ((n + 63) / 64)));
+    A(upload(*t, &t->big_nodes, T.big_nodes));
     A(dalloc(*t, &t->upcnt, nn));
     A(dalloc(*t, &t->far_cnt, nn));
     A(dalloc(*t, &t->near_cnt, nn));
-    A(dalloc(*t, &t->far_off, nn + 1));
-    A(dalloc(*t, &t->near_off, nn + 1));
-    A(dalloc(*t, &t->scan_tmp, 2 * (nn / 4096 + 2)));
-    A(dalloc(*t, &t->totals, 4));
+    A(dalloc(*t, &t->walk_flags, 4));
     A(dalloc(*t, &t->L, NLOC * nn));
     A(dalloc(*t, &t->Lf, NLOC * nn));
     A(dalloc(*t, &t->red, 16 + 16 * 512));
     if (e == hipSuccess)
-        e = hipHostMalloc((void **)&t->h_totals, 4 * sizeof(int64_t), hipHostMallocDefault);
+        e = hipHostMalloc((void **)&t->h_flags, 8 * sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&t->h_red, 16 * sizeof(double), hipHostMallocDefault);
     for (int k = 0; k < 8 && e == hipSuccess; ++k)
@@ -300,24 +317,37 @@ struct StageTimer {
     }
 };
 
-static fmm_status ensure_capacity(Tree &t, DevBuf &b, int32_t **ptr, int64_t &cap, int64_t need)
+// (Re)allocate the per-leaf list slots for capacities cap_far / cap_near.
+static fmm_status ensure_slots(Tree &t, int64_t cap_far, int64_t cap_near)
 {
-    if (need <= cap && b.p)
-        return FMM_OK;
-    int64_t nc = std::max<int64_t>(need + need / 4, 1024);
-    if (b.p) {
-        HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipFree(b.p));
-        b.p = nullptr;
+    const int64_t nl = t.topo.nleaves;
+    struct Want {
+        DevBuf *b;
+        int32_t **ptr;
+        int64_t *cap;
+        int64_t want;
+    } w[2] = {{&t.far_buf, &t.far_src, &t.cap_far, cap_far},
+              {&t.near_buf, &t.near_src, &t.cap_near, cap_near}};
+    for (auto &x : w) {
+        if (x.b->p && *x.cap == x.want)
+            continue;
+        if (x.b->p) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(x.b->p));
+            x.b->p = nullptr;
+        }
+        size_t bytes = (size_t)std::max<int64_t>(1, nl * x.want) * sizeof(int32_t);
+        void *p = nullptr;
+        HIP_TRY(hipMalloc(&p, bytes));
+        x.b->p = p;
+        x.b->bytes = bytes;
+        *x.ptr = (int32_t *)p;
+        *x.cap = x.want;
     }
-    void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, (size_t)nc * sizeof(int32_t)));
-    b.p = p;
-    b.bytes = (size_t)nc * sizeof(int32_t);
-    *ptr = (int32_t *)p;
-    cap = nc;
     return FMM_OK;
 }
+
+static int64_t round_cap(int64_t need) { return ((need + need / 4 + 64) + 63) / 64 * 64; }
 
 static std::mutex g_scratch_mu;
 static std::map<int, std::pair<double *, double *>> g_scratch;
@@ -429,13 +459,36 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
     if (!t.has_moments)
         return fail(FMM_ERR_STATE, "fmm_moments must run before fmm_forces");
     hipStream_t s = (hipStream_t)stream;
-    if (!t.has_lists || (flags & FMM_REWALK) || t.lists_policy != t.p.walk) {
-        StageTimer tm(t, s, 2);
-        HIP_TRY(launch_walk_count(t, s));
-        HIP_TRY(hipMemcpyAsync(t.h_totals, t.totals, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(t.h_totals + 2, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    const bool walk = !t.has_lists || (flags & FMM_REWALK) || t.lists_policy != t.p.walk;
+    if (walk && !t.far_buf.p) {
+        fmm_status st = ensure_slots(t, 512, 128);
+        if (st != FMM_OK)
+            return st;
+    }
+    // Optimistic order: walk, M2L, P2P, then one readback of the list maxima;
+    // if a slot overflowed, grow the slots and do it again.
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        if (walk) {
+            StageTimer tm(t, s, 2);
+            HIP_TRY(launch_walk(t, s));
+            tm.done();
+        }
+        {
+            StageTimer tm(t, s, 3);
+            HIP_TRY(launch_far(t, s));
+            tm.done();
+        }
+        {
+            StageTimer tm(t, s, 4);
+            HIP_TRY(launch_near(t, a, s));
+            tm.done();
+        }
+        if (!walk)
+            break;
+        HIP_TRY(hipMemcpyAsync(t.h_flags, t.walk_flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(t.h_flags + 4, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        uint32_t errbits = (uint32_t)(t.h_totals[2] & 0xffffffffu);
+        uint32_t errbits = (uint32_t)t.h_flags[4];
         if (errbits) {
             t.has_lists = false;
             return fail(FMM_ERR_INVALID, "bad input data:%s%s%s",
@@ -443,30 +496,33 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
                         (errbits & 2) ? " masses not positive and finite" : "",
                         (errbits & 4) ? " smoothing lengths not positive and finite" : "");
         }
-        t.n_far = t.h_totals[0];
-        t.n_near = t.h_totals[1];
-        fmm_status st = ensure_capacity(t, t.far_buf, &t.far_src, t.cap_far, t.n_far);
+        if (t.h_flags[2]) {
+            // some leaves overflowed the wide walk's stack: redo those exactly
+            HIP_TRY(launch_walk_fallback(t, s));
+            HIP_TRY(hipMemcpyAsync(t.h_flags, t.walk_flags, 4 * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        const int64_t mf = t.h_flags[0], mn = t.h_flags[1];
+        if (mf <= t.cap_far && mn <= t.cap_near) {
+            if (t.h_flags[2]) {  // lists were completed by the fallback: evaluate again
+                HIP_TRY(launch_far(t, s));
+                HIP_TRY(launch_near(t, a, s));
+            }
+            t.has_lists = true;
+            t.lists_policy = t.p.walk;
+            t.nsinks = t.topo.nleaves;
+            t.n_far = t.n_near = -1;  // totals computed on demand
+            t.has_forces = true;
+            return FMM_OK;
+        }
+        fmm_status st = ensure_slots(t, std::max(t.cap_far, round_cap(mf)),
+                                     std::max(t.cap_near, round_cap(mn)));
         if (st != FMM_OK)
             return st;
-        st = ensure_capacity(t, t.near_buf, &t.near_src, t.cap_near, t.n_near);
-        if (st != FMM_OK)
-            return st;
-        HIP_TRY(launch_walk_fill(t, s));
-        tm.done();
-        t.has_lists = true;
-        t.lists_policy = t.p.walk;
-        t.nsinks = t.topo.nleaves;
     }
-    {
-        StageTimer tm(t, s, 3);
-        HIP_TRY(launch_far(t, s));
-        tm.done();
-    }
-    {
-        StageTimer tm(t, s, 4);
-        HIP_TRY(launch_near(t, a, s));
-        tm.done();
-    }
+    if (walk)
+        return fail(FMM_ERR_CAPACITY, "interaction lists did not fit after resizing");
     t.has_forces = true;
     return FMM_OK;
 }
@@ -538,7 +594,18 @@ fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info)
         return fail(FMM_ERR_STATE, "unknown or freed tree handle");
     if (!info)
         return fail(FMM_ERR_INVALID, "info must not be NULL");
-    const Tree &t = *reinterpret_cast<const Tree *>(tree);
+    Tree &t = *const_cast<Tree *>(reinterpret_cast<const Tree *>(tree));
+    if (t.has_lists && t.n_far < 0) {
+        std::vector<int32_t> cf(t.nsinks), cn(t.nsinks);
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(cf.data(), t.far_cnt, cf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(cn.data(), t.near_cnt, cn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        t.n_far = t.n_near = 0;
+        for (int k = 0; k < t.nsinks; ++k) {
+            t.n_far += cf[k];
+            t.n_near += cn[k];
+        }
+    }
     info[0] = t.topo.n;
     info[1] = t.topo.nnodes;
     info[2] = t.topo.nleaves;
@@ -596,27 +663,39 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
     if (far_off || far_src || near_off || near_src) {
         if (!t.has_lists)
             return fail(FMM_ERR_STATE, "no interaction lists to export");
-        int ns = t.nsinks;
-        std::vector<int64_t> fo(ns + 1), no(ns + 1);
-        HIP_TRY(hipMemcpy(fo.data(), t.far_off, (ns + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(no.data(), t.near_off, (ns + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-        // sinks are leaves (indexed by leaf) -> node-indexed CSR, same entry order
-        auto to_nodes = [&](const std::vector<int64_t> &o, int64_t *out) {
-            out[0] = 0;
+        const int ns = t.nsinks;
+        std::vector<int32_t> cf(ns), cn(ns);
+        HIP_TRY(hipMemcpy(cf.data(), t.far_cnt, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(cn.data(), t.near_cnt, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+        // sinks are leaves: node-indexed CSR, entries in emission order
+        auto export_lists = [&](const std::vector<int32_t> &cnt, const int32_t *dev, int64_t cap,
+                                int64_t *off, int32_t *src) -> fmm_status {
+            std::vector<int32_t> slots((size_t)ns * cap);
+            if (src)
+                HIP_TRY(hipMemcpy(slots.data(), dev, slots.size() * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost));
+            int64_t o = 0;
+            if (off)
+                off[0] = 0;
             for (int64_t v = 0; v < nn; ++v) {
                 int lf = T.node_leaf[v];
-                out[v + 1] = out[v] + (lf >= 0 ? o[lf + 1] - o[lf] : 0);
+                if (lf >= 0) {
+                    if (src)
+                        std::memcpy(src + o, slots.data() + (size_t)lf * cap,
+                                    cnt[lf] * sizeof(int32_t));
+                    o += cnt[lf];
+                }
+                if (off)
+                    off[v + 1] = o;
             }
+            return FMM_OK;
         };
-        if (far_off)
-            to_nodes(fo, far_off);
-        if (near_off)
-            to_nodes(no, near_off);
-        if (far_src && t.n_far)
-            HIP_TRY(hipMemcpy(far_src, t.far_src, t.n_far * sizeof(int32_t), hipMemcpyDeviceToHost));
-        if (near_src && t.n_near)
-            HIP_TRY(hipMemcpy(near_src, t.near_src, t.n_near * sizeof(int32_t),
-                              hipMemcpyDeviceToHost));
+        fmm_status st = export_lists(cf, t.far_src, t.cap_far, far_off, far_src);
+        if (st != FMM_OK)
+            return st;
+        st = export_lists(cn, t.near_src, t.cap_near, near_off, near_src);
+        if (st != FMM_OK)
+            return st;
     }
     if (local) {
         std::vector<double> Lh(NLOC * nn);

@@ -36,8 +36,10 @@ __global__ void k_bbox_init(uint64_t *bbox, uint32_t *err)
         err[0] = 0u;
 }
 
-__global__ void k_bbox(const double *__restrict__ x, int64_t n, uint64_t *bbox, uint32_t *err)
+__global__ __launch_bounds__(256) void k_bbox(const double *__restrict__ x, int64_t n,
+                                              uint64_t *bbox, uint32_t *err)
 {
+    __shared__ uint64_t sh[4][7];
     uint64_t mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
     bool bad = false;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -60,14 +62,29 @@ __global__ void k_bbox(const double *__restrict__ x, int64_t n, uint64_t *bbox, 
             mn[d] = a < mn[d] ? a : mn[d];
             mx[d] = b > mx[d] ? b : mx[d];
         }
+    const int w = threadIdx.x >> 6;
     uint64_t anybad = __ballot(bad);
     if (lane_id() == 0) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            atomicMin((unsigned long long *)&bbox[d], (unsigned long long)mn[d]);
-            atomicMax((unsigned long long *)&bbox[3 + d], (unsigned long long)mx[d]);
+            sh[w][d] = mn[d];
+            sh[w][3 + d] = mx[d];
         }
-        if (anybad)
+        sh[w][6] = anybad ? 1ull : 0ull;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int k = threadIdx.x;
+        uint64_t r = sh[0][k];
+        for (int i = 1; i < 4; ++i) {
+            uint64_t o = sh[i][k];
+            r = (k < 3) ? (o < r ? o : r) : (o > r ? o : r);
+        }
+        if (k < 3)
+            atomicMin((unsigned long long *)&bbox[k], (unsigned long long)r);
+        else if (k < 6)
+            atomicMax((unsigned long long *)&bbox[k], (unsigned long long)r);
+        else if (r)
             atomicOr(err, 1u);
     }
 }
@@ -643,7 +660,7 @@ hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
     const int64_t n = T.n;
     const int gs = (int)std::min<int64_t>((n + 255) / 256, 2048);
     k_bbox_init<<<1, 64, 0, s>>>(t.bbox, t.err);
-    k_bbox<<<gs, 256, 0, s>>>(x, n, t.bbox, t.err);
+    k_bbox<<<(int)std::min<int64_t>((n + 255) / 256, 256), 256, 0, s>>>(x, n, t.bbox, t.err);
     k_morton<<<gs, 256, 0, s>>>(x, n, t.bbox, t.keys0, t.vals0);
     hipError_t e = radix_sort(t, t.keys0, t.vals0, t.keys1, t.vals1, n, 1, s);
     if (e != hipSuccess)

@@ -61,6 +61,10 @@ struct Topology {
     std::vector<int32_t> lvl_blk_off;  // nlevels_up + 1
     std::vector<int32_t> blk_node, blk_start, blk_end, blk_first;
     std::vector<int32_t> sub_root;     // roots of the LDS subtrees
+    // internal nodes grouped by level (for the bottom-up moment pass)
+    std::vector<int32_t> lvl_int_off;  // depth + 1
+    std::vector<int32_t> int_nodes;
+    std::vector<int32_t> big_nodes;    // nodes of at least 64 particles
 };
 
 void build_topology(int64_t n, int leaf_size, Topology &t);
@@ -80,7 +84,7 @@ struct Tree {
     int32_t *first = nullptr, *count = nullptr, *left = nullptr, *right = nullptr;
     int32_t *parent = nullptr, *level = nullptr, *leaf_node = nullptr, *node_leaf = nullptr;
     int32_t *blk_node = nullptr, *blk_start = nullptr, *blk_end = nullptr, *blk_first = nullptr;
-    int32_t *sub_root = nullptr, *axis = nullptr;
+    int32_t *sub_root = nullptr, *axis = nullptr, *int_nodes = nullptr;
 
     // build workspace
     uint64_t *keys0 = nullptr, *keys1 = nullptr;  // 3n each (batched sorts)
@@ -98,7 +102,7 @@ struct Tree {
     // particles in tree order
     double4 *pm = nullptr;        // x, y, z, m
     double *hs = nullptr;         // h
-    double2 *ph = nullptr;        // 1/h, 1/h^3
+    double4 *ph = nullptr;        // 1/h, 1/h^3, 4 h^2, 0
     float4 *pf = nullptr;         // FP32 form: offset from the leaf centre of mass, m
     float2 *pfh = nullptr;        // FP32 form: 1/h, 1/h^3
 
@@ -107,17 +111,20 @@ struct Tree {
     double *recQ = nullptr;       // per node: Qxx, Qxy, Qxz, Qyy, Qyz, Qzz, 0, 0
     float *recF = nullptr;        // per node FP32 mirror: M, Q[6], 0
     uint64_t *s2bits = nullptr;
+    uint64_t *s2part = nullptr;   // depth x ceil(n/64) per-wavefront maxima
+    int32_t *big_nodes = nullptr;
     int32_t *upcnt = nullptr;
 
-    // interaction lists (CSR over sinks: leaves for PHANTOM, nodes for MUTUAL)
-    int64_t *far_off = nullptr, *near_off = nullptr;
+    // interaction lists: fixed-capacity slots per sink leaf
+    //   far:  far_src[leaf * cap_far + k],  k < far_cnt[leaf]
+    //   near: near_src[leaf * cap_near + k], k < near_cnt[leaf]
     int32_t *far_src = nullptr, *near_src = nullptr;
     int64_t cap_far = 0, cap_near = 0;
     DevBuf far_buf, near_buf;
     int32_t *far_cnt = nullptr, *near_cnt = nullptr;
-    int64_t *scan_tmp = nullptr;
-    int64_t *totals = nullptr;    // device: far, near totals
-    int64_t *h_totals = nullptr;  // pinned host mirror
+    int32_t *walk_flags = nullptr;  // device: max far, max near, stack overflow, 0
+    int32_t *h_flags = nullptr;     // pinned host mirror of walk_flags + error bits
+    int wide_stack_limit = 1 << 30; // test hook: FMM_MI355_WIDE_STACK lowers it
     int nsinks = 0;
     int64_t n_far = 0, n_near = 0;
     double *L = nullptr;          // local expansions, NLOC per node
@@ -142,8 +149,8 @@ struct Tree {
 hipError_t launch_build(Tree &t, const double *x, hipStream_t s);
 hipError_t launch_moments(Tree &t, const double *x, const double *m, const double *h,
                           hipStream_t s);
-hipError_t launch_walk_count(Tree &t, hipStream_t s);
-hipError_t launch_walk_fill(Tree &t, hipStream_t s);
+hipError_t launch_walk(Tree &t, hipStream_t s);
+hipError_t launch_walk_fallback(Tree &t, hipStream_t s);
 hipError_t launch_far(Tree &t, hipStream_t s);
 hipError_t launch_near(Tree &t, void *a, hipStream_t s);
 hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,

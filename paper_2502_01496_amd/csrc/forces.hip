@@ -121,8 +121,8 @@ __device__ __forceinline__ void l2p(const T *L, T y0, T y1, T y2, T &a0, T &a1, 
 // butterfly sum over the 16 lanes (fixed order: deterministic).
 __global__ __launch_bounds__(256) void k_m2l_leaf_f64(
     const double *__restrict__ recA, const double *__restrict__ recQ,
-    const int32_t *__restrict__ leaf_node, int nleaves, const int64_t *__restrict__ far_off,
-    const int32_t *__restrict__ far_src, double *Lout)
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
+    const int32_t *__restrict__ far_src, int cap_far, double *Lout)
 {
     const int g = (blockIdx.x * 256 + threadIdx.x) >> 4;
     const int sub = threadIdx.x & 15;
@@ -134,9 +134,10 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f64(
 #pragma unroll
     for (int k = 0; k < 19; ++k)
         L[k] = 0.0;
-    const int64_t k0 = valid ? far_off[g] : 0, k1 = valid ? far_off[g + 1] : 0;
-    for (int64_t k = k0 + sub; k < k1; k += 16) {
-        const int b = far_src[k];
+    const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
+    const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
+    for (int k = sub; k < nk; k += 16) {
+        const int b = fl[k];
         const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
         const double *qb = recQ + (int64_t)NREC * b;
         const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
@@ -169,14 +170,17 @@ __device__ __forceinline__ double m4g_f64(double q, double hinv3, double u3)
 
 // One wavefront per sink leaf: lane = 8 * s + t takes sink s of the leaf and
 // source slot t of each near leaf, so a near leaf of 8 particles is one
-// 8 x 8 tile per wave step.  Larger leaves loop over 8-wide chunks.  The 8
-// partial sums of a sink are reduced with xor-shuffles; the t = 0 lane adds
-// L2P and writes G * a to the caller's slot of the particle.
+// 8 x 8 tile per wave step.  Larger leaves loop over 8-wide chunks.  When no
+// pair of a tile lies inside either smoothing support (r^2 >= 4 h^2 for both
+// particles) the tile takes the Newtonian branch only.  The 8 partial sums of
+// a sink are reduced with xor-shuffles; the t = 0 lane adds L2P and writes
+// G * a to the caller's slot of the particle.
+// ph[p] = (1/h, 1/h^3, 4 h^2, 0).
 __global__ __launch_bounds__(256) void k_p2p_leaf_f64(
-    const double4 *__restrict__ pm, const double2 *__restrict__ ph,
+    const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const int32_t *__restrict__ first, const int32_t *__restrict__ count,
-    const int32_t *__restrict__ leaf_node, int nleaves, const int64_t *__restrict__ near_off,
-    const int32_t *__restrict__ near_src, const double *__restrict__ Lloc,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
+    const int32_t *__restrict__ near_src, int cap_near, const double *__restrict__ Lloc,
     const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, int have_far,
     double *aout)
 {
@@ -188,38 +192,46 @@ __global__ __launch_bounds__(256) void k_p2p_leaf_f64(
     const int v = leaf_node[leaf];
     const int64_t f = first[v];
     const int c = count[v];
-    const int64_t k0 = near_off[leaf], k1 = near_off[leaf + 1];
+    const int nk = max(0, min(near_cnt[leaf], cap_near));
+    const int32_t *nl = near_src + (int64_t)leaf * cap_near;
     for (int sb = 0; sb < c; sb += 8) {
         const bool vi = sb + s < c;
         const int64_t i = f + sb + s;
         double4 xi = make_double4(0, 0, 0, 0);
-        double2 hi = make_double2(1, 1);
+        double4 hi = make_double4(1, 1, 0, 0);
         if (vi) {
             xi = pm[i];
             hi = ph[i];
         }
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int64_t k = k0; k < k1; ++k) {
-            const int bn = __builtin_amdgcn_readfirstlane(near_src[k]);
+        for (int k = 0; k < nk; ++k) {
+            const int bn = __builtin_amdgcn_readfirstlane(nl[k]);
             const int64_t fb = first[bn];
             const int cb = count[bn];
             for (int tb = 0; tb < cb; tb += 8) {
-                const bool vj = tb + tt < cb;
+                const bool vij = vi && (tb + tt < cb);
                 const int64_t j = fb + tb + tt;
                 double4 xj = make_double4(0, 0, 0, 0);
-                double2 hj = make_double2(1, 1);
-                if (vj) {
+                double4 hj = make_double4(1, 1, 0, 0);
+                if (tb + tt < cb) {
                     xj = pm[j];
                     hj = ph[j];
                 }
                 const double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const double u = r2 > 0.0 ? rsqrt(r2) : 0.0;
-                const double r = r2 * u;
-                const double u3 = u * u * u;
-                const double gi = m4g_f64(r * hi.x, hi.y, u3);
-                const double gj = m4g_f64(r * hj.x, hj.y, u3);
-                const double fm = (vi && vj) ? xj.w * 0.5 * (gi + gj) : 0.0;
+                const bool soft = vij && r2 < fmax(hi.z, hj.z);
+                double fm;
+                if (__ballot(soft) == 0ull) {
+                    const double u = rsqrt(r2);
+                    fm = vij ? xj.w * (u * u * u) : 0.0;
+                } else {
+                    const double u = r2 > 0.0 ? rsqrt(r2) : 0.0;
+                    const double r = r2 * u;
+                    const double u3 = u * u * u;
+                    const double gi = m4g_f64(r * hi.x, hi.y, u3);
+                    const double gj = m4g_f64(r * hj.x, hj.y, u3);
+                    fm = vij ? xj.w * 0.5 * (gi + gj) : 0.0;
+                }
                 ax -= fm * dx;
                 ay -= fm * dy;
                 az -= fm * dz;
@@ -250,13 +262,295 @@ __global__ __launch_bounds__(256) void k_p2p_leaf_f64(
     }
 }
 
+// 1/sqrt(x) for finite x > 0: hardware estimate plus one second-order
+// correction, y' = y + y e (1/2 + 3/8 e) with e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// Near field for leaves of at most 8 particles.  One wavefront per sink leaf,
+// lane = 8 s + t: sink s, source slot t.  Each step takes four near leaves, so
+// every lane evaluates four independent pairs; loads are clamped in-bounds
+// and invalid pairs are zeroed by a select.  Steps whose 256 pairs all lie
+// outside both smoothing supports (r^2 >= 4 h^2 for both particles) take the
+// Newtonian branch only.
+template <int U>
+__global__ __launch_bounds__(256) void k_p2p_leaf8_f64(
+    const double4 *__restrict__ pm, const double4 *__restrict__ ph,
+    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
+    const int32_t *__restrict__ near_src, int cap_near, const double *__restrict__ Lloc,
+    const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double *aout)
+{
+    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (leaf >= nleaves)
+        return;
+    const int lane = lane_id();
+    const int s = lane >> 3, tt = lane & 7;
+    const int v = leaf_node[leaf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const bool vi = s < c;
+    const int64_t i = f + (vi ? s : 0);
+    const double4 xi = pm[i];
+    const double4 hi = ph[i];
+    const int nk = max(0, min(near_cnt[leaf], cap_near));
+    const int32_t *nl = near_src + (int64_t)leaf * cap_near;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int k = 0; k < nk; k += U) {
+        double4 xj[U], hj[U];
+        bool vj[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int kk = k + q;
+            const int bn = kk < nk ? nl[kk] : -1;
+            const int64_t fb = bn >= 0 ? first[bn] : 0;
+            const int cb = bn >= 0 ? count[bn] : 0;
+            vj[q] = vi && tt < cb;
+            const int64_t j = fb + (tt < cb ? tt : 0);
+            xj[q] = pm[j];
+            hj[q] = ph[j];
+        }
+        double dx[U], dy[U], dz[U], r2[U];
+        bool soft = false;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            dx[q] = xi.x - xj[q].x;
+            dy[q] = xi.y - xj[q].y;
+            dz[q] = xi.z - xj[q].z;
+            r2[q] = dx[q] * dx[q] + dy[q] * dy[q] + dz[q] * dz[q];
+            soft |= vj[q] && (r2[q] < hi.z || r2[q] < hj[q].z);
+        }
+        if (__ballot(soft) == 0ull) {
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const double u = rsqrt_pos(r2[q]);
+                const double fm = vj[q] ? xj[q].w * (u * u * u) : 0.0;
+                ax -= fm * dx[q];
+                ay -= fm * dy[q];
+                az -= fm * dz[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const double u = r2[q] > 0.0 ? rsqrt_pos(r2[q]) : 0.0;
+                const double r = r2[q] * u;
+                const double u3 = u * u * u;
+                const double gi = m4g_f64(r * hi.x, hi.y, u3);
+                const double gj = m4g_f64(r * hj[q].x, hj[q].y, u3);
+                const double fm = vj[q] ? xj[q].w * 0.5 * (gi + gj) : 0.0;
+                ax -= fm * dx[q];
+                ay -= fm * dy[q];
+                az -= fm * dz[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        ax += __shfl_xor(ax, off);
+        ay += __shfl_xor(ay, off);
+        az += __shfl_xor(az, off);
+    }
+    if (vi && tt == 0) {
+        const double *rv = recA + (int64_t)NREC * v;
+        const double *L = Lloc + (int64_t)NLOC * v;
+        double Lr[19];
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            Lr[k] = L[k];
+        double fx, fy, fz;
+        l2p<double>(Lr, xi.x - rv[0], xi.y - rv[1], xi.z - rv[2], fx, fy, fz);
+        const int64_t o = 3 * (int64_t)perm[i];
+        aout[o] = G * (fx + ax);
+        aout[o + 1] = G * (fy + ay);
+        aout[o + 2] = G * (fz + az);
+    }
+}
+
+// Reduce-scatter of 12 per-lane doubles over the 64 lanes of a wavefront.
+// Each xor step halves the set of values a lane keeps (it sends the other
+// half to its partner); after the steps over lane bits 5..2 a lane holds the
+// partial sum of one value, and two plain butterfly steps finish the sum in
+// each group of four lanes.  Value index held by lane l:
+//   6 b5 + 3 b4 + (2 b3 + b2), valid when (2 b3 + b2) < 3.
+__device__ __forceinline__ double xchg_keep(double keep, double send, int off)
+{
+    return keep + __shfl_xor(send, off);
+}
+
+__device__ __forceinline__ double reduce_scatter12(const double *v, int lane, int &idx)
+{
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    double a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        a[k] = xchg_keep(b5 ? v[6 + k] : v[k], b5 ? v[k] : v[6 + k], 32);
+    double b[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        b[k] = xchg_keep(b4 ? a[3 + k] : a[k], b4 ? a[k] : a[3 + k], 16);
+    // 3 values -> pad to 4 -> 2 (bit 3)
+    const double c0 = xchg_keep(b3 ? b[2] : b[0], b3 ? b[0] : b[2], 8);
+    const double c1 = xchg_keep(b3 ? 0.0 : b[1], b3 ? b[1] : 0.0, 8);
+    // 2 -> 1 (bit 2)
+    double d = xchg_keep(b2 ? c1 : c0, b2 ? c0 : c1, 4);
+    d += __shfl_xor(d, 2);
+    d += __shfl_xor(d, 1);
+    idx = 6 * (int)b5 + 3 * (int)b4 + (2 * (int)b3 + (int)b2);
+    const bool ok = (2 * (int)b3 + (int)b2) < 3;
+    if (!ok)
+        idx = -1;
+    return d;
+}
+
+// Near field for leaves of at most 8 particles, source-per-lane form.  One
+// wavefront per sink leaf; a step takes 8 near leaves, lane = 8 g + t holds
+// source t of the g-th of them (loaded once: no redundant traffic), and the
+// sink particles, 4 per pass, are wave-uniform.  The (first, count) ranges of
+// the near leaves are staged in LDS once per leaf, and the sources of the
+// next step are loaded while the current step computes.  Missing sources are
+// placed far away with zero mass, so they add exactly zero.  For each sink, a
+// step whose 64 pairs all lie outside both smoothing supports takes the
+// Newtonian branch only.  The per-lane sums are reduce-scattered so that the
+// lane holding component c of sink s adds L2P and writes G * a.
+constexpr int P2P_RANGES = 512;  // near-leaf ranges staged in LDS per wavefront
+
+__device__ __forceinline__ void load_src(const double4 *__restrict__ pm,
+                                         const double4 *__restrict__ ph, int2 rg, int slot,
+                                         double4 &xj, double4 &hj)
+{
+    const bool valid = slot < rg.y;
+    const int64_t j = (int64_t)rg.x + (valid ? slot : 0);
+    xj = pm[j];
+    hj = ph[j];
+    if (!valid) {
+        xj = make_double4(1e30, 1e30, 1e30, 0.0);
+        hj.z = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_p2p_src_f64(
+    const double4 *__restrict__ pm, const double4 *__restrict__ ph,
+    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
+    const int32_t *__restrict__ near_src, int cap_near, const double *__restrict__ Lloc,
+    const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double *aout)
+{
+    constexpr int NS = 4;
+    __shared__ int2 rng[4][P2P_RANGES];
+    const int w = threadIdx.x >> 6;
+    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    if (leaf >= nleaves)
+        return;
+    const int lane = lane_id();
+    const int grp = lane >> 3, slot = lane & 7;
+    const int v = leaf_node[leaf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const int nk = max(0, min(near_cnt[leaf], cap_near));
+    const int32_t *nl = near_src + (int64_t)leaf * cap_near;
+    const double *rv = recA + (int64_t)NREC * v;
+    const double *Lv = Lloc + (int64_t)NLOC * v;
+    int2 *R = rng[w];
+    for (int sb = 0; sb < c; sb += NS) {
+        double sx[NS], sy[NS], sz[NS], shi[NS], sh3[NS], sh4[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int64_t is = f + min(sb + q, c - 1);
+            const double4 x4 = pm[is];
+            const double4 h4 = ph[is];
+            sx[q] = x4.x;
+            sy[q] = x4.y;
+            sz[q] = x4.z;
+            shi[q] = h4.x;
+            sh3[q] = h4.y;
+            sh4[q] = h4.z;
+        }
+        double acc[3 * NS];
+#pragma unroll
+        for (int q = 0; q < 3 * NS; ++q)
+            acc[q] = 0.0;
+        for (int c0 = 0; c0 < nk; c0 += P2P_RANGES) {
+            const int nc = min(nk - c0, P2P_RANGES);
+            // stage the ranges of this chunk of the near list (padded to 8)
+            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
+                int2 r = make_int2(0, 0);
+                if (k < nc) {
+                    const int bn = nl[c0 + k];
+                    r = make_int2(first[bn], count[bn]);
+                }
+                R[k] = r;
+            }
+            __builtin_amdgcn_wave_barrier();
+            double4 xj, hj;
+            load_src(pm, ph, R[grp], slot, xj, hj);
+            for (int kb = 0; kb < nc; kb += 8) {
+                double4 xn = xj, hn = hj;
+                if (kb + 8 < nc)
+                    load_src(pm, ph, R[kb + 8 + grp], slot, xn, hn);
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const bool soft = r2 < sh4[q] || r2 < hj.z;
+                    double fm;
+                    if (__ballot(soft) == 0ull) {
+                        const double u = rsqrt_pos(r2);
+                        fm = xj.w * (u * u * u);
+                    } else {
+                        const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+                        const double r = r2 * u;
+                        const double u3 = u * u * u;
+                        const double gi = m4g_f64(r * shi[q], sh3[q], u3);
+                        const double gj = m4g_f64(r * hj.x, hj.y, u3);
+                        fm = xj.w * 0.5 * (gi + gj);
+                    }
+                    acc[3 * q] -= fm * dx;
+                    acc[3 * q + 1] -= fm * dy;
+                    acc[3 * q + 2] -= fm * dz;
+                }
+                xj = xn;
+                hj = hn;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        int idx;
+        const double tot = reduce_scatter12(acc, lane, idx);
+        const int q = idx / 3, comp = idx - 3 * (idx / 3);
+        if (idx >= 0 && (lane & 3) == 0 && sb + q < c) {
+            // component comp of eq. (8) at sink q
+            double sxq = sx[0], syq = sy[0], szq = sz[0];
+#pragma unroll
+            for (int r = 1; r < NS; ++r)
+                if (q == r) {
+                    sxq = sx[r];
+                    syq = sy[r];
+                    szq = sz[r];
+                }
+            double Lr[19];
+#pragma unroll
+            for (int k = 0; k < 19; ++k)
+                Lr[k] = Lv[k];
+            double fx, fy, fz;
+            l2p<double>(Lr, sxq - rv[0], syq - rv[1], szq - rv[2], fx, fy, fz);
+            const double far_c = comp == 0 ? fx : (comp == 1 ? fy : fz);
+            const int64_t o = 3 * (int64_t)perm[f + sb + q] + comp;
+            aout[o] = G * (far_c + tot);
+        }
+    }
+}
+
 hipError_t launch_far(Tree &t, hipStream_t s)
 {
     const Topology &T = t.topo;
     int nl = T.nleaves;
     if (t.p.precision == FMM_FP64) {
         k_m2l_leaf_f64<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
-                                                             t.far_off, t.far_src, t.L);
+                                                             t.far_cnt, t.far_src, (int)t.cap_far,
+                                                             t.L);
     } else {
         return hipErrorNotSupported;
     }
@@ -268,9 +562,15 @@ hipError_t launch_near(Tree &t, void *a, hipStream_t s)
     const Topology &T = t.topo;
     int nl = T.nleaves;
     if (t.p.precision == FMM_FP64) {
-        k_p2p_leaf_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node,
-                                                    nl, t.near_off, t.near_src, t.L, t.recA,
-                                                    t.perm, t.p.G, 1, (double *)a);
+        if (t.p.leaf_size <= 8)
+            k_p2p_src_f64<<<(nl + 3) / 4, 256, 0, s>>>(
+                t.pm, t.ph, t.first, t.count, t.leaf_node, nl, t.near_cnt, t.near_src,
+                (int)t.cap_near, t.L, t.recA, t.perm, t.p.G, (double *)a);
+        else
+            k_p2p_leaf_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count,
+                                                        t.leaf_node, nl, t.near_cnt, t.near_src,
+                                                        (int)t.cap_near, t.L, t.recA, t.perm,
+                                                        t.p.G, 1, (double *)a);
     } else {
         return hipErrorNotSupported;
     }

@@ -1,14 +1,13 @@
 // Cell properties on gfx950 (Sec. 2 of the paper: mass, centre of mass, size
 // s, h_max; quadrupole eq. (7)).
 //
-//   k_gather     caller-order x, m, h -> tree-order SoA (x, y, z, m) and
-//                (1/h, 1/h^3); flags bad inputs; clears the per-node counters.
-//   k_leaf_up    one thread per leaf: M, sum(m x) left to right, c = S / M,
-//                h_max and the quadrupole about c; then the thread climbs:
-//                the second child to arrive at a parent (arrival counter)
-//                combines both children -- M = M_L + M_R,
-//                c = (M_L c_L + M_R c_R) / M, Q by the parallel-axis shift.
-//                The parent result does not depend on which child came last.
+//   k_gather     caller-order x, m, h -> tree-order (x, y, z, m), h and
+//                (1/h, 1/h^3, 4 h^2); flags bad inputs; clears the s^2 maxima.
+//   k_leaf_moments  one thread per leaf: M, sum(m x) left to right, c = S / M,
+//                h_max and the quadrupole about c.
+//   k_combine_level one launch per tree level, deepest first: parents from
+//                their two children -- M = M_L + M_R, c = (M_L c_L + M_R c_R) / M,
+//                Q by the parallel-axis shift, h_max = max.
 //   k_node_s2    s^2 = max over the node's particles of |x - c|^2, exactly:
 //                one thread per particle walks root -> leaf; lanes on the same
 //                node reduce with a segmented wave max, then one u64 atomicMax
@@ -23,7 +22,7 @@ namespace fmm {
 
 __global__ void k_gather(const double *__restrict__ x, const double *__restrict__ m,
                          const double *__restrict__ h, int64_t n, const int32_t *__restrict__ perm,
-                         double4 *pm, double *hs, double2 *ph, uint32_t *err, int nnodes,
+                         double4 *pm, double *hs, double4 *ph, uint32_t *err, int nnodes,
                          uint64_t *s2bits, int32_t *upcnt, int want_fp32, float2 *pfh)
 {
     int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -41,7 +40,7 @@ __global__ void k_gather(const double *__restrict__ x, const double *__restrict_
         pm[p] = make_double4(xx, yy, zz, mm);
         hs[p] = hh;
         double hi = 1.0 / hh;
-        ph[p] = make_double2(hi, hi * hi * hi);
+        ph[p] = make_double4(hi, hi * hi * hi, 4.0 * hh * hh, 0.0);
         if (want_fp32)
             pfh[p] = make_float2((float)hi, (float)(hi * hi * hi));
     }
@@ -57,12 +56,6 @@ __global__ void k_gather(const double *__restrict__ x, const double *__restrict_
         atomicOr(err, bad);
 }
 
-__device__ __forceinline__ double ld_acq(const double *p)
-{
-    uint64_t b = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)b);
-}
-
 __device__ __forceinline__ void quad_add(double *Q, double w, double y0, double y1, double y2)
 {
     double yy = y0 * y0 + y1 * y1 + y2 * y2;
@@ -74,12 +67,11 @@ __device__ __forceinline__ void quad_add(double *Q, double w, double y0, double 
     Q[5] += w * (3.0 * y2 * y2 - yy);
 }
 
-__global__ __launch_bounds__(256) void k_leaf_up(
+// P2M at the leaves: one thread per leaf.
+__global__ __launch_bounds__(256) void k_leaf_moments(
     const double4 *__restrict__ pm, const double *__restrict__ hs,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ first,
-    const int32_t *__restrict__ count, const int32_t *__restrict__ left,
-    const int32_t *__restrict__ right, const int32_t *__restrict__ parent, double *recA,
-    double *recQ, int32_t *upcnt, int want_fp32, float4 *pf)
+    const int32_t *__restrict__ count, double *recA, double *recQ, int want_fp32, float4 *pf)
 {
     int lf = blockIdx.x * blockDim.x + threadIdx.x;
     if (lf >= nleaves)
@@ -107,68 +99,72 @@ __global__ __launch_bounds__(256) void k_leaf_up(
             pf[f + k] = make_float4((float)y0, (float)y1, (float)y2, (float)q.w);
     }
     double *ra = recA + (int64_t)NREC * v;
-    ra[0] = c0;
-    ra[1] = c1;
-    ra[2] = c2;
-    ra[3] = M;
+    *(double4 *)ra = make_double4(c0, c1, c2, M);
     ra[5] = hm;
     double *rq = recQ + (int64_t)NREC * v;
     for (int k = 0; k < 6; ++k)
         rq[k] = Q[k];
-    // climb: the second child to arrive combines
-    while (v != 0) {
-        __threadfence();
-        int p = parent[v];
-        int old = atomicAdd(&upcnt[p], 1);
-        if (old == 0)
-            return;
-        __threadfence();
-        int l = left[p], r = right[p];
-        const double *al = recA + (int64_t)NREC * l, *ar = recA + (int64_t)NREC * r;
-        const double *ql = recQ + (int64_t)NREC * l, *qr = recQ + (int64_t)NREC * r;
-        double Ml = ld_acq(al + 3), Mr = ld_acq(ar + 3);
-        double cl[3] = {ld_acq(al), ld_acq(al + 1), ld_acq(al + 2)};
-        double cr[3] = {ld_acq(ar), ld_acq(ar + 1), ld_acq(ar + 2)};
-        double Mp = Ml + Mr;
-        double cp[3];
-        for (int d = 0; d < 3; ++d)
-            cp[d] = (Ml * cl[d] + Mr * cr[d]) / Mp;
-        double Qp[6] = {0, 0, 0, 0, 0, 0};
-        for (int k = 0; k < 6; ++k)
-            Qp[k] += ld_acq(ql + k);
-        quad_add(Qp, Ml, cl[0] - cp[0], cl[1] - cp[1], cl[2] - cp[2]);
-        for (int k = 0; k < 6; ++k)
-            Qp[k] += ld_acq(qr + k);
-        quad_add(Qp, Mr, cr[0] - cp[0], cr[1] - cp[1], cr[2] - cp[2]);
-        double hl = ld_acq(al + 5), hr = ld_acq(ar + 5);
-        double *pa = recA + (int64_t)NREC * p;
-        pa[0] = cp[0];
-        pa[1] = cp[1];
-        pa[2] = cp[2];
-        pa[3] = Mp;
-        pa[5] = hl > hr ? hl : hr;
-        double *pq = recQ + (int64_t)NREC * p;
-        for (int k = 0; k < 6; ++k)
-            pq[k] = Qp[k];
-        v = p;
-    }
 }
 
+// M2M for the internal nodes of one level (children were done by the
+// previous launch): M = M_L + M_R, c = (M_L c_L + M_R c_R) / M, quadrupole by
+// the parallel-axis shift of both children, h_max = max of the children.
+__global__ __launch_bounds__(256) void k_combine_level(const int32_t *__restrict__ nodes, int cnt,
+                                                       const int32_t *__restrict__ left,
+                                                       const int32_t *__restrict__ right,
+                                                       double *recA, double *recQ)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= cnt)
+        return;
+    const int p = nodes[k];
+    const int l = left[p], r = right[p];
+    const double *al = recA + (int64_t)NREC * l, *ar = recA + (int64_t)NREC * r;
+    const double *ql = recQ + (int64_t)NREC * l, *qr = recQ + (int64_t)NREC * r;
+    const double4 A = *(const double4 *)al, B = *(const double4 *)ar;
+    const double Ml = A.w, Mr = B.w;
+    const double cl[3] = {A.x, A.y, A.z}, cr[3] = {B.x, B.y, B.z};
+    const double Mp = Ml + Mr;
+    double cp[3];
+    for (int d = 0; d < 3; ++d)
+        cp[d] = (Ml * cl[d] + Mr * cr[d]) / Mp;
+    double Qp[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < 6; ++j)
+        Qp[j] += ql[j];
+    quad_add(Qp, Ml, cl[0] - cp[0], cl[1] - cp[1], cl[2] - cp[2]);
+    for (int j = 0; j < 6; ++j)
+        Qp[j] += qr[j];
+    quad_add(Qp, Mr, cr[0] - cp[0], cr[1] - cp[1], cr[2] - cp[2]);
+    const double hl = al[5], hr = ar[5];
+    double *pa = recA + (int64_t)NREC * p;
+    *(double4 *)pa = make_double4(cp[0], cp[1], cp[2], Mp);
+    pa[5] = hl > hr ? hl : hr;
+    double *pq = recQ + (int64_t)NREC * p;
+    for (int j = 0; j < 6; ++j)
+        pq[j] = Qp[j];
+}
+
+// Exact s^2 per node, phase 1: one thread per particle walks root -> leaf.
+// At each level, a wavefront whose 64 particles all lie in one node writes
+// its maximum to part[level][wave]; otherwise the lanes of each node reduce
+// with a segmented max and one atomicMax per node run (few lanes per node, so
+// little contention).
 __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm, int64_t n,
                                                  const double *__restrict__ recA,
                                                  const int32_t *__restrict__ first,
                                                  const int32_t *__restrict__ count,
                                                  const int32_t *__restrict__ left,
                                                  const int32_t *__restrict__ right,
-                                                 uint64_t *s2bits)
+                                                 uint64_t *s2bits, uint64_t *part, int64_t nwaves)
 {
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t wave = p >> 6;
     const int lane = lane_id();
     bool done = p >= n;
     double4 xp = done ? make_double4(0, 0, 0, 0) : pm[p];
     int v = 0;
-    while (__ballot(!done) != 0ull) {
-        int key = done ? -1 : v;
+    for (int lvl = 0; __ballot(!done) != 0ull; ++lvl) {
+        const int key = done ? -1 : v;
         uint64_t val = 0ull;
         if (!done) {
             const double *ra = recA + (int64_t)NREC * v;
@@ -176,6 +172,8 @@ __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm,
             double d2 = (dx * dx + dy * dy) + dz * dz;
             val = (uint64_t)__double_as_longlong(d2);
         }
+        const int k0 = __shfl(key, 0);
+        const bool uniform = __ballot(key == k0 && key >= 0) == ~0ull;
         // segmented inclusive max over runs of equal key (runs are contiguous)
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -184,10 +182,15 @@ __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm,
             if (lane >= off && ok == key)
                 val = ov > val ? ov : val;
         }
-        int nk = __shfl_down(key, 1);
-        bool tail = (lane == 63) || (nk != key);
-        if (!done && tail)
-            atomicMax((unsigned long long *)&s2bits[v], (unsigned long long)val);
+        if (uniform) {
+            if (lane == 63)
+                part[(int64_t)lvl * nwaves + wave] = val;
+        } else {
+            int nk = __shfl_down(key, 1);
+            bool tail = (lane == 63) || (nk != key);
+            if (!done && tail)
+                atomicMax((unsigned long long *)&s2bits[v], (unsigned long long)val);
+        }
         if (!done) {
             int l = left[v];
             if (l < 0)
@@ -196,6 +199,37 @@ __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm,
                 v = (p < (int64_t)first[l] + count[l]) ? l : right[v];
         }
     }
+}
+
+// Phase 2: one wavefront per node of at least 64 particles folds the partial
+// maxima of the wavefronts lying entirely inside it.
+__global__ __launch_bounds__(256) void k_node_s2_fold(const int32_t *__restrict__ big,
+                                                      int nbig,
+                                                      const int32_t *__restrict__ first,
+                                                      const int32_t *__restrict__ count,
+                                                      const int32_t *__restrict__ level,
+                                                      const uint64_t *__restrict__ part,
+                                                      int64_t nwaves, uint64_t *s2bits)
+{
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= nbig)
+        return;
+    const int v = big[k];
+    const int64_t w0 = ((int64_t)first[v] + 63) >> 6;
+    const int64_t w1 = ((int64_t)first[v] + count[v]) >> 6;
+    const uint64_t *pl = part + (int64_t)level[v] * nwaves;
+    uint64_t m = 0ull;
+    for (int64_t wv = w0 + lane_id(); wv < w1; wv += 64) {
+        uint64_t x = pl[wv];
+        m = x > m ? x : m;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t o = __shfl_xor(m, off);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0 && w1 > w0)
+        atomicMax((unsigned long long *)&s2bits[v], (unsigned long long)m);
 }
 
 __global__ void k_node_final(int nnodes, const uint64_t *__restrict__ s2bits, double *recA,
@@ -226,12 +260,22 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
     int want32 = t.p.precision == FMM_FP32;
     k_gather<<<gs, 256, 0, s>>>(x, m, h, n, t.perm, t.pm, t.hs, t.ph, t.err, T.nnodes, t.s2bits,
                                 t.upcnt, want32, t.pfh);
-    k_leaf_up<<<(T.nleaves + 255) / 256, 256, 0, s>>>(t.pm, t.hs, t.leaf_node, T.nleaves,
-                                                      t.first, t.count, t.left, t.right,
-                                                      t.parent, t.recA, t.recQ, t.upcnt, want32,
-                                                      t.pf);
+    k_leaf_moments<<<(T.nleaves + 255) / 256, 256, 0, s>>>(t.pm, t.hs, t.leaf_node, T.nleaves,
+                                                           t.first, t.count, t.recA, t.recQ,
+                                                           want32, t.pf);
+    for (int l = T.depth - 2; l >= 0; --l) {
+        int o = T.lvl_int_off[l], cnt = T.lvl_int_off[l + 1] - o;
+        if (cnt > 0)
+            k_combine_level<<<(cnt + 255) / 256, 256, 0, s>>>(t.int_nodes + o, cnt, t.left,
+                                                              t.right, t.recA, t.recQ);
+    }
+    const int64_t nwaves = (n + 63) / 64;
     k_node_s2<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, t.first, t.count, t.left,
-                                                     t.right, t.s2bits);
+                                                     t.right, t.s2bits, t.s2part, nwaves);
+    const int nbig = (int)T.big_nodes.size();
+    if (nbig > 0)
+        k_node_s2_fold<<<(nbig + 3) / 4, 256, 0, s>>>(t.big_nodes, nbig, t.first, t.count,
+                                                      t.level, t.s2part, nwaves, t.s2bits);
     k_node_final<<<(T.nnodes + 255) / 256, 256, 0, s>>>(T.nnodes, t.s2bits, t.recA, t.recQ,
                                                        want32, t.recF);
     return hipGetLastError();

@@ -8,11 +8,8 @@
 // A cell meeting neither is far (M2L); an opened leaf is near (direct sum);
 // an opened internal cell is descended.
 //
-// One wavefront walks 64 consecutive sink leaves together: it shares one DFS
-// stack whose entries carry the 64-bit mask of lanes that opened the parent,
-// so every node record is a wave-uniform load and the per-lane visit order is
-// the serial DFS order (lists come out in ascending tree order).  A count pass
-// sizes the CSR; after a scan, a fill pass writes the node ids.
+// The lists live in fixed per-leaf slots (capacities grown by the host when a
+// count exceeds them), so one pass both counts and writes.
 //
 // Compiled with -ffp-contract=off so the criteria are evaluated with exactly
 // the operations of their definition.
@@ -21,30 +18,125 @@
 namespace fmm {
 
 constexpr int WALK_STACK = 96;
+constexpr int WIDE_STACK = 1024;
 
-template <bool FILL>
+__device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, double sa, double ha,
+                                       const double *rb, double theta2, double r_kern)
+{
+    const double dx = ca0 - rb[0], dy = ca1 - rb[1], dz = ca2 - rb[2];
+    const double sb = rb[4], hb = rb[5];
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    const bool open4 = sb * sb > theta2 * r2;
+    const double tt = (sa + sb) + r_kern * (ha > hb ? ha : hb);
+    const bool open5 = r2 < tt * tt;
+    return open4 || open5;
+}
+
+// One wavefront per sink leaf.  The pending cells sit on an LDS stack; each
+// step pops up to 64 of them (one per lane), applies the two criteria, writes
+// far / near entries with ballot compaction and pushes the children of the
+// opened internal cells.  Lists go to fixed per-leaf slots of capacity
+// cap_far / cap_near; counts beyond a slot are still counted (the host then
+// grows the slots and walks again).  A full stack sets *stack_overflow and
+// the leaf is redone by k_walk_p (exact, narrow stack).
+__global__ __launch_bounds__(256) void k_walk_wide(
+    const double *__restrict__ recA, const int32_t *__restrict__ left,
+    const int32_t *__restrict__ right, const int32_t *__restrict__ leaf_node, int nleaves,
+    double theta2, double r_kern, int32_t *far_src, int cap_far, int32_t *near_src,
+    int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *maxcnt, int32_t *stack_overflow,
+    int stack_limit)
+{
+    __shared__ int32_t stk[4][WIDE_STACK];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int leaf = blockIdx.x * 4 + w;
+    if (leaf >= nleaves)
+        return;
+    const uint64_t lt = lanemask_lt();
+    const int a = leaf_node[leaf];
+    const double *ra = recA + (int64_t)NREC * a;
+    const double ca0 = ra[0], ca1 = ra[1], ca2 = ra[2], sa = ra[4], ha = ra[5];
+    int32_t *fo = far_src + (int64_t)leaf * cap_far;
+    int32_t *no = near_src + (int64_t)leaf * cap_near;
+    int nf = 0, nn = 0, sp = 1;
+    bool ovf = false;
+    if (lane == 0)
+        stk[w][0] = 0;
+    while (sp > 0) {
+        const int take = sp < 64 ? sp : 64;
+        const int base = sp - take;
+        const bool act = lane < take;
+        const int b = act ? stk[w][base + lane] : 0;
+        sp = base;
+        bool far = false, nea = false, desc = false;
+        int lb = -1, rb_ = -1;
+        if (act) {
+            const bool op = opened(ca0, ca1, ca2, sa, ha, recA + (int64_t)NREC * b, theta2, r_kern);
+            lb = left[b];
+            rb_ = right[b];
+            far = !op;
+            nea = op && lb < 0;
+            desc = op && lb >= 0;
+        }
+        const uint64_t mf = __ballot(far), mn = __ballot(nea), md = __ballot(desc);
+        if (far) {
+            const int k = nf + __popcll(mf & lt);
+            if (k < cap_far)
+                fo[k] = b;
+        }
+        if (nea) {
+            const int k = nn + __popcll(mn & lt);
+            if (k < cap_near)
+                no[k] = b;
+        }
+        nf += __popcll(mf);
+        nn += __popcll(mn);
+        const int nd = __popcll(md);
+        if (sp + 2 * nd > stack_limit) {
+            ovf = true;
+            break;
+        }
+        if (desc) {
+            const int k = sp + 2 * __popcll(md & lt);
+            stk[w][k] = rb_;
+            stk[w][k + 1] = lb;
+        }
+        sp += 2 * nd;
+    }
+    if (lane == 0) {
+        if (ovf) {
+            // marked for the narrow-stack walk; until then the leaf has no
+            // list entries (the force kernels may run before that walk)
+            atomicOr(stack_overflow, 1);
+            far_cnt[leaf] = -1;
+            near_cnt[leaf] = 0;
+        } else {
+            far_cnt[leaf] = nf;
+            near_cnt[leaf] = nn;
+        }
+    }
+}
+
+// Fallback for leaves whose wide walk overflowed its stack (far_cnt == -1):
+// 64 consecutive leaves per wave share one DFS stack whose entries carry the
+// mask of lanes that opened the parent (depth-bounded), writing the same slots.
 __global__ __launch_bounds__(256) void k_walk_p(
     const double *__restrict__ recA, const int32_t *__restrict__ left,
     const int32_t *__restrict__ right, const int32_t *__restrict__ leaf_node, int nleaves,
-    double theta2, double r_kern, int32_t *far_cnt, int32_t *near_cnt,
-    const int64_t *__restrict__ far_off, const int64_t *__restrict__ near_off, int32_t *far_src,
-    int32_t *near_src)
+    double theta2, double r_kern, int32_t *far_src, int cap_far, int32_t *near_src,
+    int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *maxcnt)
 {
     __shared__ int32_t stk_node[4][WALK_STACK];
     __shared__ uint64_t stk_mask[4][WALK_STACK];
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int leaf = blockIdx.x * 256 + threadIdx.x;
-    const bool valid = leaf < nleaves;
+    const bool valid = leaf < nleaves && far_cnt[leaf] < 0;
     const int a = valid ? leaf_node[leaf] : 0;
     const double *ra = recA + (int64_t)NREC * a;
     const double ca0 = ra[0], ca1 = ra[1], ca2 = ra[2], sa = ra[4], ha = ra[5];
-    int64_t fo = 0, no = 0;
-    if (FILL && valid) {
-        fo = far_off[leaf];
-        no = near_off[leaf];
-    }
+    int32_t *fo = far_src + (int64_t)(valid ? leaf : 0) * cap_far;
+    int32_t *no = near_src + (int64_t)(valid ? leaf : 0) * cap_near;
     int nf = 0, nn = 0;
-    uint64_t vmask = __ballot(valid);
+    const uint64_t vmask = __ballot(valid);
     if (vmask == 0ull)
         return;
     int sp = 1;
@@ -56,25 +148,17 @@ __global__ __launch_bounds__(256) void k_walk_p(
         --sp;
         const int b = __builtin_amdgcn_readfirstlane(stk_node[w][sp]);
         const uint64_t mask = stk_mask[w][sp];
-        const double *rb = recA + (int64_t)NREC * b;
-        const double cb0 = rb[0], cb1 = rb[1], cb2 = rb[2], sb = rb[4], hb = rb[5];
         const int lb = left[b];
-        const bool leafb = lb < 0;
         const bool active = (mask >> lane) & 1ull;
         bool descend = false;
         if (active) {
-            double dx = ca0 - cb0, dy = ca1 - cb1, dz = ca2 - cb2;
-            double r2 = (dx * dx + dy * dy) + dz * dz;
-            bool open4 = sb * sb > theta2 * r2;
-            double tt = (sa + sb) + r_kern * (ha > hb ? ha : hb);
-            bool open5 = r2 < tt * tt;
-            if (!(open4 || open5)) {
-                if (FILL)
-                    far_src[fo + nf] = b;
+            if (!opened(ca0, ca1, ca2, sa, ha, recA + (int64_t)NREC * b, theta2, r_kern)) {
+                if (nf < cap_far)
+                    fo[nf] = b;
                 ++nf;
-            } else if (leafb) {
-                if (FILL)
-                    near_src[no + nn] = b;
+            } else if (lb < 0) {
+                if (nn < cap_near)
+                    no[nn] = b;
                 ++nn;
             } else {
                 descend = true;
@@ -91,143 +175,75 @@ __global__ __launch_bounds__(256) void k_walk_p(
             sp += 2;
         }
     }
-    if (!FILL && valid) {
+    if (valid) {
         far_cnt[leaf] = nf;
         near_cnt[leaf] = nn;
     }
 }
 
-// ---------------------------------------------------------------- offsets
-// Exclusive scans of the far and near counts (int32 -> int64 offsets, with the
-// total at [nsinks]): per-tile sums, one scan of the tile sums, tile rescans.
-constexpr int SCAN_TILE = 4096;
-
-__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t *sh, int64_t &total)
-{
-    int t = threadIdx.x, lane = lane_id(), w = t >> 6, nw = blockDim.x >> 6;
-    int64_t inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int64_t o = __shfl_up(inc, off);
-        if (lane >= off)
-            inc += o;
-    }
-    if (lane == 63)
-        sh[w] = inc;
-    __syncthreads();
-    int64_t wb = 0, tot = 0;
-    for (int i = 0; i < nw; ++i) {
-        int64_t s = sh[i];
-        wb += i < w ? s : 0;
-        tot += s;
-    }
-    __syncthreads();
-    total = tot;
-    return wb + inc - v;
+__global__ void k_walk_init(int32_t *maxcnt) {
+    if (threadIdx.x < 4)
+        maxcnt[threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t *cf, const int32_t *cn, int ns,
-                                                    int64_t *tsum, int ntiles)
+// Largest far and near list over all leaves (one workgroup; the overflow flag
+// in maxcnt[2] is left as the walk set it).
+__global__ __launch_bounds__(1024) void k_list_max(const int32_t *__restrict__ far_cnt,
+                                                   const int32_t *__restrict__ near_cnt, int n,
+                                                   int32_t *maxcnt)
 {
-    __shared__ int64_t sh[8];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    int64_t sf = 0, sn = 0;
-    for (int k = threadIdx.x; k < SCAN_TILE; k += 256) {
-        int64_t i = base + k;
-        if (i < ns) {
-            sf += cf[i];
-            sn += cn[i];
-        }
+    __shared__ int32_t sh[2][16];
+    int mf = 0, mn = 0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        mf = max(mf, far_cnt[i]);
+        mn = max(mn, near_cnt[i]);
     }
-    int64_t tf, tn;
-    block_excl_scan_i64(sf, sh, tf);
-    block_excl_scan_i64(sn, sh, tn);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        mf = max(mf, __shfl_xor(mf, off));
+        mn = max(mn, __shfl_xor(mn, off));
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        sh[0][w] = mf;
+        sh[1][w] = mn;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        tsum[blockIdx.x] = tf;
-        tsum[ntiles + blockIdx.x] = tn;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_scan_tile_sums(int64_t *tsum, int ntiles, int64_t *totals)
-{
-    __shared__ int64_t sh[16];
-    for (int q = 0; q < 2; ++q) {
-        int64_t run = 0;
-        for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-            int i = c0 + threadIdx.x;
-            int64_t v = i < ntiles ? tsum[q * ntiles + i] : 0;
-            int64_t total;
-            int64_t ex = block_excl_scan_i64(v, sh, total);
-            if (i < ntiles)
-                tsum[q * ntiles + i] = run + ex;
-            run += total;
+        for (int i = 1; i < 16; ++i) {
+            mf = max(mf, sh[0][i]);
+            mn = max(mn, sh[1][i]);
         }
-        if (threadIdx.x == 0)
-            totals[q] = run;
+        maxcnt[0] = mf;
+        maxcnt[1] = mn;
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_write(const int32_t *cf, const int32_t *cn, int ns,
-                                                    const int64_t *tsum, int ntiles,
-                                                    int64_t *far_off, int64_t *near_off,
-                                                    const int64_t *totals)
-{
-    constexpr int PER = SCAN_TILE / 256;
-    __shared__ int64_t sh[8];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * PER;
-    int32_t vf[PER], vn[PER];
-    int64_t sf = 0, sn = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        int64_t i = base + k;
-        vf[k] = i < ns ? cf[i] : 0;
-        vn[k] = i < ns ? cn[i] : 0;
-        sf += vf[k];
-        sn += vn[k];
-    }
-    int64_t tf, tn;
-    int64_t ef = block_excl_scan_i64(sf, sh, tf) + tsum[blockIdx.x];
-    int64_t en = block_excl_scan_i64(sn, sh, tn) + tsum[ntiles + blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        int64_t i = base + k;
-        if (i < ns) {
-            far_off[i] = ef;
-            near_off[i] = en;
-        }
-        ef += vf[k];
-        en += vn[k];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        far_off[ns] = totals[0];
-        near_off[ns] = totals[1];
-    }
-}
-
-hipError_t launch_walk_count(Tree &t, hipStream_t s)
+hipError_t launch_walk(Tree &t, hipStream_t s)
 {
     const Topology &T = t.topo;
     const double theta2 = t.p.theta * t.p.theta;
-    int nl = T.nleaves;
-    k_walk_p<false><<<(nl + 255) / 256, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, nl,
-                                                     theta2, t.p.r_kern, t.far_cnt, t.near_cnt,
-                                                     nullptr, nullptr, nullptr, nullptr);
-    int ntiles = (nl + SCAN_TILE - 1) / SCAN_TILE;
-    k_scan_tiles<<<ntiles, 256, 0, s>>>(t.far_cnt, t.near_cnt, nl, t.scan_tmp, ntiles);
-    k_scan_tile_sums<<<1, 1024, 0, s>>>(t.scan_tmp, ntiles, t.totals);
-    k_scan_write<<<ntiles, 256, 0, s>>>(t.far_cnt, t.near_cnt, nl, t.scan_tmp, ntiles, t.far_off,
-                                        t.near_off, t.totals);
+    const int nl = T.nleaves;
+    k_walk_init<<<1, 64, 0, s>>>(t.walk_flags);
+    k_walk_wide<<<(nl + 3) / 4, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, nl, theta2,
+                                             t.p.r_kern, t.far_src, (int)t.cap_far, t.near_src,
+                                             (int)t.cap_near, t.far_cnt, t.near_cnt, t.walk_flags,
+                                             t.walk_flags + 2,
+                                             std::min(std::max(t.wide_stack_limit, 2), WIDE_STACK));
+    k_list_max<<<1, 1024, 0, s>>>(t.far_cnt, t.near_cnt, nl, t.walk_flags);
     return hipGetLastError();
 }
 
-hipError_t launch_walk_fill(Tree &t, hipStream_t s)
+hipError_t launch_walk_fallback(Tree &t, hipStream_t s)
 {
     const Topology &T = t.topo;
     const double theta2 = t.p.theta * t.p.theta;
-    int nl = T.nleaves;
-    k_walk_p<true><<<(nl + 255) / 256, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, nl,
-                                                    theta2, t.p.r_kern, nullptr, nullptr,
-                                                    t.far_off, t.near_off, t.far_src, t.near_src);
+    const int nl = T.nleaves;
+    k_walk_p<<<(nl + 255) / 256, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, nl, theta2,
+                                               t.p.r_kern, t.far_src, (int)t.cap_far, t.near_src,
+                                               (int)t.cap_near, t.far_cnt, t.near_cnt,
+                                               t.walk_flags);
+    k_list_max<<<1, 1024, 0, s>>>(t.far_cnt, t.near_cnt, nl, t.walk_flags);
     return hipGetLastError();
 }
 
