@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--accuracy-sinks", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-census", action="store_true")
+    ap.add_argument("--single-precision", action="store_true",
+                    help="time only --precision (default: both FP64 and FP32)")
     return ap.parse_args()
 
 
@@ -142,31 +144,19 @@ def cpu_baseline(x, m, h, theta):
                       f"same {len(m)}-particle workload, serial FP64 C oracle, {dt:.1f} s"}
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
-              "the multi-GPU sharding of this path is a design (see DESIGN.md), not built.",
-              file=sys.stderr)
-        sys.exit(2)
+def run_one(args, x_np, m_np, h_np, prec, census=True):
+    """Timed KDK steps at one precision; returns the per-precision record."""
     import numpy as np
     import torch
 
     from paper_2502_01496_amd import fmm as F
-    from paper_2502_01496_amd import workloads as W
 
-    torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    x_np, m_np, h_np, _ = W.config(args.workload)
     n = len(m_np)
-    log(f"[bench] workload {args.workload}: n={n}, setup {time.perf_counter() - t0:.1f}s")
     dev = "cuda"
     x = torch.from_numpy(x_np).to(dev)
     m = torch.from_numpy(m_np).to(dev)
     h = torch.from_numpy(h_np).to(dev)
     v = torch.zeros_like(x)
-    prec = F.FMM_FP32 if args.precision == "fp32" else F.FMM_FP64
     adt = torch.float32 if prec == F.FMM_FP32 else torch.float64
     g = F.GravityFMM(theta=args.theta, precision=prec)
     a = torch.empty((n, 3), dtype=adt, device=dev)
@@ -189,19 +179,21 @@ def main():
         step()
     torch.cuda.synchronize()
     F.fmm_set_timing(g.tree, True)
-    ratios = []
+    ratios, xcom = [], []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
         st = step()
         ratios.append(st["ratio"])
+        xcom.append(st["xcom"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
     stages = F.fmm_stage_times(g.tree)
     F.fmm_set_timing(g.tree, False)
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
-    log(f"[bench] {args.steps} steps in {elapsed:.3f}s -> {ms_step:.3f} ms/step, "
+    tag = "fp32" if prec == F.FMM_FP32 else "fp64"
+    log(f"[bench {tag}] {args.steps} steps in {elapsed:.3f}s -> {ms_step:.3f} ms/step, "
         f"{value:.4e} particle-forces/s; stages (ms/call) {stages}")
 
     info = F.fmm_tree_info(g.tree)
@@ -213,17 +205,16 @@ def main():
     got = a[sinks].double()
     rel = (torch.linalg.norm(got - ref, dim=1) / torch.linalg.norm(ref, dim=1)).cpu().numpy()
     eta = float(torch.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum()))
-    log(f"[bench] accuracy on {len(sinks)} sinks: median {np.median(rel):.3e} "
+    log(f"[bench {tag}] accuracy on {len(sinks)} sinks: median {np.median(rel):.3e} "
         f"p99 {np.percentile(rel, 99):.3e} eta {eta:.3e}")
 
     # roofline of the dominant kernel
     peak = PEAK_FP32 if prec == F.FMM_FP32 else PEAK_FP64
-    if args.no_census:
-        pairs = soft = None
-        p2p_flops = None
-    else:
+    if census:
         pairs, soft = pair_census(x, h, ex, g.leaf_size)
         p2p_flops = FLOP_PAIR_NEWTON * (pairs - soft) + FLOP_PAIR_SOFT * soft
+    else:
+        pairs = soft = p2p_flops = None
     m2l_flops = FLOP_M2L * info["n_far"]
     kern = {}
     if p2p_flops is not None and stages["near"] > 0:
@@ -234,37 +225,80 @@ def main():
     roof = None
     if dom:
         achieved = kern[dom][0] / 1e12
-        tag = {"p2p": "k_p2p_leaf", "m2l": "k_m2l_leaf"}[dom] + ("_f32" if prec else "_f64")
+        ktag = {"p2p": "k_p2p_src", "m2l": "k_m2l_leaf"}[dom] + "_" + ("f32" if prec else "f64")
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
-                "traffic": profile_traffic(tag), "kernel": tag,
+                "traffic": profile_traffic(ktag), "kernel": ktag,
                 "kernel_ms": round(kern[dom][1], 4)}
+        others = {k: {"achieved": round(kv[0] / 1e12, 3), "frac": round(kv[0] / peak, 4),
+                      "kernel_ms": round(kv[1], 4)} for k, kv in kern.items() if k != dom}
+        roof["other_kernels"] = others
+    xc = np.array(xcom)
+    rec = {
+        "value": value, "ms_per_step": ms_step, "dtype": "f32" if prec == F.FMM_FP32 else "f64",
+        "rel_err": {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
+                    "eta": eta, "sinks": int(len(sinks)), "reference": "FP64 direct sum"},
+        "sumF_ratio": {"first": st0["ratio"], "mean": float(np.mean(ratios)), "last": ratios[-1]},
+        "com_drift": float(np.linalg.norm(xc[-1] - st0["xcom"])),
+        "stages_ms": {k: round(v_, 4) for k, v_ in stages.items()},
+        "lists": {"far": info["n_far"], "near_leaf_pairs": info["n_near"], "p2p_pairs": pairs,
+                  "p2p_softened": soft},
+        "roofline": roof,
+    }
+    g.free()
+    return rec
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the multi-GPU sharding of this path is a design (see DESIGN.md), not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2502_01496_amd import fmm as F
+    from paper_2502_01496_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    x_np, m_np, h_np, _ = W.config(args.workload)
+    n = len(m_np)
+    log(f"[bench] workload {args.workload}: n={n}, setup {time.perf_counter() - t0:.1f}s")
+    main_prec = F.FMM_FP32 if args.precision == "fp32" else F.FMM_FP64
+    census = not args.no_census
+    rec = run_one(args, x_np, m_np, h_np, main_prec, census)
+    other = None
+    if not args.single_precision:
+        other = run_one(args, x_np, m_np, h_np,
+                        F.FMM_FP64 if main_prec == F.FMM_FP32 else F.FMM_FP32, census)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": rec["value"],
         "unit": "particle-forces/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == F.FMM_FP32 else "f64",
+        "dtype": rec["dtype"],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={n}, theta={args.theta}, leaf 8, "
-                               f"KDK dt={dt}, walk=leaf<-cell", "n": n, "theta": args.theta,
+                               f"KDK dt={args.dt}, walk=leaf<-cell", "n": n, "theta": args.theta,
                    "precision": args.precision},
-        "rel_err": {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
-                    "eta": eta, "sinks": int(len(sinks)), "reference": "FP64 direct sum"},
-        "sumF_ratio": {"first": st0["ratio"], "mean": float(np.mean(ratios)),
-                       "last": ratios[-1]},
-        "stages_ms": {k: round(v_, 4) for k, v_ in stages.items()},
-        "lists": {"far": info["n_far"], "near_leaf_pairs": info["n_near"],
-                  "p2p_pairs": pairs, "p2p_softened": soft},
-        "roofline": roof,
+        "rel_err": rec["rel_err"],
+        "sumF_ratio": rec["sumF_ratio"],
+        "com_drift": rec["com_drift"],
+        "stages_ms": rec["stages_ms"],
+        "lists": rec["lists"],
+        "roofline": rec["roofline"],
     }
-    g.free()
+    if other is not None:
+        out["fp32" if main_prec == F.FMM_FP64 else "fp64"] = other
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(x_np, m_np, h_np, args.theta)

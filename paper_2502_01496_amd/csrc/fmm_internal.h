@@ -104,7 +104,7 @@ struct Tree {
     double *hs = nullptr;         // h
     double4 *ph = nullptr;        // 1/h, 1/h^3, 4 h^2, 0
     float4 *pf = nullptr;         // FP32 form: offset from the leaf centre of mass, m
-    float2 *pfh = nullptr;        // FP32 form: 1/h, 1/h^3
+    float4 *pfh = nullptr;        // FP32 form: 1/h, 1/h^3, 4 h^2, 0
 
     // nodes
     double *recA = nullptr;       // per node: cx, cy, cz, M, s, hmax, 0, 0

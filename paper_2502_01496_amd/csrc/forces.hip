@@ -168,100 +168,6 @@ __device__ __forceinline__ double m4g_f64(double q, double hinv3, double u3)
     return q < 1.0 ? p1 : (q < 2.0 ? p2 : u3);
 }
 
-// One wavefront per sink leaf: lane = 8 * s + t takes sink s of the leaf and
-// source slot t of each near leaf, so a near leaf of 8 particles is one
-// 8 x 8 tile per wave step.  Larger leaves loop over 8-wide chunks.  When no
-// pair of a tile lies inside either smoothing support (r^2 >= 4 h^2 for both
-// particles) the tile takes the Newtonian branch only.  The 8 partial sums of
-// a sink are reduced with xor-shuffles; the t = 0 lane adds L2P and writes
-// G * a to the caller's slot of the particle.
-// ph[p] = (1/h, 1/h^3, 4 h^2, 0).
-__global__ __launch_bounds__(256) void k_p2p_leaf_f64(
-    const double4 *__restrict__ pm, const double4 *__restrict__ ph,
-    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
-    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
-    const int32_t *__restrict__ near_src, int cap_near, const double *__restrict__ Lloc,
-    const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, int have_far,
-    double *aout)
-{
-    const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (leaf >= nleaves)
-        return;
-    const int lane = lane_id();
-    const int s = lane >> 3, tt = lane & 7;
-    const int v = leaf_node[leaf];
-    const int64_t f = first[v];
-    const int c = count[v];
-    const int nk = max(0, min(near_cnt[leaf], cap_near));
-    const int32_t *nl = near_src + (int64_t)leaf * cap_near;
-    for (int sb = 0; sb < c; sb += 8) {
-        const bool vi = sb + s < c;
-        const int64_t i = f + sb + s;
-        double4 xi = make_double4(0, 0, 0, 0);
-        double4 hi = make_double4(1, 1, 0, 0);
-        if (vi) {
-            xi = pm[i];
-            hi = ph[i];
-        }
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int k = 0; k < nk; ++k) {
-            const int bn = __builtin_amdgcn_readfirstlane(nl[k]);
-            const int64_t fb = first[bn];
-            const int cb = count[bn];
-            for (int tb = 0; tb < cb; tb += 8) {
-                const bool vij = vi && (tb + tt < cb);
-                const int64_t j = fb + tb + tt;
-                double4 xj = make_double4(0, 0, 0, 0);
-                double4 hj = make_double4(1, 1, 0, 0);
-                if (tb + tt < cb) {
-                    xj = pm[j];
-                    hj = ph[j];
-                }
-                const double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const bool soft = vij && r2 < fmax(hi.z, hj.z);
-                double fm;
-                if (__ballot(soft) == 0ull) {
-                    const double u = rsqrt(r2);
-                    fm = vij ? xj.w * (u * u * u) : 0.0;
-                } else {
-                    const double u = r2 > 0.0 ? rsqrt(r2) : 0.0;
-                    const double r = r2 * u;
-                    const double u3 = u * u * u;
-                    const double gi = m4g_f64(r * hi.x, hi.y, u3);
-                    const double gj = m4g_f64(r * hj.x, hj.y, u3);
-                    fm = vij ? xj.w * 0.5 * (gi + gj) : 0.0;
-                }
-                ax -= fm * dx;
-                ay -= fm * dy;
-                az -= fm * dz;
-            }
-        }
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-            ax += __shfl_xor(ax, off);
-            ay += __shfl_xor(ay, off);
-            az += __shfl_xor(az, off);
-        }
-        if (vi && tt == 0) {
-            double fx = 0.0, fy = 0.0, fz = 0.0;
-            if (have_far) {
-                const double *rv = recA + (int64_t)NREC * v;
-                const double *L = Lloc + (int64_t)NLOC * v;
-                double Lr[19];
-#pragma unroll
-                for (int k = 0; k < 19; ++k)
-                    Lr[k] = L[k];
-                l2p<double>(Lr, xi.x - rv[0], xi.y - rv[1], xi.z - rv[2], fx, fy, fz);
-            }
-            const int64_t o = 3 * (int64_t)perm[i];
-            aout[o] = G * (fx + ax);
-            aout[o + 1] = G * (fy + ay);
-            aout[o + 2] = G * (fz + az);
-        }
-    }
-}
-
 // 1/sqrt(x) for finite x > 0: hardware estimate plus one second-order
 // correction, y' = y + y e (1/2 + 3/8 e) with e = 1 - x y^2.
 __device__ __forceinline__ double rsqrt_pos(double x)
@@ -269,105 +175,6 @@ __device__ __forceinline__ double rsqrt_pos(double x)
     const double y = __builtin_amdgcn_rsq(x);
     const double e = fma(-x * y, y, 1.0);
     return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-
-// Near field for leaves of at most 8 particles.  One wavefront per sink leaf,
-// lane = 8 s + t: sink s, source slot t.  Each step takes four near leaves, so
-// every lane evaluates four independent pairs; loads are clamped in-bounds
-// and invalid pairs are zeroed by a select.  Steps whose 256 pairs all lie
-// outside both smoothing supports (r^2 >= 4 h^2 for both particles) take the
-// Newtonian branch only.
-template <int U>
-__global__ __launch_bounds__(256) void k_p2p_leaf8_f64(
-    const double4 *__restrict__ pm, const double4 *__restrict__ ph,
-    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
-    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
-    const int32_t *__restrict__ near_src, int cap_near, const double *__restrict__ Lloc,
-    const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double *aout)
-{
-    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (leaf >= nleaves)
-        return;
-    const int lane = lane_id();
-    const int s = lane >> 3, tt = lane & 7;
-    const int v = leaf_node[leaf];
-    const int64_t f = first[v];
-    const int c = count[v];
-    const bool vi = s < c;
-    const int64_t i = f + (vi ? s : 0);
-    const double4 xi = pm[i];
-    const double4 hi = ph[i];
-    const int nk = max(0, min(near_cnt[leaf], cap_near));
-    const int32_t *nl = near_src + (int64_t)leaf * cap_near;
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int k = 0; k < nk; k += U) {
-        double4 xj[U], hj[U];
-        bool vj[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const int kk = k + q;
-            const int bn = kk < nk ? nl[kk] : -1;
-            const int64_t fb = bn >= 0 ? first[bn] : 0;
-            const int cb = bn >= 0 ? count[bn] : 0;
-            vj[q] = vi && tt < cb;
-            const int64_t j = fb + (tt < cb ? tt : 0);
-            xj[q] = pm[j];
-            hj[q] = ph[j];
-        }
-        double dx[U], dy[U], dz[U], r2[U];
-        bool soft = false;
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            dx[q] = xi.x - xj[q].x;
-            dy[q] = xi.y - xj[q].y;
-            dz[q] = xi.z - xj[q].z;
-            r2[q] = dx[q] * dx[q] + dy[q] * dy[q] + dz[q] * dz[q];
-            soft |= vj[q] && (r2[q] < hi.z || r2[q] < hj[q].z);
-        }
-        if (__ballot(soft) == 0ull) {
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const double u = rsqrt_pos(r2[q]);
-                const double fm = vj[q] ? xj[q].w * (u * u * u) : 0.0;
-                ax -= fm * dx[q];
-                ay -= fm * dy[q];
-                az -= fm * dz[q];
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const double u = r2[q] > 0.0 ? rsqrt_pos(r2[q]) : 0.0;
-                const double r = r2[q] * u;
-                const double u3 = u * u * u;
-                const double gi = m4g_f64(r * hi.x, hi.y, u3);
-                const double gj = m4g_f64(r * hj[q].x, hj[q].y, u3);
-                const double fm = vj[q] ? xj[q].w * 0.5 * (gi + gj) : 0.0;
-                ax -= fm * dx[q];
-                ay -= fm * dy[q];
-                az -= fm * dz[q];
-            }
-        }
-    }
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-        ax += __shfl_xor(ax, off);
-        ay += __shfl_xor(ay, off);
-        az += __shfl_xor(az, off);
-    }
-    if (vi && tt == 0) {
-        const double *rv = recA + (int64_t)NREC * v;
-        const double *L = Lloc + (int64_t)NLOC * v;
-        double Lr[19];
-#pragma unroll
-        for (int k = 0; k < 19; ++k)
-            Lr[k] = L[k];
-        double fx, fy, fz;
-        l2p<double>(Lr, xi.x - rv[0], xi.y - rv[1], xi.z - rv[2], fx, fy, fz);
-        const int64_t o = 3 * (int64_t)perm[i];
-        aout[o] = G * (fx + ax);
-        aout[o + 1] = G * (fy + ay);
-        aout[o + 2] = G * (fz + az);
-    }
 }
 
 // Reduce-scatter of 12 per-lane doubles over the 64 lanes of a wavefront.
@@ -406,17 +213,18 @@ __device__ __forceinline__ double reduce_scatter12(const double *v, int lane, in
     return d;
 }
 
-// Near field for leaves of at most 8 particles, source-per-lane form.  One
-// wavefront per sink leaf; a step takes 8 near leaves, lane = 8 g + t holds
-// source t of the g-th of them (loaded once: no redundant traffic), and the
-// sink particles, 4 per pass, are wave-uniform.  The (first, count) ranges of
-// the near leaves are staged in LDS once per leaf, and the sources of the
-// next step are loaded while the current step computes.  Missing sources are
-// placed far away with zero mass, so they add exactly zero.  For each sink, a
-// step whose 64 pairs all lie outside both smoothing supports takes the
-// Newtonian branch only.  The per-lane sums are reduce-scattered so that the
-// lane holding component c of sink s adds L2P and writes G * a.
-constexpr int P2P_RANGES = 512;  // near-leaf ranges staged in LDS per wavefront
+// Near field, source-per-lane form.  One wavefront per sink leaf; a step
+// takes 8 source blocks (a near leaf contributes ceil(leaf_size / 8) blocks of
+// at most 8 particles), lane = 8 g + t holds particle t of the g-th block
+// (loaded once: no redundant traffic), and the sink particles, 4 per pass, are
+// wave-uniform.  The block ranges are staged in LDS once per chunk of the near
+// list, and the sources of the next step are loaded while the current step
+// computes.  Missing sources are placed far away with zero mass, so they add
+// exactly zero.  For each sink, a step whose 64 pairs all lie outside both
+// smoothing supports takes the Newtonian branch only.  The per-lane sums are
+// reduce-scattered so that the lane holding component c of sink s adds L2P
+// and writes G * a.
+constexpr int P2P_RANGES = 512;  // source blocks staged in LDS per wavefront
 
 __device__ __forceinline__ void load_src(const double4 *__restrict__ pm,
                                          const double4 *__restrict__ ph, int2 rg, int slot,
@@ -432,11 +240,11 @@ __device__ __forceinline__ void load_src(const double4 *__restrict__ pm,
     }
 }
 
-__global__ __launch_bounds__(256) void k_p2p_src_f64(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_p2p_src_f64(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const int32_t *__restrict__ first, const int32_t *__restrict__ count,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
-    const int32_t *__restrict__ near_src, int cap_near, const double *__restrict__ Lloc,
+    const int32_t *__restrict__ near_src, int cap_near, int nsub, const double *__restrict__ Lloc,
     const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double *aout)
 {
     constexpr int NS = 4;
@@ -450,7 +258,7 @@ __global__ __launch_bounds__(256) void k_p2p_src_f64(
     const int v = leaf_node[leaf];
     const int64_t f = first[v];
     const int c = count[v];
-    const int nk = max(0, min(near_cnt[leaf], cap_near));
+    const int nb = max(0, min(near_cnt[leaf], cap_near)) * nsub;
     const int32_t *nl = near_src + (int64_t)leaf * cap_near;
     const double *rv = recA + (int64_t)NREC * v;
     const double *Lv = Lloc + (int64_t)NLOC * v;
@@ -473,14 +281,15 @@ __global__ __launch_bounds__(256) void k_p2p_src_f64(
 #pragma unroll
         for (int q = 0; q < 3 * NS; ++q)
             acc[q] = 0.0;
-        for (int c0 = 0; c0 < nk; c0 += P2P_RANGES) {
-            const int nc = min(nk - c0, P2P_RANGES);
-            // stage the ranges of this chunk of the near list (padded to 8)
+        for (int c0 = 0; c0 < nb; c0 += P2P_RANGES) {
+            const int nc = min(nb - c0, P2P_RANGES);
+            // stage the source blocks of this chunk (padded to a multiple of 8)
             for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
                 int2 r = make_int2(0, 0);
                 if (k < nc) {
-                    const int bn = nl[c0 + k];
-                    r = make_int2(first[bn], count[bn]);
+                    const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
+                    const int bn = nl[e];
+                    r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
                 }
                 R[k] = r;
             }
@@ -543,37 +352,252 @@ __global__ __launch_bounds__(256) void k_p2p_src_f64(
     }
 }
 
+// ---------------------------------------------------------------- FP32 form
+// M2L in FP32: r = c_sink - c_source is formed in FP64 and rounded, M and Q
+// come from the FP32 mirror of the cell records, and the 19 coefficients are
+// accumulated in FP32.
+__global__ __launch_bounds__(256) void k_m2l_leaf_f32(
+    const double *__restrict__ recA, const float *__restrict__ recF,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
+    const int32_t *__restrict__ far_src, int cap_far, float *Lout)
+{
+    const int g = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    const bool valid = g < nleaves;
+    const int v = valid ? leaf_node[g] : 0;
+    const double *rv = recA + (int64_t)NREC * v;
+    const double c0 = rv[0], c1 = rv[1], c2 = rv[2];
+    float L[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        L[k] = 0.0f;
+    const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
+    const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
+    for (int k = sub; k < nk; k += 16) {
+        const int b = fl[k];
+        const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
+        const float4 f0 = *(const float4 *)(recF + (int64_t)NREC * b);
+        const float4 f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
+        const float Q[6] = {f0.y, f0.z, f0.w, f1.x, f1.y, f1.z};
+        m2l_acc<float>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            L[k] += __shfl_xor(L[k], off);
+    if (valid && sub == 0) {
+        float *o = Lout + (int64_t)NLOC * v;
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            o[k] = L[k];
+        o[19] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ float m4g_f32(float q, float hinv3, float u3)
+{
+    const float p1 = hinv3 * (4.0f / 3.0f + q * q * (-1.2f + 0.5f * q));
+    const float p2 = hinv3 * (8.0f / 3.0f + q * (-3.0f + q * (1.2f - q * (1.0f / 6.0f)))) -
+                     u3 * (1.0f / 15.0f);
+    return q < 1.0f ? p1 : (q < 2.0f ? p2 : u3);
+}
+
+__device__ __forceinline__ float xchg_keep_f(float keep, float send, int off)
+{
+    return keep + __shfl_xor(send, off);
+}
+
+// Reduce-scatter of 24 per-lane floats over the wavefront (same scheme as
+// the 12-value FP64 version, one more halving).  Value index held by lane l:
+//   12 b5 + 6 b4 + 3 b3 + (2 b2 + b1), valid when (2 b2 + b1) < 3.
+__device__ __forceinline__ float reduce_scatter24(const float *v, int lane, int &idx)
+{
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    float a[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        a[k] = xchg_keep_f(b5 ? v[12 + k] : v[k], b5 ? v[k] : v[12 + k], 32);
+    float b[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        b[k] = xchg_keep_f(b4 ? a[6 + k] : a[k], b4 ? a[k] : a[6 + k], 16);
+    float cc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        cc[k] = xchg_keep_f(b3 ? b[3 + k] : b[k], b3 ? b[k] : b[3 + k], 8);
+    const float d0 = xchg_keep_f(b2 ? cc[2] : cc[0], b2 ? cc[0] : cc[2], 4);
+    const float d1 = xchg_keep_f(b2 ? 0.0f : cc[1], b2 ? cc[1] : 0.0f, 4);
+    float e = xchg_keep_f(b1 ? d1 : d0, b1 ? d0 : d1, 2);
+    e += __shfl_xor(e, 1);
+    const int sub = 2 * (int)b2 + (int)b1;
+    idx = sub < 3 ? 12 * (int)b5 + 6 * (int)b4 + 3 * (int)b3 + sub : -1;
+    return e;
+}
+
+// FP32 near field with leaf-relative offsets: for a sink in leaf a and a
+// source in leaf b, x_i - x_j = (c_a - c_b) + (y_i - y_j) with c_a - c_b formed
+// in FP64 and rounded once per leaf pair, and y = x - c_leaf stored in FP32.
+// Eight sinks per pass (wave-uniform), FP32 accumulation.  pf[p] = (y, m),
+// pfh[p] = (1/h, 1/h^3, 4 h^2, 0), all rounded from FP64.
+__device__ __forceinline__ float rsq_pos_f(float x) { return __builtin_amdgcn_rsqf(x); }
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_p2p_src_f32(
+    const float4 *__restrict__ pf, const float4 *__restrict__ pfh,
+    const int32_t *__restrict__ first,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
+    const int32_t *__restrict__ near_cnt, const int32_t *__restrict__ near_src, int cap_near,
+    int nsub, const float *__restrict__ Lloc, const double *__restrict__ recA,
+    const int32_t *__restrict__ perm, float G, float *aout)
+{
+    constexpr int NS = 8;
+    constexpr int NR = P2P_RANGES / 2;
+    __shared__ int2 rng[4][NR];
+    __shared__ float4 dcs[4][NR];
+    const int w = threadIdx.x >> 6;
+    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    if (leaf >= nleaves)
+        return;
+    const int lane = lane_id();
+    const int grp = lane >> 3, slot = lane & 7;
+    const int v = leaf_node[leaf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const int nb = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int32_t *nl = near_src + (int64_t)leaf * cap_near;
+    const double *rv = recA + (int64_t)NREC * v;
+    const double ca0 = rv[0], ca1 = rv[1], ca2 = rv[2];
+    const float *Lv = Lloc + (int64_t)NLOC * v;
+    int2 *R = rng[w];
+    float4 *D = dcs[w];
+    for (int sb = 0; sb < c; sb += NS) {
+        float sx[NS], sy[NS], sz[NS], shi[NS], sh3[NS], sh4[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int64_t is = f + min(sb + q, c - 1);
+            const float4 y4 = pf[is];
+            const float4 h4 = pfh[is];
+            sx[q] = y4.x;
+            sy[q] = y4.y;
+            sz[q] = y4.z;
+            shi[q] = h4.x;
+            sh3[q] = h4.y;
+            sh4[q] = h4.z;
+        }
+        float acc[3 * NS];
+#pragma unroll
+        for (int q = 0; q < 3 * NS; ++q)
+            acc[q] = 0.0f;
+        for (int c0 = 0; c0 < nb; c0 += NR) {
+            const int nc = min(nb - c0, NR);
+            // stage the source blocks of this chunk (padded to a multiple of 8):
+            // their particle range and the leaf-centre difference c_a - c_b,
+            // formed in FP64 and rounded to FP32
+            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
+                int2 r = make_int2(0, 0);
+                float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k < nc) {
+                    const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
+                    const int bn = nl[e];
+                    r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
+                    const double *rb = recA + (int64_t)NREC * bn;
+                    d = make_float4((float)(ca0 - rb[0]), (float)(ca1 - rb[1]),
+                                    (float)(ca2 - rb[2]), 0.f);
+                }
+                R[k] = r;
+                D[k] = d;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int kb = 0; kb < nc; kb += 8) {
+                const int2 rg = R[kb + grp];
+                const float4 dc = D[kb + grp];
+                const bool valid = slot < rg.y;
+                const int64_t j = (int64_t)rg.x + (valid ? slot : 0);
+                float4 yj = pf[j];
+                float4 hj = pfh[j];
+                if (!valid) {
+                    yj = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+                    hj.z = 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const float dx = dc.x + (sx[q] - yj.x), dy = dc.y + (sy[q] - yj.y),
+                                dz = dc.z + (sz[q] - yj.z);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const bool soft = r2 < sh4[q] || r2 < hj.z;
+                    float fm;
+                    if (__ballot(soft) == 0ull) {
+                        const float u = rsq_pos_f(r2);
+                        fm = yj.w * (u * u * u);
+                    } else {
+                        const float u = r2 > 0.0f ? rsq_pos_f(r2) : 0.0f;
+                        const float r = r2 * u;
+                        const float u3 = u * u * u;
+                        const float gi = m4g_f32(r * shi[q], sh3[q], u3);
+                        const float gj = m4g_f32(r * hj.x, hj.y, u3);
+                        fm = yj.w * 0.5f * (gi + gj);
+                    }
+                    acc[3 * q] -= fm * dx;
+                    acc[3 * q + 1] -= fm * dy;
+                    acc[3 * q + 2] -= fm * dz;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        int idx;
+        const float tot = reduce_scatter24(acc, lane, idx);
+        const int q = idx / 3, comp = idx - 3 * (idx / 3);
+        if (idx >= 0 && (lane & 1) == 0 && sb + q < c) {
+            float sxq = sx[0], syq = sy[0], szq = sz[0];
+#pragma unroll
+            for (int r = 1; r < NS; ++r)
+                if (q == r) {
+                    sxq = sx[r];
+                    syq = sy[r];
+                    szq = sz[r];
+                }
+            float Lr[19];
+#pragma unroll
+            for (int k = 0; k < 19; ++k)
+                Lr[k] = Lv[k];
+            float fx, fy, fz;
+            l2p<float>(Lr, sxq, syq, szq, fx, fy, fz);
+            const float far_c = comp == 0 ? fx : (comp == 1 ? fy : fz);
+            const int64_t o = 3 * (int64_t)perm[f + sb + q] + comp;
+            aout[o] = G * (far_c + tot);
+        }
+    }
+}
+
 hipError_t launch_far(Tree &t, hipStream_t s)
 {
     const Topology &T = t.topo;
-    int nl = T.nleaves;
-    if (t.p.precision == FMM_FP64) {
+    const int nl = T.nleaves;
+    if (t.p.precision == FMM_FP64)
         k_m2l_leaf_f64<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
                                                              t.far_cnt, t.far_src, (int)t.cap_far,
                                                              t.L);
-    } else {
-        return hipErrorNotSupported;
-    }
+    else
+        k_m2l_leaf_f32<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recF, t.leaf_node, nl,
+                                                             t.far_cnt, t.far_src, (int)t.cap_far,
+                                                             t.Lf);
     return hipGetLastError();
 }
 
 hipError_t launch_near(Tree &t, void *a, hipStream_t s)
 {
     const Topology &T = t.topo;
-    int nl = T.nleaves;
-    if (t.p.precision == FMM_FP64) {
-        if (t.p.leaf_size <= 8)
-            k_p2p_src_f64<<<(nl + 3) / 4, 256, 0, s>>>(
-                t.pm, t.ph, t.first, t.count, t.leaf_node, nl, t.near_cnt, t.near_src,
-                (int)t.cap_near, t.L, t.recA, t.perm, t.p.G, (double *)a);
-        else
-            k_p2p_leaf_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count,
-                                                        t.leaf_node, nl, t.near_cnt, t.near_src,
-                                                        (int)t.cap_near, t.L, t.recA, t.perm,
-                                                        t.p.G, 1, (double *)a);
-    } else {
-        return hipErrorNotSupported;
-    }
+    const int nl = T.nleaves;
+    const int nsub = (T.leaf_size + 7) / 8;
+    if (t.p.precision == FMM_FP64)
+        k_p2p_src_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node, nl,
+                                                   t.near_cnt, t.near_src, (int)t.cap_near, nsub,
+                                                   t.L, t.recA, t.perm, t.p.G, (double *)a);
+    else
+        k_p2p_src_f32<<<(nl + 3) / 4, 256, 0, s>>>(t.pf, t.pfh, t.first, t.count,
+                                                   t.leaf_node, nl, t.near_cnt, t.near_src,
+                                                   (int)t.cap_near, nsub, t.Lf, t.recA, t.perm,
+                                                   (float)t.p.G, (float *)a);
     return hipGetLastError();
 }
 

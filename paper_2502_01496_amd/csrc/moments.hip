@@ -23,7 +23,7 @@ namespace fmm {
 __global__ void k_gather(const double *__restrict__ x, const double *__restrict__ m,
                          const double *__restrict__ h, int64_t n, const int32_t *__restrict__ perm,
                          double4 *pm, double *hs, double4 *ph, uint32_t *err, int nnodes,
-                         uint64_t *s2bits, int32_t *upcnt, int want_fp32, float2 *pfh)
+                         uint64_t *s2bits, int32_t *upcnt, int want_fp32, float4 *pfh)
 {
     int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -42,7 +42,7 @@ __global__ void k_gather(const double *__restrict__ x, const double *__restrict_
         double hi = 1.0 / hh;
         ph[p] = make_double4(hi, hi * hi * hi, 4.0 * hh * hh, 0.0);
         if (want_fp32)
-            pfh[p] = make_float2((float)hi, (float)(hi * hi * hi));
+            pfh[p] = make_float4((float)hi, (float)(hi * hi * hi), (float)(4.0 * hh * hh), 0.0f);
     }
     for (int64_t v = gid; v < nnodes; v += stride) {
         s2bits[v] = 0ull;
