@@ -150,6 +150,7 @@ static hipError_t upload(Tree &t, P **out, const std::vector<P> &v)
 static void release(Tree *t)
 {
     (void)hipDeviceSynchronize();
+    release_vjp(*t);
     for (auto &b : t->owned)
         (void)hipFree(b.p);
     t->owned.clear();
@@ -510,6 +511,7 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
                 HIP_TRY(launch_near(t, a, s));
             }
             t.has_lists = true;
+            t.has_transposed = false;
             t.lists_policy = t.p.walk;
             t.nsinks = t.topo.nleaves;
             t.n_far = t.n_near = -1;  // totals computed on demand
@@ -537,6 +539,8 @@ fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *
     Tree &t = *reinterpret_cast<Tree *>(tree);
     if (!t.has_forces)
         return fail(FMM_ERR_STATE, "fmm_forces must run on this tree state before the VJP");
+    if (!t.has_lists)
+        return fail(FMM_ERR_STATE, "no interaction lists: call fmm_forces first");
     hipStream_t s = (hipStream_t)stream;
     StageTimer tm(t, s, 5);
     hipError_t e = launch_vjp(t, a_bar, x_bar, m_bar, s);

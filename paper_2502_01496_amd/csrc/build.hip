@@ -299,23 +299,34 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     }
 }
 
-// Sort B arrays; the result ends in (k0, v0) after an even number of passes.
-static hipError_t radix_sort(Tree &t, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
-                             int64_t n, int B, hipStream_t s)
+// Sort B arrays of n (key, value) pairs by the low 8 * passes key bits.  The
+// result ends in (k0, v0) after an even number of passes, in (k1, v1) after
+// an odd one.  hist needs B * 256 * ceil(n / RS_TILE) words, tot
+// passes * B * 256.
+hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
 {
     int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
-    k_rs_zero<<<64, 256, 0, s>>>(t.rs_tot, (int64_t)RS_PASSES * B * 256);
-    for (int pass = 0; pass < RS_PASSES; ++pass) {
+    if (nblk == 0)
+        return hipSuccess;
+    k_rs_zero<<<64, 256, 0, s>>>(tot, (int64_t)passes * B * 256);
+    for (int pass = 0; pass < passes; ++pass) {
         int shift = 8 * pass;
         uint64_t *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
         uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
-        uint32_t *tot = t.rs_tot + (int64_t)pass * B * 256;
+        uint32_t *tp = tot + (int64_t)pass * B * 256;
         dim3 g(nblk, B);
-        k_rs_hist<<<g, RS_THREADS, 0, s>>>(ki, n, shift, t.rs_hist, tot, nblk);
-        k_rs_scan<<<dim3(256, B), RS_THREADS, 0, s>>>(t.rs_hist, tot, nblk);
-        k_rs_scatter<<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, t.rs_hist, nblk);
+        k_rs_hist<<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
+        k_rs_scan<<<dim3(256, B), RS_THREADS, 0, s>>>(hist, tp, nblk);
+        k_rs_scatter<<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
     }
     return hipGetLastError();
+}
+
+static hipError_t radix_sort(Tree &t, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                             int64_t n, int B, hipStream_t s)
+{
+    return radix_sort_u64(k0, v0, k1, v1, n, B, RS_PASSES, t.rs_hist, t.rs_tot, s);
 }
 
 // ---------------------------------------------------------------- level kernels

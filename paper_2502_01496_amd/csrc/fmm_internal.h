@@ -102,7 +102,7 @@ struct Tree {
     // particles in tree order
     double4 *pm = nullptr;        // x, y, z, m
     double *hs = nullptr;         // h
-    double4 *ph = nullptr;        // 1/h, 1/h^3, 4 h^2, 0
+    double4 *ph = nullptr;        // 1/h, 1/h^3, 4 h^2, h
     float4 *pf = nullptr;         // FP32 form: offset from the leaf centre of mass, m
     float4 *pfh = nullptr;        // FP32 form: 1/h, 1/h^3, 4 h^2, 0
 
@@ -134,6 +134,26 @@ struct Tree {
     double *red = nullptr;
     double *h_red = nullptr;
 
+    // VJP workspace (allocated on first use, grown on demand)
+    struct Transposed {
+        int64_t *off = nullptr;   // nnodes + 1, CSR over target node ids
+        uint32_t *src = nullptr;  // sink node ids, ascending per target
+        int64_t npairs = 0;
+    } farT, nearT;
+    bool has_transposed = false;
+    std::vector<DevBuf> vjp_owned;
+    int64_t vjp_pair_cap = 0;
+    uint64_t *vk0 = nullptr, *vk1 = nullptr;
+    uint32_t *vv0 = nullptr, *vv1 = nullptr, *vhist = nullptr, *vtot = nullptr;
+    int64_t *pair_off = nullptr;   // nleaves + 1 offsets of the compacted pairs
+    int64_t *vscan = nullptr;
+    double *abt = nullptr;         // G * abar, tree order, 3 per particle
+    double *xbt = nullptr;         // xbar accumulator, tree order, 3 per particle
+    double *mbt = nullptr;         // mbar accumulator, tree order
+    double *Lbar = nullptr;        // NLOC per node
+    double *nadj = nullptr;        // 16 per node: cbar_sink[3], cbar_src[3], Mbar, Qbar[6]
+    int64_t *h_pairs = nullptr;    // pinned: far, near pair totals
+
     bool has_tree = false, has_moments = false, has_lists = false, has_forces = false;
     int lists_policy = -1;
 
@@ -145,6 +165,9 @@ struct Tree {
     int64_t acc_n[8] = {};
 };
 
+hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s);
+
 // launchers (return hipError_t of the last launch / runtime call)
 hipError_t launch_build(Tree &t, const double *x, hipStream_t s);
 hipError_t launch_moments(Tree &t, const double *x, const double *m, const double *h,
@@ -155,7 +178,9 @@ hipError_t launch_far(Tree &t, hipStream_t s);
 hipError_t launch_near(Tree &t, void *a, hipStream_t s);
 hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,
                         int a_fp32, int64_t n, double *red, double *h_out, hipStream_t s);
+hipError_t launch_far_f64(Tree &t, hipStream_t s);
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s);
+void release_vjp(Tree &t);
 hipError_t launch_kick_drift(double *x, double *v, const void *a, int a_fp32, int64_t n,
                              double kick, double drift, hipStream_t s);
 

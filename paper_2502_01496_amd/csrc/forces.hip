@@ -584,6 +584,14 @@ hipError_t launch_far(Tree &t, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_far_f64(Tree &t, hipStream_t s)
+{
+    const int nl = t.topo.nleaves;
+    k_m2l_leaf_f64<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
+                                                         t.far_cnt, t.far_src, (int)t.cap_far, t.L);
+    return hipGetLastError();
+}
+
 hipError_t launch_near(Tree &t, void *a, hipStream_t s)
 {
     const Topology &T = t.topo;

@@ -2,7 +2,7 @@
 // s, h_max; quadrupole eq. (7)).
 //
 //   k_gather     caller-order x, m, h -> tree-order (x, y, z, m), h and
-//                (1/h, 1/h^3, 4 h^2); flags bad inputs; clears the s^2 maxima.
+//                (1/h, 1/h^3, 4 h^2, h); flags bad inputs; clears the s^2 maxima.
 //   k_leaf_moments  one thread per leaf: M, sum(m x) left to right, c = S / M,
 //                h_max and the quadrupole about c.
 //   k_combine_level one launch per tree level, deepest first: parents from
@@ -40,7 +40,7 @@ __global__ void k_gather(const double *__restrict__ x, const double *__restrict_
         pm[p] = make_double4(xx, yy, zz, mm);
         hs[p] = hh;
         double hi = 1.0 / hh;
-        ph[p] = make_double4(hi, hi * hi * hi, 4.0 * hh * hh, 0.0);
+        ph[p] = make_double4(hi, hi * hi * hi, 4.0 * hh * hh, hh);
         if (want_fp32)
             pfh[p] = make_float4((float)hi, (float)(hi * hi * hi), (float)(4.0 * hh * hh), 0.0f);
     }

@@ -1,11 +1,984 @@
-// Vector-Jacobian product of the accelerations (tree and lists held fixed).
+// Vector-Jacobian product of the FMM accelerations on gfx950, with the tree
+// membership and the interaction lists held fixed (the cell moments do
+// depend on x and m).
+//
+// With abar' = G abar, the accelerations are
+//   a_i = L2P(L_a, x_i - c_a) - sum_{b in near(a)} sum_{j in b} m_j G_ij (x_i - x_j),
+//   L_a = sum_{b in far(a)} K(c_a - c_b; M_b, Q_b)                (eqs. (6)-(8))
+// and the reverse pass is:
+//   1. L2P^T per leaf: Lbar_a = sum_i d<abar'_i, L2P>/dL, xbar_i += (L2 + L3 y_i)^T abar'_i,
+//      cbar_a -= the same sum over the leaf;
+//   2. M2L^T, sink side per leaf over its far list (cbar_a += rbar) and source
+//      side per cell over the transposed far list (Mbar_b, Qbar_b, cbar_b -= rbar);
+//      the adjoint of one M2L term is the reverse-mode derivative of the
+//      forward factorisation (a0, a1, a2, b2, b3, b4, q) and needs g_1..g_6;
+//   3. P2P^T: per pair dbar = -m_j [G_ij abar'_i + (G'_ij / r)(d . abar'_i) d],
+//      xbar_i += dbar (sink side, near lists), xbar_j -= dbar and
+//      mbar_j -= G_ij (d . abar'_i) (source side, transposed near lists);
+//   4. moments: for every cell n holding particle j, with y = x_j - c_n,
+//      xbar_j += m_j / M_n cbar_n + m_j (6 Qf y - 2 tr(Qf) y),
+//      mbar_j += Mbar_n + cbar_n . y / M_n + 3 y^T Qf y - |y|^2 tr(Qf),
+//      (Qf: the symmetric matrix whose stored entries give Qbar; the dependence
+//      of Q on c cancels because sum m y = 0), evaluated by one thread per
+//      particle walking root -> leaf.
+// Every accumulator has exactly one owning thread (no floating-point
+// atomics), so the result is bitwise reproducible.  The arithmetic is FP64.
 #include "fmm_internal.h"
 
 namespace fmm {
 
-hipError_t launch_vjp(Tree &, const void *, void *, void *, hipStream_t)
+__device__ __forceinline__ constexpr int sym2(int i, int j)
 {
-    return hipErrorNotSupported;
+    return i > j ? sym2(j, i) : (i == 0 ? j : (i == 1 ? 2 + j : 5));
+}
+
+__device__ __forceinline__ constexpr int sym3(int i, int j, int k)
+{
+    // sort (i, j, k) then index xxx,xxy,xxz,xyy,xyz,xzz,yyy,yyz,yzz,zzz
+    return (i > j) ? sym3(j, i, k)
+                   : (j > k) ? sym3(i, k, j)
+                             : (i == 0 ? (j == 0 ? k : (j == 1 ? 2 + k : 5))
+                                       : (i == 1 ? (j == 1 ? 5 + k : 8) : 9));
+}
+
+__device__ __forceinline__ constexpr double mult3(int i, int j, int k)
+{
+    return (i == j && j == k) ? 1.0 : ((i == j || j == k || i == k) ? 3.0 : 6.0);
+}
+
+// ---------------------------------------------------------------- M2L adjoint
+// Given the stored cotangent Lb[19] of one M2L term K(r; M, Q), accumulate
+// d<Lb, K>/dr into rb, d/dM into Mb and d/dQ (stored entries) into Qb.
+__device__ __forceinline__ void m2l_vjp(const double r[3], double M, const double *Qs,
+                                        const double *Lb, double rb[3], double &Mb, double Qb[6])
+{
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double u = rsqrt(r2);
+    const double u2 = u * u;
+    const double g1 = -u * u2, g2 = -3.0 * g1 * u2, g3 = -5.0 * g2 * u2, g4 = -7.0 * g3 * u2,
+                 g5 = -9.0 * g4 * u2, g6 = -11.0 * g5 * u2;
+    double Qf[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Qf[i][j] = Qs[sym2(i, j)];
+    double q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        q[i] = Qf[i][0] * r[0] + Qf[i][1] * r[1] + Qf[i][2] * r[2];
+    const double qq = q[0] * r[0] + q[1] * r[1] + q[2] * r[2];
+    const double a0 = M * g1 + g3 * qq / 6.0, a1 = M * g2 + g4 * qq / 6.0,
+                 a2 = M * g3 + g5 * qq / 6.0;
+    const double b2 = g2 / 3.0, b3 = g3 / 3.0, b4 = g4 / 3.0;
+    // full symmetric cotangent tensors
+    const double A[3] = {Lb[0], Lb[1], Lb[2]};
+    double B[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            B[i][j] = Lb[3 + sym2(i, j)] * (i == j ? 1.0 : 0.5);
+    double T[3][3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                T[i][j][k] = Lb[9 + sym3(i, j, k)] / mult3(i, j, k);
+    // contractions
+    double Br[3], Bq[3], tr1[3], Trr[3], Trq[3], TQ[3], Tr[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        Br[m] = B[m][0] * r[0] + B[m][1] * r[1] + B[m][2] * r[2];
+        Bq[m] = B[m][0] * q[0] + B[m][1] * q[1] + B[m][2] * q[2];
+        tr1[m] = T[0][0][m] + T[1][1][m] + T[2][2][m];
+        double s_rr = 0.0, s_rq = 0.0, s_Q = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                s_rr += T[i][j][m] * r[i] * r[j];
+                s_rq += T[i][j][m] * r[i] * q[j];
+                s_Q += T[m][i][j] * Qf[i][j];
+            }
+        Trr[m] = s_rr;
+        Trq[m] = s_rq;
+        TQ[m] = s_Q;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Tr[m][k] = T[0][m][k] * r[0] + T[1][m][k] * r[1] + T[2][m][k] * r[2];
+    }
+    const double Ar = A[0] * r[0] + A[1] * r[1] + A[2] * r[2];
+    const double Aq = A[0] * q[0] + A[1] * q[1] + A[2] * q[2];
+    const double trB = B[0][0] + B[1][1] + B[2][2];
+    const double Brr = Br[0] * r[0] + Br[1] * r[1] + Br[2] * r[2];
+    const double Brq = Bq[0] * r[0] + Bq[1] * r[1] + Bq[2] * r[2];
+    double BQ = 0.0, TrQ = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            BQ += B[i][j] * Qf[i][j];
+            TrQ += Tr[i][j] * Qf[i][j];
+        }
+    const double tr1r = tr1[0] * r[0] + tr1[1] * r[1] + tr1[2] * r[2];
+    const double tr1q = tr1[0] * q[0] + tr1[1] * q[1] + tr1[2] * q[2];
+    const double Trrr = Trr[0] * r[0] + Trr[1] * r[1] + Trr[2] * r[2];
+    const double Trrq = Trr[0] * q[0] + Trr[1] * q[1] + Trr[2] * q[2];
+    // cotangents of the scalar coefficients
+    const double a0b = Ar + trB;
+    const double a1b = Brr + 3.0 * tr1r;
+    const double a2b = Trrr;
+    const double b2b = Aq + BQ;
+    const double b3b = 2.0 * Brq + 3.0 * tr1q + 3.0 * TrQ;
+    const double b4b = 3.0 * Trrq;
+    // explicit dependence on r, q, Q
+    double rbl[3], qb[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        rbl[m] = a0 * A[m] + 2.0 * a1 * Br[m] + 2.0 * b3 * Bq[m] + 3.0 * a2 * Trr[m] +
+                 3.0 * a1 * tr1[m] + 6.0 * b4 * Trq[m] + 3.0 * b3 * TQ[m];
+        qb[m] = b2 * A[m] + 2.0 * b3 * Br[m] + 3.0 * b4 * Trr[m] + 3.0 * b3 * tr1[m];
+    }
+    // through the coefficients
+    Mb += a0b * g1 + a1b * g2 + a2b * g3;
+    const double qqb = (a0b * g3 + a1b * g4 + a2b * g5) / 6.0;
+    const double gb1 = a0b * M;
+    const double gb2 = a1b * M + b2b / 3.0;
+    const double gb3 = a2b * M + a0b * qq / 6.0 + b3b / 3.0;
+    const double gb4 = a1b * qq / 6.0 + b4b / 3.0;
+    const double gb5 = a2b * qq / 6.0;
+    const double sg = gb1 * g2 + gb2 * g3 + gb3 * g4 + gb4 * g5 + gb5 * g6;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        qb[m] += qqb * r[m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        rb[m] += rbl[m] + qqb * q[m] + (qb[0] * Qf[0][m] + qb[1] * Qf[1][m] + qb[2] * Qf[2][m]) +
+                 sg * r[m];
+    // stored quadrupole entries: explicit symmetric part + q = Qf r
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            const double ex = b2 * B[i][j] + 3.0 * b3 * Tr[i][j];
+            if (i == j)
+                Qb[sym2(i, j)] += ex + qb[i] * r[i];
+            else
+                Qb[sym2(i, j)] += 2.0 * ex + qb[i] * r[j] + qb[j] * r[i];
+        }
+}
+
+// ---------------------------------------------------------------- L2P adjoint
+// Stored-coefficient cotangent of a = L2P(L, y) for the cotangent ab.
+__device__ __forceinline__ void l2p_vjp_L(double a0, double a1, double a2, double y0, double y1,
+                                          double y2, double *Lb)
+{
+    Lb[0] += a0;
+    Lb[1] += a1;
+    Lb[2] += a2;
+    Lb[3] += a0 * y0;
+    Lb[4] += a0 * y1 + a1 * y0;
+    Lb[5] += a0 * y2 + a2 * y0;
+    Lb[6] += a1 * y1;
+    Lb[7] += a1 * y2 + a2 * y1;
+    Lb[8] += a2 * y2;
+    Lb[9] += 0.5 * a0 * y0 * y0;
+    Lb[10] += a0 * y0 * y1 + 0.5 * a1 * y0 * y0;
+    Lb[11] += a0 * y0 * y2 + 0.5 * a2 * y0 * y0;
+    Lb[12] += 0.5 * a0 * y1 * y1 + a1 * y0 * y1;
+    Lb[13] += a0 * y1 * y2 + a1 * y0 * y2 + a2 * y0 * y1;
+    Lb[14] += 0.5 * a0 * y2 * y2 + a2 * y0 * y2;
+    Lb[15] += 0.5 * a1 * y1 * y1;
+    Lb[16] += a1 * y1 * y2 + 0.5 * a2 * y1 * y1;
+    Lb[17] += 0.5 * a1 * y2 * y2 + a2 * y1 * y2;
+    Lb[18] += 0.5 * a2 * y2 * y2;
+}
+
+// (L2 + L3 y)^T ab
+__device__ __forceinline__ void l2p_vjp_y(const double *L, double a0, double a1, double a2,
+                                          double y0, double y1, double y2, double &b0, double &b1,
+                                          double &b2)
+{
+    const double t00 = L[3] + L[9] * y0 + L[10] * y1 + L[11] * y2;
+    const double t01 = L[4] + L[10] * y0 + L[12] * y1 + L[13] * y2;
+    const double t02 = L[5] + L[11] * y0 + L[13] * y1 + L[14] * y2;
+    const double t11 = L[6] + L[12] * y0 + L[15] * y1 + L[16] * y2;
+    const double t12 = L[7] + L[13] * y0 + L[16] * y1 + L[17] * y2;
+    const double t22 = L[8] + L[14] * y0 + L[17] * y1 + L[18] * y2;
+    b0 = a0 * t00 + a1 * t01 + a2 * t02;
+    b1 = a0 * t01 + a1 * t11 + a2 * t12;
+    b2 = a0 * t02 + a1 * t12 + a2 * t22;
+}
+
+// ---------------------------------------------------------------- pair kernel
+__device__ __forceinline__ double m4g(double q, double hinv3, double u3)
+{
+    const double p1 = hinv3 * (4.0 / 3.0 + q * q * (-1.2 + 0.5 * q));
+    const double p2 = hinv3 * (8.0 / 3.0 + q * (-3.0 + q * (1.2 - q * (1.0 / 6.0)))) -
+                      u3 * (1.0 / 15.0);
+    return q < 1.0 ? p1 : (q < 2.0 ? p2 : u3);
+}
+
+// (dg/dr) / r for the M4 kernel: h^-5 (-12/5 + 3/2 q) for q < 1,
+// h^-5 (-3/q + 12/5 - q/2 + 1/(5 q^5)) for 1 <= q < 2, -3 / r^5 beyond.
+__device__ __forceinline__ double m4dgr(double q, double hinv, double hinv3, double h, double u)
+{
+    const double h5 = hinv3 * hinv * hinv;
+    const double iq = h * u;  // 1 / q
+    const double iq2 = iq * iq;
+    const double p1 = h5 * (-2.4 + 1.5 * q);
+    const double p2 = h5 * (-3.0 * iq + 2.4 - 0.5 * q + 0.2 * iq2 * iq2 * iq);
+    const double u2 = u * u;
+    return q < 1.0 ? p1 : (q < 2.0 ? p2 : -3.0 * u2 * u2 * u);
+}
+
+// G_ij and G'_ij / r for a pair at squared distance r2 > 0.
+__device__ __forceinline__ void pair_gdg(double r2, double4 hi, double4 hj, double &Gp,
+                                         double &dGr)
+{
+    const double u = rsqrt(r2);
+    const double r = r2 * u;
+    const double u3 = u * u * u;
+    const double qi = r * hi.x, qj = r * hj.x;
+    Gp = 0.5 * (m4g(qi, hi.y, u3) + m4g(qj, hj.y, u3));
+    dGr = 0.5 * (m4dgr(qi, hi.x, hi.y, hi.w, u) + m4dgr(qj, hj.x, hj.y, hj.w, u));
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double xk(double keep, double send, int off)
+{
+    return keep + __shfl_xor(send, off);
+}
+
+// Reduce-scatter of 12 doubles over the wavefront; value index held by lane l
+// is 6 b5 + 3 b4 + (2 b3 + b2) when (2 b3 + b2) < 3 (sum complete in every lane
+// of the group of four).
+__device__ __forceinline__ double rs12(const double *v, int lane, int &idx)
+{
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    double a[6], b[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        a[k] = xk(b5 ? v[6 + k] : v[k], b5 ? v[k] : v[6 + k], 32);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        b[k] = xk(b4 ? a[3 + k] : a[k], b4 ? a[k] : a[3 + k], 16);
+    const double c0 = xk(b3 ? b[2] : b[0], b3 ? b[0] : b[2], 8);
+    const double c1 = xk(b3 ? 0.0 : b[1], b3 ? b[1] : 0.0, 8);
+    double d = xk(b2 ? c1 : c0, b2 ? c0 : c1, 4);
+    d += __shfl_xor(d, 2);
+    d += __shfl_xor(d, 1);
+    const int sub = 2 * (int)b3 + (int)b2;
+    idx = sub < 3 ? 6 * (int)b5 + 3 * (int)b4 + sub : -1;
+    return d;
+}
+
+// Reduce-scatter of 16 doubles; lane l holds value 8 b5 + 4 b4 + 2 b3 + b2.
+__device__ __forceinline__ double rs16(const double *v, int lane, int &idx)
+{
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    double a[8], b[4], c[2];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        a[k] = xk(b5 ? v[8 + k] : v[k], b5 ? v[k] : v[8 + k], 32);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        b[k] = xk(b4 ? a[4 + k] : a[k], b4 ? a[k] : a[4 + k], 16);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        c[k] = xk(b3 ? b[2 + k] : b[k], b3 ? b[k] : b[2 + k], 8);
+    double d = xk(b2 ? c[1] : c[0], b2 ? c[0] : c[1], 4);
+    d += __shfl_xor(d, 2);
+    d += __shfl_xor(d, 1);
+    idx = 8 * (int)b5 + 4 * (int)b4 + 2 * (int)b3 + (int)b2;
+    return d;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------- kernels
+template <typename TA>
+__global__ void k_vjp_prep(const TA *__restrict__ abar, int64_t n, const int32_t *__restrict__ perm,
+                           double G, double *abt)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = perm[p];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            abt[3 * p + d] = G * (double)abar[3 * i + d];
+    }
+}
+
+// 1. L2P^T: one thread per leaf.
+__global__ __launch_bounds__(256) void k_vjp_l2p(const double4 *__restrict__ pm,
+                                                 const double *__restrict__ abt,
+                                                 const int32_t *__restrict__ leaf_node, int nleaves,
+                                                 const int32_t *__restrict__ first,
+                                                 const int32_t *__restrict__ count,
+                                                 const double *__restrict__ recA,
+                                                 const double *__restrict__ Lloc, double *Lbar,
+                                                 double *xbt, double *nadj)
+{
+    const int lf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves)
+        return;
+    const int v = leaf_node[lf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const double *rv = recA + (int64_t)NREC * v;
+    const double *Lv = Lloc + (int64_t)NLOC * v;
+    double L[19], Lb[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+        L[k] = Lv[k];
+        Lb[k] = 0.0;
+    }
+    double cb0 = 0.0, cb1 = 0.0, cb2 = 0.0;
+    for (int k = 0; k < c; ++k) {
+        const int64_t p = f + k;
+        const double4 x = pm[p];
+        const double y0 = x.x - rv[0], y1 = x.y - rv[1], y2 = x.z - rv[2];
+        const double a0 = abt[3 * p], a1 = abt[3 * p + 1], a2 = abt[3 * p + 2];
+        l2p_vjp_L(a0, a1, a2, y0, y1, y2, Lb);
+        double b0, b1, b2;
+        l2p_vjp_y(L, a0, a1, a2, y0, y1, y2, b0, b1, b2);
+        xbt[3 * p] = b0;
+        xbt[3 * p + 1] = b1;
+        xbt[3 * p + 2] = b2;
+        cb0 -= b0;
+        cb1 -= b1;
+        cb2 -= b2;
+    }
+    double *o = Lbar + (int64_t)NLOC * v;
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        o[k] = Lb[k];
+    double *na = nadj + 16 * (int64_t)v;
+    na[0] = cb0;
+    na[1] = cb1;
+    na[2] = cb2;
+}
+
+// 2a. M2L^T, sink side: 16 lanes per leaf over its far list, cbar_sink += rbar.
+__global__ __launch_bounds__(256) void k_vjp_m2l_sink(
+    const double *__restrict__ recA, const double *__restrict__ recQ,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
+    const int32_t *__restrict__ far_src, int cap_far, const double *__restrict__ Lbar, double *nadj)
+{
+    const int g = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    const bool valid = g < nleaves;
+    const int v = valid ? leaf_node[g] : 0;
+    const double *rv = recA + (int64_t)NREC * v;
+    double Lb[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        Lb[k] = Lbar[(int64_t)NLOC * v + k];
+    double rb[3] = {0.0, 0.0, 0.0};
+    const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
+    const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
+    for (int k = sub; k < nk; k += 16) {
+        const int b = fl[k];
+        const double *rbp = recA + (int64_t)NREC * b;
+        const double r[3] = {rv[0] - rbp[0], rv[1] - rbp[1], rv[2] - rbp[2]};
+        double Mb = 0.0, Qb[6] = {0, 0, 0, 0, 0, 0};
+        m2l_vjp(r, rbp[3], recQ + (int64_t)NREC * b, Lb, rb, Mb, Qb);
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            rb[d] += __shfl_xor(rb[d], off);
+    if (valid && sub == 0) {
+        double *na = nadj + 16 * (int64_t)v;
+        na[0] += rb[0];
+        na[1] += rb[1];
+        na[2] += rb[2];
+    }
+}
+
+// 2b. M2L^T, source side: one wavefront per cell over the sinks that took it
+// as far field; writes Mbar, Qbar and cbar_src for every cell (zero if none),
+// and zeroes cbar_sink of internal cells.
+__global__ __launch_bounds__(256) void k_vjp_m2l_src(
+    const double *__restrict__ recA, const double *__restrict__ recQ, int nnodes,
+    const int32_t *__restrict__ left, const int64_t *__restrict__ toff,
+    const uint32_t *__restrict__ tsrc, const double *__restrict__ Lbar, double *nadj)
+{
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= nnodes)
+        return;
+    const int lane = lane_id();
+    const double *rbp = recA + (int64_t)NREC * b;
+    const double cb0 = rbp[0], cb1 = rbp[1], cb2 = rbp[2], M = rbp[3];
+    const double *Qs = recQ + (int64_t)NREC * b;
+    double acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+        acc[k] = 0.0;
+    for (int64_t e = toff[b] + lane; e < toff[b + 1]; e += 64) {
+        const int sgm = (int)tsrc[e];
+        const double *rs = recA + (int64_t)NREC * sgm;
+        const double r[3] = {rs[0] - cb0, rs[1] - cb1, rs[2] - cb2};
+        double Lb[19];
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            Lb[k] = Lbar[(int64_t)NLOC * sgm + k];
+        double rb[3] = {0.0, 0.0, 0.0}, Mb = 0.0, Qb[6] = {0, 0, 0, 0, 0, 0};
+        m2l_vjp(r, M, Qs, Lb, rb, Mb, Qb);
+        acc[0] += Mb;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            acc[1 + k] += Qb[k];
+        acc[7] -= rb[0];
+        acc[8] -= rb[1];
+        acc[9] -= rb[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+        acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+        double *na = nadj + 16 * (int64_t)b;
+        na[3] = acc[7];
+        na[4] = acc[8];
+        na[5] = acc[9];
+        na[6] = acc[0];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            na[7 + k] = acc[1 + k];
+        if (left[b] >= 0)
+            na[0] = na[1] = na[2] = 0.0;
+    }
+}
+
+// 3a. P2P^T, sink side: like the forward near field (source per lane, four
+// wave-uniform sinks per pass), pair function dbar.  xbt += the sum.
+constexpr int VJP_RANGES = 256;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_sink(
+    const double4 *__restrict__ pm, const double4 *__restrict__ ph,
+    const double *__restrict__ abt, const int32_t *__restrict__ first,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
+    const int32_t *__restrict__ near_cnt, const int32_t *__restrict__ near_src, int cap_near,
+    int nsub, double *xbt)
+{
+    constexpr int NS = 4;
+    __shared__ int2 rng[4][VJP_RANGES];
+    const int w = threadIdx.x >> 6;
+    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    if (leaf >= nleaves)
+        return;
+    const int lane = lane_id();
+    const int grp = lane >> 3, slot = lane & 7;
+    const int v = leaf_node[leaf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const int nb = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int32_t *nl = near_src + (int64_t)leaf * cap_near;
+    int2 *R = rng[w];
+    for (int sb = 0; sb < c; sb += NS) {
+        double4 xs[NS], hsn[NS];
+        double as0[NS], as1[NS], as2[NS];
+        int64_t is[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            is[q] = f + min(sb + q, c - 1);
+            xs[q] = pm[is[q]];
+            hsn[q] = ph[is[q]];
+            as0[q] = abt[3 * is[q]];
+            as1[q] = abt[3 * is[q] + 1];
+            as2[q] = abt[3 * is[q] + 2];
+        }
+        double acc[3 * NS];
+#pragma unroll
+        for (int q = 0; q < 3 * NS; ++q)
+            acc[q] = 0.0;
+        for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
+            const int nc = min(nb - c0, VJP_RANGES);
+            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
+                int2 r = make_int2(0, 0);
+                if (k < nc) {
+                    const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
+                    const int bn = nl[e];
+                    r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
+                }
+                R[k] = r;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int kb = 0; kb < nc; kb += 8) {
+                const int2 rg = R[kb + grp];
+                const bool valid = slot < rg.y;
+                const int64_t j = (int64_t)rg.x + (valid ? slot : 0);
+                double4 xj = pm[j];
+                const double4 hj = ph[j];
+                if (!valid)
+                    xj = make_double4(1e30, 1e30, 1e30, 0.0);
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const double dx = xs[q].x - xj.x, dy = xs[q].y - xj.y, dz = xs[q].z - xj.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    double Gp = 0.0, dGr = 0.0;
+                    if (j != is[q] && r2 > 0.0)
+                        pair_gdg(r2, hsn[q], hj, Gp, dGr);
+                    else if (j != is[q])  // distinct particles at one point: d = 0
+                        Gp = 0.5 * (hsn[q].y + hj.y) * (4.0 / 3.0);
+                    const double da = dx * as0[q] + dy * as1[q] + dz * as2[q];
+                    const double t = dGr * da;
+                    acc[3 * q] -= xj.w * (Gp * as0[q] + t * dx);
+                    acc[3 * q + 1] -= xj.w * (Gp * as1[q] + t * dy);
+                    acc[3 * q + 2] -= xj.w * (Gp * as2[q] + t * dz);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        int idx;
+        const double tot = rs12(acc, lane, idx);
+        const int q = idx / 3, comp = idx - 3 * (idx / 3);
+        if (idx >= 0 && (lane & 3) == 0 && sb + q < c)
+            xbt[3 * (f + sb + q) + comp] += tot;
+    }
+}
+
+// 3b. P2P^T, source side: one wavefront per source leaf b over the sink leaves
+// whose near list holds b (transposed, ascending); lanes hold sink particles,
+// four source particles of b per pass are wave-uniform.  xbt[j] -= sum dbar,
+// mbt[j] = sum -G_ij (d . abar'_i).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_src(
+    const double4 *__restrict__ pm, const double4 *__restrict__ ph,
+    const double *__restrict__ abt, const int32_t *__restrict__ first,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
+    const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc, int nsub, double *xbt,
+    double *mbt)
+{
+    constexpr int NS = 4;
+    __shared__ int2 rng[4][VJP_RANGES];
+    const int w = threadIdx.x >> 6;
+    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    if (leaf >= nleaves)
+        return;
+    const int lane = lane_id();
+    const int grp = lane >> 3, slot = lane & 7;
+    const int v = leaf_node[leaf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const int64_t e0 = toff[v];
+    const int nb = (int)(toff[v + 1] - e0) * nsub;
+    int2 *R = rng[w];
+    for (int sb = 0; sb < c; sb += NS) {
+        double4 xs[NS], hsn[NS];
+        int64_t js[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            js[q] = f + min(sb + q, c - 1);
+            xs[q] = pm[js[q]];
+            hsn[q] = ph[js[q]];
+        }
+        double acc[4 * NS];
+#pragma unroll
+        for (int q = 0; q < 4 * NS; ++q)
+            acc[q] = 0.0;
+        for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
+            const int nc = min(nb - c0, VJP_RANGES);
+            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
+                int2 r = make_int2(0, 0);
+                if (k < nc) {
+                    const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
+                    const int an = (int)tsrc[e0 + e];
+                    r = make_int2(first[an] + 8 * u, max(0, min(8, count[an] - 8 * u)));
+                }
+                R[k] = r;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int kb = 0; kb < nc; kb += 8) {
+                const int2 rg = R[kb + grp];
+                const bool valid = slot < rg.y;
+                const int64_t i = (int64_t)rg.x + (valid ? slot : 0);
+                double4 xi = pm[i];
+                const double4 hi = ph[i];
+                double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
+                if (!valid) {
+                    xi = make_double4(1e30, 1e30, 1e30, 0.0);
+                    ai0 = ai1 = ai2 = 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const double dx = xi.x - xs[q].x, dy = xi.y - xs[q].y, dz = xi.z - xs[q].z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    double Gp = 0.0, dGr = 0.0;
+                    if (i != js[q] && r2 > 0.0)
+                        pair_gdg(r2, hi, hsn[q], Gp, dGr);
+                    else if (i != js[q])  // distinct particles at one point: d = 0
+                        Gp = 0.5 * (hi.y + hsn[q].y) * (4.0 / 3.0);
+                    const double da = dx * ai0 + dy * ai1 + dz * ai2;
+                    const double t = dGr * da;
+                    const double mj = xs[q].w;
+                    // xbar_j -= dbar = -m_j [G abar_i + t d]
+                    acc[4 * q] += mj * (Gp * ai0 + t * dx);
+                    acc[4 * q + 1] += mj * (Gp * ai1 + t * dy);
+                    acc[4 * q + 2] += mj * (Gp * ai2 + t * dz);
+                    acc[4 * q + 3] -= Gp * da;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        int idx;
+        const double tot = rs16(acc, lane, idx);
+        const int q = idx >> 2, comp = idx & 3;
+        if ((lane & 3) == 0 && sb + q < c) {
+            const int64_t jj = f + sb + q;
+            if (comp < 3)
+                xbt[3 * jj + comp] += tot;
+            else
+                mbt[jj] = tot;
+        }
+    }
+}
+
+// 4. Moments adjoint and output: one thread per particle walks root -> leaf.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_vjp_moments(
+    const double4 *__restrict__ pm, int64_t n, const double *__restrict__ recA,
+    const double *__restrict__ nadj, const int32_t *__restrict__ first,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ left,
+    const int32_t *__restrict__ right, const double *__restrict__ xbt,
+    const double *__restrict__ mbt, const int32_t *__restrict__ perm, TO *xbar, TO *mbar)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    const double4 x = pm[p];
+    double gx = xbt[3 * p], gy = xbt[3 * p + 1], gz = xbt[3 * p + 2], gm = mbt[p];
+    int v = 0;
+    while (true) {
+        const double *ra = recA + (int64_t)NREC * v;
+        const double *na = nadj + 16 * (int64_t)v;
+        const double M = ra[3];
+        const double y0 = x.x - ra[0], y1 = x.y - ra[1], y2 = x.z - ra[2];
+        const double c0 = na[0] + na[3], c1 = na[1] + na[4], c2 = na[2] + na[5];
+        // Qf: stored cotangent -> symmetric matrix (off-diagonals halved)
+        const double qxx = na[7], qxy = 0.5 * na[8], qxz = 0.5 * na[9], qyy = na[10],
+                     qyz = 0.5 * na[11], qzz = na[12];
+        const double tr = qxx + qyy + qzz;
+        const double Qy0 = qxx * y0 + qxy * y1 + qxz * y2;
+        const double Qy1 = qxy * y0 + qyy * y1 + qyz * y2;
+        const double Qy2 = qxz * y0 + qyz * y1 + qzz * y2;
+        const double wm = x.w / M;
+        gx += wm * c0 + x.w * (6.0 * Qy0 - 2.0 * tr * y0);
+        gy += wm * c1 + x.w * (6.0 * Qy1 - 2.0 * tr * y1);
+        gz += wm * c2 + x.w * (6.0 * Qy2 - 2.0 * tr * y2);
+        gm += na[6] + (c0 * y0 + c1 * y1 + c2 * y2) / M +
+              3.0 * (y0 * Qy0 + y1 * Qy1 + y2 * Qy2) - (y0 * y0 + y1 * y1 + y2 * y2) * tr;
+        const int l = left[v];
+        if (l < 0)
+            break;
+        v = (p < (int64_t)first[l] + count[l]) ? l : right[v];
+    }
+    const int64_t i = perm[p];
+    xbar[3 * i] = (TO)gx;
+    xbar[3 * i + 1] = (TO)gy;
+    xbar[3 * i + 2] = (TO)gz;
+    mbar[i] = (TO)gm;
+}
+
+// ---------------------------------------------------------------- transposition
+constexpr int SCAN_TILE = 4096;
+
+__device__ __forceinline__ int64_t block_scan_i64(int64_t v, int64_t *sh, int64_t &total)
+{
+    int t = threadIdx.x, lane = lane_id(), w = t >> 6, nw = blockDim.x >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int64_t o = __shfl_up(inc, off);
+        if (lane >= off)
+            inc += o;
+    }
+    if (lane == 63)
+        sh[w] = inc;
+    __syncthreads();
+    int64_t wb = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        int64_t s = sh[i];
+        wb += i < w ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return wb + inc - v;
+}
+
+// exclusive scan of min(cnt, cap) over nl leaves -> off[0..nl]
+__global__ __launch_bounds__(256) void k_cnt_tiles(const int32_t *cnt, int cap, int nl,
+                                                   int64_t *tsum)
+{
+    __shared__ int64_t sh[8];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t sacc = 0;
+    for (int k = threadIdx.x; k < SCAN_TILE; k += 256) {
+        const int64_t i = base + k;
+        if (i < nl)
+            sacc += max(0, min(cnt[i], cap));
+    }
+    int64_t tot;
+    block_scan_i64(sacc, sh, tot);
+    if (threadIdx.x == 0)
+        tsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_cnt_tile_scan(int64_t *tsum, int ntiles, int64_t *total)
+{
+    __shared__ int64_t sh[16];
+    int64_t run = 0;
+    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int64_t v = i < ntiles ? tsum[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_scan_i64(v, sh, tot);
+        if (i < ntiles)
+            tsum[i] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0)
+        *total = run;
+}
+
+__global__ __launch_bounds__(256) void k_cnt_write(const int32_t *cnt, int cap, int nl,
+                                                   const int64_t *tsum, const int64_t *total,
+                                                   int64_t *off)
+{
+    constexpr int PER = SCAN_TILE / 256;
+    __shared__ int64_t sh[8];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * PER;
+    int32_t v[PER];
+    int64_t sacc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = base + k;
+        v[k] = i < nl ? max(0, min(cnt[i], cap)) : 0;
+        sacc += v[k];
+    }
+    int64_t tot;
+    int64_t e = block_scan_i64(sacc, sh, tot) + tsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = base + k;
+        if (i < nl)
+            off[i] = e;
+        e += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        off[nl] = *total;
+}
+
+// (target, sink) pairs in sink-major order: key = target node, value = sink node
+__global__ void k_pairs_write(const int32_t *__restrict__ cnt, const int32_t *__restrict__ slots,
+                              int cap, int nl, const int32_t *__restrict__ leaf_node,
+                              const int64_t *__restrict__ off, uint64_t *keys, uint32_t *vals)
+{
+    const int lf = blockIdx.x;
+    const int c = max(0, min(cnt[lf], cap));
+    const int64_t o = off[lf];
+    const uint32_t sink = (uint32_t)leaf_node[lf];
+    for (int k = threadIdx.x; k < c; k += blockDim.x) {
+        keys[o + k] = (uint64_t)(uint32_t)slots[(int64_t)lf * cap + k];
+        vals[o + k] = sink;
+    }
+}
+
+// CSR offsets over targets from the sorted keys: off[b] = first index with key >= b
+__global__ void k_lower_bound(const uint64_t *__restrict__ keys, int64_t np, int nnodes,
+                              int64_t *off)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= nnodes;
+         b += gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = np;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < (uint64_t)b)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        off[b] = lo;
+    }
+}
+
+template <typename P>
+static hipError_t valloc(Tree &t, P **out, size_t elems)
+{
+    void *p = nullptr;
+    size_t bytes = std::max<size_t>(elems * sizeof(P), 256);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+        return e;
+    t.vjp_owned.push_back({p, bytes});
+    *out = (P *)p;
+    return hipSuccess;
+}
+
+static hipError_t ensure_vjp_base(Tree &t)
+{
+    if (t.abt)
+        return hipSuccess;
+    const Topology &T = t.topo;
+    const int64_t n = T.n, nn = T.nnodes;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = valloc(t, &t.abt, 3 * n);
+    if (e == hipSuccess) e = valloc(t, &t.xbt, 3 * n);
+    if (e == hipSuccess) e = valloc(t, &t.mbt, n);
+    if (e == hipSuccess) e = valloc(t, &t.Lbar, NLOC * nn);
+    if (e == hipSuccess) e = valloc(t, &t.nadj, 16 * nn);
+    if (e == hipSuccess) e = valloc(t, &t.pair_off, T.nleaves + 1);
+    if (e == hipSuccess) e = valloc(t, &t.vscan, T.nleaves / SCAN_TILE + 2);
+    if (e == hipSuccess) e = valloc(t, &t.farT.off, nn + 1);
+    if (e == hipSuccess) e = valloc(t, &t.nearT.off, nn + 1);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&t.h_pairs, 4 * sizeof(int64_t), hipHostMallocDefault);
+    return e;
+}
+
+static int key_passes(int nnodes)
+{
+    int bits = 1;
+    while ((1ll << bits) <= nnodes)
+        ++bits;
+    return (bits + 7) / 8;
+}
+
+// Build one transposed list (sink-major pairs -> target-major CSR, stable).
+static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *slots, int64_t cap,
+                                  Tree::Transposed &out, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const int nl = T.nleaves;
+    const int ntiles = (nl + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t *total = t.vscan + ntiles;
+    k_cnt_tiles<<<ntiles, 256, 0, s>>>(cnt, (int)cap, nl, t.vscan);
+    k_cnt_tile_scan<<<1, 1024, 0, s>>>(t.vscan, ntiles, total);
+    k_cnt_write<<<ntiles, 256, 0, s>>>(cnt, (int)cap, nl, t.vscan, total, t.pair_off);
+    hipError_t e = hipMemcpyAsync(t.h_pairs, total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return e;
+    const int64_t np = t.h_pairs[0];
+    if (np > t.vjp_pair_cap) {
+        // (re)allocate the pair sort buffers
+        e = hipStreamSynchronize(s);
+        for (void *pp : {(void *)t.vk0, (void *)t.vk1, (void *)t.vv0, (void *)t.vv1,
+                         (void *)t.vhist, (void *)t.vtot})
+            if (pp)
+                (void)hipFree(pp);
+        const int64_t cp = np + np / 4 + 1024;
+        const int64_t nblk = (cp + RS_TILE - 1) / RS_TILE;
+        e = hipMalloc((void **)&t.vk0, cp * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&t.vk1, cp * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&t.vv0, cp * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&t.vv1, cp * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&t.vhist, 256 * nblk * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&t.vtot, 8 * 256 * sizeof(uint32_t));
+        if (e != hipSuccess)
+            return e;
+        t.vjp_pair_cap = cp;
+    }
+    if (nl > 0)
+        k_pairs_write<<<nl, 64, 0, s>>>(cnt, slots, (int)cap, nl, t.leaf_node, t.pair_off, t.vk0,
+                                        t.vv0);
+    const int passes = key_passes(T.nnodes);
+    e = radix_sort_u64(t.vk0, t.vv0, t.vk1, t.vv1, np, 1, passes, t.vhist, t.vtot, s);
+    if (e != hipSuccess)
+        return e;
+    uint64_t *ks = (passes & 1) ? t.vk1 : t.vk0;
+    uint32_t *vs = (passes & 1) ? t.vv1 : t.vv0;
+    k_lower_bound<<<(T.nnodes + 256) / 256, 256, 0, s>>>(ks, np, T.nnodes, out.off);
+    // keep the sorted values
+    if (out.src && out.npairs < np) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(out.src);
+        out.src = nullptr;
+    }
+    if (!out.src) {
+        e = hipMalloc((void **)&out.src, std::max<int64_t>(np, 1) * sizeof(uint32_t));
+        if (e != hipSuccess)
+            return e;
+    }
+    out.npairs = np;
+    e = hipMemcpyAsync(out.src, vs, np * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const int64_t n = T.n;
+    const int nl = T.nleaves;
+    hipError_t e = ensure_vjp_base(t);
+    if (e != hipSuccess)
+        return e;
+    if (!t.has_transposed) {
+        e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, t.farT, s);
+        if (e == hipSuccess)
+            e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, t.nearT, s);
+        if (e != hipSuccess)
+            return e;
+        t.has_transposed = true;
+    }
+    const bool fp32 = t.p.precision == FMM_FP32;
+    if (fp32) {
+        // the reverse pass runs in FP64: form the FP64 local expansions
+        e = launch_far_f64(t, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    const int gs = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    if (fp32)
+        k_vjp_prep<float><<<gs, 256, 0, s>>>((const float *)abar, n, t.perm, t.p.G, t.abt);
+    else
+        k_vjp_prep<double><<<gs, 256, 0, s>>>((const double *)abar, n, t.perm, t.p.G, t.abt);
+    k_vjp_l2p<<<(nl + 255) / 256, 256, 0, s>>>(t.pm, t.abt, t.leaf_node, nl, t.first, t.count,
+                                               t.recA, t.L, t.Lbar, t.xbt, t.nadj);
+    k_vjp_m2l_sink<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
+                                                         t.far_cnt, t.far_src, (int)t.cap_far,
+                                                         t.Lbar, t.nadj);
+    k_vjp_m2l_src<<<(T.nnodes + 3) / 4, 256, 0, s>>>(t.recA, t.recQ, T.nnodes, t.left,
+                                                     t.farT.off, t.farT.src, t.Lbar, t.nadj);
+    const int nsub = (T.leaf_size + 7) / 8;
+    k_vjp_p2p_sink<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
+                                                nl, t.near_cnt, t.near_src, (int)t.cap_near,
+                                                nsub, t.xbt);
+    k_vjp_p2p_src<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
+                                               nl, t.nearT.off, t.nearT.src, nsub, t.xbt, t.mbt);
+    if (fp32)
+        k_vjp_moments<float><<<(int)((n + 255) / 256), 256, 0, s>>>(
+            t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, t.xbt, t.mbt, t.perm,
+            (float *)xbar, (float *)mbar);
+    else
+        k_vjp_moments<double><<<(int)((n + 255) / 256), 256, 0, s>>>(
+            t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, t.xbt, t.mbt, t.perm,
+            (double *)xbar, (double *)mbar);
+    return hipGetLastError();
+}
+
+void release_vjp(Tree &t)
+{
+    for (auto &b : t.vjp_owned)
+        (void)hipFree(b.p);
+    t.vjp_owned.clear();
+    for (void *pp : {(void *)t.vk0, (void *)t.vk1, (void *)t.vv0, (void *)t.vv1, (void *)t.vhist,
+                     (void *)t.vtot, (void *)t.farT.src, (void *)t.nearT.src})
+        if (pp)
+            (void)hipFree(pp);
+    if (t.h_pairs)
+        (void)hipHostFree(t.h_pairs);
 }
 
 }  // namespace fmm

@@ -44,3 +44,28 @@ def force_err(a, ref):
 
 def eta(a, ref):
     return float(np.sqrt(((a - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repeat=1):
+    """build -> moments -> forces -> VJP on the GPU; returns (a, [(xbar, mbar)] * repeat)."""
+    import torch
+
+    X, Mt, H = to_dev(x, m, h)
+    dt = torch.float32 if precision == F.FMM_FP32 else torch.float64
+    AB = torch.from_numpy(np.ascontiguousarray(abar)).to("cuda").to(dt)
+    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision)
+    t = F.fmm_build_tree(X, p)
+    out = []
+    try:
+        F.fmm_moments(t, X, Mt, H)
+        A = torch.empty((len(m), 3), dtype=dt, device="cuda")
+        F.fmm_forces(t, A)
+        for _ in range(repeat):
+            XB = torch.empty((len(m), 3), dtype=dt, device="cuda")
+            MB = torch.empty(len(m), dtype=dt, device="cuda")
+            F.fmm_forces_vjp(t, AB, XB, MB)
+            torch.cuda.synchronize()
+            out.append((XB.cpu().numpy().astype(np.float64), MB.cpu().numpy().astype(np.float64)))
+    finally:
+        F.fmm_tree_free(t)
+    return A.cpu().numpy().astype(np.float64), out

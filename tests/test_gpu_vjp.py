@@ -1,0 +1,100 @@
+"""GPU vector-Jacobian product of the FMM accelerations (tree membership and
+interaction lists held fixed) against the CPU oracle.
+
+Checks: central finite differences (eps = 1e-4, FP64) of <abar, a(x, m)> computed
+by the oracle's frozen-tree FMM along normalised random directions, within 1e-6
+of |xbar| |e| (resp. |mbar| |e|); at theta = 0 the FMM is the direct sum, so the
+VJP must equal the oracle's analytic direct-sum adjoint to 1e-12; at theta = 0.5
+it differs from that adjoint only by the FMM truncation (at most five times the
+forward error eta of the same configuration); bitwise reproducible."""
+import numpy as np
+import pytest
+
+from paper_2502_01496_amd import fmm as F
+from paper_2502_01496_amd import workloads as W
+from tests.gpu_util import gpu_vjp, say
+
+pytestmark = pytest.mark.gpu
+
+
+def fd_check(orc, x, m, h, abar, xb, mb, theta, leaf, ndir=4, eps=1e-4, seed=0):
+    ref = orc.fmm(x, m, h, theta=theta, leaf_size=leaf)
+    tree, lists = ref.tree, ref.lists
+    phi = lambda xx, mm: float((orc.fmm_frozen(xx, mm, h, tree, lists) * abar).sum())
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for _ in range(ndir):
+        e = rng.standard_normal(x.shape)
+        e /= np.linalg.norm(e)
+        fd = (phi(x + eps * e, m) - phi(x - eps * e, m)) / (2 * eps)
+        err = abs((xb * e).sum() - fd) / np.linalg.norm(xb)
+        worst = max(worst, err)
+        em = rng.standard_normal(m.shape)
+        em /= np.linalg.norm(em)
+        epm = eps * m.mean()
+        fd = (phi(x, m + epm * em) - phi(x, m - epm * em)) / (2 * epm)
+        err = abs((mb * em).sum() - fd) / np.linalg.norm(mb)
+        worst = max(worst, err)
+    return worst
+
+
+@pytest.mark.parametrize("name", ["plummer_4096", "binary_2x2048", "leaf10_3000", "clumpy_6000"])
+def test_vjp_matches_finite_differences(orc, name):
+    leaf, theta = 8, 0.5
+    if name == "plummer_4096":
+        x, m, h = W.plummer(4096, 1)
+    elif name == "binary_2x2048":
+        x, m, h = W.polytrope_binary(2048, 2, cache=False)
+    elif name == "leaf10_3000":
+        x, m, h = W.plummer(3000, 15)
+        leaf = 10
+    else:
+        x, m, h = W.clumpy_cube(6000, 3, cache=False)
+    abar = W.cotangent(len(m), 31)
+    say(f"[gpu vjp] finite differences, case={name} n={len(m)}")
+    _, [(xb, mb)] = gpu_vjp(x, m, h, abar, theta=theta, leaf=leaf)
+    worst = fd_check(orc, x, m, h, abar, xb, mb, theta, leaf)
+    say(f"    worst directional error {worst:.2e}")
+    assert worst <= 1e-6
+
+
+def test_vjp_theta0_is_direct_adjoint(orc):
+    x, m, h = W.plummer(2048, 16)
+    h = h * 5.0  # many softened pairs
+    abar = W.cotangent(len(m), 32)
+    say("[gpu vjp] theta = 0 against the direct-sum adjoint, plummer_2048")
+    _, [(xb, mb)] = gpu_vjp(x, m, h, abar, theta=0.0)
+    xr, mr = orc.direct_vjp(x, m, h, abar)
+    assert np.abs(xb - xr).max() <= 1e-12 * np.abs(xr).max()
+    assert np.abs(mb - mr).max() <= 1e-12 * np.abs(mr).max()
+
+
+@pytest.mark.parametrize("name", ["plummer_4096", "binary_2x4096"])
+def test_vjp_close_to_direct_adjoint(orc, name):
+    # the FMM adjoint differs from the direct-sum adjoint by the FMM's own
+    # truncation: bounded by a small multiple of the forward error eta
+    if name == "plummer_4096":
+        x, m, h = W.plummer(4096, 1)
+    else:
+        x, m, h = W.polytrope_binary(4096, 2, cache=False)
+    abar = W.cotangent(len(m), 33)
+    say(f"[gpu vjp] theta = 0.5 against the direct-sum adjoint, {name}")
+    a, [(xb, mb)] = gpu_vjp(x, m, h, abar, theta=0.5)
+    d = orc.direct(x, m, h)
+    eta_fwd = np.sqrt(((a - d) ** 2).sum() / (d ** 2).sum())
+    xr, mr = orc.direct_vjp(x, m, h, abar)
+    ex = np.linalg.norm(xb - xr) / np.linalg.norm(xr)
+    em = np.linalg.norm(mb - mr) / np.linalg.norm(mr)
+    say(f"    forward eta {eta_fwd:.2e}; relative difference: xbar {ex:.2e}, mbar {em:.2e}")
+    assert ex <= 5 * eta_fwd and em <= 5 * eta_fwd
+
+
+def test_vjp_deterministic_and_fp32(orc):
+    x, m, h = W.polytrope_binary(4096, 2, cache=False)
+    abar = W.cotangent(len(m), 34)
+    say("[gpu vjp] determinism and FP32 form, binary_2x4096")
+    _, [(x1, m1), (x2, m2)] = gpu_vjp(x, m, h, abar, repeat=2)
+    assert np.array_equal(x1, x2) and np.array_equal(m1, m2)
+    _, [(x3, m3)] = gpu_vjp(x, m, h, abar, precision=F.FMM_FP32)
+    assert np.linalg.norm(x3 - x1) <= 1e-5 * np.linalg.norm(x1)
+    assert np.linalg.norm(m3 - m1) <= 1e-5 * np.linalg.norm(m1)
