@@ -30,7 +30,7 @@ HBM_PEAK = 8.0e12        # B/s
 # Algorithmic flops (FMA = 2, reciprocal square root = 1):
 FLOP_PAIR_NEWTON = 20    # d (3), r^2 (5), 1/r (1), 1/r^3 (2), m 1/r^3 (1), a -= f d (6), + 2 select
 FLOP_PAIR_SOFT = 40      # + r, two q's, two spline polynomials with h^-3, the mean
-FLOP_M2L = 250           # one cell-cell interaction, 19 coefficients
+FLOP_M2L = 300           # one cell-cell interaction: FP64 ops of the compiled M2L inner loop (FMA = 2)
 
 
 def parse():
@@ -234,6 +234,7 @@ def run_one(args, x_np, m_np, h_np, prec, census=True):
                       "kernel_ms": round(kv[1], 4)} for k, kv in kern.items() if k != dom}
         roof["other_kernels"] = others
     xc = np.array(xcom)
+    fo_ms = stages["walk"] + stages["far"] + stages["near"]
     rec = {
         "value": value, "ms_per_step": ms_step, "dtype": "f32" if prec == F.FMM_FP32 else "f64",
         "rel_err": {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
@@ -241,6 +242,8 @@ def run_one(args, x_np, m_np, h_np, prec, census=True):
         "sumF_ratio": {"first": st0["ratio"], "mean": float(np.mean(ratios)), "last": ratios[-1]},
         "com_drift": float(np.linalg.norm(xc[-1] - st0["xcom"])),
         "stages_ms": {k: round(v_, 4) for k, v_ in stages.items()},
+        "forces_only": {"value": n / (fo_ms * 1e-3) if fo_ms > 0 else None,
+                        "unit": "particle-forces/s", "stages": "walk + M2L + P2P/L2P"},
         "lists": {"far": info["n_far"], "near_leaf_pairs": info["n_near"], "p2p_pairs": pairs,
                   "p2p_softened": soft},
         "roofline": roof,
@@ -254,7 +257,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
-              "the multi-GPU sharding of this path is a design (see DESIGN.md), not built.",
+              "sharding this path over several GPUs is designed but not built.",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -294,6 +297,7 @@ def main():
         "sumF_ratio": rec["sumF_ratio"],
         "com_drift": rec["com_drift"],
         "stages_ms": rec["stages_ms"],
+        "forces_only": rec["forces_only"],
         "lists": rec["lists"],
         "roofline": rec["roofline"],
     }
