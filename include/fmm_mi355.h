@@ -143,7 +143,8 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream);
 
 /* Vector-Jacobian product of the accelerations of the last fmm_forces call
  * with respect to the positions and masses, with the tree membership and the
- * interaction lists held fixed (the moments do depend on x and m):
+ * interaction lists held fixed (the moments do depend on x and m).  Lists of
+ * the leaf <- cell walk only (FMM_ERR_STATE after a mutual walk):
  *   a_bar  device, [n][3] cotangent of a (double or float per precision);
  *   x_bar  device, [n][3] output, same precision;
  *   m_bar  device, [n] output, same precision.
@@ -187,7 +188,11 @@ fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info);
  *   far_off   int64[nodes+1], far_src int32[far entries]  (CSR over sink node ids)
  *   near_off  int64[nodes+1], near_src int32[near entries]
  *   local     double[nodes][19]: local expansions L1(3), L2(6), L3(10) of the
- *             last fmm_forces (zero where a node has no far field) */
+ *             leaves in the last FP64 fmm_forces, about their centres of mass,
+ *             with every far contribution (for the mutual walk also those
+ *             passed down from the ancestors by L2L); zero for internal nodes.
+ * Far lists are CSR over sink node ids: leaves only for the leaf <- cell walk,
+ * every node for the mutual walk; near lists have leaf sinks only. */
 fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first, int32_t *count,
                             int32_t *left, int32_t *right, int32_t *axis, double *rec,
                             int64_t *far_off, int32_t *far_src, int64_t *near_off,

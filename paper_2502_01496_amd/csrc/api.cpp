@@ -154,6 +154,13 @@ static void release(Tree *t)
     for (auto &b : t->owned)
         (void)hipFree(b.p);
     t->owned.clear();
+    for (DevBuf *b : {&t->mw.b_task, &t->mw.b_fkeys, &t->mw.b_nkeys, &t->mw.b_hist})
+        if (b->p)
+            (void)hipFree(b->p);
+    for (auto &b : t->mw.owned)
+        (void)hipFree(b.p);
+    if (t->mw.h_cnt)
+        (void)hipHostFree(t->mw.h_cnt);
     if (t->far_buf.p)
         (void)hipFree(t->far_buf.p);
     if (t->near_buf.p)
@@ -179,6 +186,10 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     // the exact narrow-stack walk.
     if (const char *e = std::getenv("FMM_MI355_WIDE_STACK"))
         t->wide_stack_limit = std::atoi(e);
+    // Test hook: small first capacities for the mutual walk's frontier and
+    // pair buffers exercise their overflow-and-retry path.
+    if (const char *e = std::getenv("FMM_MI355_MW_CAP"))
+        t->mw_init_cap = std::max<int64_t>(1, std::atoll(e));
     build_topology(n, p.leaf_size, t->topo);
     const Topology &T = t->topo;
     const int64_t nn = T.nnodes;
@@ -272,8 +283,6 @@ static fmm_status check_params(const fmm_params *p)
         return fail(FMM_ERR_INVALID, "leaf_size must lie in [1, %d]", MAX_LEAF);
     if (p->walk != FMM_WALK_PHANTOM && p->walk != FMM_WALK_MUTUAL)
         return fail(FMM_ERR_INVALID, "unknown walk policy %d", p->walk);
-    if (p->walk == FMM_WALK_MUTUAL)
-        return fail(FMM_ERR_INVALID, "the mutual walk is not available in this library build");
     if (p->precision != FMM_FP64 && p->precision != FMM_FP32)
         return fail(FMM_ERR_INVALID, "unknown precision %d", p->precision);
     if (p->reserved != 0)
@@ -349,6 +358,188 @@ static fmm_status ensure_slots(Tree &t, int64_t cap_far, int64_t cap_near)
 }
 
 static int64_t round_cap(int64_t need) { return ((need + need / 4 + 64) + 63) / 64 * 64; }
+
+// (Re)allocate a growable device buffer to at least `bytes` (contents lost).
+static fmm_status grow(DevBuf &b, size_t bytes)
+{
+    if (b.p && b.bytes >= bytes)
+        return FMM_OK;
+    if (b.p) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    HIP_TRY(hipMalloc(&b.p, std::max<size_t>(bytes, 256)));
+    b.bytes = std::max<size_t>(bytes, 256);
+    return FMM_OK;
+}
+
+static fmm_status mw_alloc(std::vector<DevBuf> &owned, void **out, size_t bytes)
+{
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, std::max<size_t>(bytes, 256)));
+    owned.push_back({p, bytes});
+    *out = p;
+    return FMM_OK;
+}
+
+// Buffers of the mutual walk for the given capacities (pairs / frontier).
+static fmm_status ensure_mutual(Tree &t, int64_t cap_task, int64_t cap_far, int64_t cap_near)
+{
+    MutualLists &M = t.mw;
+    const Topology &T = t.topo;
+    fmm_status st = FMM_OK;
+    if (!M.cnt) {
+        void *p = nullptr;
+        if ((st = mw_alloc(M.owned, &p, MW_CNT * sizeof(unsigned long long))) != FMM_OK)
+            return st;
+        M.cnt = (unsigned long long *)p;
+        if ((st = mw_alloc(M.owned, &p, 2 * (size_t)T.nnodes * sizeof(int64_t))) != FMM_OK)
+            return st;
+        M.fstart = (int64_t *)p;
+        M.fend = M.fstart + T.nnodes;
+        if ((st = mw_alloc(M.owned, &p, (size_t)T.nleaves * sizeof(int64_t))) != FMM_OK)
+            return st;
+        M.nstart = (int64_t *)p;
+        if ((st = mw_alloc(M.owned, &p, (size_t)RS_PASSES * 256 * sizeof(uint32_t))) != FMM_OK)
+            return st;
+        M.tot = (uint32_t *)p;
+        HIP_TRY(hipHostMalloc((void **)&M.h_cnt, MW_CNT * sizeof(unsigned long long),
+                              hipHostMallocDefault));
+    }
+    if (t.p.precision == FMM_FP64 && !M.Lown) {
+        void *p = nullptr;
+        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.nnodes * sizeof(double))) != FMM_OK)
+            return st;
+        M.Lown = (double *)p;
+    }
+    if (t.p.precision == FMM_FP32 && !M.Lownf) {
+        void *p = nullptr;
+        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.nnodes * sizeof(float))) != FMM_OK)
+            return st;
+        M.Lownf = (float *)p;
+    }
+    if (cap_task > M.cap_task) {
+        if ((st = grow(M.b_task, 2 * (size_t)cap_task * sizeof(int2))) != FMM_OK)
+            return st;
+        M.task[0] = (int2 *)M.b_task.p;
+        M.task[1] = M.task[0] + cap_task;
+        M.cap_task = cap_task;
+    }
+    if (cap_far > M.cap_far) {
+        if ((st = grow(M.b_fkeys, 2 * (size_t)cap_far * sizeof(uint64_t))) != FMM_OK)
+            return st;
+        M.fkeys[0] = (uint64_t *)M.b_fkeys.p;
+        M.fkeys[1] = M.fkeys[0] + cap_far;
+        M.cap_far = cap_far;
+    }
+    if (cap_near > M.cap_near) {
+        if ((st = grow(M.b_nkeys, 2 * (size_t)cap_near * sizeof(uint64_t))) != FMM_OK)
+            return st;
+        M.nkeys[0] = (uint64_t *)M.b_nkeys.p;
+        M.nkeys[1] = M.nkeys[0] + cap_near;
+        M.cap_near = cap_near;
+    }
+    const int64_t tiles = (std::max(M.cap_far, M.cap_near) + RS_TILE - 1) / RS_TILE;
+    if ((st = grow(M.b_hist, (size_t)256 * tiles * sizeof(uint32_t))) != FMM_OK)
+        return st;
+    M.hist = (uint32_t *)M.b_hist.p;
+    return FMM_OK;
+}
+
+static fmm_status bad_input(uint32_t errbits)
+{
+    return fail(FMM_ERR_INVALID, "bad input data:%s%s%s",
+                (errbits & 1) ? " non-finite positions" : "",
+                (errbits & 2) ? " masses not positive and finite" : "",
+                (errbits & 4) ? " smoothing lengths not positive and finite" : "");
+}
+
+// fmm_forces for the mutual walk: walk (one readback of the pair counts,
+// buffers grown and the walk redone if they overflowed), sort into lists,
+// then M2L + L2L and the near field.
+static fmm_status forces_mutual(Tree &t, void *a, bool walk, hipStream_t s)
+{
+    MutualLists &M = t.mw;
+    const Topology &T = t.topo;
+    if (walk) {
+        // first capacities: above the frontier and pair counts of theta = 0.5
+        // with 58-neighbour smoothing lengths (grown on overflow, then kept)
+        const int64_t c0 = t.mw_init_cap;
+        fmm_status st = ensure_mutual(t, c0 ? c0 : 48 * (int64_t)T.nnodes + 4096,
+                                      c0 ? c0 : 96 * (int64_t)T.nnodes + 4096,
+                                      c0 ? c0 : 192 * (int64_t)T.nleaves + 4096);
+        if (st != FMM_OK)
+            return st;
+        if (!t.far_buf.p && (st = ensure_slots(t, 1, 128)) != FMM_OK)
+            return st;
+        const int nit = mutual_iterations(t);
+        if (MW_IT + nit + 1 > MW_CNT)
+            return fail(FMM_ERR_INVALID, "tree too deep for the mutual walk (%d levels)", T.depth);
+        bool done = false;
+        for (int attempt = 0; attempt < 8 && !done; ++attempt) {
+            StageTimer tm(t, s, 2);
+            HIP_TRY(launch_mutual_walk(t, s));
+            HIP_TRY(hipMemcpyAsync(M.h_cnt, M.cnt, (MW_IT + nit + 1) * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(t.h_flags + 4, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            const uint32_t errbits = (uint32_t)t.h_flags[4];
+            if (errbits) {
+                t.has_lists = false;
+                return bad_input(errbits);
+            }
+            const uint64_t flags = M.h_cnt[MW_FLAGS];
+            const int64_t nf = (int64_t)M.h_cnt[MW_NFAR], nn = (int64_t)M.h_cnt[MW_NNEAR];
+            if (flags) {
+                int64_t mt = 0;
+                for (int k = 0; k <= nit; ++k)
+                    mt = std::max<int64_t>(mt, (int64_t)M.h_cnt[MW_IT + k]);
+                st = ensure_mutual(t, (flags & 1) ? std::max(2 * M.cap_task, round_cap(mt)) : 0,
+                                   (flags & 2) ? round_cap(nf) : 0,
+                                   (flags & 4) ? round_cap(nn) : 0);
+                if (st != FMM_OK)
+                    return st;
+                continue;
+            }
+            if (M.h_cnt[MW_IT + nit] != 0)
+                return fail(FMM_ERR_CAPACITY, "mutual walk did not finish in %d levels", nit);
+            const int64_t mx = (int64_t)M.h_cnt[MW_MAXNEAR];
+            if (mx > t.cap_near && (st = ensure_slots(t, t.cap_far, round_cap(mx))) != FMM_OK)
+                return st;
+            HIP_TRY(launch_mutual_lists(t, nf, nn, s));
+            tm.done();
+            M.n_far = nf;
+            M.n_near = nn;
+            done = true;
+        }
+        if (!done)
+            return fail(FMM_ERR_CAPACITY, "mutual walk buffers did not fit after resizing");
+        t.has_lists = true;
+        t.has_transposed = false;
+        t.lists_policy = FMM_WALK_MUTUAL;
+        t.nsinks = T.nnodes;
+        t.n_far = M.n_far;
+        t.n_near = M.n_near;
+    } else {
+        fmm_status st = ensure_mutual(t, 0, 0, 0);  // Lown of the current precision
+        if (st != FMM_OK)
+            return st;
+    }
+    {
+        StageTimer tm(t, s, 3);
+        HIP_TRY(launch_far_mutual(t, s));
+        tm.done();
+    }
+    {
+        StageTimer tm(t, s, 4);
+        HIP_TRY(launch_near(t, a, s));
+        tm.done();
+    }
+    t.has_forces = true;
+    return FMM_OK;
+}
 
 static std::mutex g_scratch_mu;
 static std::map<int, std::pair<double *, double *>> g_scratch;
@@ -461,6 +652,8 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
         return fail(FMM_ERR_STATE, "fmm_moments must run before fmm_forces");
     hipStream_t s = (hipStream_t)stream;
     const bool walk = !t.has_lists || (flags & FMM_REWALK) || t.lists_policy != t.p.walk;
+    if (t.p.walk == FMM_WALK_MUTUAL)
+        return forces_mutual(t, a, walk, s);
     if (walk && !t.far_buf.p) {
         fmm_status st = ensure_slots(t, 512, 128);
         if (st != FMM_OK)
@@ -492,10 +685,7 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
         uint32_t errbits = (uint32_t)t.h_flags[4];
         if (errbits) {
             t.has_lists = false;
-            return fail(FMM_ERR_INVALID, "bad input data:%s%s%s",
-                        (errbits & 1) ? " non-finite positions" : "",
-                        (errbits & 2) ? " masses not positive and finite" : "",
-                        (errbits & 4) ? " smoothing lengths not positive and finite" : "");
+            return bad_input(errbits);
         }
         if (t.h_flags[2]) {
             // some leaves overflowed the wide walk's stack: redo those exactly
@@ -541,6 +731,8 @@ fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *
         return fail(FMM_ERR_STATE, "fmm_forces must run on this tree state before the VJP");
     if (!t.has_lists)
         return fail(FMM_ERR_STATE, "no interaction lists: call fmm_forces first");
+    if (t.lists_policy != FMM_WALK_PHANTOM)
+        return fail(FMM_ERR_STATE, "the VJP is available for the leaf <- cell walk only");
     hipStream_t s = (hipStream_t)stream;
     StageTimer tm(t, s, 5);
     hipError_t e = launch_vjp(t, a_bar, x_bar, m_bar, s);
@@ -599,7 +791,7 @@ fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info)
     if (!info)
         return fail(FMM_ERR_INVALID, "info must not be NULL");
     Tree &t = *const_cast<Tree *>(reinterpret_cast<const Tree *>(tree));
-    if (t.has_lists && t.n_far < 0) {
+    if (t.has_lists && t.n_far < 0 && t.lists_policy == FMM_WALK_PHANTOM) {
         std::vector<int32_t> cf(t.nsinks), cn(t.nsinks);
         HIP_TRY(hipDeviceSynchronize());
         HIP_TRY(hipMemcpy(cf.data(), t.far_cnt, cf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -667,9 +859,10 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
     if (far_off || far_src || near_off || near_src) {
         if (!t.has_lists)
             return fail(FMM_ERR_STATE, "no interaction lists to export");
-        const int ns = t.nsinks;
+        const int ns = T.nleaves;
         std::vector<int32_t> cf(ns), cn(ns);
-        HIP_TRY(hipMemcpy(cf.data(), t.far_cnt, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (t.lists_policy == FMM_WALK_PHANTOM)
+            HIP_TRY(hipMemcpy(cf.data(), t.far_cnt, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(cn.data(), t.near_cnt, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
         // sinks are leaves: node-indexed CSR, entries in emission order
         auto export_lists = [&](const std::vector<int32_t> &cnt, const int32_t *dev, int64_t cap,
@@ -694,9 +887,33 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
             }
             return FMM_OK;
         };
-        fmm_status st = export_lists(cf, t.far_src, t.cap_far, far_off, far_src);
-        if (st != FMM_OK)
-            return st;
+        fmm_status st = FMM_OK;
+        if (t.lists_policy == FMM_WALK_PHANTOM) {
+            st = export_lists(cf, t.far_src, t.cap_far, far_off, far_src);
+            if (st != FMM_OK)
+                return st;
+        } else if (far_off || far_src) {
+            // mutual walk: sorted (sink, source) keys with a CSR range per sink cell
+            const MutualLists &M = t.mw;
+            std::vector<int64_t> se(2 * nn);
+            std::vector<uint64_t> keys(M.n_far);
+            HIP_TRY(hipMemcpy(se.data(), M.fstart, se.size() * sizeof(int64_t),
+                              hipMemcpyDeviceToHost));
+            if (M.n_far)
+                HIP_TRY(hipMemcpy(keys.data(), M.far_sorted, keys.size() * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost));
+            const uint64_t mask = (1ull << mutual_key_bits(t)) - 1ull;
+            int64_t o = 0;
+            if (far_off)
+                far_off[0] = 0;
+            for (int64_t v = 0; v < nn; ++v) {
+                for (int64_t k = se[v]; k < se[nn + v]; ++k, ++o)
+                    if (far_src)
+                        far_src[o] = (int32_t)(keys[k] & mask);
+                if (far_off)
+                    far_off[v + 1] = o;
+            }
+        }
         st = export_lists(cn, t.near_src, t.cap_near, near_off, near_src);
         if (st != FMM_OK)
             return st;

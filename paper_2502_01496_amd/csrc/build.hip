@@ -255,7 +255,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         wrun[i][t] = 0u;
     __syncthreads();
     const uint64_t *k = kin + (int64_t)b * n;
-    const uint32_t *v = vin + (int64_t)b * n;
+    const uint32_t *v = vin ? vin + (int64_t)b * n : nullptr;
     int64_t wbase = (int64_t)blk * RS_TILE + (int64_t)w * (RS_TILE / 4);
     uint32_t rank[RS_ROUNDS];
     uint32_t dig[RS_ROUNDS];
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     }
     __syncthreads();
     uint64_t *ko = kout + (int64_t)b * n;
-    uint32_t *vo = vout + (int64_t)b * n;
+    uint32_t *vo = vin ? vout + (int64_t)b * n : nullptr;
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         int64_t i = wbase + r * 64 + lane;
@@ -294,12 +294,14 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
             uint32_t d = dig[r];
             int64_t pos = (int64_t)gofs[d] + wrun[w][d] + rank[r];
             ko[pos] = k[i];
-            vo[pos] = v[i];
+            if (v)
+                vo[pos] = v[i];
         }
     }
 }
 
-// Sort B arrays of n (key, value) pairs by the low 8 * passes key bits.  The
+// Sort B arrays of n (key, value) pairs by the low 8 * passes key bits
+// (v0 == v1 == nullptr: keys only).  The
 // result ends in (k0, v0) after an even number of passes, in (k1, v1) after
 // an odd one.  hist needs B * 256 * ceil(n / RS_TILE) words, tot
 // passes * B * 256.

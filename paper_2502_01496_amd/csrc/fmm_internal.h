@@ -74,6 +74,31 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Mutual walk state: pair frontier, far / near pair buffers (sorted by
+// (sink, source) keys), CSR ranges of the far lists, and the counters
+//   cnt[MW_NFAR], cnt[MW_NNEAR]  pairs appended,
+//   cnt[MW_FLAGS]                overflow bits (1 frontier, 2 far, 4 near),
+//   cnt[MW_MAXNEAR]              largest near count of a leaf,
+//   cnt[MW_IT + k]               size of the frontier at recursion level k.
+constexpr int MW_NFAR = 0, MW_NNEAR = 1, MW_FLAGS = 2, MW_MAXNEAR = 3, MW_IT = 8, MW_CNT = 160;
+struct MutualLists {
+    int2 *task[2] = {nullptr, nullptr};
+    uint64_t *fkeys[2] = {nullptr, nullptr};
+    uint64_t *nkeys[2] = {nullptr, nullptr};
+    int64_t cap_task = 0, cap_far = 0, cap_near = 0;
+    const uint64_t *far_sorted = nullptr;  // fkeys[0] or fkeys[1] after the sort
+    int64_t *fstart = nullptr, *fend = nullptr;  // per node (fend = fstart + nnodes)
+    int64_t *nstart = nullptr;                   // per leaf
+    uint32_t *hist = nullptr, *tot = nullptr;
+    unsigned long long *cnt = nullptr;           // device, MW_CNT
+    unsigned long long *h_cnt = nullptr;         // pinned host mirror
+    double *Lown = nullptr;                      // NLOC per node: M2L sums only
+    float *Lownf = nullptr;
+    DevBuf b_task, b_fkeys, b_nkeys, b_hist;
+    std::vector<DevBuf> owned;                   // fixed-size parts
+    int64_t n_far = 0, n_near = 0;
+};
+
 struct Tree {
     uint32_t magic = 0;
     fmm_params p{};
@@ -154,6 +179,9 @@ struct Tree {
     double *nadj = nullptr;        // 16 per node: cbar_sink[3], cbar_src[3], Mbar, Qbar[6]
     int64_t *h_pairs = nullptr;    // pinned: far, near pair totals
 
+    MutualLists mw;
+    int64_t mw_init_cap = 0;        // test hook: FMM_MI355_MW_CAP sets small first capacities
+
     bool has_tree = false, has_moments = false, has_lists = false, has_forces = false;
     int lists_policy = -1;
 
@@ -179,6 +207,11 @@ hipError_t launch_near(Tree &t, void *a, hipStream_t s);
 hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,
                         int a_fp32, int64_t n, double *red, double *h_out, hipStream_t s);
 hipError_t launch_far_f64(Tree &t, hipStream_t s);
+int mutual_key_bits(const Tree &t);
+int mutual_iterations(const Tree &t);
+hipError_t launch_mutual_walk(Tree &t, hipStream_t s);
+hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream_t s);
+hipError_t launch_far_mutual(Tree &t, hipStream_t s);
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s);
 void release_vjp(Tree &t);
 hipError_t launch_kick_drift(double *x, double *v, const void *a, int a_fp32, int64_t n,

@@ -569,6 +569,160 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     }
 }
 
+// ---------------------------------------------------------------- mutual walk
+// Far field of the mutual walk: M2L into every sink cell over its CSR range
+// of the sorted (sink, source) keys, then L2L down to the leaves.
+template <typename T>
+__device__ __forceinline__ void m2l_node_src(const double *recA, const double *recQ,
+                                             const float *recF, int b, double c0, double c1,
+                                             double c2, T *L);
+template <>
+__device__ __forceinline__ void m2l_node_src<double>(const double *recA, const double *recQ,
+                                                     const float *, int b, double c0, double c1,
+                                                     double c2, double *L)
+{
+    const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
+    const double *qb = recQ + (int64_t)NREC * b;
+    const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
+                  q45 = *(const double2 *)(qb + 4);
+    const double Q[6] = {q01.x, q01.y, q23.x, q23.y, q45.x, q45.y};
+    m2l_acc<double>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
+}
+template <>
+__device__ __forceinline__ void m2l_node_src<float>(const double *recA, const double *,
+                                                    const float *recF, int b, double c0,
+                                                    double c1, double c2, float *L)
+{
+    const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
+    const float4 f0 = *(const float4 *)(recF + (int64_t)NREC * b);
+    const float4 f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
+    const float Q[6] = {f0.y, f0.z, f0.w, f1.x, f1.y, f1.z};
+    m2l_acc<float>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
+}
+
+// 16 lanes per sink cell (all cells; zero where the range is empty).
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_node(const double *__restrict__ recA,
+                                                  const double *__restrict__ recQ,
+                                                  const float *__restrict__ recF, int nnodes,
+                                                  const int64_t *__restrict__ fstart,
+                                                  const int64_t *__restrict__ fend,
+                                                  const uint64_t *__restrict__ keys,
+                                                  uint64_t mask, T *Lown)
+{
+    const int v = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    const bool valid = v < nnodes;
+    const double *rv = recA + (int64_t)NREC * (valid ? v : 0);
+    const double c0 = rv[0], c1 = rv[1], c2 = rv[2];
+    T L[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        L[k] = T(0);
+    const int64_t e0 = valid ? fstart[v] : 0, e1 = valid ? fend[v] : 0;
+    for (int64_t k = e0 + sub; k < e1; k += 16)
+        m2l_node_src<T>(recA, recQ, recF, (int)(keys[k] & mask), c0, c1, c2, L);
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            L[k] += __shfl_xor(L[k], off);
+    if (valid && sub == 0) {
+        T *o = Lown + (int64_t)NLOC * v;
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            o[k] = L[k];
+        o[19] = T(0);
+    }
+}
+
+// L2L: re-expansion of the quadratic field about a point shifted by d (exact):
+//   L1' = L1 + L2 d + 1/2 L3 : d d,  L2' = L2 + L3 d,  L3' = L3.
+template <typename T>
+__device__ __forceinline__ void l2l_shift(T *L, T d0, T d1, T d2)
+{
+    T a0, a1, a2;
+    l2p<T>(L, d0, d1, d2, a0, a1, a2);
+    const T s3 = L[3] + L[9] * d0 + L[10] * d1 + L[11] * d2;
+    const T s4 = L[4] + L[10] * d0 + L[12] * d1 + L[13] * d2;
+    const T s5 = L[5] + L[11] * d0 + L[13] * d1 + L[14] * d2;
+    const T s6 = L[6] + L[12] * d0 + L[15] * d1 + L[16] * d2;
+    const T s7 = L[7] + L[13] * d0 + L[16] * d1 + L[17] * d2;
+    const T s8 = L[8] + L[14] * d0 + L[17] * d1 + L[18] * d2;
+    L[0] = a0;
+    L[1] = a1;
+    L[2] = a2;
+    L[3] = s3;
+    L[4] = s4;
+    L[5] = s5;
+    L[6] = s6;
+    L[7] = s7;
+    L[8] = s8;
+}
+
+// One thread per leaf: descend from the root (pre-order ids: the leaf lies in
+// the left subtree of v iff its id is below right[v]), at each step shifting
+// the parent's total expansion to the child's centre of mass and adding the
+// child's own M2L sum.  Only the leaves' totals are needed (for L2P).
+template <typename T>
+__global__ __launch_bounds__(256) void k_l2l_chain(const double *__restrict__ recA,
+                                                   const int32_t *__restrict__ left,
+                                                   const int32_t *__restrict__ right,
+                                                   const int32_t *__restrict__ leaf_node,
+                                                   int nleaves, const T *__restrict__ Lown, T *Lout)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= nleaves)
+        return;
+    const int u = leaf_node[g];
+    T L[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        L[k] = Lown[k];
+    int v = 0;
+    double p0 = recA[0], p1 = recA[1], p2 = recA[2];
+    while (v != u) {
+        const int ch = u < right[v] ? left[v] : right[v];
+        const double *rc = recA + (int64_t)NREC * ch;
+        const double q0 = rc[0], q1 = rc[1], q2 = rc[2];
+        l2l_shift<T>(L, (T)(q0 - p0), (T)(q1 - p1), (T)(q2 - p2));
+        const T *lo = Lown + (int64_t)NLOC * ch;
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            L[k] = lo[k] + L[k];
+        v = ch;
+        p0 = q0;
+        p1 = q1;
+        p2 = q2;
+    }
+    T *o = Lout + (int64_t)NLOC * u;
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        o[k] = L[k];
+    o[19] = T(0);
+}
+
+hipError_t launch_far_mutual(Tree &t, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const MutualLists &M = t.mw;
+    const uint64_t mask = (1ull << mutual_key_bits(t)) - 1ull;
+    const int gm = (int)(((int64_t)T.nnodes * 16 + 255) / 256);
+    const int gl = (T.nleaves + 255) / 256;
+    if (t.p.precision == FMM_FP64) {
+        k_m2l_node<double><<<gm, 256, 0, s>>>(t.recA, t.recQ, t.recF, T.nnodes, M.fstart, M.fend,
+                                              M.far_sorted, mask, M.Lown);
+        k_l2l_chain<double><<<gl, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, T.nleaves,
+                                               M.Lown, t.L);
+    } else {
+        k_m2l_node<float><<<gm, 256, 0, s>>>(t.recA, t.recQ, t.recF, T.nnodes, M.fstart, M.fend,
+                                             M.far_sorted, mask, M.Lownf);
+        k_l2l_chain<float><<<gl, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, T.nleaves,
+                                              M.Lownf, t.Lf);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_far(Tree &t, hipStream_t s)
 {
     const Topology &T = t.topo;

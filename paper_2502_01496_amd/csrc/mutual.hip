@@ -1,0 +1,315 @@
+// Mutual (symmetric) dual-tree walk on gfx950.
+//
+// Sec. 7 of the paper traces the momentum error of the leaf <- cell walk to
+// interactions that are formed in one direction only, and names symmetric
+// opening criteria as the remedy.  Here a pair of cells (A, B) is well
+// separated iff
+//   (s_A + s_B)^2 <= theta^2 r^2   and   r^2 >= (s_A + s_B + R_kern max(h_A, h_B))^2
+// (the second condition is the negation of eq. (5)), with r = |c_A - c_B|.
+// Starting from the pairs (left child, right child) of every internal cell,
+// a pair that is well separated interacts through M2L in both directions;
+// a pair of leaves that is not goes to the near field in both directions;
+// otherwise the cell with the larger s (A on ties; never a leaf) is split and
+// both halves are paired with the other cell.  Every leaf is also near to
+// itself.  Every particle pair is then covered exactly once, by a far pair
+// or a near pair of cells.
+//
+// GPU form: breadth-first expansion of the pair frontier, one launch per
+// level of the recursion with a fixed grid (counts stay on the device), and
+// wavefront-aggregated appends to the next frontier and to the far / near
+// pair buffers.  The pairs are then sorted by the key (sink, source), which
+// makes the lists independent of the order of the appends: far lists become
+// CSR ranges of sink cells, near lists fill the per-leaf slots read by the
+// near-field kernel.
+//
+// Compiled with -ffp-contract=off so the criterion is evaluated with exactly
+// the operations of its definition.
+#include "fmm_internal.h"
+
+namespace fmm {
+
+constexpr int MW_GRID = 1024;  // workgroups of a frontier step (grid-stride)
+
+__device__ __forceinline__ bool separated(const double *ra, const double *rb, double theta2,
+                                          double r_kern)
+{
+    const double dx = ra[0] - rb[0], dy = ra[1] - rb[1], dz = ra[2] - rb[2];
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    const double sa = ra[4], sb = rb[4], ha = ra[5], hb = rb[5];
+    const double ss = sa + sb;
+    const bool ok4 = theta2 * r2 >= ss * ss;
+    const double tt = ss + r_kern * (ha > hb ? ha : hb);
+    const bool ok5 = r2 >= tt * tt;
+    return ok4 && ok5;
+}
+
+// Reserve cnt slots per active lane of the wavefront (aggregated: one atomic
+// per wavefront); returns the lane's first slot.
+__device__ __forceinline__ uint64_t wave_append(unsigned long long *ctr, bool act, int per)
+{
+    const uint64_t m = __ballot(act);
+    if (m == 0ull)
+        return 0;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader)
+        base = atomicAdd(ctr, (unsigned long long)(per * __popcll(m)));
+    base = __shfl(base, leader);
+    return base + (uint64_t)(per * __popcll(m & lanemask_lt()));
+}
+
+__global__ void k_mw_zero(unsigned long long *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = 0ull;
+}
+
+// Seed: the (left, right) pair of every internal cell, and the self pair of
+// every leaf (near count 1).
+__global__ __launch_bounds__(256) void k_mw_init(
+    const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+    const int32_t *__restrict__ node_leaf, int nnodes, int bits, int2 *tout, int64_t cap_task,
+    uint64_t *nkeys, int64_t cap_n, int32_t *near_cnt, unsigned long long *cnt)
+{
+    const int v = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = v < nnodes;
+    const int lv = valid ? left[v] : -1;
+    const bool internal = valid && lv >= 0;
+    const bool leaf = valid && lv < 0;
+    const uint64_t kt = wave_append(&cnt[MW_IT], internal, 1);
+    if (internal) {
+        if ((int64_t)kt < cap_task)
+            tout[kt] = make_int2(lv, right[v]);
+        else
+            atomicOr(&cnt[MW_FLAGS], 1ull);
+    }
+    const uint64_t kn = wave_append(&cnt[MW_NNEAR], leaf, 1);
+    if (leaf) {
+        const int lf = node_leaf[v];
+        near_cnt[lf] = 1;
+        if ((int64_t)kn < cap_n)
+            nkeys[kn] = ((uint64_t)lf << bits) | (uint64_t)v;
+        else
+            atomicOr(&cnt[MW_FLAGS], 4ull);
+    }
+}
+
+// One level of the pair recursion: frontier cnt[MW_IT + it] -> cnt[MW_IT + it + 1].
+__global__ __launch_bounds__(256) void k_mw_step(
+    const int2 *__restrict__ tin, int2 *tout, int it, int64_t cap_task,
+    const double *__restrict__ recA, const int32_t *__restrict__ left,
+    const int32_t *__restrict__ right, const int32_t *__restrict__ node_leaf, double theta2,
+    double r_kern, int bits, uint64_t *fkeys, int64_t cap_f, uint64_t *nkeys, int64_t cap_n,
+    int32_t *near_cnt, unsigned long long *cnt)
+{
+    const int64_t nin = min((int64_t)cnt[MW_IT + it], cap_task);
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nin;
+         base += stride) {
+        const int64_t i = base + lane;
+        const bool valid = i < nin;
+        int a = 0, b = 0;
+        bool far = false, nea = false, split = false;
+        int c0 = 0, c1 = 0, o = 0;
+        bool o_first = false;
+        if (valid) {
+            const int2 tk = tin[i];
+            a = tk.x;
+            b = tk.y;
+            const double *ra = recA + (int64_t)NREC * a;
+            const double *rb = recA + (int64_t)NREC * b;
+            if (separated(ra, rb, theta2, r_kern)) {
+                far = true;
+            } else {
+                const int la = left[a], lb = left[b];
+                if (la < 0 && lb < 0) {
+                    nea = true;
+                } else {
+                    split = true;
+                    const bool split_a = lb < 0 || (la >= 0 && ra[4] >= rb[4]);
+                    if (split_a) {
+                        c0 = la;
+                        c1 = right[a];
+                        o = b;
+                        o_first = false;
+                    } else {
+                        c0 = lb;
+                        c1 = right[b];
+                        o = a;
+                        o_first = true;
+                    }
+                }
+            }
+        }
+        const uint64_t kf = wave_append(&cnt[MW_NFAR], far, 2);
+        // Each reserved slot below the capacity is written, so a consumer that
+        // clamps a count to the capacity reads written entries only.
+        if (far) {
+            if ((int64_t)kf < cap_f)
+                fkeys[kf] = ((uint64_t)a << bits) | (uint64_t)b;
+            if ((int64_t)kf + 1 < cap_f)
+                fkeys[kf + 1] = ((uint64_t)b << bits) | (uint64_t)a;
+            else
+                atomicOr(&cnt[MW_FLAGS], 2ull);
+        }
+        const uint64_t kn = wave_append(&cnt[MW_NNEAR], nea, 2);
+        if (nea) {
+            const int fa = node_leaf[a], fb = node_leaf[b];
+            atomicAdd(&near_cnt[fa], 1);
+            atomicAdd(&near_cnt[fb], 1);
+            if ((int64_t)kn < cap_n)
+                nkeys[kn] = ((uint64_t)fa << bits) | (uint64_t)b;
+            if ((int64_t)kn + 1 < cap_n)
+                nkeys[kn + 1] = ((uint64_t)fb << bits) | (uint64_t)a;
+            else
+                atomicOr(&cnt[MW_FLAGS], 4ull);
+        }
+        const uint64_t kt = wave_append(&cnt[MW_IT + it + 1], split, 2);
+        if (split) {
+            if ((int64_t)kt < cap_task)
+                tout[kt] = o_first ? make_int2(o, c0) : make_int2(c0, o);
+            if ((int64_t)kt + 1 < cap_task)
+                tout[kt + 1] = o_first ? make_int2(o, c1) : make_int2(c1, o);
+            else
+                atomicOr(&cnt[MW_FLAGS], 1ull);
+        }
+    }
+}
+
+// Far pairs sorted by (sink, source): CSR range [fstart, fend) per sink cell.
+// fstart / fend must be zero on entry.
+__global__ __launch_bounds__(256) void k_mw_far_bounds(const uint64_t *__restrict__ keys,
+                                                       int64_t n, int bits, int64_t *fstart,
+                                                       int64_t *fend)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    const uint64_t s = keys[p] >> bits;
+    if (p == 0 || (keys[p - 1] >> bits) != s)
+        fstart[s] = p;
+    if (p == n - 1 || (keys[p + 1] >> bits) != s)
+        fend[s] = p + 1;
+}
+
+__global__ __launch_bounds__(256) void k_mw_fill64(int64_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+
+// Near pairs sorted by (sink leaf, source): first position of each sink leaf
+// (every leaf has its self pair, so each one is present).
+__global__ __launch_bounds__(256) void k_mw_near_start(const uint64_t *__restrict__ keys,
+                                                       int64_t n, int bits, int64_t *nstart)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    const uint64_t s = keys[p] >> bits;
+    if (p == 0 || (keys[p - 1] >> bits) != s)
+        nstart[s] = p;
+}
+
+// ... then each pair goes to slot (p - start) of its sink leaf.
+__global__ __launch_bounds__(256) void k_mw_near_scatter(const uint64_t *__restrict__ keys,
+                                                         int64_t n, int bits,
+                                                         const int64_t *__restrict__ nstart,
+                                                         int32_t *near_src, int64_t cap_near)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    const uint64_t key = keys[p];
+    const uint64_t s = key >> bits;
+    const int64_t k = p - nstart[s];
+    if (k < cap_near)
+        near_src[(int64_t)s * cap_near + k] = (int32_t)(key & ((1ull << bits) - 1ull));
+}
+
+// Largest near count over the leaves -> cnt[MW_MAXNEAR] (one workgroup).
+__global__ __launch_bounds__(1024) void k_mw_near_max(const int32_t *__restrict__ near_cnt, int n,
+                                                      unsigned long long *cnt)
+{
+    __shared__ int32_t sh[16];
+    int m = 0;
+    for (int i = threadIdx.x; i < n; i += 1024)
+        m = max(m, near_cnt[i]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        m = max(m, __shfl_xor(m, off));
+    if (lane_id() == 0)
+        sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 16; ++i)
+            m = max(m, sh[i]);
+        cnt[MW_MAXNEAR] = (unsigned long long)m;
+    }
+}
+
+static int bit_width(int64_t v)
+{
+    int b = 1;
+    while (b < 62 && (int64_t(1) << b) < v)
+        ++b;
+    return b;
+}
+
+int mutual_key_bits(const Tree &t) { return bit_width(t.topo.nnodes); }
+
+int mutual_iterations(const Tree &t) { return 2 * t.topo.depth + 2; }
+
+hipError_t launch_mutual_walk(Tree &t, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const MutualLists &M = t.mw;
+    const int bits = mutual_key_bits(t);
+    const int nit = mutual_iterations(t);
+    const double theta2 = t.p.theta * t.p.theta;
+    k_mw_zero<<<1, 256, 0, s>>>(M.cnt, MW_IT + nit + 1);
+    k_mw_init<<<(T.nnodes + 255) / 256, 256, 0, s>>>(t.left, t.right, t.node_leaf, T.nnodes, bits,
+                                                     M.task[0], M.cap_task, M.nkeys[0],
+                                                     M.cap_near, t.near_cnt, M.cnt);
+    for (int it = 0; it < nit; ++it)
+        k_mw_step<<<MW_GRID, 256, 0, s>>>(M.task[it & 1], M.task[(it + 1) & 1], it, M.cap_task,
+                                          t.recA, t.left, t.right, t.node_leaf, theta2,
+                                          t.p.r_kern, bits, M.fkeys[0], M.cap_far, M.nkeys[0],
+                                          M.cap_near, t.near_cnt, M.cnt);
+    k_mw_near_max<<<1, 1024, 0, s>>>(t.near_cnt, T.nleaves, M.cnt);
+    return hipGetLastError();
+}
+
+// Sort the pairs and lay out the lists (n_far / n_near: the counts read back
+// after the walk; the caller checked that they fit the buffers).
+hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    MutualLists &M = t.mw;
+    const int bits = mutual_key_bits(t);
+    const int pf = (2 * bits + 7) / 8;
+    const int pn = (bit_width(T.nleaves) + bits + 7) / 8;
+    hipError_t e = radix_sort_u64(M.fkeys[0], nullptr, M.fkeys[1], nullptr, n_far, 1, pf,
+                                  M.hist, M.tot, s);
+    if (e != hipSuccess)
+        return e;
+    M.far_sorted = (pf & 1) ? M.fkeys[1] : M.fkeys[0];
+    e = radix_sort_u64(M.nkeys[0], nullptr, M.nkeys[1], nullptr, n_near, 1, pn, M.hist, M.tot, s);
+    if (e != hipSuccess)
+        return e;
+    const uint64_t *ns = (pn & 1) ? M.nkeys[1] : M.nkeys[0];
+    k_mw_fill64<<<256, 256, 0, s>>>(M.fstart, 2 * (int64_t)T.nnodes);
+    if (n_far > 0)
+        k_mw_far_bounds<<<(int)((n_far + 255) / 256), 256, 0, s>>>(M.far_sorted, n_far, bits,
+                                                                   M.fstart, M.fend);
+    if (n_near > 0) {
+        const int g = (int)((n_near + 255) / 256);
+        k_mw_near_start<<<g, 256, 0, s>>>(ns, n_near, bits, M.nstart);
+        k_mw_near_scatter<<<g, 256, 0, s>>>(ns, n_near, bits, M.nstart, t.near_src, t.cap_near);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fmm

@@ -15,12 +15,13 @@ def to_dev(*arrs):
     return [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in arrs]
 
 
-def gpu_run(x, m, h, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, export=True, local=False):
+def gpu_run(x, m, h, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, export=True, local=False,
+            walk=F.FMM_WALK_PHANTOM):
     """build -> moments -> forces on the GPU; returns (a, export dict, info)."""
     import torch
 
     X, Mt, H = to_dev(x, m, h)
-    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision)
+    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision, walk=walk)
     t = F.fmm_build_tree(X, p)
     try:
         F.fmm_moments(t, X, Mt, H)
