@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--no-census", action="store_true")
     ap.add_argument("--single-precision", action="store_true",
                     help="time only --precision (default: both FP64 and FP32)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (the known-size "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--mutual-steps", type=int, default=5,
+                    help="KDK steps of the mutual-walk contrast (FP64; 0 = skip)")
     return ap.parse_args()
 
 
@@ -144,8 +149,8 @@ def cpu_baseline(x, m, h, theta):
                       f"same {len(m)}-particle workload, serial FP64 C oracle, {dt:.1f} s"}
 
 
-def run_one(args, x_np, m_np, h_np, prec, census=True):
-    """Timed KDK steps at one precision; returns the per-precision record."""
+def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
+    """Timed KDK steps at one precision and walk policy; returns its record."""
     import numpy as np
     import torch
 
@@ -158,7 +163,8 @@ def run_one(args, x_np, m_np, h_np, prec, census=True):
     h = torch.from_numpy(h_np).to(dev)
     v = torch.zeros_like(x)
     adt = torch.float32 if prec == F.FMM_FP32 else torch.float64
-    g = F.GravityFMM(theta=args.theta, precision=prec)
+    g = F.GravityFMM(theta=args.theta, precision=prec, walk=walk)
+    steps = args.steps if steps is None else steps
     a = torch.empty((n, 3), dtype=adt, device=dev)
     dt = args.dt
 
@@ -182,7 +188,7 @@ def run_one(args, x_np, m_np, h_np, prec, census=True):
     ratios, xcom = [], []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         st = step()
         ratios.append(st["ratio"])
         xcom.append(st["xcom"])
@@ -190,10 +196,10 @@ def run_one(args, x_np, m_np, h_np, prec, census=True):
     elapsed = time.perf_counter() - t1
     stages = F.fmm_stage_times(g.tree)
     F.fmm_set_timing(g.tree, False)
-    ms_step = 1e3 * elapsed / args.steps
-    value = n * args.steps / elapsed
-    tag = "fp32" if prec == F.FMM_FP32 else "fp64"
-    log(f"[bench {tag}] {args.steps} steps in {elapsed:.3f}s -> {ms_step:.3f} ms/step, "
+    ms_step = 1e3 * elapsed / steps
+    value = n * steps / elapsed
+    tag = ("fp32" if prec == F.FMM_FP32 else "fp64") + ("/mutual" if walk else "")
+    log(f"[bench {tag}] {steps} steps in {elapsed:.3f}s -> {ms_step:.3f} ms/step, "
         f"{value:.4e} particle-forces/s; stages (ms/call) {stages}")
 
     info = F.fmm_tree_info(g.tree)
@@ -225,7 +231,8 @@ def run_one(args, x_np, m_np, h_np, prec, census=True):
     roof = None
     if dom:
         achieved = kern[dom][0] / 1e12
-        ktag = {"p2p": "k_p2p_src", "m2l": "k_m2l_leaf"}[dom] + "_" + ("f32" if prec else "f64")
+        ktag = {"p2p": "k_p2p_src", "m2l": "k_m2l_node" if walk else "k_m2l_leaf"}[dom] + \
+            "_" + ("f32" if prec else "f64")
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
                 "traffic": profile_traffic(ktag), "kernel": ktag,
@@ -252,8 +259,24 @@ def run_one(args, x_np, m_np, h_np, prec, census=True):
     return rec
 
 
+def copy_calibration(mib):
+    """A plain copy of mib MiB (reads and writes mib MiB each time)."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {mib} MiB")
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
@@ -303,6 +326,13 @@ def main():
     }
     if other is not None:
         out["fp32" if main_prec == F.FMM_FP64 else "fp64"] = other
+    if args.mutual_steps > 0:
+        mut = run_one(args, x_np, m_np, h_np, F.FMM_FP64, census=False, walk=F.FMM_WALK_MUTUAL,
+                      steps=args.mutual_steps)
+        out["mutual_fp64"] = {k: mut[k] for k in ("value", "ms_per_step", "rel_err", "sumF_ratio",
+                                                  "com_drift", "stages_ms", "forces_only",
+                                                  "lists")}
+        out["mutual_fp64"]["steps"] = args.mutual_steps
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(x_np, m_np, h_np, args.theta)

@@ -24,6 +24,8 @@
 //
 // Compiled with -ffp-contract=off so the criterion is evaluated with exactly
 // the operations of its definition.
+#include <algorithm>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -43,58 +45,85 @@ __device__ __forceinline__ bool separated(const double *ra, const double *rb, do
     return ok4 && ok5;
 }
 
-// Reserve cnt slots per active lane of the wavefront (aggregated: one atomic
-// per wavefront); returns the lane's first slot.
-__device__ __forceinline__ uint64_t wave_append(unsigned long long *ctr, bool act, int per)
-{
-    const uint64_t m = __ballot(act);
-    if (m == 0ull)
-        return 0;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane_id() == leader)
-        base = atomicAdd(ctr, (unsigned long long)(per * __popcll(m)));
-    base = __shfl(base, leader);
-    return base + (uint64_t)(per * __popcll(m & lanemask_lt()));
-}
-
 __global__ void k_mw_zero(unsigned long long *p, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
         p[i] = 0ull;
 }
 
-// Seed: the (left, right) pair of every internal cell, and the self pair of
-// every leaf (near count 1).
+// Seed (no atomics: the seeds are known): the (left, right) pair of every
+// internal cell, and the self pair of every leaf (near count 1).
 __global__ __launch_bounds__(256) void k_mw_init(
     const int32_t *__restrict__ left, const int32_t *__restrict__ right,
-    const int32_t *__restrict__ node_leaf, int nnodes, int bits, int2 *tout, int64_t cap_task,
-    uint64_t *nkeys, int64_t cap_n, int32_t *near_cnt, unsigned long long *cnt)
+    const int32_t *__restrict__ int_nodes, int n_int, const int32_t *__restrict__ leaf_node,
+    int nleaves, int bits, int2 *tout, int64_t cap_task, uint64_t *nkeys, int64_t cap_n,
+    int32_t *near_cnt, unsigned long long *cnt)
 {
-    const int v = blockIdx.x * 256 + threadIdx.x;
-    const bool valid = v < nnodes;
-    const int lv = valid ? left[v] : -1;
-    const bool internal = valid && lv >= 0;
-    const bool leaf = valid && lv < 0;
-    const uint64_t kt = wave_append(&cnt[MW_IT], internal, 1);
-    if (internal) {
-        if ((int64_t)kt < cap_task)
-            tout[kt] = make_int2(lv, right[v]);
-        else
-            atomicOr(&cnt[MW_FLAGS], 1ull);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n_int && i < cap_task) {
+        const int v = int_nodes[i];
+        tout[i] = make_int2(left[v], right[v]);
     }
-    const uint64_t kn = wave_append(&cnt[MW_NNEAR], leaf, 1);
-    if (leaf) {
-        const int lf = node_leaf[v];
-        near_cnt[lf] = 1;
-        if ((int64_t)kn < cap_n)
-            nkeys[kn] = ((uint64_t)lf << bits) | (uint64_t)v;
-        else
-            atomicOr(&cnt[MW_FLAGS], 4ull);
+    if (i < nleaves) {
+        near_cnt[i] = 1;
+        if (i < cap_n)
+            nkeys[i] = ((uint64_t)i << bits) | (uint64_t)leaf_node[i];
+    }
+    if (i == 0) {
+        cnt[MW_IT] = (unsigned long long)n_int;
+        cnt[MW_NNEAR] = (unsigned long long)nleaves;
+        cnt[MW_FLAGS] = (n_int > cap_task ? 1ull : 0ull) | (nleaves > cap_n ? 4ull : 0ull);
     }
 }
 
+// Block-wide exclusive offsets of three per-thread counts, with one atomic
+// per counter per workgroup of 256 threads (same-address atomics from every
+// wavefront would serialise in L2).
+__device__ __forceinline__ void block_append3(const uint32_t (&v)[3],
+                                              unsigned long long *const (&ctr)[3], uint64_t (&pos)[3])
+{
+    __shared__ uint32_t wsum[3][4];
+    __shared__ unsigned long long gbase[3];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        inc[c] = v[c];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc[c], off);
+            if (lane >= off)
+                inc[c] += o;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            wsum[c][w] = inc[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        const uint32_t tot = wsum[c][0] + wsum[c][1] + wsum[c][2] + wsum[c][3];
+        gbase[c] = tot ? atomicAdd(ctr[c], (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        uint32_t woff = 0;
+        for (int k = 0; k < w; ++k)
+            woff += wsum[c][k];
+        pos[c] = gbase[c] + woff + inc[c] - v[c];
+    }
+    __syncthreads();  // wsum / gbase are reused by the next call
+}
+
 // One level of the pair recursion: frontier cnt[MW_IT + it] -> cnt[MW_IT + it + 1].
+// A workgroup takes MW_K x 256 consecutive pairs per round: it classifies
+// them (far / near / split A / split B), reserves the outputs of the whole
+// round with one atomic per output buffer, then writes them.
+constexpr int MW_K = 16;
+
 __global__ __launch_bounds__(256) void k_mw_step(
     const int2 *__restrict__ tin, int2 *tout, int it, int64_t cap_task,
     const double *__restrict__ recA, const int32_t *__restrict__ left,
@@ -103,77 +132,84 @@ __global__ __launch_bounds__(256) void k_mw_step(
     int32_t *near_cnt, unsigned long long *cnt)
 {
     const int64_t nin = min((int64_t)cnt[MW_IT + it], cap_task);
-    const int lane = lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nin;
-         base += stride) {
-        const int64_t i = base + lane;
-        const bool valid = i < nin;
-        int a = 0, b = 0;
-        bool far = false, nea = false, split = false;
-        int c0 = 0, c1 = 0, o = 0;
-        bool o_first = false;
-        if (valid) {
-            const int2 tk = tin[i];
-            a = tk.x;
-            b = tk.y;
-            const double *ra = recA + (int64_t)NREC * a;
-            const double *rb = recA + (int64_t)NREC * b;
-            if (separated(ra, rb, theta2, r_kern)) {
-                far = true;
-            } else {
-                const int la = left[a], lb = left[b];
-                if (la < 0 && lb < 0) {
-                    nea = true;
+    unsigned long long *const ctr[3] = {&cnt[MW_NFAR], &cnt[MW_NNEAR], &cnt[MW_IT + it + 1]};
+    const int t = threadIdx.x;
+    for (int64_t r0 = (int64_t)blockIdx.x * (256 * MW_K); r0 < nin;
+         r0 += (int64_t)gridDim.x * (256 * MW_K)) {
+        int2 tk[MW_K];
+        uint64_t code = 0;  // 3 bits per pair: 0 none, 1 far, 2 near, 3 split A, 4 split B
+        uint32_t num[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int k = 0; k < MW_K; ++k) {
+            const int64_t i = r0 + k * 256 + t;
+            tk[k] = make_int2(0, 0);
+            uint32_t c = 0;
+            if (i < nin) {
+                tk[k] = tin[i];
+                const int a = tk[k].x, b = tk[k].y;
+                const double *ra = recA + (int64_t)NREC * a;
+                const double *rb = recA + (int64_t)NREC * b;
+                if (separated(ra, rb, theta2, r_kern)) {
+                    c = 1;
                 } else {
-                    split = true;
-                    const bool split_a = lb < 0 || (la >= 0 && ra[4] >= rb[4]);
-                    if (split_a) {
-                        c0 = la;
-                        c1 = right[a];
-                        o = b;
-                        o_first = false;
-                    } else {
-                        c0 = lb;
-                        c1 = right[b];
-                        o = a;
-                        o_first = true;
-                    }
+                    const int la = left[a], lb = left[b];
+                    if (la < 0 && lb < 0)
+                        c = 2;
+                    else
+                        c = (lb < 0 || (la >= 0 && ra[4] >= rb[4])) ? 3 : 4;
                 }
             }
+            code |= (uint64_t)c << (3 * k);
+            num[0] += c == 1 ? 2u : 0u;
+            num[1] += c == 2 ? 2u : 0u;
+            num[2] += c >= 3 ? 2u : 0u;
         }
-        const uint64_t kf = wave_append(&cnt[MW_NFAR], far, 2);
-        // Each reserved slot below the capacity is written, so a consumer that
-        // clamps a count to the capacity reads written entries only.
-        if (far) {
-            if ((int64_t)kf < cap_f)
-                fkeys[kf] = ((uint64_t)a << bits) | (uint64_t)b;
-            if ((int64_t)kf + 1 < cap_f)
-                fkeys[kf + 1] = ((uint64_t)b << bits) | (uint64_t)a;
-            else
-                atomicOr(&cnt[MW_FLAGS], 2ull);
+        uint64_t pos[3];
+        block_append3(num, ctr, pos);
+        uint32_t ovf = 0;
+#pragma unroll
+        for (int k = 0; k < MW_K; ++k) {
+            const uint32_t c = (uint32_t)(code >> (3 * k)) & 7u;
+            const int a = tk[k].x, b = tk[k].y;
+            // every reserved slot below a capacity is written, so a consumer
+            // that clamps a count to the capacity reads written entries only
+            if (c == 1) {
+                const int64_t q = (int64_t)pos[0];
+                if (q < cap_f)
+                    fkeys[q] = ((uint64_t)a << bits) | (uint64_t)b;
+                if (q + 1 < cap_f)
+                    fkeys[q + 1] = ((uint64_t)b << bits) | (uint64_t)a;
+                else
+                    ovf |= 2u;
+                pos[0] += 2;
+            } else if (c == 2) {
+                const int fa = node_leaf[a], fb = node_leaf[b];
+                atomicAdd(&near_cnt[fa], 1);
+                atomicAdd(&near_cnt[fb], 1);
+                const int64_t q = (int64_t)pos[1];
+                if (q < cap_n)
+                    nkeys[q] = ((uint64_t)fa << bits) | (uint64_t)b;
+                if (q + 1 < cap_n)
+                    nkeys[q + 1] = ((uint64_t)fb << bits) | (uint64_t)a;
+                else
+                    ovf |= 4u;
+                pos[1] += 2;
+            } else if (c >= 3) {
+                const bool sa = c == 3;
+                const int sp = sa ? a : b, o = sa ? b : a;
+                const int c0 = left[sp], c1 = right[sp];
+                const int64_t q = (int64_t)pos[2];
+                if (q < cap_task)
+                    tout[q] = sa ? make_int2(c0, o) : make_int2(o, c0);
+                if (q + 1 < cap_task)
+                    tout[q + 1] = sa ? make_int2(c1, o) : make_int2(o, c1);
+                else
+                    ovf |= 1u;
+                pos[2] += 2;
+            }
         }
-        const uint64_t kn = wave_append(&cnt[MW_NNEAR], nea, 2);
-        if (nea) {
-            const int fa = node_leaf[a], fb = node_leaf[b];
-            atomicAdd(&near_cnt[fa], 1);
-            atomicAdd(&near_cnt[fb], 1);
-            if ((int64_t)kn < cap_n)
-                nkeys[kn] = ((uint64_t)fa << bits) | (uint64_t)b;
-            if ((int64_t)kn + 1 < cap_n)
-                nkeys[kn + 1] = ((uint64_t)fb << bits) | (uint64_t)a;
-            else
-                atomicOr(&cnt[MW_FLAGS], 4ull);
-        }
-        const uint64_t kt = wave_append(&cnt[MW_IT + it + 1], split, 2);
-        if (split) {
-            if ((int64_t)kt < cap_task)
-                tout[kt] = o_first ? make_int2(o, c0) : make_int2(c0, o);
-            if ((int64_t)kt + 1 < cap_task)
-                tout[kt + 1] = o_first ? make_int2(o, c1) : make_int2(c1, o);
-            else
-                atomicOr(&cnt[MW_FLAGS], 1ull);
-        }
+        if (ovf)
+            atomicOr(&cnt[MW_FLAGS], (unsigned long long)ovf);
     }
 }
 
@@ -270,9 +306,10 @@ hipError_t launch_mutual_walk(Tree &t, hipStream_t s)
     const int nit = mutual_iterations(t);
     const double theta2 = t.p.theta * t.p.theta;
     k_mw_zero<<<1, 256, 0, s>>>(M.cnt, MW_IT + nit + 1);
-    k_mw_init<<<(T.nnodes + 255) / 256, 256, 0, s>>>(t.left, t.right, t.node_leaf, T.nnodes, bits,
-                                                     M.task[0], M.cap_task, M.nkeys[0],
-                                                     M.cap_near, t.near_cnt, M.cnt);
+    const int n_int = T.nnodes - T.nleaves;
+    k_mw_init<<<(std::max(n_int, T.nleaves) + 255) / 256, 256, 0, s>>>(
+        t.left, t.right, t.int_nodes, n_int, t.leaf_node, T.nleaves, bits, M.task[0], M.cap_task,
+        M.nkeys[0], M.cap_near, t.near_cnt, M.cnt);
     for (int it = 0; it < nit; ++it)
         k_mw_step<<<MW_GRID, 256, 0, s>>>(M.task[it & 1], M.task[(it + 1) & 1], it, M.cap_task,
                                           t.recA, t.left, t.right, t.node_leaf, theta2,
