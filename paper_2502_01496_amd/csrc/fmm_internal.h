@@ -46,6 +46,17 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This bijection of [0, nblocks) gives XCD x a contiguous range of
+// logical block indices, so neighbouring leaves (which share most of their
+// interaction partners) are processed behind the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks)
+{
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // ------------------------------------------------------------------ host
 // Data-independent shape of the median-split tree: with ceil(n/2) / floor(n/2)
 // children, node sizes (and so first/count/left/right) depend on n and the

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f64(
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
     const int32_t *__restrict__ far_src, int cap_far, double *Lout)
 {
-    const int g = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
     const int sub = threadIdx.x & 15;
     const bool valid = g < nleaves;
     const int v = valid ? leaf_node[g] : 0;
@@ -177,6 +177,18 @@ __device__ __forceinline__ double rsqrt_pos(double x)
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// m / r^3 for finite r2 > 0: hardware reciprocal square root y, refined with
+// the series (1 - e)^(-3/2) = 1 + 3/2 e + 15/8 e^2 + O(e^3), e = 1 - r2 y^2
+// (r^-3 = y^3 (1 - e)^(-3/2)).
+__device__ __forceinline__ double m_over_r3(double r2, double m)
+{
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double t = y * y;
+    const double e = fma(-r2, t, 1.0);
+    const double my3 = m * (t * y);
+    return fma(my3, e * fma(e, 1.875, 1.5), my3);
+}
+
 // Reduce-scatter of 12 per-lane doubles over the 64 lanes of a wavefront.
 // Each xor step halves the set of values a lane keeps (it sends the other
 // half to its partner); after the steps over lane bits 5..2 a lane holds the
@@ -226,6 +238,28 @@ __device__ __forceinline__ double reduce_scatter12(const double *v, int lane, in
 // and writes G * a.
 constexpr int P2P_RANGES = 512;  // source blocks staged in LDS per wavefront
 
+// While staging a chunk of the near list, source blocks of leaves whose
+// centre lies within CLOSE_FRAC of the softening bound of eq. (5),
+//   |c_a - c_b| < CLOSE_FRAC ((s_a + s_b) + R_kern max(h_a, h_b)),
+// are placed first and the others after them (each group in list order).
+// The softened branch runs for a whole step of eight source blocks if any
+// pair in it is softened, so gathering the close leaves leaves more steps
+// on the Newtonian branch.  Deterministic: the order depends on the list only.
+constexpr double CLOSE_FRAC2 = 0.49;  // CLOSE_FRAC = 0.7, squared
+
+// Position of a block in the partitioned chunk; front / back are the
+// wave-uniform fill positions (front grows from 0, back shrinks from nc).
+__device__ __forceinline__ int close_first_slot(bool act, bool close, int &front, int &back)
+{
+    const uint64_t lt = lanemask_lt();
+    const uint64_t mc = __ballot(act && close), mf = __ballot(act && !close);
+    const int nf = __popcll(mf);
+    const int pos = close ? front + __popcll(mc & lt) : back - nf + __popcll(mf & lt);
+    front += __popcll(mc);
+    back -= nf;
+    return pos;
+}
+
 __device__ __forceinline__ void load_src(const double4 *__restrict__ pm,
                                          const double4 *__restrict__ ph, int2 rg, int slot,
                                          double4 &xj, double4 &hj)
@@ -245,12 +279,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int32_t *__restrict__ first, const int32_t *__restrict__ count,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
     const int32_t *__restrict__ near_src, int cap_near, int nsub, const double *__restrict__ Lloc,
-    const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double *aout)
+    const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double r_kern,
+    double *aout)
 {
     constexpr int NS = 4;
     __shared__ int2 rng[4][P2P_RANGES];
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
         return;
     const int lane = lane_id();
@@ -283,15 +318,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             acc[q] = 0.0;
         for (int c0 = 0; c0 < nb; c0 += P2P_RANGES) {
             const int nc = min(nb - c0, P2P_RANGES);
-            // stage the source blocks of this chunk (padded to a multiple of 8)
-            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
+            // stage the source blocks of this chunk (padded to a multiple of
+            // 8), close leaves first
+            int front = 0, back = nc;
+            for (int k0 = 0; k0 < ((nc + 7) & ~7); k0 += 64) {
+                const int k = k0 + lane;
+                const bool act = k < nc;
                 int2 r = make_int2(0, 0);
-                if (k < nc) {
+                bool close = false;
+                if (act) {
                     const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
                     const int bn = nl[e];
                     r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
+                    const double *rb = recA + (int64_t)NREC * bn;
+                    const double dx = rv[0] - rb[0], dy = rv[1] - rb[1], dz = rv[2] - rb[2];
+                    const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
+                    close = dx * dx + dy * dy + dz * dz < CLOSE_FRAC2 * t5 * t5;
                 }
-                R[k] = r;
+                const int pos = close_first_slot(act, close, front, back);
+                if (act)
+                    R[pos] = r;
+                else if (k < ((nc + 7) & ~7))
+                    R[k] = r;
             }
             __builtin_amdgcn_wave_barrier();
             double4 xj, hj;
@@ -304,11 +352,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 for (int q = 0; q < NS; ++q) {
                     const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    const bool soft = r2 < sh4[q] || r2 < hj.z;
                     double fm;
-                    if (__ballot(soft) == 0ull) {
-                        const double u = rsqrt_pos(r2);
-                        fm = xj.w * (u * u * u);
+                    if ((__ballot(r2 < hj.z) | __ballot(r2 < sh4[q])) == 0ull) {
+                        fm = m_over_r3(r2, xj.w);
                     } else {
                         const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
                         const double r = r2 * u;
@@ -361,7 +407,7 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f32(
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
     const int32_t *__restrict__ far_src, int cap_far, float *Lout)
 {
-    const int g = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
     const int sub = threadIdx.x & 15;
     const bool valid = g < nleaves;
     const int v = valid ? leaf_node[g] : 0;
@@ -448,14 +494,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
     const int32_t *__restrict__ near_cnt, const int32_t *__restrict__ near_src, int cap_near,
     int nsub, const float *__restrict__ Lloc, const double *__restrict__ recA,
-    const int32_t *__restrict__ perm, float G, float *aout)
+    const int32_t *__restrict__ perm, float G, double r_kern, float *aout)
 {
     constexpr int NS = 8;
     constexpr int NR = P2P_RANGES / 2;
     __shared__ int2 rng[4][NR];
     __shared__ float4 dcs[4][NR];
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
         return;
     const int lane = lane_id();
@@ -492,20 +538,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             const int nc = min(nb - c0, NR);
             // stage the source blocks of this chunk (padded to a multiple of 8):
             // their particle range and the leaf-centre difference c_a - c_b,
-            // formed in FP64 and rounded to FP32
-            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
+            // formed in FP64 and rounded to FP32; close leaves first
+            int front = 0, back = nc;
+            for (int k0 = 0; k0 < ((nc + 7) & ~7); k0 += 64) {
+                const int k = k0 + lane;
+                const bool act = k < nc;
                 int2 r = make_int2(0, 0);
                 float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (k < nc) {
+                bool close = false;
+                if (act) {
                     const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
                     const int bn = nl[e];
                     r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
                     const double *rb = recA + (int64_t)NREC * bn;
-                    d = make_float4((float)(ca0 - rb[0]), (float)(ca1 - rb[1]),
-                                    (float)(ca2 - rb[2]), 0.f);
+                    const double dx = ca0 - rb[0], dy = ca1 - rb[1], dz = ca2 - rb[2];
+                    d = make_float4((float)dx, (float)dy, (float)dz, 0.f);
+                    const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
+                    close = dx * dx + dy * dy + dz * dz < CLOSE_FRAC2 * t5 * t5;
                 }
-                R[k] = r;
-                D[k] = d;
+                const int pos = close_first_slot(act, close, front, back);
+                if (act) {
+                    R[pos] = r;
+                    D[pos] = d;
+                } else if (k < ((nc + 7) & ~7)) {
+                    R[k] = r;
+                    D[k] = d;
+                }
             }
             __builtin_amdgcn_wave_barrier();
             for (int kb = 0; kb < nc; kb += 8) {
@@ -524,9 +582,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                     const float dx = dc.x + (sx[q] - yj.x), dy = dc.y + (sy[q] - yj.y),
                                 dz = dc.z + (sz[q] - yj.z);
                     const float r2 = dx * dx + dy * dy + dz * dz;
-                    const bool soft = r2 < sh4[q] || r2 < hj.z;
                     float fm;
-                    if (__ballot(soft) == 0ull) {
+                    if ((__ballot(r2 < hj.z) | __ballot(r2 < sh4[q])) == 0ull) {
                         const float u = rsq_pos_f(r2);
                         fm = yj.w * (u * u * u);
                     } else {
@@ -754,12 +811,13 @@ hipError_t launch_near(Tree &t, void *a, hipStream_t s)
     if (t.p.precision == FMM_FP64)
         k_p2p_src_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node, nl,
                                                    t.near_cnt, t.near_src, (int)t.cap_near, nsub,
-                                                   t.L, t.recA, t.perm, t.p.G, (double *)a);
+                                                   t.L, t.recA, t.perm, t.p.G, t.p.r_kern,
+                                                   (double *)a);
     else
         k_p2p_src_f32<<<(nl + 3) / 4, 256, 0, s>>>(t.pf, t.pfh, t.first, t.count,
                                                    t.leaf_node, nl, t.near_cnt, t.near_src,
                                                    (int)t.cap_near, nsub, t.Lf, t.recA, t.perm,
-                                                   (float)t.p.G, (float *)a);
+                                                   (float)t.p.G, t.p.r_kern, (float *)a);
     return hipGetLastError();
 }
 

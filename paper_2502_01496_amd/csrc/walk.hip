@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_walk_wide(
 {
     __shared__ int32_t stk[4][WIDE_STACK];
     const int w = threadIdx.x >> 6, lane = lane_id();
-    const int leaf = blockIdx.x * 4 + w;
+    const int leaf = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (leaf >= nleaves)
         return;
     const uint64_t lt = lanemask_lt();
