@@ -153,7 +153,7 @@ __global__ void k_rank_gather(const double *__restrict__ x, int64_t n, const uin
 // Stable LSD radix sort of B independent (key u64, value u32) arrays of
 // length n laid out back to back.  Per 8-bit pass: per-tile digit histograms,
 // a scan per (digit, array) over the tiles, then a stable scatter.  Inside a
-// tile the four waves take consecutive quarters; a wave ranks its 64 keys of a
+// tile the 16 waves take consecutive sixteenths; a wave ranks its 64 keys of a
 // round with ballot-based digit matching, so rank order = input order.
 __global__ void k_rs_zero(uint32_t *p, int64_t cnt)
 {
@@ -168,21 +168,24 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
 {
     __shared__ uint32_t h[256];
     int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
-    h[t] = 0u;
+    if (t < 256)
+        h[t] = 0u;
     __syncthreads();
     const uint64_t *k = keys + (int64_t)b * n;
     int64_t base = (int64_t)blk * RS_TILE;
-#pragma unroll 4
+#pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         int64_t i = base + r * RS_THREADS + t;
         if (i < n)
             atomicAdd(&h[(uint32_t)(k[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    uint32_t c = h[t];
-    hist[((int64_t)b * 256 + t) * nblk + blk] = c;
-    if (c)
-        atomicAdd(&tot[b * 256 + t], c);
+    if (t < 256) {
+        uint32_t c = h[t];
+        hist[((int64_t)b * 256 + t) * nblk + blk] = c;
+        if (c)
+            atomicAdd(&tot[b * 256 + t], c);
+    }
 }
 
 // Exclusive scan across one block of up to 256 threads (values <= 2^32).
@@ -210,8 +213,8 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *sh
     return wbase + inc - v;
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scan(uint32_t *hist, const uint32_t *tot,
-                                                        int nblk)
+__global__ __launch_bounds__(RS_SCAN_THREADS) void k_rs_scan(uint32_t *hist, const uint32_t *tot,
+                                                             int nblk)
 {
     __shared__ uint32_t sh[8];
     int d = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scan(uint32_t *hist, const ui
     block_excl_scan_u32(mine, sh, base);
     uint32_t *row = hist + ((int64_t)b * 256 + d) * nblk;
     uint32_t run = base;
-    for (int c0 = 0; c0 < nblk; c0 += RS_THREADS) {
+    for (int c0 = 0; c0 < nblk; c0 += RS_SCAN_THREADS) {
         int i = c0 + t;
         uint32_t v = i < nblk ? row[i] : 0u;
         uint32_t total;
@@ -247,24 +250,29 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
     uint32_t *vout, int64_t n, int shift, const uint32_t *__restrict__ hist, int nblk)
 {
-    __shared__ uint32_t wrun[4][256];
+    __shared__ uint32_t wrun[RS_WAVES][256];
     __shared__ uint32_t gofs[256];
     int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = lane_id();
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        wrun[i][t] = 0u;
+    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS)
+        (&wrun[0][0])[i] = 0u;
     __syncthreads();
     const uint64_t *k = kin + (int64_t)b * n;
     const uint32_t *v = vin ? vin + (int64_t)b * n : nullptr;
-    int64_t wbase = (int64_t)blk * RS_TILE + (int64_t)w * (RS_TILE / 4);
+    int64_t wbase = (int64_t)blk * RS_TILE + (int64_t)w * (RS_TILE / RS_WAVES);
+    uint64_t key[RS_ROUNDS];
     uint32_t rank[RS_ROUNDS];
     uint32_t dig[RS_ROUNDS];
     uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         int64_t i = wbase + r * 64 + lane;
+        key[r] = i < n ? k[i] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        int64_t i = wbase + r * 64 + lane;
         bool valid = i < n;
-        uint32_t d = valid ? (uint32_t)(k[i] >> shift) & 255u : 0u;
+        uint32_t d = valid ? (uint32_t)(key[r] >> shift) & 255u : 0u;
         uint64_t peers = match_u8(d, valid);
         uint32_t cur = wrun[w][d];
         rank[r] = cur + (uint32_t)__popcll(peers & lt);
@@ -274,10 +282,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
             wrun[w][d] = cur + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    {
+    if (t < 256) {
         uint32_t s = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < RS_WAVES; ++i) {
             uint32_t c = wrun[i][t];
             wrun[i][t] = s;
             s += c;
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         if (i < n) {
             uint32_t d = dig[r];
             int64_t pos = (int64_t)gofs[d] + wrun[w][d] + rank[r];
-            ko[pos] = k[i];
+            ko[pos] = key[r];
             if (v)
                 vo[pos] = v[i];
         }
@@ -319,7 +327,7 @@ hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
         uint32_t *tp = tot + (int64_t)pass * B * 256;
         dim3 g(nblk, B);
         k_rs_hist<<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
-        k_rs_scan<<<dim3(256, B), RS_THREADS, 0, s>>>(hist, tp, nblk);
+        k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
         k_rs_scatter<<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
     }
     return hipGetLastError();

@@ -20,10 +20,12 @@ constexpr int SUBTREE_THREADS = 512;
 // Positions handled by one workgroup in the per-level partition kernels.
 constexpr int LVL_CHUNK = 2048;
 constexpr int LVL_THREADS = 256;
-// Radix sort: 4 waves x 16 rounds x 64 lanes = 4096 keys per tile, 8-bit digits.
-constexpr int RS_THREADS = 256;
-constexpr int RS_ROUNDS = 16;
+// Radix sort: 16 waves x 4 rounds x 64 lanes = 4096 keys per tile, 8-bit digits.
+constexpr int RS_THREADS = 1024;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ROUNDS = 4;
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
+constexpr int RS_SCAN_THREADS = 256;
 constexpr int RS_PASSES = 8;
 constexpr int MAX_LEAF = 64;
 constexpr int NREC = 8;   // doubles per node record (geometry / quadrupole)
