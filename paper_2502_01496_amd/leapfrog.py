@@ -130,7 +130,9 @@ def com_drift_loss_grad(x0, xT, m):
     L = float((D * D).sum())
     gxT = (2.0 / M) * m[:, None] * D[None, :]
     gx0 = -gxT
-    gm = (2.0 / M) * (((xT - XT) - (x0 - X0)) @ D)
+    # elementwise product and row sum (a matrix-vector call fails for very
+    # tall matrices in the BLAS library)
+    gm = (2.0 / M) * (((xT - XT) - (x0 - X0)) * D[None, :]).sum(1)
     return L, gxT, gx0, gm
 
 
