@@ -180,6 +180,11 @@ const char *fmm_last_error(void);
  * near entries, list sinks, has_lists. */
 fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info);
 
+/* Device memory the library holds for a tree (its topology, workspace,
+ * interaction lists and VJP workspace), in bytes, to *bytes (host).  Memory
+ * the caller owns (inputs, outputs) is not included. */
+fmm_status fmm_tree_device_bytes(const fmm_tree *tree, int64_t *bytes);
+
 /* Copy the tree, cell records and interaction lists to HOST buffers (test and
  * bring-up aid; synchronises).  Any pointer may be NULL to skip it.
  *   perm      int32[n]      tree position -> caller index

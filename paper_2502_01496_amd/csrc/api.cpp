@@ -813,6 +813,27 @@ fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info)
     return FMM_OK;
 }
 
+fmm_status fmm_tree_device_bytes(const fmm_tree *tree, int64_t *bytes)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!bytes)
+        return fail(FMM_ERR_INVALID, "bytes must not be NULL");
+    const Tree &t = *reinterpret_cast<const Tree *>(tree);
+    int64_t b = 0;
+    for (const auto &d : t.owned)
+        b += (int64_t)d.bytes;
+    for (const auto &d : t.vjp_owned)
+        b += (int64_t)d.bytes;
+    for (const auto &d : t.mw.owned)
+        b += (int64_t)d.bytes;
+    for (const DevBuf *d : {&t.far_buf, &t.near_buf, &t.mw.b_task, &t.mw.b_fkeys, &t.mw.b_nkeys,
+                            &t.mw.b_hist})
+        b += (int64_t)d->bytes;
+    *bytes = b;
+    return FMM_OK;
+}
+
 fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first, int32_t *count,
                             int32_t *left, int32_t *right, int32_t *axis, double *rec,
                             int64_t *far_off, int32_t *far_src, int64_t *near_off,

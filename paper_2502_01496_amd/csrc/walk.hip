@@ -32,64 +32,84 @@ __device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, doubl
     return open4 || open5;
 }
 
-// One wavefront per sink leaf.  The pending cells sit on an LDS stack; each
-// step pops up to 64 of them (one per lane), applies the two criteria, writes
-// far / near entries with ballot compaction and pushes the children of the
-// opened internal cells.  Lists go to fixed per-leaf slots of capacity
-// cap_far / cap_near; counts beyond a slot are still counted (the host then
-// grows the slots and walks again).  A full stack sets *stack_overflow and
-// the leaf is redone by k_walk_p (exact, narrow stack).
-__global__ __launch_bounds__(256) void k_walk_wide(
+// Group walk: one wavefront walks WG consecutive sink leaves (in pre-order,
+// a compact group) together.  A stack entry carries a cell and the mask of
+// the group's leaves for which it is pending (all of them had its parent
+// opened); each step pops up to 64 entries, loads each cell's record once and
+// applies the criteria for every pending leaf, writes the far / near entries
+// of each leaf with ballot compaction, and pushes the children with the mask
+// of the leaves that opened the cell.  Per leaf the decisions, and so the
+// lists, are those of the single-leaf walk.  A full stack marks the group's
+// leaves for the exact narrow-stack walk.
+constexpr int WG = 4;
+
+__global__ __launch_bounds__(256) void k_walk_group(
     const double *__restrict__ recA, const int32_t *__restrict__ left,
     const int32_t *__restrict__ right, const int32_t *__restrict__ leaf_node, int nleaves,
     double theta2, double r_kern, int32_t *far_src, int cap_far, int32_t *near_src,
-    int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *maxcnt, int32_t *stack_overflow,
-    int stack_limit)
+    int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *stack_overflow, int stack_limit)
 {
     __shared__ int32_t stk[4][WIDE_STACK];
+    __shared__ uint8_t msk[4][WIDE_STACK];
     const int w = threadIdx.x >> 6, lane = lane_id();
-    const int leaf = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
-    if (leaf >= nleaves)
+    const int g0 = __builtin_amdgcn_readfirstlane((xcd_block(blockIdx.x, gridDim.x) * 4 + w) * WG);
+    if (g0 >= nleaves)
         return;
+    const int ng = min(WG, nleaves - g0);
     const uint64_t lt = lanemask_lt();
-    const int a = leaf_node[leaf];
-    const double *ra = recA + (int64_t)NREC * a;
-    const double ca0 = ra[0], ca1 = ra[1], ca2 = ra[2], sa = ra[4], ha = ra[5];
-    int32_t *fo = far_src + (int64_t)leaf * cap_far;
-    int32_t *no = near_src + (int64_t)leaf * cap_near;
-    int nf = 0, nn = 0, sp = 1;
+    double ca0[WG], ca1[WG], ca2[WG], sa[WG], ha[WG];
+#pragma unroll
+    for (int g = 0; g < WG; ++g) {
+        const double *ra = recA + (int64_t)NREC * leaf_node[g0 + min(g, ng - 1)];
+        ca0[g] = ra[0];
+        ca1[g] = ra[1];
+        ca2[g] = ra[2];
+        sa[g] = ra[4];
+        ha[g] = ra[5];
+    }
+    int nf[WG], nn[WG];
+#pragma unroll
+    for (int g = 0; g < WG; ++g)
+        nf[g] = nn[g] = 0;
+    int sp = 1;
     bool ovf = false;
-    if (lane == 0)
+    if (lane == 0) {
         stk[w][0] = 0;
+        msk[w][0] = (uint8_t)((1u << ng) - 1u);
+    }
     while (sp > 0) {
         const int take = sp < 64 ? sp : 64;
         const int base = sp - take;
         const bool act = lane < take;
         const int b = act ? stk[w][base + lane] : 0;
+        const uint32_t m = act ? msk[w][base + lane] : 0u;
         sp = base;
-        bool far = false, nea = false, desc = false;
-        int lb = -1, rb_ = -1;
-        if (act) {
-            const bool op = opened(ca0, ca1, ca2, sa, ha, recA + (int64_t)NREC * b, theta2, r_kern);
-            lb = left[b];
-            rb_ = right[b];
-            far = !op;
-            nea = op && lb < 0;
-            desc = op && lb >= 0;
+        const double *rb = recA + (int64_t)NREC * b;
+        const int lb = left[b], rgt = right[b];
+        uint32_t open = 0;
+#pragma unroll
+        for (int g = 0; g < WG; ++g) {
+            const bool live = (m >> g) & 1u;
+            const bool op = live && opened(ca0[g], ca1[g], ca2[g], sa[g], ha[g], rb, theta2, r_kern);
+            const bool far = live && !op;
+            const bool nea = op && lb < 0;
+            open |= (op ? 1u : 0u) << g;
+            const uint64_t mf = __ballot(far), mn = __ballot(nea);
+            if (far) {
+                const int k = nf[g] + __popcll(mf & lt);
+                if (k < cap_far)
+                    far_src[(int64_t)(g0 + g) * cap_far + k] = b;
+            }
+            if (nea) {
+                const int k = nn[g] + __popcll(mn & lt);
+                if (k < cap_near)
+                    near_src[(int64_t)(g0 + g) * cap_near + k] = b;
+            }
+            nf[g] += __popcll(mf);
+            nn[g] += __popcll(mn);
         }
-        const uint64_t mf = __ballot(far), mn = __ballot(nea), md = __ballot(desc);
-        if (far) {
-            const int k = nf + __popcll(mf & lt);
-            if (k < cap_far)
-                fo[k] = b;
-        }
-        if (nea) {
-            const int k = nn + __popcll(mn & lt);
-            if (k < cap_near)
-                no[k] = b;
-        }
-        nf += __popcll(mf);
-        nn += __popcll(mn);
+        const bool desc = open != 0u && lb >= 0;
+        const uint64_t md = __ballot(desc);
         const int nd = __popcll(md);
         if (sp + 2 * nd > stack_limit) {
             ovf = true;
@@ -97,23 +117,33 @@ __global__ __launch_bounds__(256) void k_walk_wide(
         }
         if (desc) {
             const int k = sp + 2 * __popcll(md & lt);
-            stk[w][k] = rb_;
+            stk[w][k] = rgt;
+            msk[w][k] = (uint8_t)open;
             stk[w][k + 1] = lb;
+            msk[w][k + 1] = (uint8_t)open;
         }
         sp += 2 * nd;
     }
-    if (lane == 0) {
+    if (lane < ng) {
+        int f = 0, q = 0;
+#pragma unroll
+        for (int g = 0; g < WG; ++g)
+            if (g == lane) {
+                f = nf[g];
+                q = nn[g];
+            }
         if (ovf) {
             // marked for the narrow-stack walk; until then the leaf has no
             // list entries (the force kernels may run before that walk)
-            atomicOr(stack_overflow, 1);
-            far_cnt[leaf] = -1;
-            near_cnt[leaf] = 0;
+            far_cnt[g0 + lane] = -1;
+            near_cnt[g0 + lane] = 0;
         } else {
-            far_cnt[leaf] = nf;
-            near_cnt[leaf] = nn;
+            far_cnt[g0 + lane] = f;
+            near_cnt[g0 + lane] = q;
         }
     }
+    if (ovf && lane == 0)
+        atomicOr(stack_overflow, 1);
 }
 
 // Fallback for leaves whose wide walk overflowed its stack (far_cnt == -1):
@@ -225,11 +255,11 @@ hipError_t launch_walk(Tree &t, hipStream_t s)
     const double theta2 = t.p.theta * t.p.theta;
     const int nl = T.nleaves;
     k_walk_init<<<1, 64, 0, s>>>(t.walk_flags);
-    k_walk_wide<<<(nl + 3) / 4, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, nl, theta2,
-                                             t.p.r_kern, t.far_src, (int)t.cap_far, t.near_src,
-                                             (int)t.cap_near, t.far_cnt, t.near_cnt, t.walk_flags,
-                                             t.walk_flags + 2,
-                                             std::min(std::max(t.wide_stack_limit, 2), WIDE_STACK));
+    const int groups = (nl + WG - 1) / WG;
+    k_walk_group<<<(groups + 3) / 4, 256, 0, s>>>(
+        t.recA, t.left, t.right, t.leaf_node, nl, theta2, t.p.r_kern, t.far_src, (int)t.cap_far,
+        t.near_src, (int)t.cap_near, t.far_cnt, t.near_cnt, t.walk_flags + 2,
+        std::min(std::max(t.wide_stack_limit, 2), WIDE_STACK));
     k_list_max<<<1, 1024, 0, s>>>(t.far_cnt, t.near_cnt, nl, t.walk_flags);
     return hipGetLastError();
 }

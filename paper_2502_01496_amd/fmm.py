@@ -83,6 +83,8 @@ def lib() -> C.CDLL:
     L.fmm_tree_free.restype = None
     L.fmm_tree_info.argtypes = [_vp, _vp]
     L.fmm_tree_info.restype = st
+    L.fmm_tree_device_bytes.argtypes = [_vp, C.POINTER(C.c_int64)]
+    L.fmm_tree_device_bytes.restype = st
     L.fmm_debug_export.argtypes = [_vp] * 13
     L.fmm_debug_export.restype = st
     L.fmm_set_timing.argtypes = [_vp, C.c_int32]
@@ -211,6 +213,13 @@ def fmm_tree_info(tree) -> dict:
     _check(lib().fmm_tree_info(C.c_void_p(tree), info.ctypes.data_as(C.c_void_p)))
     keys = ("n", "nodes", "leaves", "depth", "n_far", "n_near", "sinks", "has_lists")
     return {k: int(v) for k, v in zip(keys, info)}
+
+
+def fmm_tree_device_bytes(tree) -> int:
+    """Device memory the library holds for the tree, in bytes."""
+    b = C.c_int64(0)
+    _check(lib().fmm_tree_device_bytes(C.c_void_p(tree), C.byref(b)))
+    return int(b.value)
 
 
 def fmm_set_timing(tree, on: bool):
