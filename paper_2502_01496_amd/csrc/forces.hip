@@ -162,10 +162,12 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f64(
 // ---------------------------------------------------------------- P2P + L2P, FP64
 __device__ __forceinline__ double m4g_f64(double q, double hinv3, double u3)
 {
+    // both pieces are evaluated and selected (no divergent branches)
     const double p1 = hinv3 * (4.0 / 3.0 + q * q * (-1.2 + 0.5 * q));
     const double p2 = hinv3 * (8.0 / 3.0 + q * (-3.0 + q * (1.2 - q * (1.0 / 6.0)))) -
                       u3 * (1.0 / 15.0);
-    return q < 1.0 ? p1 : (q < 2.0 ? p2 : u3);
+    const double g = __builtin_unpredictable(q < 2.0) ? p2 : u3;
+    return __builtin_unpredictable(q < 1.0) ? p1 : g;
 }
 
 // 1/sqrt(x) for finite x > 0: hardware estimate plus one second-order
@@ -443,10 +445,12 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f32(
 
 __device__ __forceinline__ float m4g_f32(float q, float hinv3, float u3)
 {
+    // both pieces are evaluated and selected (no divergent branches)
     const float p1 = hinv3 * (4.0f / 3.0f + q * q * (-1.2f + 0.5f * q));
     const float p2 = hinv3 * (8.0f / 3.0f + q * (-3.0f + q * (1.2f - q * (1.0f / 6.0f)))) -
                      u3 * (1.0f / 15.0f);
-    return q < 1.0f ? p1 : (q < 2.0f ? p2 : u3);
+    const float g = __builtin_unpredictable(q < 2.0f) ? p2 : u3;
+    return __builtin_unpredictable(q < 1.0f) ? p1 : g;
 }
 
 __device__ __forceinline__ float xchg_keep_f(float keep, float send, int off)
