@@ -246,65 +246,98 @@ __device__ __forceinline__ uint64_t match_u8(uint32_t d, bool valid)
     return m;
 }
 
+// Stable scatter of one tile: rank the keys by digit (per wave, ballot
+// matching; waves in order), place the tile digit-sorted in LDS, then write
+// each digit's run to its global position with consecutive threads on
+// consecutive addresses.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
     uint32_t *vout, int64_t n, int shift, const uint32_t *__restrict__ hist, int nblk)
 {
-    __shared__ uint32_t wrun[RS_WAVES][256];
+    __shared__ uint64_t skey[RS_TILE];
+    __shared__ uint32_t sval[RS_TILE];
+    __shared__ uint16_t wrun[RS_WAVES][256];
+    __shared__ uint32_t loff[256];
     __shared__ uint32_t gofs[256];
-    int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = lane_id();
+    __shared__ uint32_t wtot[4];
+    const int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = lane_id();
     for (int i = t; i < RS_WAVES * 256; i += RS_THREADS)
-        (&wrun[0][0])[i] = 0u;
+        (&wrun[0][0])[i] = 0;
     __syncthreads();
     const uint64_t *k = kin + (int64_t)b * n;
     const uint32_t *v = vin ? vin + (int64_t)b * n : nullptr;
-    int64_t wbase = (int64_t)blk * RS_TILE + (int64_t)w * (RS_TILE / RS_WAVES);
+    const int64_t tile0 = (int64_t)blk * RS_TILE;
+    const int nv = (int)min((int64_t)RS_TILE, n - tile0);
+    const int wbase = w * (RS_TILE / RS_WAVES);
     uint64_t key[RS_ROUNDS];
+    uint32_t val[RS_ROUNDS];
     uint32_t rank[RS_ROUNDS];
-    uint32_t dig[RS_ROUNDS];
-    uint64_t lt = lanemask_lt();
+    const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
-        int64_t i = wbase + r * 64 + lane;
-        key[r] = i < n ? k[i] : 0ull;
+        const int i = wbase + r * 64 + lane;
+        key[r] = i < nv ? k[tile0 + i] : 0ull;
+        val[r] = (v && i < nv) ? v[tile0 + i] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
-        int64_t i = wbase + r * 64 + lane;
-        bool valid = i < n;
-        uint32_t d = valid ? (uint32_t)(key[r] >> shift) & 255u : 0u;
-        uint64_t peers = match_u8(d, valid);
-        uint32_t cur = wrun[w][d];
+        const bool valid = wbase + r * 64 + lane < nv;
+        const uint32_t d = valid ? (uint32_t)(key[r] >> shift) & 255u : 0u;
+        const uint64_t peers = match_u8(d, valid);
+        const uint32_t cur = wrun[w][d];
         rank[r] = cur + (uint32_t)__popcll(peers & lt);
-        dig[r] = d;
-        bool leader = valid && ((peers & lt) == 0ull);
-        if (leader)
-            wrun[w][d] = cur + (uint32_t)__popcll(peers);
+        if (valid && (peers & lt) == 0ull)
+            wrun[w][d] = (uint16_t)(cur + (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    // per digit: offsets of the waves, then the tile-local digit offsets
+    uint32_t cnt = 0;
+    if (t < 256) {
+#pragma unroll
+        for (int i = 0; i < RS_WAVES; ++i) {
+            const uint32_t c = wrun[i][t];
+            wrun[i][t] = (uint16_t)cnt;
+            cnt += c;
+        }
+        gofs[t] = hist[((int64_t)b * 256 + t) * nblk + blk];
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off);
+            if (lane >= off)
+                inc += o;
+        }
+        if (lane == 63)
+            wtot[w] = inc;
+        loff[t] = inc - cnt;
     }
     __syncthreads();
     if (t < 256) {
-        uint32_t s = 0;
+        uint32_t add = 0;
+        for (int i = 0; i < w; ++i)
+            add += wtot[i];
+        loff[t] += add;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int i = 0; i < RS_WAVES; ++i) {
-            uint32_t c = wrun[i][t];
-            wrun[i][t] = s;
-            s += c;
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        if (wbase + r * 64 + lane < nv) {
+            const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+            const uint32_t lp = loff[d] + wrun[w][d] + rank[r];
+            skey[lp] = key[r];
+            sval[lp] = val[r];
         }
-        gofs[t] = hist[((int64_t)b * 256 + t) * nblk + blk];
     }
     __syncthreads();
     uint64_t *ko = kout + (int64_t)b * n;
     uint32_t *vo = vin ? vout + (int64_t)b * n : nullptr;
-#pragma unroll
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-        int64_t i = wbase + r * 64 + lane;
-        if (i < n) {
-            uint32_t d = dig[r];
-            int64_t pos = (int64_t)gofs[d] + wrun[w][d] + rank[r];
-            ko[pos] = key[r];
-            if (v)
-                vo[pos] = v[i];
-        }
+    for (int j = t; j < nv; j += RS_THREADS) {
+        const uint64_t kk = skey[j];
+        const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+        const int64_t gp = (int64_t)gofs[d] + (j - (int)loff[d]);
+        ko[gp] = kk;
+        if (vo)
+            vo[gp] = sval[j];
     }
 }
 
