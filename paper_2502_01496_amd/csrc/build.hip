@@ -14,7 +14,8 @@
 //   5. for cells larger than SUBTREE_MAX, one level at a time: the median of
 //      the longest axis is the middle entry of that axis's sorted segment, so
 //      the split is a stable partition of the four lists (three axis lists +
-//      the rank list) by a per-particle side flag;
+//      the rank list); an entry's side follows from comparing its key
+//      (coordinate bits, rank) with that of the last left entry;
 //   6. every cell of at most SUBTREE_MAX particles is finished by one
 //      workgroup in LDS (all levels below it), which writes the final order.
 //
@@ -392,32 +393,53 @@ __device__ __forceinline__ int node_axis(const uint32_t *L, int64_t n, const dou
     return ax;
 }
 
-__global__ __launch_bounds__(LVL_THREADS) void k_lvl_flags(
-    const uint32_t *__restrict__ L, int64_t n, const double *__restrict__ xr,
-    const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
-    const int32_t *first, const int32_t *count, uint8_t *flag, int32_t *axis_out)
+// The split of a cell: the left child takes the first ceil(c/2) entries of
+// the longest axis's list, i.e. the particles whose key (ordered coordinate
+// bits, Morton rank) is at most the key of entry ceil(c/2) - 1.
+struct Split {
+    int64_t f, nl;
+    int ax;
+    uint64_t ob;  // ordered coordinate bits of the last left entry
+    uint32_t rm;  // its Morton rank
+};
+
+__device__ __forceinline__ Split node_split(const uint32_t *L, int64_t n, const double *xr,
+                                            int64_t f, int64_t c)
 {
-    int b = blockIdx.x;
-    int v = blk_node[b];
-    int64_t f = first[v], c = count[v], nl = (c + 1) / 2;
-    int ax = node_axis(L, n, xr, f, c);
-    if (threadIdx.x == 0 && blk_start[b] == f)
-        axis_out[v] = ax;
-    const uint32_t *La = L + ax * n;
-    for (int64_t p = blk_start[b] + threadIdx.x; p < blk_end[b]; p += LVL_THREADS)
-        flag[La[p]] = (uint8_t)(p - f < nl);
+    Split S;
+    S.f = f;
+    S.nl = (c + 1) / 2;
+    S.ax = node_axis(L, n, xr, f, c);
+    S.rm = L[S.ax * n + f + S.nl - 1];
+    S.ob = ordbits(xr[S.ax * n + S.rm]);
+    return S;
+}
+
+// Side of the entry at position p of list d (rank r): 1 = left child.
+__device__ __forceinline__ uint32_t goes_left(const Split &S, const double *xr, int64_t n, int d,
+                                              int64_t p, uint32_t r)
+{
+    if (d == S.ax)
+        return p - S.f < S.nl ? 1u : 0u;
+    const uint64_t o = ordbits(xr[S.ax * n + r]);
+    return (o < S.ob || (o == S.ob && r <= S.rm)) ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(LVL_THREADS) void k_lvl_count(
-    const uint32_t *__restrict__ L, int64_t n, const int32_t *blk_start, const int32_t *blk_end,
-    const uint8_t *__restrict__ flag, int32_t *cnt, int stride)
+    const uint32_t *__restrict__ L, int64_t n, const double *__restrict__ xr,
+    const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
+    const int32_t *first, const int32_t *count, int32_t *axis_out, int32_t *cnt, int stride)
 {
     __shared__ uint32_t sh[8];
     int b = blockIdx.x, d = blockIdx.y;
+    const int v = blk_node[b];
+    const Split S = node_split(L, n, xr, first[v], count[v]);
+    if (d == 0 && threadIdx.x == 0 && blk_start[b] == S.f)
+        axis_out[v] = S.ax;
     const uint32_t *Ld = L + d * n;
     uint32_t c = 0;
     for (int64_t p = blk_start[b] + threadIdx.x; p < blk_end[b]; p += LVL_THREADS)
-        c += flag[Ld[p]];
+        c += goes_left(S, xr, n, d, p, Ld[p]);
     uint32_t total;
     block_excl_scan_u32(c, sh, total);
     if (threadIdx.x == 0)
@@ -442,16 +464,17 @@ __global__ __launch_bounds__(1024) void k_lvl_scan(const int32_t *cnt, int32_t *
 }
 
 __global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
-    const uint32_t *__restrict__ Lsrc, uint32_t *Ldst, int64_t n, const int32_t *blk_node,
-    const int32_t *blk_start, const int32_t *blk_end, const int32_t *blk_first,
-    const int32_t *first, const int32_t *count, const uint8_t *__restrict__ flag,
-    const int32_t *pre, int stride)
+    const uint32_t *__restrict__ Lsrc, uint32_t *Ldst, int64_t n, const double *__restrict__ xr,
+    const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
+    const int32_t *blk_first, const int32_t *first, const int32_t *count, const int32_t *pre,
+    int stride)
 {
     constexpr int PER = LVL_CHUNK / LVL_THREADS;
     __shared__ uint32_t sh[8];
     int b = blockIdx.x, d = blockIdx.y;
     int v = blk_node[b];
-    int64_t f = first[v], c = count[v], nl = (c + 1) / 2;
+    const Split S = node_split(Lsrc, n, xr, first[v], count[v]);
+    const int64_t f = S.f, nl = S.nl;
     int64_t s = blk_start[b], e = blk_end[b];
     const uint32_t *Ls = Lsrc + d * n;
     uint32_t *Ld = Ldst + d * n;
@@ -463,7 +486,7 @@ __global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
     for (int k = 0; k < PER; ++k) {
         int64_t p = p0 + k;
         r[k] = p < e ? Ls[p] : 0u;
-        fl[k] = p < e ? flag[r[k]] : 0u;
+        fl[k] = p < e ? goes_left(S, xr, n, d, p, r[k]) : 0u;
         mine += fl[k];
     }
     uint32_t total;
@@ -734,14 +757,13 @@ hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
         int b0 = T.lvl_blk_off[l], nb = T.lvl_blk_off[l + 1] - b0;
         const uint32_t *Ls = (l & 1) ? L1 : L0;
         uint32_t *Ld = (l & 1) ? L0 : L1;
-        k_lvl_flags<<<nb, LVL_THREADS, 0, s>>>(Ls, n, t.xr, t.blk_node + b0, t.blk_start + b0,
-                                              t.blk_end + b0, t.first, t.count, t.flag, t.axis);
-        k_lvl_count<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(Ls, n, t.blk_start + b0, t.blk_end + b0,
-                                                       t.flag, t.lvl_cnt, T.max_lvl_blocks);
+        k_lvl_count<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
+            Ls, n, t.xr, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.first, t.count,
+            t.axis, t.lvl_cnt, T.max_lvl_blocks);
         k_lvl_scan<<<4, 1024, 0, s>>>(t.lvl_cnt, t.lvl_pre, nb, T.max_lvl_blocks);
         k_lvl_scatter<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
-            Ls, Ld, n, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.blk_first + b0,
-            t.first, t.count, t.flag, t.lvl_pre, T.max_lvl_blocks);
+            Ls, Ld, n, t.xr, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0,
+            t.blk_first + b0, t.first, t.count, t.lvl_pre, T.max_lvl_blocks);
     }
     int nsub = (int)T.sub_root.size();
     k_subtree<<<nsub, SUBTREE_THREADS, 0, s>>>(t.lists, n, t.xr, t.r2o, t.sub_root, t.first,
