@@ -350,6 +350,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 double4 xn = xj, hn = hj;
                 if (kb + 8 < nc)
                     load_src(pm, ph, R[kb + 8 + grp], slot, xn, hn);
+                const double mh = 0.5 * xj.w;
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
                     const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                         const double u3 = u * u * u;
                         const double gi = m4g_f64(r * shi[q], sh3[q], u3);
                         const double gj = m4g_f64(r * hj.x, hj.y, u3);
-                        fm = xj.w * 0.5 * (gi + gj);
+                        fm = mh * (gi + gj);
                     }
                     acc[3 * q] -= fm * dx;
                     acc[3 * q + 1] -= fm * dy;
