@@ -136,8 +136,12 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f64(
         L[k] = 0.0;
     const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
     const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
+    // the next source's index is loaded one interaction ahead
+    int bn = sub < nk ? fl[sub] : 0;
     for (int k = sub; k < nk; k += 16) {
-        const int b = fl[k];
+        const int b = bn;
+        if (k + 16 < nk)
+            bn = fl[k + 16];
         const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
         const double *qb = recQ + (int64_t)NREC * b;
         const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
@@ -422,8 +426,11 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f32(
         L[k] = 0.0f;
     const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
     const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
+    int bn = sub < nk ? fl[sub] : 0;
     for (int k = sub; k < nk; k += 16) {
-        const int b = fl[k];
+        const int b = bn;
+        if (k + 16 < nk)
+            bn = fl[k + 16];
         const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
         const float4 f0 = *(const float4 *)(recF + (int64_t)NREC * b);
         const float4 f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
