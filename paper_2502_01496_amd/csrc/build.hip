@@ -425,10 +425,13 @@ __device__ __forceinline__ uint32_t goes_left(const Split &S, const double *xr, 
     return (o < S.ob || (o == S.ob && r <= S.rm)) ? 1u : 0u;
 }
 
+// Sides of a chunk of one list (also stored per position for the scatter)
+// and the chunk's left count.
 __global__ __launch_bounds__(LVL_THREADS) void k_lvl_count(
     const uint32_t *__restrict__ L, int64_t n, const double *__restrict__ xr,
     const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
-    const int32_t *first, const int32_t *count, int32_t *axis_out, int32_t *cnt, int stride)
+    const int32_t *first, const int32_t *count, int32_t *axis_out, uint8_t *side, int32_t *cnt,
+    int stride)
 {
     __shared__ uint32_t sh[8];
     int b = blockIdx.x, d = blockIdx.y;
@@ -437,9 +440,13 @@ __global__ __launch_bounds__(LVL_THREADS) void k_lvl_count(
     if (d == 0 && threadIdx.x == 0 && blk_start[b] == S.f)
         axis_out[v] = S.ax;
     const uint32_t *Ld = L + d * n;
+    uint8_t *sd = side + d * n;
     uint32_t c = 0;
-    for (int64_t p = blk_start[b] + threadIdx.x; p < blk_end[b]; p += LVL_THREADS)
-        c += goes_left(S, xr, n, d, p, Ld[p]);
+    for (int64_t p = blk_start[b] + threadIdx.x; p < blk_end[b]; p += LVL_THREADS) {
+        const uint32_t g = goes_left(S, xr, n, d, p, Ld[p]);
+        sd[p] = (uint8_t)g;
+        c += g;
+    }
     uint32_t total;
     block_excl_scan_u32(c, sh, total);
     if (threadIdx.x == 0)
@@ -463,49 +470,58 @@ __global__ __launch_bounds__(1024) void k_lvl_scan(const int32_t *cnt, int32_t *
     }
 }
 
+// Stable partition of one chunk of one list: the chunk is staged in LDS,
+// each thread ranks PER consecutive entries, the chunk's left and right runs
+// are assembled in LDS and written out as two contiguous runs.
 __global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
-    const uint32_t *__restrict__ Lsrc, uint32_t *Ldst, int64_t n, const double *__restrict__ xr,
+    const uint32_t *__restrict__ Lsrc, uint32_t *Ldst, int64_t n, const uint8_t *__restrict__ side,
     const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
     const int32_t *blk_first, const int32_t *first, const int32_t *count, const int32_t *pre,
     int stride)
 {
     constexpr int PER = LVL_CHUNK / LVL_THREADS;
     __shared__ uint32_t sh[8];
-    int b = blockIdx.x, d = blockIdx.y;
-    int v = blk_node[b];
-    const Split S = node_split(Lsrc, n, xr, first[v], count[v]);
-    const int64_t f = S.f, nl = S.nl;
-    int64_t s = blk_start[b], e = blk_end[b];
-    const uint32_t *Ls = Lsrc + d * n;
+    __shared__ uint32_t sv[LVL_CHUNK];
+    __shared__ uint32_t so[LVL_CHUNK];
+    __shared__ uint8_t sf[LVL_CHUNK];
+    const int b = blockIdx.x, d = blockIdx.y, t = threadIdx.x;
+    const int v = blk_node[b];
+    const int64_t f = first[v], nl = (count[v] + 1) / 2;
+    const int64_t s = blk_start[b];
+    const int len = (int)(blk_end[b] - s);
+    const uint32_t *Ls = Lsrc + d * n + s;
+    const uint8_t *sd = side + d * n + s;
     uint32_t *Ld = Ldst + d * n;
-    uint32_t r[PER];
+    for (int i = t; i < len; i += LVL_THREADS) {
+        sv[i] = Ls[i];
+        sf[i] = sd[i];
+    }
+    __syncthreads();
     uint32_t fl[PER];
     uint32_t mine = 0;
-    int64_t p0 = s + (int64_t)threadIdx.x * PER;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        int64_t p = p0 + k;
-        r[k] = p < e ? Ls[p] : 0u;
-        fl[k] = p < e ? goes_left(S, xr, n, d, p, r[k]) : 0u;
+        const int i = t * PER + k;
+        fl[k] = i < len ? sf[i] : 0u;
         mine += fl[k];
     }
-    uint32_t total;
-    uint32_t ex = block_excl_scan_u32(mine, sh, total);
-    int64_t nb = (int64_t)(pre[d * stride + b] - pre[d * stride + blk_first[b]]) + ex;
+    uint32_t nleft;
+    uint32_t lx = block_excl_scan_u32(mine, sh, nleft);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        int64_t p = p0 + k;
-        if (p < e) {
-            int64_t pos;
-            if (fl[k]) {
-                pos = f + nb;
-                ++nb;
-            } else {
-                pos = f + nl + (p - f - nb);
-            }
-            Ld[pos] = r[k];
+        const int i = t * PER + k;
+        if (i < len) {
+            const uint32_t pos = fl[k] ? lx : nleft + (uint32_t)i - lx;
+            so[pos] = sv[i];
+            lx += fl[k];
         }
     }
+    __syncthreads();
+    // left entries of the node before this chunk, then the two runs
+    const int64_t nb = (int64_t)(pre[d * stride + b] - pre[d * stride + blk_first[b]]);
+    const int64_t lbase = f + nb, rbase = f + nl + (s - f - nb);
+    for (int i = t; i < len; i += LVL_THREADS)
+        Ld[i < (int)nleft ? lbase + i : rbase + (i - (int)nleft)] = so[i];
 }
 
 // ---------------------------------------------------------------- LDS subtrees
@@ -759,10 +775,10 @@ hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
         uint32_t *Ld = (l & 1) ? L0 : L1;
         k_lvl_count<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
             Ls, n, t.xr, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.first, t.count,
-            t.axis, t.lvl_cnt, T.max_lvl_blocks);
+            t.axis, t.side, t.lvl_cnt, T.max_lvl_blocks);
         k_lvl_scan<<<4, 1024, 0, s>>>(t.lvl_cnt, t.lvl_pre, nb, T.max_lvl_blocks);
         k_lvl_scatter<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
-            Ls, Ld, n, t.xr, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0,
+            Ls, Ld, n, t.side, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0,
             t.blk_first + b0, t.first, t.count, t.lvl_pre, T.max_lvl_blocks);
     }
     int nsub = (int)T.sub_root.size();
