@@ -16,7 +16,7 @@ namespace fmm {
 // workgroup's LDS (all their descendants in one launch).
 constexpr int SUBTREE_MAX = 2048;
 constexpr int SUBTREE_MAXSEG = SUBTREE_MAX / 2;
-constexpr int SUBTREE_THREADS = 512;
+constexpr int SUBTREE_THREADS = 1024;
 // Positions handled by one workgroup in the per-level partition kernels.
 constexpr int LVL_CHUNK = 2048;
 constexpr int LVL_THREADS = 256;
