@@ -228,9 +228,9 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->bbox, 8));
     A(dalloc(*t, &t->err, 4));
     A(dalloc(*t, &t->perm, n));
-    A(dalloc(*t, &t->pm, n));
+    A(dalloc(*t, &t->pm, n + 1));  // + the null source record
     A(dalloc(*t, &t->hs, n));
-    A(dalloc(*t, &t->ph, n));
+    A(dalloc(*t, &t->ph, n + 1));
     A(dalloc(*t, &t->pf, n));
     A(dalloc(*t, &t->pfh, n));
     A(dalloc(*t, &t->recA, NREC * nn));

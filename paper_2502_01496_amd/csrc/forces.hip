@@ -266,17 +266,44 @@ __device__ __forceinline__ int close_first_slot(bool act, bool close, int &front
     return pos;
 }
 
+// Missing sources read the null record at index n (far away, zero mass,
+// zero smoothing length), so they add exactly zero.
 __device__ __forceinline__ void load_src(const double4 *__restrict__ pm,
-                                         const double4 *__restrict__ ph, int2 rg, int slot,
-                                         double4 &xj, double4 &hj)
+                                         const double4 *__restrict__ ph, int64_t nnull, int2 rg,
+                                         int slot, double4 &xj, double4 &hj)
 {
-    const bool valid = slot < rg.y;
-    const int64_t j = (int64_t)rg.x + (valid ? slot : 0);
+    const int64_t j = slot < rg.y ? (int64_t)rg.x + slot : nnull;
     xj = pm[j];
     hj = ph[j];
-    if (!valid) {
-        xj = make_double4(1e30, 1e30, 1e30, 0.0);
-        hj.z = 0.0;
+}
+
+// Pairs of one step: the NS wave-uniform sinks against this lane's source.
+template <int NS>
+__device__ __forceinline__ void p2p_step_f64(const double (&sx)[NS], const double (&sy)[NS],
+                                             const double (&sz)[NS], const double (&shi)[NS],
+                                             const double (&sh3)[NS], const double (&sh4)[NS],
+                                             const double4 xj, const double4 hj,
+                                             double (&acc)[3 * NS])
+{
+    const double mh = 0.5 * xj.w;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double fm;
+        if ((__ballot(r2 < hj.z) | __ballot(r2 < sh4[q])) == 0ull) {
+            fm = m_over_r3(r2, xj.w);
+        } else {
+            const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+            const double r = r2 * u;
+            const double u3 = u * u * u;
+            const double gi = m4g_f64(r * shi[q], sh3[q], u3);
+            const double gj = m4g_f64(r * hj.x, hj.y, u3);
+            fm = mh * (gi + gj);
+        }
+        acc[3 * q] -= fm * dx;
+        acc[3 * q + 1] -= fm * dy;
+        acc[3 * q + 2] -= fm * dz;
     }
 }
 
@@ -286,7 +313,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
     const int32_t *__restrict__ near_src, int cap_near, int nsub, const double *__restrict__ Lloc,
     const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double r_kern,
-    double *aout)
+    int64_t nnull, double *aout)
 {
     constexpr int NS = 4;
     __shared__ int2 rng[4][P2P_RANGES];
@@ -348,32 +375,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     R[k] = r;
             }
             __builtin_amdgcn_wave_barrier();
+            // the next step's sources load while the current step computes
             double4 xj, hj;
-            load_src(pm, ph, R[grp], slot, xj, hj);
+            load_src(pm, ph, nnull, R[grp], slot, xj, hj);
             for (int kb = 0; kb < nc; kb += 8) {
                 double4 xn = xj, hn = hj;
                 if (kb + 8 < nc)
-                    load_src(pm, ph, R[kb + 8 + grp], slot, xn, hn);
-                const double mh = 0.5 * xj.w;
-#pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    double fm;
-                    if ((__ballot(r2 < hj.z) | __ballot(r2 < sh4[q])) == 0ull) {
-                        fm = m_over_r3(r2, xj.w);
-                    } else {
-                        const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
-                        const double r = r2 * u;
-                        const double u3 = u * u * u;
-                        const double gi = m4g_f64(r * shi[q], sh3[q], u3);
-                        const double gj = m4g_f64(r * hj.x, hj.y, u3);
-                        fm = mh * (gi + gj);
-                    }
-                    acc[3 * q] -= fm * dx;
-                    acc[3 * q + 1] -= fm * dy;
-                    acc[3 * q + 2] -= fm * dz;
-                }
+                    load_src(pm, ph, nnull, R[kb + 8 + grp], slot, xn, hn);
+                p2p_step_f64<NS>(sx, sy, sz, shi, sh3, sh4, xj, hj, acc);
                 xj = xn;
                 hj = hn;
             }
@@ -824,7 +833,7 @@ hipError_t launch_near(Tree &t, void *a, hipStream_t s)
         k_p2p_src_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node, nl,
                                                    t.near_cnt, t.near_src, (int)t.cap_near, nsub,
                                                    t.L, t.recA, t.perm, t.p.G, t.p.r_kern,
-                                                   (double *)a);
+                                                   T.n, (double *)a);
     else
         k_p2p_src_f32<<<(nl + 3) / 4, 256, 0, s>>>(t.pf, t.pfh, t.first, t.count,
                                                    t.leaf_node, nl, t.near_cnt, t.near_src,

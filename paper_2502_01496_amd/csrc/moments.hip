@@ -48,6 +48,10 @@ __global__ void k_gather(const double *__restrict__ x, const double *__restrict_
         s2bits[v] = 0ull;
         upcnt[v] = 0;
     }
+    if (gid == 0) {  // null source record at index n (far away, no mass, no smoothing)
+        pm[n] = make_double4(1e30, 1e30, 1e30, 0.0);
+        ph[n] = make_double4(0.0, 0.0, 0.0, 0.0);
+    }
     // OR-reduce the error bits over the wave, one atomic per wave
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
