@@ -219,6 +219,8 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->vals1, 3 * n));
     A(dalloc(*t, &t->rs_hist, 3 * 256 * nblk));
     A(dalloc(*t, &t->rs_tot, (size_t)RS_PASSES * 3 * 256));
+    A(dalloc(*t, &t->run_cnt, 1));
+    A(dalloc(*t, &t->run_list, 3 * (n / 65 + 1)));
     A(dalloc(*t, &t->r2o, n));
     A(dalloc(*t, &t->xr, 3 * n));
     A(dalloc(*t, &t->lists, 8 * n));
@@ -450,6 +452,8 @@ static fmm_status ensure_mutual(Tree &t, int64_t cap_task, int64_t cap_far, int6
 
 static fmm_status bad_input(uint32_t errbits)
 {
+    if (!(errbits & 7u))
+        return fail(FMM_ERR_HIP, "internal error in the tree build (flags 0x%x)", errbits);
     return fail(FMM_ERR_INVALID, "bad input data:%s%s%s",
                 (errbits & 1) ? " non-finite positions" : "",
                 (errbits & 2) ? " masses not positive and finite" : "",

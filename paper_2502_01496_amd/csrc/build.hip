@@ -367,11 +367,203 @@ hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
     return hipGetLastError();
 }
 
-static hipError_t radix_sort(Tree &t, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
-                             int64_t n, int B, hipStream_t s)
+// ---------------------------------------------------------------- (key, value) by halves
+// Order by (key, value), the values being the input positions (so this is a
+// stable sort by key): four LSD passes over the high 32 key bits, then the
+// runs of equal high halves are put in (low half, value) order.  Runs of at
+// most RUN_SHORT entries are ranked by one thread per entry; the (rare)
+// longer ones by one workgroup each.  For the sorts of the build (Morton keys
+// and ordered coordinate bits of spread-out particles) nearly every run has
+// one entry, so this replaces the four low passes by one light pass.
+constexpr int RUN_SHORT = 64;
+
+__device__ __forceinline__ uint32_t hi32(uint64_t k) { return (uint32_t)(k >> 32); }
+
+__global__ __launch_bounds__(256) void k_run_fix(const uint64_t *__restrict__ kin,
+                                                 const uint32_t *__restrict__ vin, uint64_t *kout,
+                                                 uint32_t *vout, int64_t n, uint32_t *long_cnt,
+                                                 int64_t *long_list, int64_t long_cap,
+                                                 uint32_t *err)
 {
-    return radix_sort_u64(k0, v0, k1, v1, n, B, RS_PASSES, t.rs_hist, t.rs_tot, s);
+    const int b = blockIdx.y;
+    const uint64_t *k = kin + (int64_t)b * n;
+    const uint32_t *v = vin + (int64_t)b * n;
+    uint64_t *ko = kout + (int64_t)b * n;
+    uint32_t *vo = vout + (int64_t)b * n;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * 256) {
+        const uint64_t kp = k[p];
+        const uint32_t hp = hi32(kp);
+        int64_t a = p;
+        while (a > 0 && p - a < RUN_SHORT && hi32(k[a - 1]) == hp)
+            --a;
+        bool lng = a > 0 && hi32(k[a - 1]) == hp;
+        int64_t e = p + 1;
+        while (!lng && e < n && e - p <= RUN_SHORT && hi32(k[e]) == hp)
+            ++e;
+        lng = lng || (e < n && hi32(k[e]) == hp) || e - a > RUN_SHORT;
+        if (lng) {
+            if (a == p && (p == 0 || hi32(k[p - 1]) != hp)) {
+                const uint32_t slot = atomicAdd(long_cnt, 1u);
+                if ((int64_t)slot < long_cap)
+                    long_list[slot] = ((int64_t)b << 40) | p;
+                else
+                    atomicOr(err, 8u);
+            }
+            continue;
+        }
+        const uint32_t vp = v[p];
+        if (e - a == 1) {
+            ko[p] = kp;
+            vo[p] = vp;
+            continue;
+        }
+        const uint32_t lp = (uint32_t)kp;
+        int64_t r = 0;
+        for (int64_t q = a; q < e; ++q) {
+            const uint32_t lq = (uint32_t)k[q], vq = v[q];
+            r += (lq < lp || (lq == lp && vq < vp)) ? 1 : 0;
+        }
+        ko[a + r] = kp;
+        vo[a + r] = vp;
+    }
 }
+
+// One workgroup per long run: find its end, then a stable LSD radix sort of
+// the composite (low key half, value) in eight 8-bit passes, ping-ponging
+// between the run's segments of the input and output arrays.
+__global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t *vin,
+                                                         uint64_t *kout, uint32_t *vout, int64_t n,
+                                                         const uint32_t *__restrict__ long_cnt,
+                                                         const int64_t *__restrict__ long_list,
+                                                         int64_t long_cap)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    __shared__ uint32_t ctot[256];
+    __shared__ int64_t end_sh;
+    const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const int64_t nl = min((int64_t)*long_cnt, long_cap);
+    for (int64_t r = blockIdx.x; r < nl; r += gridDim.x) {
+        const int64_t code = long_list[r];
+        const int b = (int)(code >> 40);
+        const int64_t a = code & ((1ll << 40) - 1);
+        uint64_t *K[2] = {kin + (int64_t)b * n, kout + (int64_t)b * n};
+        uint32_t *V[2] = {vin + (int64_t)b * n, vout + (int64_t)b * n};
+        const uint32_t hp = hi32(K[0][a]);
+        // end of the run: first position with another high half (or n)
+        if (t == 0)
+            end_sh = n;
+        __syncthreads();
+        for (int64_t c0 = a; c0 < n; c0 += RS_THREADS) {
+            const int64_t q = c0 + t;
+            if (q < n && hi32(K[0][q]) != hp)
+                atomicMin((unsigned long long *)&end_sh, (unsigned long long)q);
+            __syncthreads();
+            const bool found = end_sh < n;
+            __syncthreads();
+            if (found)
+                break;
+        }
+        const int64_t L = end_sh - a;
+        for (int pass = 0; pass < 8; ++pass) {
+            const int src = pass & 1, dst = src ^ 1;
+            const uint64_t *ks = K[src] + a;
+            const uint32_t *vs = V[src] + a;
+            uint64_t *kd = K[dst] + a;
+            uint32_t *vd = V[dst] + a;
+            const int sh = 8 * (pass & 3);
+            auto digit = [&](int64_t i) -> uint32_t {
+                return pass < 4 ? (vs[i] >> sh) & 255u : ((uint32_t)ks[i] >> sh) & 255u;
+            };
+            if (t < 256)
+                hist[t] = 0u;
+            __syncthreads();
+            for (int64_t i = t; i < L; i += RS_THREADS)
+                atomicAdd(&hist[digit(i)], 1u);
+            __syncthreads();
+            if (t == 0) {
+                uint32_t run = 0;
+                for (int d = 0; d < 256; ++d) {
+                    base[d] = run;
+                    run += hist[d];
+                }
+            }
+            __syncthreads();
+            for (int64_t c0 = 0; c0 < L; c0 += RS_THREADS) {
+                const int64_t i = c0 + t;
+                const bool valid = i < L;
+                const uint32_t d = valid ? digit(i) : 0u;
+                for (int j = t; j < RS_WAVES * 256; j += RS_THREADS)
+                    (&wcnt[0][0])[j] = 0u;
+                __syncthreads();
+                const uint64_t peers = match_u8(d, valid);
+                const uint32_t rk = (uint32_t)__popcll(peers & lt);
+                if (valid && (peers & lt) == 0ull)
+                    wcnt[w][d] = (uint32_t)__popcll(peers);
+                __syncthreads();
+                if (t < 256) {
+                    uint32_t run = 0;
+                    for (int ww = 0; ww < RS_WAVES; ++ww) {
+                        const uint32_t c = wcnt[ww][t];
+                        wcnt[ww][t] = run;
+                        run += c;
+                    }
+                    ctot[t] = run;
+                }
+                __syncthreads();
+                if (valid) {
+                    const int64_t pos = (int64_t)base[d] + wcnt[w][d] + rk;
+                    kd[pos] = ks[i];
+                    vd[pos] = vs[i];
+                }
+                __syncthreads();
+                if (t < 256)
+                    base[t] += ctot[t];
+                __syncthreads();
+            }
+        }
+        // eight passes end in the input arrays: copy the run to the output
+        for (int64_t i = t; i < L; i += RS_THREADS) {
+            K[1][a + i] = K[0][a + i];
+            V[1][a + i] = V[0][a + i];
+        }
+        __syncthreads();
+    }
+}
+
+// Sort B arrays of (key, position) pairs held in (k0, v0); the result lands
+// in (k1, v1).  work: B * (n / (RUN_SHORT + 1) + 1) int64 for the long-run
+// list plus one counter word.
+hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
+                          int B, uint32_t *hist, uint32_t *tot, uint32_t *long_cnt,
+                          int64_t *long_list, uint32_t *err, hipStream_t s)
+{
+    const int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
+    if (nblk == 0)
+        return hipSuccess;
+    const int64_t long_cap = (int64_t)B * (n / (RUN_SHORT + 1) + 1);
+    k_rs_zero<<<64, 256, 0, s>>>(tot, (int64_t)4 * B * 256);
+    k_rs_zero<<<1, 64, 0, s>>>(long_cnt, 1);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 32 + 8 * pass;
+        uint64_t *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
+        uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
+        uint32_t *tp = tot + (int64_t)pass * B * 256;
+        dim3 g(nblk, B);
+        k_rs_hist<<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
+        k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
+        k_rs_scatter<<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
+    }
+    const int gf = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    k_run_fix<<<dim3(gf, B), 256, 0, s>>>(k0, v0, k1, v1, n, long_cnt, long_list, long_cap, err);
+    k_run_long<<<256, RS_THREADS, 0, s>>>(k0, v0, k1, v1, n, long_cnt, long_list, long_cap);
+    return hipGetLastError();
+}
+
+
 
 // ---------------------------------------------------------------- level kernels
 // Longest axis of a node from its three sorted lists (first = min, last = max).
@@ -754,19 +946,22 @@ hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
     const int gs = (int)std::min<int64_t>((n + 255) / 256, 2048);
     k_bbox_init<<<1, 64, 0, s>>>(t.bbox, t.err);
     k_bbox<<<(int)std::min<int64_t>((n + 255) / 256, 256), 256, 0, s>>>(x, n, t.bbox, t.err);
-    k_morton<<<gs, 256, 0, s>>>(x, n, t.bbox, t.keys0, t.vals0);
-    hipError_t e = radix_sort(t, t.keys0, t.vals0, t.keys1, t.vals1, n, 1, s);
+    // Morton keys in (keys1, vals1) -> sorted into (keys0, vals0)
+    k_morton<<<gs, 256, 0, s>>>(x, n, t.bbox, t.keys1, t.vals1);
+    hipError_t e = sort_by_halves(t.keys1, t.vals1, t.keys0, t.vals0, n, 1, t.rs_hist, t.rs_tot,
+                                  t.run_cnt, t.run_list, t.err, s);
     if (e != hipSuccess)
         return e;
     // lists buffer 0: axis lists 0..2 and the rank list 3
     uint32_t *L0 = t.lists, *L1 = t.lists + 4 * n;
     k_rank_gather<<<gs, 256, 0, s>>>(x, n, t.vals0, t.r2o, t.xr, t.keys1, t.vals1, L0 + 3 * n);
-    // sort the three axis arrays (keys1, vals1) -> result in keys1/vals1 after 8 passes;
-    // the values are the Morton ranks, copied into list buffer 0.
-    e = radix_sort(t, t.keys1, t.vals1, t.keys0, t.vals0, n, 3, s);
+    // the three axis arrays (keys1, vals1) -> sorted into (keys0, vals0); the
+    // values are the Morton ranks, copied into list buffer 0.
+    e = sort_by_halves(t.keys1, t.vals1, t.keys0, t.vals0, n, 3, t.rs_hist, t.rs_tot, t.run_cnt,
+                       t.run_list, t.err, s);
     if (e != hipSuccess)
         return e;
-    e = hipMemcpyAsync(L0, t.vals1, sizeof(uint32_t) * 3 * n, hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(L0, t.vals0, sizeof(uint32_t) * 3 * n, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess)
         return e;
     for (int l = 0; l < T.nlevels_up; ++l) {

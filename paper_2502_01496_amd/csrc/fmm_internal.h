@@ -128,6 +128,8 @@ struct Tree {
     uint64_t *keys0 = nullptr, *keys1 = nullptr;  // 3n each (batched sorts)
     uint32_t *vals0 = nullptr, *vals1 = nullptr;
     uint32_t *rs_hist = nullptr, *rs_tot = nullptr;
+    uint32_t *run_cnt = nullptr;  // long runs of equal high key halves: count, list
+    int64_t *run_list = nullptr;
     int32_t *r2o = nullptr;       // Morton rank -> caller index
     double *xr = nullptr;         // coordinates by Morton rank, 3 x n SoA
     uint32_t *lists = nullptr;    // 2 buffers x 4 lists x n
