@@ -226,7 +226,6 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->lists, 8 * n));
     A(dalloc(*t, &t->side, 4 * n));
     A(dalloc(*t, &t->lvl_cnt, 4 * (size_t)std::max(1, T.max_lvl_blocks)));
-    A(dalloc(*t, &t->lvl_pre, 4 * (size_t)std::max(1, T.max_lvl_blocks)));
     A(dalloc(*t, &t->bbox, 8));
     A(dalloc(*t, &t->err, 4));
     A(dalloc(*t, &t->perm, n));

@@ -645,30 +645,13 @@ __global__ __launch_bounds__(LVL_THREADS) void k_lvl_count(
         cnt[d * stride + b] = (int32_t)total;
 }
 
-__global__ __launch_bounds__(1024) void k_lvl_scan(const int32_t *cnt, int32_t *pre, int nb,
-                                                   int stride)
-{
-    __shared__ uint32_t sh[16];
-    int d = blockIdx.x;
-    uint32_t run = 0;
-    for (int c0 = 0; c0 < nb; c0 += 1024) {
-        int i = c0 + threadIdx.x;
-        uint32_t v = i < nb ? (uint32_t)cnt[d * stride + i] : 0u;
-        uint32_t total;
-        uint32_t ex = block_excl_scan_u32(v, sh, total);
-        if (i < nb)
-            pre[d * stride + i] = (int32_t)(run + ex);
-        run += total;
-    }
-}
-
 // Stable partition of one chunk of one list: the chunk is staged in LDS,
 // each thread ranks PER consecutive entries, the chunk's left and right runs
 // are assembled in LDS and written out as two contiguous runs.
 __global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
     const uint32_t *__restrict__ Lsrc, uint32_t *Ldst, int64_t n, const uint8_t *__restrict__ side,
     const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
-    const int32_t *blk_first, const int32_t *first, const int32_t *count, const int32_t *pre,
+    const int32_t *blk_first, const int32_t *first, const int32_t *count, const int32_t *cnt,
     int stride)
 {
     constexpr int PER = LVL_CHUNK / LVL_THREADS;
@@ -709,8 +692,14 @@ __global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
         }
     }
     __syncthreads();
-    // left entries of the node before this chunk, then the two runs
-    const int64_t nb = (int64_t)(pre[d * stride + b] - pre[d * stride + blk_first[b]]);
+    // left entries of the node before this chunk (sum of the counts of the
+    // node's earlier chunks), then the two runs
+    uint32_t part = 0;
+    for (int j = blk_first[b] + t; j < b; j += LVL_THREADS)
+        part += (uint32_t)cnt[d * stride + j];
+    uint32_t before;
+    block_excl_scan_u32(part, sh, before);
+    const int64_t nb = (int64_t)before;
     const int64_t lbase = f + nb, rbase = f + nl + (s - f - nb);
     for (int i = t; i < len; i += LVL_THREADS)
         Ld[i < (int)nleft ? lbase + i : rbase + (i - (int)nleft)] = so[i];
@@ -971,10 +960,9 @@ hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
         k_lvl_count<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
             Ls, n, t.xr, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.first, t.count,
             t.axis, t.side, t.lvl_cnt, T.max_lvl_blocks);
-        k_lvl_scan<<<4, 1024, 0, s>>>(t.lvl_cnt, t.lvl_pre, nb, T.max_lvl_blocks);
         k_lvl_scatter<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
             Ls, Ld, n, t.side, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0,
-            t.blk_first + b0, t.first, t.count, t.lvl_pre, T.max_lvl_blocks);
+            t.blk_first + b0, t.first, t.count, t.lvl_cnt, T.max_lvl_blocks);
     }
     int nsub = (int)T.sub_root.size();
     k_subtree<<<nsub, SUBTREE_THREADS, 0, s>>>(t.lists, n, t.xr, t.r2o, t.sub_root, t.first,

@@ -134,7 +134,7 @@ struct Tree {
     double *xr = nullptr;         // coordinates by Morton rank, 3 x n SoA
     uint32_t *lists = nullptr;    // 2 buffers x 4 lists x n
     uint8_t *side = nullptr;      // 4 x n: side of each list entry at the current level
-    int32_t *lvl_cnt = nullptr, *lvl_pre = nullptr;
+    int32_t *lvl_cnt = nullptr;
     uint64_t *bbox = nullptr;     // ordered bits: min xyz, max xyz
     uint32_t *err = nullptr;      // device error flags (bit 0 x, bit 1 m, bit 2 h)
     int32_t *perm = nullptr;      // tree position -> caller index

@@ -13,6 +13,8 @@
 //
 // Compiled with -ffp-contract=off so the criteria are evaluated with exactly
 // the operations of their definition.
+#include <algorithm>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -216,15 +218,18 @@ __global__ void k_walk_init(int32_t *maxcnt) {
         maxcnt[threadIdx.x] = 0;
 }
 
-// Largest far and near list over all leaves (one workgroup; the overflow flag
-// in maxcnt[2] is left as the walk set it).
+// Largest far and near list over all leaves: per-workgroup maxima, then one
+// atomicMax per workgroup into maxcnt[0..1] (zeroed by k_walk_init; the
+// overflow flag in maxcnt[2] is left as the walk set it).
+constexpr int LIST_MAX_BLOCKS = 64;
+
 __global__ __launch_bounds__(1024) void k_list_max(const int32_t *__restrict__ far_cnt,
                                                    const int32_t *__restrict__ near_cnt, int n,
                                                    int32_t *maxcnt)
 {
     __shared__ int32_t sh[2][16];
     int mf = 0, mn = 0;
-    for (int i = threadIdx.x; i < n; i += 1024) {
+    for (int i = blockIdx.x * 1024 + threadIdx.x; i < n; i += gridDim.x * 1024) {
         mf = max(mf, far_cnt[i]);
         mn = max(mn, near_cnt[i]);
     }
@@ -244,8 +249,8 @@ __global__ __launch_bounds__(1024) void k_list_max(const int32_t *__restrict__ f
             mf = max(mf, sh[0][i]);
             mn = max(mn, sh[1][i]);
         }
-        maxcnt[0] = mf;
-        maxcnt[1] = mn;
+        atomicMax(&maxcnt[0], mf);
+        atomicMax(&maxcnt[1], mn);
     }
 }
 
@@ -260,7 +265,8 @@ hipError_t launch_walk(Tree &t, hipStream_t s)
         t.recA, t.left, t.right, t.leaf_node, nl, theta2, t.p.r_kern, t.far_src, (int)t.cap_far,
         t.near_src, (int)t.cap_near, t.far_cnt, t.near_cnt, t.walk_flags + 2,
         std::min(std::max(t.wide_stack_limit, 2), WIDE_STACK));
-    k_list_max<<<1, 1024, 0, s>>>(t.far_cnt, t.near_cnt, nl, t.walk_flags);
+    k_list_max<<<std::min(LIST_MAX_BLOCKS, (nl + 1023) / 1024), 1024, 0, s>>>(t.far_cnt, t.near_cnt,
+                                                                           nl, t.walk_flags);
     return hipGetLastError();
 }
 
@@ -273,7 +279,8 @@ hipError_t launch_walk_fallback(Tree &t, hipStream_t s)
                                                t.p.r_kern, t.far_src, (int)t.cap_far, t.near_src,
                                                (int)t.cap_near, t.far_cnt, t.near_cnt,
                                                t.walk_flags);
-    k_list_max<<<1, 1024, 0, s>>>(t.far_cnt, t.near_cnt, nl, t.walk_flags);
+    k_list_max<<<std::min(LIST_MAX_BLOCKS, (nl + 1023) / 1024), 1024, 0, s>>>(t.far_cnt, t.near_cnt,
+                                                                           nl, t.walk_flags);
     return hipGetLastError();
 }
 
