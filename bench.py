@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--vjp-reps", type=int, default=5,
+                    help="timed VJP calls at the final state (0 = skip)")
     ap.add_argument("--mutual-steps", type=int, default=5,
                     help="KDK steps of the mutual-walk contrast (FP64; 0 = skip)")
     return ap.parse_args()
@@ -201,6 +203,22 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
     tag = ("fp32" if prec == F.FMM_FP32 else "fp64") + ("/mutual" if walk else "")
     log(f"[bench {tag}] {steps} steps in {elapsed:.3f}s -> {ms_step:.3f} ms/step, "
         f"{value:.4e} particle-forces/s; stages (ms/call) {stages}")
+    # reverse pass at the final state (tree and lists of the last step), timed
+    # by the library's events: VJP of the accelerations for a normal cotangent
+    vjp_ms = None
+    if walk == F.FMM_WALK_PHANTOM and args.vjp_reps > 0:
+        abar = torch.randn((n, 3), dtype=adt, device=dev, generator=torch.Generator(dev).manual_seed(7))
+        xb = torch.empty((n, 3), dtype=adt, device=dev)
+        mb = torch.empty(n, dtype=adt, device=dev)
+        F.fmm_forces_vjp(g.tree, abar, xb, mb)        # builds the transposed lists
+        torch.cuda.synchronize()
+        F.fmm_set_timing(g.tree, True)
+        for _ in range(args.vjp_reps):
+            F.fmm_forces_vjp(g.tree, abar, xb, mb)
+        torch.cuda.synchronize()
+        vjp_ms = F.fmm_stage_times(g.tree)["vjp"]
+        F.fmm_set_timing(g.tree, False)
+        log(f"[bench {tag}] VJP {vjp_ms:.3f} ms per call (transposed lists reused)")
 
     info = F.fmm_tree_info(g.tree)
     ex = F.fmm_debug_export(g.tree, lists=True)
@@ -249,6 +267,7 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
         "sumF_ratio": {"first": st0["ratio"], "mean": float(np.mean(ratios)), "last": ratios[-1]},
         "com_drift": float(np.linalg.norm(xc[-1] - st0["xcom"])),
         "stages_ms": {k: round(v_, 4) for k, v_ in stages.items()},
+        "vjp_ms": round(vjp_ms, 4) if vjp_ms is not None else None,
         "forces_only": {"value": n / (fo_ms * 1e-3) if fo_ms > 0 else None,
                         "unit": "particle-forces/s", "stages": "walk + M2L + P2P/L2P"},
         "lists": {"far": info["n_far"], "near_leaf_pairs": info["n_near"], "p2p_pairs": pairs,
@@ -320,6 +339,7 @@ def main():
         "sumF_ratio": rec["sumF_ratio"],
         "com_drift": rec["com_drift"],
         "stages_ms": rec["stages_ms"],
+        "vjp_ms": rec["vjp_ms"],
         "forces_only": rec["forces_only"],
         "lists": rec["lists"],
         "roofline": rec["roofline"],

@@ -192,7 +192,14 @@ struct Tree {
     double *mbt = nullptr;         // mbar accumulator, tree order
     double *Lbar = nullptr;        // NLOC per node
     double *nadj = nullptr;        // 16 per node: cbar_sink[3], cbar_src[3], Mbar, Qbar[6]
-    int64_t *h_pairs = nullptr;    // pinned: far, near pair totals
+    int64_t *h_pairs = nullptr;    // pinned: pair totals, piece total
+    // pieces of the transposed far lists (source side of M2L^T)
+    int32_t *pcnt = nullptr;       // pieces per cell
+    int64_t *poff = nullptr;       // nnodes + 1 piece offsets
+    int64_t *pscan = nullptr;      // scan workspace
+    int32_t *pnode = nullptr;      // cell of each piece
+    double *ppart = nullptr;       // 10 sums per piece
+    int64_t npieces = 0, piece_cap = 0;
 
     MutualLists mw;
     int64_t mw_init_cap = 0;        // test hook: FMM_MI355_MW_CAP sets small first capacities

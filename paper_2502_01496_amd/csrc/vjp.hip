@@ -407,18 +407,41 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_sink(
     }
 }
 
-// 2b. M2L^T, source side: one wavefront per cell over the sinks that took it
-// as far field; writes Mbar, Qbar and cbar_src for every cell (zero if none),
-// and zeroes cbar_sink of internal cells.
-__global__ __launch_bounds__(256) void k_vjp_m2l_src(
-    const double *__restrict__ recA, const double *__restrict__ recQ, int nnodes,
-    const int32_t *__restrict__ left, const int64_t *__restrict__ toff,
-    const uint32_t *__restrict__ tsrc, const double *__restrict__ Lbar, double *nadj)
+// 2b. M2L^T, source side.  The sinks that took a cell as far field are
+// processed in pieces of M2LT_PIECE pairs (a cell high in the tree is far
+// field for a large part of the leaves, so one wavefront per cell would leave
+// a few wavefronts with most of the work): one wavefront per piece writes the
+// piece's sums, then one thread per cell adds its pieces in order
+// (deterministic).  Per cell: Mbar, Qbar and cbar_src (zero if none), and
+// cbar_sink of internal cells zeroed.
+constexpr int M2LT_PIECE = 256;
+
+__global__ void k_piece_count(const int64_t *__restrict__ toff, int nnodes, int32_t *pc)
 {
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (b >= nnodes)
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nnodes; b += gridDim.x * blockDim.x)
+        pc[b] = (int32_t)((toff[b + 1] - toff[b] + M2LT_PIECE - 1) / M2LT_PIECE);
+}
+
+__global__ void k_piece_fill(const int64_t *__restrict__ poff, int nnodes, int32_t *pnode)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nnodes; b += gridDim.x * blockDim.x)
+        for (int64_t j = poff[b]; j < poff[b + 1]; ++j)
+            pnode[j] = b;
+}
+
+__global__ __launch_bounds__(256) void k_vjp_m2l_src_piece(
+    const double *__restrict__ recA, const double *__restrict__ recQ,
+    const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc,
+    const double *__restrict__ Lbar, const int32_t *__restrict__ pnode,
+    const int64_t *__restrict__ poff, int64_t npieces, double *part)
+{
+    const int64_t pc = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pc >= npieces)
         return;
     const int lane = lane_id();
+    const int b = pnode[pc];
+    const int64_t e0 = toff[b] + (pc - poff[b]) * M2LT_PIECE;
+    const int64_t e1 = min(e0 + M2LT_PIECE, toff[b + 1]);
     const double *rbp = recA + (int64_t)NREC * b;
     const double cb0 = rbp[0], cb1 = rbp[1], cb2 = rbp[2], M = rbp[3];
     const double *Qs = recQ + (int64_t)NREC * b;
@@ -426,7 +449,7 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_src(
 #pragma unroll
     for (int k = 0; k < 10; ++k)
         acc[k] = 0.0;
-    for (int64_t e = toff[b] + lane; e < toff[b + 1]; e += 64) {
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
         const int sgm = (int)tsrc[e];
         const double *rs = recA + (int64_t)NREC * sgm;
         const double r[3] = {rs[0] - cb0, rs[1] - cb1, rs[2] - cb2};
@@ -448,17 +471,40 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_src(
     for (int k = 0; k < 10; ++k)
         acc[k] = wave_sum(acc[k]);
     if (lane == 0) {
-        double *na = nadj + 16 * (int64_t)b;
-        na[3] = acc[7];
-        na[4] = acc[8];
-        na[5] = acc[9];
-        na[6] = acc[0];
+        double *pp = part + 10 * pc;
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-            na[7 + k] = acc[1 + k];
-        if (left[b] >= 0)
-            na[0] = na[1] = na[2] = 0.0;
+        for (int k = 0; k < 10; ++k)
+            pp[k] = acc[k];
     }
+}
+
+__global__ __launch_bounds__(256) void k_vjp_m2l_src_fold(const int32_t *__restrict__ left,
+                                                          int nnodes,
+                                                          const int64_t *__restrict__ poff,
+                                                          const double *__restrict__ part,
+                                                          double *nadj)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nnodes)
+        return;
+    double acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+        acc[k] = 0.0;
+    for (int64_t pc = poff[b]; pc < poff[b + 1]; ++pc)
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            acc[k] += part[10 * pc + k];
+    double *na = nadj + 16 * (int64_t)b;
+    na[3] = acc[7];
+    na[4] = acc[8];
+    na[5] = acc[9];
+    na[6] = acc[0];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        na[7 + k] = acc[1 + k];
+    if (left[b] >= 0)
+        na[0] = na[1] = na[2] = 0.0;
 }
 
 // 3a. P2P^T, sink side: like the forward near field (source per lane, four
@@ -841,6 +887,9 @@ static hipError_t ensure_vjp_base(Tree &t)
     if (e == hipSuccess) e = valloc(t, &t.pair_off, T.nleaves + 1);
     if (e == hipSuccess) e = valloc(t, &t.vscan, T.nleaves / SCAN_TILE + 2);
     if (e == hipSuccess) e = valloc(t, &t.farT.off, nn + 1);
+    if (e == hipSuccess) e = valloc(t, &t.pcnt, nn);
+    if (e == hipSuccess) e = valloc(t, &t.poff, nn + 1);
+    if (e == hipSuccess) e = valloc(t, &t.pscan, nn / SCAN_TILE + 2);
     if (e == hipSuccess) e = valloc(t, &t.nearT.off, nn + 1);
     if (e == hipSuccess) e = hipHostMalloc((void **)&t.h_pairs, 4 * sizeof(int64_t), hipHostMallocDefault);
     return e;
@@ -916,6 +965,44 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     return e;
 }
 
+// Pieces of the transposed far lists for the source side of M2L^T.
+static hipError_t build_m2lt_pieces(Tree &t, hipStream_t s)
+{
+    const int nn = t.topo.nnodes;
+    const int ntiles = (nn + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t *total = t.pscan + ntiles;
+    const int g = (nn + 255) / 256;
+    k_piece_count<<<g, 256, 0, s>>>(t.farT.off, nn, t.pcnt);
+    k_cnt_tiles<<<ntiles, 256, 0, s>>>(t.pcnt, INT32_MAX, nn, t.pscan);
+    k_cnt_tile_scan<<<1, 1024, 0, s>>>(t.pscan, ntiles, total);
+    k_cnt_write<<<ntiles, 256, 0, s>>>(t.pcnt, INT32_MAX, nn, t.pscan, total, t.poff);
+    hipError_t e = hipMemcpyAsync(t.h_pairs + 1, total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return e;
+    const int64_t np = t.h_pairs[1];
+    if (np > t.piece_cap) {
+        for (void *pp : {(void *)t.pnode, (void *)t.ppart})
+            if (pp)
+                (void)hipFree(pp);
+        t.pnode = nullptr;
+        t.ppart = nullptr;
+        const int64_t cp = np + np / 4 + 256;
+        e = hipMalloc((void **)&t.pnode, cp * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&t.ppart, 10 * cp * sizeof(double));
+        if (e != hipSuccess) {
+            t.piece_cap = 0;
+            return e;
+        }
+        t.piece_cap = cp;
+    }
+    t.npieces = np;
+    k_piece_fill<<<g, 256, 0, s>>>(t.poff, nn, t.pnode);
+    return hipGetLastError();
+}
+
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s)
 {
     const Topology &T = t.topo;
@@ -926,6 +1013,8 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
         return e;
     if (!t.has_transposed) {
         e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, t.farT, s);
+        if (e == hipSuccess)
+            e = build_m2lt_pieces(t, s);
         if (e == hipSuccess)
             e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, t.nearT, s);
         if (e != hipSuccess)
@@ -949,8 +1038,11 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
     k_vjp_m2l_sink<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
                                                          t.far_cnt, t.far_src, (int)t.cap_far,
                                                          t.Lbar, t.nadj);
-    k_vjp_m2l_src<<<(T.nnodes + 3) / 4, 256, 0, s>>>(t.recA, t.recQ, T.nnodes, t.left,
-                                                     t.farT.off, t.farT.src, t.Lbar, t.nadj);
+    if (t.npieces > 0)
+        k_vjp_m2l_src_piece<<<(int)((t.npieces + 3) / 4), 256, 0, s>>>(
+            t.recA, t.recQ, t.farT.off, t.farT.src, t.Lbar, t.pnode, t.poff, t.npieces, t.ppart);
+    k_vjp_m2l_src_fold<<<(T.nnodes + 255) / 256, 256, 0, s>>>(t.left, T.nnodes, t.poff, t.ppart,
+                                                              t.nadj);
     const int nsub = (T.leaf_size + 7) / 8;
     k_vjp_p2p_sink<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
                                                 nl, t.near_cnt, t.near_src, (int)t.cap_near,
@@ -974,7 +1066,8 @@ void release_vjp(Tree &t)
         (void)hipFree(b.p);
     t.vjp_owned.clear();
     for (void *pp : {(void *)t.vk0, (void *)t.vk1, (void *)t.vv0, (void *)t.vv1, (void *)t.vhist,
-                     (void *)t.vtot, (void *)t.farT.src, (void *)t.nearT.src})
+                     (void *)t.vtot, (void *)t.farT.src, (void *)t.nearT.src, (void *)t.pnode,
+                     (void *)t.ppart})
         if (pp)
             (void)hipFree(pp);
     if (t.h_pairs)
