@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--sigma-sweep", action="store_true",
+                    help="only run the |sum F| ~ N^sigma sweep over a single polytrope and exit")
+    ap.add_argument("--sweep-min-log2", type=int, default=14)
+    ap.add_argument("--sweep-max-log2", type=int, default=22)
     ap.add_argument("--vjp-reps", type=int, default=5,
                     help="timed VJP calls at the final state (0 = skip)")
     ap.add_argument("--mutual-steps", type=int, default=5,
@@ -278,6 +282,46 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
     return rec
 
 
+def sigma_sweep(args):
+    """|sum F| of one n=1 polytrope against N for several theta, and the
+    power-law fit |sum F| ~ N^sigma (the scaling argued for the total force
+    of the one-sided interactions).  The leaf <- cell walk, FP64, the static
+    initial configuration, three seeds per (N, theta)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_01496_amd import fmm as F
+    from paper_2502_01496_amd import workloads as W
+
+    sizes = [1 << k for k in range(args.sweep_min_log2, args.sweep_max_log2 + 1)]
+    thetas = [0.2, 0.3, 0.5, 0.7]
+    seeds = [101, 102, 103]
+    res = {th: {} for th in thetas}
+    for n in sizes:
+        for sd in seeds:
+            x_np, m_np, h_np = W.polytrope_single(n, sd)
+            x = torch.from_numpy(x_np).cuda()
+            m = torch.from_numpy(m_np).cuda()
+            h = torch.from_numpy(h_np).cuda()
+            for th in thetas:
+                g = F.GravityFMM(theta=th)
+                a = g.forces(x, m, h)
+                st = F.fmm_momentum_stats(x, None, m, a)
+                g.free()
+                res[th].setdefault(n, []).append(float(np.linalg.norm(st["sumF"])))
+            log(f"[sweep] n={n} seed={sd}: " + ", ".join(
+                f"theta {th}: |sumF| {res[th][n][-1]:.3e}" for th in thetas))
+    out = {"sweep": "polytrope n=1, M=R=1, 58-neighbour h, leaf<-cell walk, FP64",
+           "sizes": sizes, "seeds": seeds, "theta": {}}
+    for th in thetas:
+        mean = np.array([np.mean(res[th][n]) for n in sizes])
+        sig, c = np.polyfit(np.log(sizes), np.log(mean), 1)
+        out["theta"][str(th)] = {"sumF_mean": [float(v) for v in mean],
+                                 "sumF_all": [res[th][n] for n in sizes], "sigma": float(sig)}
+        log(f"[sweep] theta {th}: sigma = {sig:.3f}")
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(mib):
     """A plain copy of mib MiB (reads and writes mib MiB each time)."""
     import torch
@@ -295,6 +339,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.sigma_sweep:
+        sigma_sweep(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -128,6 +128,20 @@ def polytrope_binary(n_per_star: int, seed: int, separation: float = 4.0,
     return _cached(f"polytrope_binary:{n_per_star}:{seed}:{separation}", make)
 
 
+def polytrope_single(n: int, seed: int, cache: bool = True):
+    """One n=1 polytrope (M = 1, R = 1) of n equal-mass particles at the
+    origin, h from the 58-neighbour estimate."""
+
+    def make():
+        rng = _rng(seed)
+        x = np.ascontiguousarray(polytrope_star(n, rng))
+        return x, np.full(n, 1.0 / n), knn_h(x)
+
+    if not cache:
+        return make()
+    return _cached(f"polytrope_single:{n}:{seed}", make)
+
+
 def clumpy_cube(n: int, seed: int, n_clumps: int = 64, sigma: float = 0.02,
                 clump_mass: float = 0.3, mass_sigma: float = 0.5, cache: bool = True):
     """Uniform [0,1)^3 background plus n_clumps Gaussian clumps holding
