@@ -48,6 +48,15 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// 1/sqrt(x) for finite x > 0: hardware estimate plus one second-order
+// correction, y' = y + y e (1/2 + 3/8 e) with e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  This bijection of [0, nblocks) gives XCD x a contiguous range of
 // logical block indices, so neighbouring leaves (which share most of their

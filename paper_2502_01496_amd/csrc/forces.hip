@@ -174,15 +174,6 @@ __device__ __forceinline__ double m4g_f64(double q, double hinv3, double u3)
     return __builtin_unpredictable(q < 1.0) ? p1 : g;
 }
 
-// 1/sqrt(x) for finite x > 0: hardware estimate plus one second-order
-// correction, y' = y + y e (1/2 + 3/8 e) with e = 1 - x y^2.
-__device__ __forceinline__ double rsqrt_pos(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-x * y, y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-
 // m / r^3 for finite r2 > 0: hardware reciprocal square root y, refined with
 // the series (1 - e)^(-3/2) = 1 + 3/2 e + 15/8 e^2 + O(e^3), e = 1 - r2 y^2
 // (r^-3 = y^3 (1 - e)^(-3/2)).

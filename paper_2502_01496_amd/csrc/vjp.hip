@@ -27,18 +27,23 @@
 
 namespace fmm {
 
+// Index of the stored entry of a symmetric 3x3 tensor (xx, xy, xz, yy, yz, zz)
+// and of a symmetric 3x3x3 tensor (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz,
+// yzz, zzz).  Written without recursion so that, with unrolled loops, every
+// index folds to a constant and the tensors stay in registers.
 __device__ __forceinline__ constexpr int sym2(int i, int j)
 {
-    return i > j ? sym2(j, i) : (i == 0 ? j : (i == 1 ? 2 + j : 5));
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return a == 0 ? b : (a == 1 ? 2 + b : 5);
 }
 
 __device__ __forceinline__ constexpr int sym3(int i, int j, int k)
 {
-    // sort (i, j, k) then index xxx,xxy,xxz,xyy,xyz,xzz,yyy,yyz,yzz,zzz
-    return (i > j) ? sym3(j, i, k)
-                   : (j > k) ? sym3(i, k, j)
-                             : (i == 0 ? (j == 0 ? k : (j == 1 ? 2 + k : 5))
-                                       : (i == 1 ? (j == 1 ? 5 + k : 8) : 9));
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const int a = lo < k ? lo : k;
+    const int c = hi > k ? hi : k;
+    const int b = i + j + k - a - c;
+    return a == 0 ? (b == 0 ? c : (b == 1 ? 2 + c : 5)) : (a == 1 ? (b == 1 ? 5 + c : 8) : 9);
 }
 
 __device__ __forceinline__ constexpr double mult3(int i, int j, int k)
@@ -53,7 +58,7 @@ __device__ __forceinline__ void m2l_vjp(const double r[3], double M, const doubl
                                         const double *Lb, double rb[3], double &Mb, double Qb[6])
 {
     const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    const double u = rsqrt(r2);
+    const double u = rsqrt_pos(r2);  // r2 > 0: far pairs are separated
     const double u2 = u * u;
     const double g1 = -u * u2, g2 = -3.0 * g1 * u2, g3 = -5.0 * g2 * u2, g4 = -7.0 * g3 * u2,
                  g5 = -9.0 * g4 * u2, g6 = -11.0 * g5 * u2;
@@ -68,9 +73,12 @@ __device__ __forceinline__ void m2l_vjp(const double r[3], double M, const doubl
     for (int i = 0; i < 3; ++i)
         q[i] = Qf[i][0] * r[0] + Qf[i][1] * r[1] + Qf[i][2] * r[2];
     const double qq = q[0] * r[0] + q[1] * r[1] + q[2] * r[2];
-    const double a0 = M * g1 + g3 * qq / 6.0, a1 = M * g2 + g4 * qq / 6.0,
-                 a2 = M * g3 + g5 * qq / 6.0;
-    const double b2 = g2 / 3.0, b3 = g3 / 3.0, b4 = g4 / 3.0;
+    // divisions by the constants 3 and 6 are taken as products with their
+    // rounded reciprocals (no FP64 divide in the loop)
+    constexpr double k3 = 1.0 / 3.0, k6 = 1.0 / 6.0;
+    const double qq6 = qq * k6;
+    const double a0 = M * g1 + g3 * qq6, a1 = M * g2 + g4 * qq6, a2 = M * g3 + g5 * qq6;
+    const double b2 = g2 * k3, b3 = g3 * k3, b4 = g4 * k3;
     // full symmetric cotangent tensors
     const double A[3] = {Lb[0], Lb[1], Lb[2]};
     double B[3][3];
@@ -86,7 +94,7 @@ __device__ __forceinline__ void m2l_vjp(const double r[3], double M, const doubl
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                T[i][j][k] = Lb[9 + sym3(i, j, k)] / mult3(i, j, k);
+                T[i][j][k] = Lb[9 + sym3(i, j, k)] * (1.0 / mult3(i, j, k));
     // contractions
     double Br[3], Bq[3], tr1[3], Trr[3], Trq[3], TQ[3], Tr[3][3];
 #pragma unroll
@@ -144,12 +152,12 @@ __device__ __forceinline__ void m2l_vjp(const double r[3], double M, const doubl
     }
     // through the coefficients
     Mb += a0b * g1 + a1b * g2 + a2b * g3;
-    const double qqb = (a0b * g3 + a1b * g4 + a2b * g5) / 6.0;
+    const double qqb = (a0b * g3 + a1b * g4 + a2b * g5) * k6;
     const double gb1 = a0b * M;
-    const double gb2 = a1b * M + b2b / 3.0;
-    const double gb3 = a2b * M + a0b * qq / 6.0 + b3b / 3.0;
-    const double gb4 = a1b * qq / 6.0 + b4b / 3.0;
-    const double gb5 = a2b * qq / 6.0;
+    const double gb2 = a1b * M + b2b * k3;
+    const double gb3 = a2b * M + a0b * qq6 + b3b * k3;
+    const double gb4 = a1b * qq6 + b4b * k3;
+    const double gb5 = a2b * qq6;
     const double sg = gb1 * g2 + gb2 * g3 + gb3 * g4 + gb4 * g5 + gb5 * g6;
 #pragma unroll
     for (int m = 0; m < 3; ++m)
@@ -235,18 +243,6 @@ __device__ __forceinline__ double m4dgr(double q, double hinv, double hinv3, dou
     return q < 1.0 ? p1 : (q < 2.0 ? p2 : -3.0 * u2 * u2 * u);
 }
 
-// G_ij and G'_ij / r for a pair at squared distance r2 > 0.
-__device__ __forceinline__ void pair_gdg(double r2, double4 hi, double4 hj, double &Gp,
-                                         double &dGr)
-{
-    const double u = rsqrt(r2);
-    const double r = r2 * u;
-    const double u3 = u * u * u;
-    const double qi = r * hi.x, qj = r * hj.x;
-    Gp = 0.5 * (m4g(qi, hi.y, u3) + m4g(qj, hj.y, u3));
-    dGr = 0.5 * (m4dgr(qi, hi.x, hi.y, hi.w, u) + m4dgr(qj, hj.x, hj.y, hj.w, u));
-}
-
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double xk(double keep, double send, int off)
 {
@@ -317,6 +313,8 @@ __global__ void k_vjp_prep(const TA *__restrict__ abar, int64_t n, const int32_t
         for (int d = 0; d < 3; ++d)
             abt[3 * p + d] = G * (double)abar[3 * i + d];
     }
+    if (blockIdx.x == 0 && threadIdx.x < 3)  // null record: no adjoint
+        abt[3 * n + threadIdx.x] = 0.0;
 }
 
 // 1. L2P^T: one thread per leaf.
@@ -429,7 +427,7 @@ __global__ void k_piece_fill(const int64_t *__restrict__ poff, int nnodes, int32
             pnode[j] = b;
 }
 
-__global__ __launch_bounds__(256) void k_vjp_m2l_src_piece(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_m2l_src_piece(
     const double *__restrict__ recA, const double *__restrict__ recQ,
     const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc,
     const double *__restrict__ Lbar, const int32_t *__restrict__ pnode,
@@ -508,20 +506,97 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_src_fold(const int32_t *__restr
 }
 
 // 3a. P2P^T, sink side: like the forward near field (source per lane, four
-// wave-uniform sinks per pass), pair function dbar.  xbt += the sum.
+// wave-uniform sinks per pass, source blocks of the close leaves staged
+// first, the next step's sources loaded while the current one computes),
+// pair function dbar.  xbt += the sum.
 constexpr int VJP_RANGES = 256;
+constexpr double VJP_CLOSE_FRAC2 = 0.49;  // close leaf: |c_a - c_b| < 0.7 x the bound of eq. (5)
+
+// Stage the source blocks of list entries [c0, c0 + nc) (each list entry,
+// a node id, stands for nsub blocks of at most 8 particles) in R, padded to a
+// multiple of 8 with empty blocks; blocks of leaves within the close radius
+// of the wavefront's own leaf rv come first, each group in list order, so
+// that steps whose pairs are all Newtonian are gathered at the end.
+template <typename IX>
+__device__ __forceinline__ void stage_blocks(const IX *__restrict__ lst, int c0, int nc, int nsub,
+                                             const int32_t *__restrict__ first,
+                                             const int32_t *__restrict__ count,
+                                             const double *__restrict__ recA, const double *rv,
+                                             double r_kern, int lane, int2 *R)
+{
+    int front = 0, back = nc;
+    const int ncp = (nc + 7) & ~7;
+    const uint64_t lt = lanemask_lt();
+    for (int k0 = 0; k0 < ncp; k0 += 64) {
+        const int k = k0 + lane;
+        const bool act = k < nc;
+        int2 r = make_int2(0, 0);
+        bool close = false;
+        if (act) {
+            const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
+            const int bn = (int)lst[e];
+            r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
+            const double *rb = recA + (int64_t)NREC * bn;
+            const double dx = rv[0] - rb[0], dy = rv[1] - rb[1], dz = rv[2] - rb[2];
+            const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
+            close = dx * dx + dy * dy + dz * dz < VJP_CLOSE_FRAC2 * t5 * t5;
+        }
+        const uint64_t mc = __ballot(act && close), mf = __ballot(act && !close);
+        const int nf = __popcll(mf);
+        const int pos = close ? front + __popcll(mc & lt) : back - nf + __popcll(mf & lt);
+        front += __popcll(mc);
+        back -= nf;
+        if (act)
+            R[pos] = r;
+        else if (k < ncp)
+            R[k] = r;
+    }
+}
+
+// Particle index of this lane in a staged block; missing particles read the
+// null record at index nnull (far away, zero mass, zero smoothing length,
+// zero adjoint), so their pairs add exactly zero.
+__device__ __forceinline__ int64_t block_particle(int2 rg, int slot, int64_t nnull)
+{
+    return slot < rg.y ? (int64_t)rg.x + slot : nnull;
+}
+
+// G_ij and G'_ij / r of one pair (eq. (3) with the symmetric pair kernel).
+// A step in which no pair of the wavefront lies inside a smoothing support
+// takes the Newtonian branch, G = r^-3, G' / r = -3 r^-5.  Otherwise the
+// spline branch also covers r = 0: two distinct particles at one point have
+// G = (g_i(0) + g_j(0)) / 2 and d = 0; a particle paired with itself (self)
+// gets G = 0, so the pair adds nothing.
+__device__ __forceinline__ void pair_gdg_step(double r2, double4 ha, double4 hb, bool self,
+                                              double &Gp, double &dGr)
+{
+    if ((__ballot(r2 < ha.z) | __ballot(r2 < hb.z)) == 0ull) {
+        const double u = rsqrt_pos(r2);
+        const double u2 = u * u;
+        Gp = u2 * u;
+        dGr = -3.0 * (Gp * u2);
+    } else {
+        const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+        const double r = r2 * u;
+        const double u3 = u * u * u;
+        const double qa = r * ha.x, qb = r * hb.x;
+        Gp = 0.5 * (m4g(qa, ha.y, u3) + m4g(qb, hb.y, u3));
+        dGr = 0.5 * (m4dgr(qa, ha.x, ha.y, ha.w, u) + m4dgr(qb, hb.x, hb.y, hb.w, u));
+        Gp = self ? 0.0 : Gp;
+    }
+}
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_sink(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
     const int32_t *__restrict__ near_cnt, const int32_t *__restrict__ near_src, int cap_near,
-    int nsub, double *xbt)
+    int nsub, const double *__restrict__ recA, double r_kern, int64_t nnull, double *xbt)
 {
     constexpr int NS = 4;
     __shared__ int2 rng[4][VJP_RANGES];
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
         return;
     const int lane = lane_id();
@@ -531,6 +606,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int c = count[v];
     const int nb = max(0, min(near_cnt[leaf], cap_near)) * nsub;
     const int32_t *nl = near_src + (int64_t)leaf * cap_near;
+    const double *rv = recA + (int64_t)NREC * v;
     int2 *R = rng[w];
     for (int sb = 0; sb < c; sb += NS) {
         double4 xs[NS], hsn[NS];
@@ -551,39 +627,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             acc[q] = 0.0;
         for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
             const int nc = min(nb - c0, VJP_RANGES);
-            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
-                int2 r = make_int2(0, 0);
-                if (k < nc) {
-                    const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
-                    const int bn = nl[e];
-                    r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
-                }
-                R[k] = r;
-            }
+            stage_blocks(nl, c0, nc, nsub, first, count, recA, rv, r_kern, lane, R);
             __builtin_amdgcn_wave_barrier();
+            int64_t j = block_particle(R[grp], slot, nnull);
+            double4 xj = pm[j], hj = ph[j];
             for (int kb = 0; kb < nc; kb += 8) {
-                const int2 rg = R[kb + grp];
-                const bool valid = slot < rg.y;
-                const int64_t j = (int64_t)rg.x + (valid ? slot : 0);
-                double4 xj = pm[j];
-                const double4 hj = ph[j];
-                if (!valid)
-                    xj = make_double4(1e30, 1e30, 1e30, 0.0);
+                int64_t jn = j;
+                double4 xn = xj, hn = hj;
+                if (kb + 8 < nc) {
+                    jn = block_particle(R[kb + 8 + grp], slot, nnull);
+                    xn = pm[jn];
+                    hn = ph[jn];
+                }
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
                     const double dx = xs[q].x - xj.x, dy = xs[q].y - xj.y, dz = xs[q].z - xj.z;
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    double Gp = 0.0, dGr = 0.0;
-                    if (j != is[q] && r2 > 0.0)
-                        pair_gdg(r2, hsn[q], hj, Gp, dGr);
-                    else if (j != is[q])  // distinct particles at one point: d = 0
-                        Gp = 0.5 * (hsn[q].y + hj.y) * (4.0 / 3.0);
+                    double Gp, dGr;
+                    pair_gdg_step(r2, hsn[q], hj, j == is[q], Gp, dGr);
                     const double da = dx * as0[q] + dy * as1[q] + dz * as2[q];
                     const double t = dGr * da;
                     acc[3 * q] -= xj.w * (Gp * as0[q] + t * dx);
                     acc[3 * q + 1] -= xj.w * (Gp * as1[q] + t * dy);
                     acc[3 * q + 2] -= xj.w * (Gp * as2[q] + t * dz);
                 }
+                j = jn;
+                xj = xn;
+                hj = hn;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -596,20 +666,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 }
 
 // 3b. P2P^T, source side: one wavefront per source leaf b over the sink leaves
-// whose near list holds b (transposed, ascending); lanes hold sink particles,
-// four source particles of b per pass are wave-uniform.  xbt[j] -= sum dbar,
-// mbt[j] = sum -G_ij (d . abar'_i).
+// whose near list holds b (transposed, ascending, close leaves staged first);
+// lanes hold sink particles, four source particles of b per pass are
+// wave-uniform.  xbt[j] -= sum dbar, mbt[j] = sum -G_ij (d . abar'_i).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_src(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
-    const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc, int nsub, double *xbt,
-    double *mbt)
+    const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc, int nsub,
+    const double *__restrict__ recA, double r_kern, int64_t nnull, double *xbt, double *mbt)
 {
     constexpr int NS = 4;
     __shared__ int2 rng[4][VJP_RANGES];
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
         return;
     const int lane = lane_id();
@@ -619,6 +689,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int c = count[v];
     const int64_t e0 = toff[v];
     const int nb = (int)(toff[v + 1] - e0) * nsub;
+    const double *rv = recA + (int64_t)NREC * v;
     int2 *R = rng[w];
     for (int sb = 0; sb < c; sb += NS) {
         double4 xs[NS], hsn[NS];
@@ -635,36 +706,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             acc[q] = 0.0;
         for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
             const int nc = min(nb - c0, VJP_RANGES);
-            for (int k = lane; k < ((nc + 7) & ~7); k += 64) {
-                int2 r = make_int2(0, 0);
-                if (k < nc) {
-                    const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
-                    const int an = (int)tsrc[e0 + e];
-                    r = make_int2(first[an] + 8 * u, max(0, min(8, count[an] - 8 * u)));
-                }
-                R[k] = r;
-            }
+            stage_blocks(tsrc + e0, c0, nc, nsub, first, count, recA, rv, r_kern, lane, R);
             __builtin_amdgcn_wave_barrier();
+            int64_t i = block_particle(R[grp], slot, nnull);
+            double4 xi = pm[i], hi = ph[i];
             for (int kb = 0; kb < nc; kb += 8) {
-                const int2 rg = R[kb + grp];
-                const bool valid = slot < rg.y;
-                const int64_t i = (int64_t)rg.x + (valid ? slot : 0);
-                double4 xi = pm[i];
-                const double4 hi = ph[i];
-                double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
-                if (!valid) {
-                    xi = make_double4(1e30, 1e30, 1e30, 0.0);
-                    ai0 = ai1 = ai2 = 0.0;
+                const double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
+                int64_t in = i;
+                double4 xn = xi, hn = hi;
+                if (kb + 8 < nc) {
+                    in = block_particle(R[kb + 8 + grp], slot, nnull);
+                    xn = pm[in];
+                    hn = ph[in];
                 }
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
                     const double dx = xi.x - xs[q].x, dy = xi.y - xs[q].y, dz = xi.z - xs[q].z;
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    double Gp = 0.0, dGr = 0.0;
-                    if (i != js[q] && r2 > 0.0)
-                        pair_gdg(r2, hi, hsn[q], Gp, dGr);
-                    else if (i != js[q])  // distinct particles at one point: d = 0
-                        Gp = 0.5 * (hi.y + hsn[q].y) * (4.0 / 3.0);
+                    double Gp, dGr;
+                    pair_gdg_step(r2, hi, hsn[q], i == js[q], Gp, dGr);
                     const double da = dx * ai0 + dy * ai1 + dz * ai2;
                     const double t = dGr * da;
                     const double mj = xs[q].w;
@@ -674,6 +734,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                     acc[4 * q + 2] += mj * (Gp * ai2 + t * dz);
                     acc[4 * q + 3] -= Gp * da;
                 }
+                i = in;
+                xi = xn;
+                hi = hn;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -879,7 +942,7 @@ static hipError_t ensure_vjp_base(Tree &t)
     const Topology &T = t.topo;
     const int64_t n = T.n, nn = T.nnodes;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = valloc(t, &t.abt, 3 * n);
+    if (e == hipSuccess) e = valloc(t, &t.abt, 3 * (n + 1));  // + null record
     if (e == hipSuccess) e = valloc(t, &t.xbt, 3 * n);
     if (e == hipSuccess) e = valloc(t, &t.mbt, n);
     if (e == hipSuccess) e = valloc(t, &t.Lbar, NLOC * nn);
@@ -1046,9 +1109,10 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
     const int nsub = (T.leaf_size + 7) / 8;
     k_vjp_p2p_sink<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
                                                 nl, t.near_cnt, t.near_src, (int)t.cap_near,
-                                                nsub, t.xbt);
+                                                nsub, t.recA, t.p.r_kern, n, t.xbt);
     k_vjp_p2p_src<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
-                                               nl, t.nearT.off, t.nearT.src, nsub, t.xbt, t.mbt);
+                                               nl, t.nearT.off, t.nearT.src, nsub, t.recA,
+                                               t.p.r_kern, n, t.xbt, t.mbt);
     if (fp32)
         k_vjp_moments<float><<<(int)((n + 255) / 256), 256, 0, s>>>(
             t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, t.xbt, t.mbt, t.perm,
