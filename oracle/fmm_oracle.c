@@ -24,7 +24,9 @@
  *     leaf <- cell walk of Sec. 4, plus the mutual walk recommended in Sec. 7;
  *   - the cell field to second order, eq. (6) and its first two r-derivatives,
  *     the Taylor evaluation at a particle, eq. (8), and the exact re-expansion
- *     of that quadratic polynomial to another centre;
+ *     of that quadratic polynomial to another centre; and the alternative
+ *     expansion of Sec. 4, eqs. (25)-(26) with p = 3 (combined order of the
+ *     source and sink offsets at most 2);
  *   - near-field softened pair sums, momentum diagnostics (Secs. 5-6) and the
  *     adjoint of the direct sum.
  *
@@ -647,8 +649,20 @@ static double kd(int i, int j) { return i == j ? 1.0 : 0.0; }
  *            + 2 g3 (r_i Q_jk + r_j Q_ik + r_k Q_ij)]
  * Pinned by: symbolic differentiation of eq. (6), finite differences, the
  * direct field of explicit particle clusters, the pair-force closed form and
- * the three-cell expansion of Sec. 4 (eq. (31)). */
-ORC_API void orc_m2l(const double *rv, double M, const double *Q, double *L)
+ * the three-cell expansion of Sec. 4 (eq. (31)).
+ *
+ * form = 1 selects the expansion of eqs. (25)-(26) with p = 3 and the
+ * octupoles dropped: every term x^n y^m with |n| + |m| <= 2 is kept, so with
+ * the dipole zero about the centre of mass the quadrupole enters L1 only
+ * (L1 is eq. (6) again) and L2, L3 are the derivatives of the monopole field:
+ *   L2_ij  = M (g2 r_i r_j + g1 d_ij)
+ *   L3_ijk = M (g3 r_i r_j r_k + g2 (d_ij r_k + d_ik r_j + d_jk r_i)),
+ * whose highest power of 1/r is 4 (against 6 for form 0).  Pinned by:
+ * symbolic derivatives of the point-mass field, the truncated double Taylor
+ * series of eqs. (25)-(26) built from explicit particle clusters, the
+ * difference to form 0 being the (n, m) = (1, 2), (2, 2) terms of Sec. 4, and
+ * the per-pair third law. */
+ORC_API void orc_m2l(int32_t form, const double *rv, double M, const double *Q, double *L)
 {
     double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
     double r = sqrt(r2);
@@ -685,10 +699,11 @@ ORC_API void orc_m2l(const double *rv, double M, const double *Q, double *L)
     double qq = q[0] * rv[0] + q[1] * rv[1] + q[2] * rv[2];
     for (int i = 0; i < 3; ++i)
         for (int j = i; j < 3; ++j) {
-            double v = M * (g2 * rv[i] * rv[j] + g1 * kd(i, j)) +
-                       (g4 * qq * rv[i] * rv[j] + g3 * qq * kd(i, j) +
-                        2.0 * g3 * (rv[i] * q[j] + q[i] * rv[j]) + 2.0 * g2 * Qf[i][j]) /
-                           6.0;
+            double v = M * (g2 * rv[i] * rv[j] + g1 * kd(i, j));
+            if (form == 0)
+                v += (g4 * qq * rv[i] * rv[j] + g3 * qq * kd(i, j) +
+                      2.0 * g3 * (rv[i] * q[j] + q[i] * rv[j]) + 2.0 * g2 * Qf[i][j]) /
+                     6.0;
             L[3 + sym2(i, j)] = v;
         }
     for (int i = 0; i < 3; ++i)
@@ -699,10 +714,11 @@ ORC_API void orc_m2l(const double *rv, double M, const double *Q, double *L)
                 double rrq = rv[i] * rv[j] * q[k] + rv[i] * rv[k] * q[j] + rv[j] * rv[k] * q[i];
                 double dq = kd(i, j) * q[k] + kd(i, k) * q[j] + kd(j, k) * q[i];
                 double rQ = rv[i] * Qf[j][k] + rv[j] * Qf[i][k] + rv[k] * Qf[i][j];
-                double v = M * (g3 * rrr + g2 * dr) +
-                           (g5 * qq * rrr + g4 * qq * dr + 2.0 * g4 * rrq + 2.0 * g3 * dq +
-                            2.0 * g3 * rQ) /
-                               6.0;
+                double v = M * (g3 * rrr + g2 * dr);
+                if (form == 0)
+                    v += (g5 * qq * rrr + g4 * qq * dr + 2.0 * g4 * rrq + 2.0 * g3 * dq +
+                          2.0 * g3 * rQ) /
+                         6.0;
                 L[9 + sym3(i, j, k)] = v;
             }
 }
@@ -739,11 +755,11 @@ ORC_API void orc_l2l(const double *L, const double *delta, double *out)
         out[9 + k] = L[9 + k];
 }
 
-/* Local expansions of every sink node: M2L over its far list, in list order;
- * with the mutual walk also the L2L pass from each node into its children,
- * parents first (pre-order).  L is nnodes x 19, zero for nodes without a far
- * field. */
-ORC_API void orc_far_field(int32_t policy, int32_t nnodes, const int32_t *left,
+/* Local expansions of every sink node: M2L (expansion form `form`) over its
+ * far list, in list order; with the mutual walk also the L2L pass from each
+ * node into its children, parents first (pre-order).  L is nnodes x 19, zero
+ * for nodes without a far field. */
+ORC_API void orc_far_field(int32_t policy, int32_t form, int32_t nnodes, const int32_t *left,
                            const int32_t *right, const double *M, const double *c,
                            const double *Q, const int32_t *far_off, const int32_t *far_src,
                            double *L)
@@ -757,7 +773,7 @@ ORC_API void orc_far_field(int32_t policy, int32_t nnodes, const int32_t *left,
             int32_t b = far_src[e];
             double rv[3] = {c[3 * v] - c[3 * b], c[3 * v + 1] - c[3 * b + 1],
                             c[3 * v + 2] - c[3 * b + 2]};
-            orc_m2l(rv, M[b], Q + 6 * b, t);
+            orc_m2l(form, rv, M[b], Q + 6 * b, t);
             for (int k = 0; k < 19; ++k)
                 Lv[k] += t[k];
         }

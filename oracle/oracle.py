@@ -76,10 +76,10 @@ def lib():
         L.orc_p2m.argtypes = [I64, _d, _d, _d, _d, _d]
         L.orc_walk.argtypes = [I32, I32, _i32, _i32, _d, _d, _d, D, D,
                                _i32, _opt(_i32), _i32, _opt(_i32), _i64]
-        L.orc_m2l.argtypes = [_d, D, _d, _d]
+        L.orc_m2l.argtypes = [I32, _d, D, _d, _d]
         L.orc_l2p.argtypes = [_d, _d, _d]
         L.orc_l2l.argtypes = [_d, _d, _d]
-        L.orc_far_field.argtypes = [I32, I32, _i32, _i32, _d, _d, _d, _i32, _i32, _d]
+        L.orc_far_field.argtypes = [I32, I32, I32, _i32, _i32, _d, _d, _d, _i32, _i32, _d]
         L.orc_near_and_l2p.argtypes = [I64, _d, _d, _d, _i32, I32, _i32, _i32, _i32, _d, _d,
                                        _i32, _i32, D, _d]
         L.orc_stats.argtypes = [I64, _d, _opt(_d), _d, _d, _d]
@@ -216,6 +216,8 @@ class Lists:
 
 PHANTOM = 0   # leaf <- cell walk (Sec. 4)
 MUTUAL = 1    # symmetric walk (Sec. 7)
+PHANTOM_FORM = 0  # M2L as eq. (6) and its r-derivatives (quadrupole at every order)
+DEHNEN_FORM = 1   # M2L as eqs. (25)-(26), p = 3: combined source + sink order <= 2
 
 
 def walk(tree: Tree, mom: Moments, theta=0.5, r_kern=2.0, policy=PHANTOM) -> Lists:
@@ -236,9 +238,11 @@ def walk(tree: Tree, mom: Moments, theta=0.5, r_kern=2.0, policy=PHANTOM) -> Lis
 # --------------------------------------------------------------------------
 # Far field (eqs. (6)-(8)) and near field (eqs. (12)-(16))
 # --------------------------------------------------------------------------
-def m2l(r, M, Q):
+def m2l(r, M, Q, form=PHANTOM_FORM):
+    """M2L: form PHANTOM_FORM = eq. (6) and its r-derivatives; DEHNEN_FORM =
+    eqs. (25)-(26) with p = 3 (combined source + sink order <= 2)."""
     L = np.empty(19)
-    lib().orc_m2l(_f64(r), float(M), _f64(Q), L)
+    lib().orc_m2l(int(form), _f64(r), float(M), _f64(Q), L)
     return L
 
 
@@ -254,11 +258,11 @@ def l2l(L, delta):
     return out
 
 
-def far_field(tree: Tree, mom: Moments, lists: Lists, policy=PHANTOM):
+def far_field(tree: Tree, mom: Moments, lists: Lists, policy=PHANTOM, form=PHANTOM_FORM):
     nn = tree.nnodes
     L = np.empty((nn, 19))
     fs = lists.far_src if len(lists.far_src) else np.zeros(1, np.int32)
-    lib().orc_far_field(policy, nn, tree.left, tree.right, mom.M, mom.c, mom.Q,
+    lib().orc_far_field(policy, int(form), nn, tree.left, tree.right, mom.M, mom.c, mom.Q,
                         lists.far_off, np.ascontiguousarray(fs, np.int32), L)
     return L
 
@@ -282,21 +286,22 @@ class FmmResult:
     L: np.ndarray
 
 
-def fmm(x, m, h, theta=0.5, r_kern=2.0, G=1.0, leaf_size=8, policy=PHANTOM) -> FmmResult:
+def fmm(x, m, h, theta=0.5, r_kern=2.0, G=1.0, leaf_size=8, policy=PHANTOM,
+        form=PHANTOM_FORM) -> FmmResult:
     """Serial kd-tree FMM: build, moments, walk, M2L (+L2L), L2P + near field."""
     tree = build_tree(x, leaf_size)
     mom = moments(x, m, h, tree)
     lists = walk(tree, mom, theta, r_kern, policy)
-    L = far_field(tree, mom, lists, policy)
+    L = far_field(tree, mom, lists, policy, form)
     a = near_and_l2p(x, m, h, tree, mom, L, lists, G)
     return FmmResult(a, tree, mom, lists, L)
 
 
-def fmm_frozen(x, m, h, tree: Tree, lists: Lists, G=1.0, policy=PHANTOM):
+def fmm_frozen(x, m, h, tree: Tree, lists: Lists, G=1.0, policy=PHANTOM, form=PHANTOM_FORM):
     """FMM with the tree membership and interaction lists held fixed and the
     moments recomputed from (x, m, h): the function whose derivative the VJP is."""
     mom = moments(x, m, h, tree)
-    L = far_field(tree, mom, lists, policy)
+    L = far_field(tree, mom, lists, policy, form)
     return near_and_l2p(x, m, h, tree, mom, L, lists, G)
 
 
