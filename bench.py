@@ -54,6 +54,10 @@ def parse():
                     help="only run the |sum F| ~ N^sigma sweep over a single polytrope and exit")
     ap.add_argument("--sweep-min-log2", type=int, default=14)
     ap.add_argument("--sweep-max-log2", type=int, default=22)
+    ap.add_argument("--sweep-seeds", type=int, default=3)
+    ap.add_argument("--forms", action="store_true",
+                    help="only compare the two M2L expansion forms (momentum, accuracy, far-field "
+                         "time) for both walks and three theta on the workload, and exit")
     ap.add_argument("--vjp-reps", type=int, default=5,
                     help="timed VJP calls at the final state (0 = skip)")
     ap.add_argument("--mutual-steps", type=int, default=5,
@@ -295,7 +299,7 @@ def sigma_sweep(args):
 
     sizes = [1 << k for k in range(args.sweep_min_log2, args.sweep_max_log2 + 1)]
     thetas = [0.2, 0.3, 0.5, 0.7]
-    seeds = [101, 102, 103]
+    seeds = [101 + k for k in range(args.sweep_seeds)]
     res = {th: {} for th in thetas}
     for n in sizes:
         for sd in seeds:
@@ -322,6 +326,52 @@ def sigma_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def forms_compare(args):
+    """The two M2L expansion forms (eq. (6) with its derivatives, and the
+    combined-order-2 series of eqs. (25)-(26)) under both walks: |sum F| /
+    sum |F|, eta against the FP64 direct sum on sampled sinks, and the far-field
+    stage time, at theta 0.3, 0.5, 0.7 (FP64, static initial configuration)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_01496_amd import fmm as F
+    from paper_2502_01496_amd import workloads as W
+
+    x_np, m_np, h_np, _ = W.config(args.workload)
+    n = len(m_np)
+    x = torch.from_numpy(x_np).cuda()
+    m = torch.from_numpy(m_np).cuda()
+    h = torch.from_numpy(h_np).cuda()
+    rng = np.random.default_rng(123)
+    sinks = torch.from_numpy(rng.choice(n, size=min(args.accuracy_sinks, n), replace=False)).cuda()
+    ref = direct_reference(x, m, h, sinks)
+    rows = []
+    for th in (0.3, 0.5, 0.7):
+        for walk in (F.FMM_WALK_PHANTOM, F.FMM_WALK_MUTUAL):
+            for form in (F.FMM_EXPANSION_PHANTOM, F.FMM_EXPANSION_DEHNEN):
+                g = F.GravityFMM(theta=th, walk=walk, expansion=form)
+                a = g.forces(x, m, h)
+                F.fmm_set_timing(g.tree, True)
+                for _ in range(5):
+                    g.forces(x, m, h, out=a, rebuild=False)
+                torch.cuda.synchronize()
+                far_ms = F.fmm_stage_times(g.tree)["far"]
+                F.fmm_set_timing(g.tree, False)
+                st = F.fmm_momentum_stats(x, None, m, a)
+                got = a[sinks]
+                eta = float(torch.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum()))
+                g.free()
+                row = {"theta": th, "walk": "mutual" if walk else "leaf<-cell",
+                       "form": "dehnen" if form else "phantom", "ratio": st["ratio"],
+                       "sumF": float(np.linalg.norm(st["sumF"])), "eta": eta,
+                       "far_ms": round(far_ms, 4)}
+                rows.append(row)
+                log(f"[forms] theta {th} {row['walk']:10s} {row['form']:7s}: "
+                    f"|sumF|/sum|F| {st['ratio']:.3e}  eta {eta:.3e}  far {far_ms:.3f} ms")
+    print(json.dumps({"forms": f"{args.workload}: n={n}, FP64, static", "rows": rows}),
+          flush=True)
+
+
 def copy_calibration(mib):
     """A plain copy of mib MiB (reads and writes mib MiB each time)."""
     import torch
@@ -342,6 +392,9 @@ def main():
         return
     if args.sigma_sweep:
         sigma_sweep(args)
+        return
+    if args.forms:
+        forms_compare(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -66,6 +66,18 @@ enum { FMM_FP64 = 0, FMM_FP32 = 1 };
  *   sinks, and local expansions are passed down the tree (L2L). */
 enum { FMM_WALK_PHANTOM = 0, FMM_WALK_MUTUAL = 1 };
 
+/* Expansion form of the far field (M2L), Sec. 4.
+ * FMM_EXPANSION_PHANTOM: eq. (6) for the cell field and its first two
+ *   r-derivatives for the sink offset (eq. (8)); the quadrupole enters every
+ *   order, the highest power of 1/r is 6.
+ * FMM_EXPANSION_DEHNEN: the series (25)-(26) with p = 3 and octupoles dropped:
+ *   terms are kept while the combined order of the source and sink offsets is
+ *   at most 2, so the quadrupole enters the field itself only and the two
+ *   derivative orders come from the monopole; the highest power of 1/r is 4.
+ * Both forms conserve momentum for every mutual cell pair; neither does with
+ * the leaf <- cell lists. */
+enum { FMM_EXPANSION_PHANTOM = 0, FMM_EXPANSION_DEHNEN = 1 };
+
 /* fmm_forces flags */
 enum { FMM_REWALK = 1 /* rebuild the interaction lists even if present */ };
 
@@ -76,7 +88,7 @@ typedef struct fmm_params {
     int32_t leaf_size; /* a cell with at most this many particles is a leaf; 1..64 (default 8) */
     int32_t walk;      /* FMM_WALK_* (default PHANTOM) */
     int32_t precision; /* FMM_FP64 or FMM_FP32 (default FP64) */
-    int32_t reserved;  /* must be 0 */
+    int32_t expansion; /* FMM_EXPANSION_* (default PHANTOM) */
 } fmm_params;
 
 /* Momentum diagnostics of Secs. 5-6, accumulated in FP64.

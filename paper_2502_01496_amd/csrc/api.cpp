@@ -286,8 +286,8 @@ static fmm_status check_params(const fmm_params *p)
         return fail(FMM_ERR_INVALID, "unknown walk policy %d", p->walk);
     if (p->precision != FMM_FP64 && p->precision != FMM_FP32)
         return fail(FMM_ERR_INVALID, "unknown precision %d", p->precision);
-    if (p->reserved != 0)
-        return fail(FMM_ERR_INVALID, "reserved must be 0");
+    if (p->expansion != FMM_EXPANSION_PHANTOM && p->expansion != FMM_EXPANSION_DEHNEN)
+        return fail(FMM_ERR_INVALID, "unknown expansion form %d", p->expansion);
     return FMM_OK;
 }
 
@@ -580,7 +580,7 @@ void fmm_default_params(fmm_params *p)
     p->leaf_size = 8;
     p->walk = FMM_WALK_PHANTOM;
     p->precision = FMM_FP64;
-    p->reserved = 0;
+    p->expansion = FMM_EXPANSION_PHANTOM;
 }
 
 const char *fmm_last_error(void) { return g_err.c_str(); }

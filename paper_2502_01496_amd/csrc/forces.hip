@@ -12,6 +12,11 @@
 //   L3_ijk = a2 r_i r_j r_k + a1 (d_ij r_k + d_ik r_j + d_jk r_i)
 //            + b4 (r_i r_j q_k + r_i r_k q_j + r_j r_k q_i)
 //            + b3 (d_ij q_k + d_ik q_j + d_jk q_i) + b3 (r_i Q_jk + r_j Q_ik + r_k Q_ij)
+// The second expansion form (eqs. (25)-(26) with p = 3: combined order of the
+// source and sink offsets at most 2) keeps L1 and replaces L2, L3 by the
+// derivatives of the monopole field alone:
+//   L2_ij  = A1 r_i r_j + A0 d_ij,  L3_ijk = A2 r_i r_j r_k + A1 (d_ij r_k + d_ik r_j + d_jk r_i),
+//   A0 = M g1, A1 = M g2, A2 = M g3 (highest power of 1/r: 4, against 6).
 // L2P (eq. (8)): a(y) = L1 + L2 y + 1/2 L3 : y y, y = x - c_sink.
 // Near field (Sec. 3, eqs. (12)-(15), M4 kernel, R_kern = 2): particle i gets
 //   -m_j * 1/2 [g(r, h_i) + g(r, h_j)] * (x_i - x_j) from every j != i of its
@@ -33,10 +38,56 @@ __device__ __forceinline__ double rsqrt_t<double>(double x) { return rsqrt(x); }
 template <>
 __device__ __forceinline__ float rsqrt_t<float>(float x) { return rsqrtf(x); }
 
-// One source -> sink M2L, accumulated into L[19].
+// Second expansion form: L1 as eq. (6), L2 and L3 from the monopole only.
 template <typename T>
+__device__ __forceinline__ void m2l_acc_dehnen(T rx, T ry, T rz, T M, const T *Q, T *L)
+{
+    const T r2 = rx * rx + ry * ry + rz * rz;
+    const T u = rsqrt_t<T>(r2);
+    const T u2 = u * u;
+    const T g1 = -u * u2;
+    const T g2 = T(-3) * g1 * u2;
+    const T g3 = T(-5) * g2 * u2;
+    const T Qxx = Q[0], Qxy = Q[1], Qxz = Q[2], Qyy = Q[3], Qyz = Q[4], Qzz = Q[5];
+    const T qx = Qxx * rx + Qxy * ry + Qxz * rz;
+    const T qy = Qxy * rx + Qyy * ry + Qyz * rz;
+    const T qz = Qxz * rx + Qyz * ry + Qzz * rz;
+    const T qq = qx * rx + qy * ry + qz * rz;
+    const T sixth = T(1) / T(6), third = T(1) / T(3);
+    const T a0 = M * g1 + g3 * qq * sixth;
+    const T b2 = g2 * third;
+    const T A0 = M * g1, A1 = M * g2, A2 = M * g3;
+    L[0] += a0 * rx + b2 * qx;
+    L[1] += a0 * ry + b2 * qy;
+    L[2] += a0 * rz + b2 * qz;
+    const T A1x = A1 * rx, A1y = A1 * ry, A1z = A1 * rz;
+    L[3] += A1x * rx + A0;
+    L[4] += A1x * ry;
+    L[5] += A1x * rz;
+    L[6] += A1y * ry + A0;
+    L[7] += A1y * rz;
+    L[8] += A1z * rz + A0;
+    const T A2x = A2 * rx, A2y = A2 * ry, A2z = A2 * rz;
+    L[9] += A2x * rx * rx + T(3) * A1x;
+    L[10] += A2x * rx * ry + A1y;
+    L[11] += A2x * rx * rz + A1z;
+    L[12] += A2x * ry * ry + A1x;
+    L[13] += A2x * ry * rz;
+    L[14] += A2x * rz * rz + A1x;
+    L[15] += A2y * ry * ry + T(3) * A1y;
+    L[16] += A2y * ry * rz + A1z;
+    L[17] += A2y * rz * rz + A1y;
+    L[18] += A2z * rz * rz + T(3) * A1z;
+}
+
+// One source -> sink M2L, accumulated into L[19]; FORM is FMM_EXPANSION_*.
+template <typename T, int FORM>
 __device__ __forceinline__ void m2l_acc(T rx, T ry, T rz, T M, const T *Q, T *L)
 {
+    if constexpr (FORM == FMM_EXPANSION_DEHNEN) {
+        m2l_acc_dehnen<T>(rx, ry, rz, M, Q, L);
+        return;
+    }
     const T r2 = rx * rx + ry * ry + rz * rz;
     const T u = rsqrt_t<T>(r2);
     const T u2 = u * u;
@@ -119,6 +170,7 @@ __device__ __forceinline__ void l2p(const T *L, T y0, T y1, T y2, T &a0, T &a1, 
 // ---------------------------------------------------------------- M2L, FP64
 // 16 lanes per sink leaf, 4 sinks per wave; lanes stride the far list, then a
 // butterfly sum over the 16 lanes (fixed order: deterministic).
+template <int FORM>
 __global__ __launch_bounds__(256) void k_m2l_leaf_f64(
     const double *__restrict__ recA, const double *__restrict__ recQ,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
@@ -147,7 +199,7 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f64(
         const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
                       q45 = *(const double2 *)(qb + 4);
         const double Q[6] = {q01.x, q01.y, q23.x, q23.y, q45.x, q45.y};
-        m2l_acc<double>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
+        m2l_acc<double, FORM>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
     }
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1)
@@ -409,6 +461,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 // M2L in FP32: r = c_sink - c_source is formed in FP64 and rounded, M and Q
 // come from the FP32 mirror of the cell records, and the 19 coefficients are
 // accumulated in FP32.
+template <int FORM>
 __global__ __launch_bounds__(256) void k_m2l_leaf_f32(
     const double *__restrict__ recA, const float *__restrict__ recF,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
@@ -435,7 +488,8 @@ __global__ __launch_bounds__(256) void k_m2l_leaf_f32(
         const float4 f0 = *(const float4 *)(recF + (int64_t)NREC * b);
         const float4 f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
         const float Q[6] = {f0.y, f0.z, f0.w, f1.x, f1.y, f1.z};
-        m2l_acc<float>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
+        m2l_acc<float, FORM>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q,
+                             L);
     }
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1)
@@ -641,36 +695,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
 // ---------------------------------------------------------------- mutual walk
 // Far field of the mutual walk: M2L into every sink cell over its CSR range
 // of the sorted (sink, source) keys, then L2L down to the leaves.
-template <typename T>
+template <int FORM>
 __device__ __forceinline__ void m2l_node_src(const double *recA, const double *recQ,
-                                             const float *recF, int b, double c0, double c1,
-                                             double c2, T *L);
-template <>
-__device__ __forceinline__ void m2l_node_src<double>(const double *recA, const double *recQ,
-                                                     const float *, int b, double c0, double c1,
-                                                     double c2, double *L)
+                                             const float *, int b, double c0, double c1,
+                                             double c2, double *L)
 {
     const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
     const double *qb = recQ + (int64_t)NREC * b;
     const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
                   q45 = *(const double2 *)(qb + 4);
     const double Q[6] = {q01.x, q01.y, q23.x, q23.y, q45.x, q45.y};
-    m2l_acc<double>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
+    m2l_acc<double, FORM>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
 }
-template <>
-__device__ __forceinline__ void m2l_node_src<float>(const double *recA, const double *,
-                                                    const float *recF, int b, double c0,
-                                                    double c1, double c2, float *L)
+template <int FORM>
+__device__ __forceinline__ void m2l_node_src(const double *recA, const double *,
+                                             const float *recF, int b, double c0, double c1,
+                                             double c2, float *L)
 {
     const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
     const float4 f0 = *(const float4 *)(recF + (int64_t)NREC * b);
     const float4 f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
     const float Q[6] = {f0.y, f0.z, f0.w, f1.x, f1.y, f1.z};
-    m2l_acc<float>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
+    m2l_acc<float, FORM>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
 }
 
 // 16 lanes per sink cell (all cells; zero where the range is empty).
-template <typename T>
+template <typename T, int FORM>
 __global__ __launch_bounds__(256) void k_m2l_node(const double *__restrict__ recA,
                                                   const double *__restrict__ recQ,
                                                   const float *__restrict__ recF, int nnodes,
@@ -690,7 +740,7 @@ __global__ __launch_bounds__(256) void k_m2l_node(const double *__restrict__ rec
         L[k] = T(0);
     const int64_t e0 = valid ? fstart[v] : 0, e1 = valid ? fend[v] : 0;
     for (int64_t k = e0 + sub; k < e1; k += 16)
-        m2l_node_src<T>(recA, recQ, recF, (int)(keys[k] & mask), c0, c1, c2, L);
+        m2l_node_src<FORM>(recA, recQ, recF, (int)(keys[k] & mask), c0, c1, c2, L);
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1)
 #pragma unroll
@@ -771,7 +821,8 @@ __global__ __launch_bounds__(256) void k_l2l_chain(const double *__restrict__ re
     o[19] = T(0);
 }
 
-hipError_t launch_far_mutual(Tree &t, hipStream_t s)
+template <int FORM>
+static void far_mutual(Tree &t, hipStream_t s)
 {
     const Topology &T = t.topo;
     const MutualLists &M = t.mw;
@@ -779,41 +830,55 @@ hipError_t launch_far_mutual(Tree &t, hipStream_t s)
     const int gm = (int)(((int64_t)T.nnodes * 16 + 255) / 256);
     const int gl = (T.nleaves + 255) / 256;
     if (t.p.precision == FMM_FP64) {
-        k_m2l_node<double><<<gm, 256, 0, s>>>(t.recA, t.recQ, t.recF, T.nnodes, M.fstart, M.fend,
-                                              M.far_sorted, mask, M.Lown);
+        k_m2l_node<double, FORM><<<gm, 256, 0, s>>>(t.recA, t.recQ, t.recF, T.nnodes, M.fstart,
+                                                    M.fend, M.far_sorted, mask, M.Lown);
         k_l2l_chain<double><<<gl, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, T.nleaves,
                                                M.Lown, t.L);
     } else {
-        k_m2l_node<float><<<gm, 256, 0, s>>>(t.recA, t.recQ, t.recF, T.nnodes, M.fstart, M.fend,
-                                             M.far_sorted, mask, M.Lownf);
+        k_m2l_node<float, FORM><<<gm, 256, 0, s>>>(t.recA, t.recQ, t.recF, T.nnodes, M.fstart,
+                                                   M.fend, M.far_sorted, mask, M.Lownf);
         k_l2l_chain<float><<<gl, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, T.nleaves,
                                               M.Lownf, t.Lf);
     }
+}
+
+hipError_t launch_far_mutual(Tree &t, hipStream_t s)
+{
+    if (t.p.expansion == FMM_EXPANSION_DEHNEN)
+        far_mutual<FMM_EXPANSION_DEHNEN>(t, s);
+    else
+        far_mutual<FMM_EXPANSION_PHANTOM>(t, s);
+    return hipGetLastError();
+}
+
+template <int FORM>
+static void far_leaf(Tree &t, bool fp64, hipStream_t s)
+{
+    const int nl = t.topo.nleaves;
+    const int g = (nl * 16 + 255) / 256;
+    if (fp64)
+        k_m2l_leaf_f64<FORM><<<g, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl, t.far_cnt,
+                                               t.far_src, (int)t.cap_far, t.L);
+    else
+        k_m2l_leaf_f32<FORM><<<g, 256, 0, s>>>(t.recA, t.recF, t.leaf_node, nl, t.far_cnt,
+                                               t.far_src, (int)t.cap_far, t.Lf);
+}
+
+static hipError_t far_leaves(Tree &t, bool fp64, hipStream_t s)
+{
+    if (t.p.expansion == FMM_EXPANSION_DEHNEN)
+        far_leaf<FMM_EXPANSION_DEHNEN>(t, fp64, s);
+    else
+        far_leaf<FMM_EXPANSION_PHANTOM>(t, fp64, s);
     return hipGetLastError();
 }
 
 hipError_t launch_far(Tree &t, hipStream_t s)
 {
-    const Topology &T = t.topo;
-    const int nl = T.nleaves;
-    if (t.p.precision == FMM_FP64)
-        k_m2l_leaf_f64<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
-                                                             t.far_cnt, t.far_src, (int)t.cap_far,
-                                                             t.L);
-    else
-        k_m2l_leaf_f32<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recF, t.leaf_node, nl,
-                                                             t.far_cnt, t.far_src, (int)t.cap_far,
-                                                             t.Lf);
-    return hipGetLastError();
+    return far_leaves(t, t.p.precision == FMM_FP64, s);
 }
 
-hipError_t launch_far_f64(Tree &t, hipStream_t s)
-{
-    const int nl = t.topo.nleaves;
-    k_m2l_leaf_f64<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
-                                                         t.far_cnt, t.far_src, (int)t.cap_far, t.L);
-    return hipGetLastError();
-}
+hipError_t launch_far_f64(Tree &t, hipStream_t s) { return far_leaves(t, true, s); }
 
 hipError_t launch_near(Tree &t, void *a, hipStream_t s)
 {

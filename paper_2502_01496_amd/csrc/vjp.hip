@@ -52,11 +52,103 @@ __device__ __forceinline__ constexpr double mult3(int i, int j, int k)
 }
 
 // ---------------------------------------------------------------- M2L adjoint
+// Adjoint of the second expansion form: L1 = a0 r + b2 q (a0 = M g1 + g3 qq / 6,
+// b2 = g2 / 3), L2 = A1 r r + A0 d, L3 = A2 r r r + A1 (d r + d r + d r).
+__device__ __forceinline__ void m2l_vjp_dehnen(const double r[3], double M, const double *Qs,
+                                               const double *Lb, double rb[3], double &Mb,
+                                               double Qb[6])
+{
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double u = rsqrt_pos(r2);  // r2 > 0: far pairs are separated
+    const double u2 = u * u;
+    const double g1 = -u * u2, g2 = -3.0 * g1 * u2, g3 = -5.0 * g2 * u2, g4 = -7.0 * g3 * u2;
+    double Qf[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Qf[i][j] = Qs[sym2(i, j)];
+    double q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        q[i] = Qf[i][0] * r[0] + Qf[i][1] * r[1] + Qf[i][2] * r[2];
+    const double qq = q[0] * r[0] + q[1] * r[1] + q[2] * r[2];
+    constexpr double k3 = 1.0 / 3.0, k6 = 1.0 / 6.0;
+    const double qq6 = qq * k6;
+    const double a0 = M * g1 + g3 * qq6, b2 = g2 * k3;
+    const double A1 = M * g2, A2 = M * g3;
+    const double A[3] = {Lb[0], Lb[1], Lb[2]};
+    double B[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            B[i][j] = Lb[3 + sym2(i, j)] * (i == j ? 1.0 : 0.5);
+    double T[3][3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                T[i][j][k] = Lb[9 + sym3(i, j, k)] * (1.0 / mult3(i, j, k));
+    double Br[3], tr1[3], Trr[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        Br[m] = B[m][0] * r[0] + B[m][1] * r[1] + B[m][2] * r[2];
+        tr1[m] = T[0][0][m] + T[1][1][m] + T[2][2][m];
+        double s_rr = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                s_rr += T[i][j][m] * r[i] * r[j];
+        Trr[m] = s_rr;
+    }
+    const double Ar = A[0] * r[0] + A[1] * r[1] + A[2] * r[2];
+    const double Aq = A[0] * q[0] + A[1] * q[1] + A[2] * q[2];
+    const double trB = B[0][0] + B[1][1] + B[2][2];
+    const double Brr = Br[0] * r[0] + Br[1] * r[1] + Br[2] * r[2];
+    const double tr1r = tr1[0] * r[0] + tr1[1] * r[1] + tr1[2] * r[2];
+    const double Trrr = Trr[0] * r[0] + Trr[1] * r[1] + Trr[2] * r[2];
+    // cotangents of a0, b2 (L1) and A0, A1, A2 (L2, L3)
+    const double a0b = Ar, b2b = Aq;
+    const double A0b = trB, A1b = Brr + 3.0 * tr1r, A2b = Trrr;
+    double qb[3];
+    Mb += (a0b + A0b) * g1 + A1b * g2 + A2b * g3;
+    const double qqb = a0b * g3 * k6;
+    const double gb1 = (a0b + A0b) * M;
+    const double gb2 = A1b * M + b2b * k3;
+    const double gb3 = A2b * M + a0b * qq6;
+    const double sg = gb1 * g2 + gb2 * g3 + gb3 * g4;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        qb[m] = b2 * A[m] + qqb * r[m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        rb[m] += a0 * A[m] + 2.0 * A1 * Br[m] + 3.0 * A2 * Trr[m] + 3.0 * A1 * tr1[m] +
+                 qqb * q[m] + (qb[0] * Qf[0][m] + qb[1] * Qf[1][m] + qb[2] * Qf[2][m]) + sg * r[m];
+    // stored quadrupole entries, through q = Qf r only
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j)
+            Qb[sym2(i, j)] += i == j ? qb[i] * r[i] : qb[i] * r[j] + qb[j] * r[i];
+}
+
 // Given the stored cotangent Lb[19] of one M2L term K(r; M, Q), accumulate
 // d<Lb, K>/dr into rb, d/dM into Mb and d/dQ (stored entries) into Qb.
+// FORM = FMM_EXPANSION_DEHNEN: K's second and third orders come from the
+// monopole alone (A0 = M g1, A1 = M g2, A2 = M g3 in place of a0, a1, a2 and
+// no b3, b4 terms), so the quadrupole is reached through L1 only.
+template <int FORM>
 __device__ __forceinline__ void m2l_vjp(const double r[3], double M, const double *Qs,
                                         const double *Lb, double rb[3], double &Mb, double Qb[6])
 {
+    if constexpr (FORM == FMM_EXPANSION_DEHNEN) {
+        m2l_vjp_dehnen(r, M, Qs, Lb, rb, Mb, Qb);
+        return;
+    }
     const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
     const double u = rsqrt_pos(r2);  // r2 > 0: far pairs are separated
     const double u2 = u * u;
@@ -368,6 +460,7 @@ __global__ __launch_bounds__(256) void k_vjp_l2p(const double4 *__restrict__ pm,
 }
 
 // 2a. M2L^T, sink side: 16 lanes per leaf over its far list, cbar_sink += rbar.
+template <int FORM>
 __global__ __launch_bounds__(256) void k_vjp_m2l_sink(
     const double *__restrict__ recA, const double *__restrict__ recQ,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
@@ -390,7 +483,7 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_sink(
         const double *rbp = recA + (int64_t)NREC * b;
         const double r[3] = {rv[0] - rbp[0], rv[1] - rbp[1], rv[2] - rbp[2]};
         double Mb = 0.0, Qb[6] = {0, 0, 0, 0, 0, 0};
-        m2l_vjp(r, rbp[3], recQ + (int64_t)NREC * b, Lb, rb, Mb, Qb);
+        m2l_vjp<FORM>(r, rbp[3], recQ + (int64_t)NREC * b, Lb, rb, Mb, Qb);
     }
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1)
@@ -427,6 +520,7 @@ __global__ void k_piece_fill(const int64_t *__restrict__ poff, int nnodes, int32
             pnode[j] = b;
 }
 
+template <int FORM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_m2l_src_piece(
     const double *__restrict__ recA, const double *__restrict__ recQ,
     const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc,
@@ -456,7 +550,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int k = 0; k < 19; ++k)
             Lb[k] = Lbar[(int64_t)NLOC * sgm + k];
         double rb[3] = {0.0, 0.0, 0.0}, Mb = 0.0, Qb[6] = {0, 0, 0, 0, 0, 0};
-        m2l_vjp(r, M, Qs, Lb, rb, Mb, Qb);
+        m2l_vjp<FORM>(r, M, Qs, Lb, rb, Mb, Qb);
         acc[0] += Mb;
 #pragma unroll
         for (int k = 0; k < 6; ++k)
@@ -1066,6 +1160,18 @@ static hipError_t build_m2lt_pieces(Tree &t, hipStream_t s)
     return hipGetLastError();
 }
 
+// M2L^T, sink side per leaf and source side in pieces.
+template <int FORM>
+static void vjp_m2l(Tree &t, hipStream_t s)
+{
+    const int nl = t.topo.nleaves;
+    k_vjp_m2l_sink<FORM><<<(nl * 16 + 255) / 256, 256, 0, s>>>(
+        t.recA, t.recQ, t.leaf_node, nl, t.far_cnt, t.far_src, (int)t.cap_far, t.Lbar, t.nadj);
+    if (t.npieces > 0)
+        k_vjp_m2l_src_piece<FORM><<<(int)((t.npieces + 3) / 4), 256, 0, s>>>(
+            t.recA, t.recQ, t.farT.off, t.farT.src, t.Lbar, t.pnode, t.poff, t.npieces, t.ppart);
+}
+
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s)
 {
     const Topology &T = t.topo;
@@ -1098,12 +1204,10 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
         k_vjp_prep<double><<<gs, 256, 0, s>>>((const double *)abar, n, t.perm, t.p.G, t.abt);
     k_vjp_l2p<<<(nl + 255) / 256, 256, 0, s>>>(t.pm, t.abt, t.leaf_node, nl, t.first, t.count,
                                                t.recA, t.L, t.Lbar, t.xbt, t.nadj);
-    k_vjp_m2l_sink<<<(nl * 16 + 255) / 256, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl,
-                                                         t.far_cnt, t.far_src, (int)t.cap_far,
-                                                         t.Lbar, t.nadj);
-    if (t.npieces > 0)
-        k_vjp_m2l_src_piece<<<(int)((t.npieces + 3) / 4), 256, 0, s>>>(
-            t.recA, t.recQ, t.farT.off, t.farT.src, t.Lbar, t.pnode, t.poff, t.npieces, t.ppart);
+    if (t.p.expansion == FMM_EXPANSION_DEHNEN)
+        vjp_m2l<FMM_EXPANSION_DEHNEN>(t, s);
+    else
+        vjp_m2l<FMM_EXPANSION_PHANTOM>(t, s);
     k_vjp_m2l_src_fold<<<(T.nnodes + 255) / 256, 256, 0, s>>>(t.left, T.nnodes, t.poff, t.ppart,
                                                               t.nadj);
     const int nsub = (T.leaf_size + 7) / 8;

@@ -23,6 +23,7 @@ FMM_OK, FMM_ERR_INVALID, FMM_ERR_ALLOC, FMM_ERR_CAPACITY, FMM_ERR_HIP, FMM_ERR_S
     0, -1, -2, -3, -4, -5)
 FMM_FP64, FMM_FP32 = 0, 1
 FMM_WALK_PHANTOM, FMM_WALK_MUTUAL = 0, 1
+FMM_EXPANSION_PHANTOM, FMM_EXPANSION_DEHNEN = 0, 1
 FMM_REWALK = 1
 
 _STATUS = {0: "FMM_OK", -1: "FMM_ERR_INVALID", -2: "FMM_ERR_ALLOC", -3: "FMM_ERR_CAPACITY",
@@ -38,7 +39,7 @@ class FmmError(RuntimeError):
 class fmm_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("r_kern", C.c_double), ("G", C.c_double),
                 ("leaf_size", C.c_int32), ("walk", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("expansion", C.c_int32)]
 
 
 class fmm_stats(C.Structure):
@@ -134,7 +135,10 @@ def _ptr(t, dtype, shape=None, name="tensor"):
 def default_params(**kw) -> fmm_params:
     p = fmm_params()
     lib().fmm_default_params(C.byref(p))
+    fields = {f[0] for f in fmm_params._fields_}
     for k, v in kw.items():
+        if k not in fields:
+            raise TypeError(f"fmm_params has no field {k!r}")
         setattr(p, k, v)
     return p
 
@@ -273,13 +277,14 @@ class GravityFMM:
     leaf_size: int = 8
     walk: int = FMM_WALK_PHANTOM
     precision: int = FMM_FP64
+    expansion: int = FMM_EXPANSION_PHANTOM
     tree: int | None = None
     n: int = 0
 
     def params(self) -> fmm_params:
         return default_params(theta=self.theta, r_kern=self.r_kern, G=self.G,
                               leaf_size=self.leaf_size, walk=self.walk,
-                              precision=self.precision)
+                              precision=self.precision, expansion=self.expansion)
 
     def build(self, x, stream=None):
         if self.tree is not None and x.shape[0] != self.n:

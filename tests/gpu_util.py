@@ -16,12 +16,13 @@ def to_dev(*arrs):
 
 
 def gpu_run(x, m, h, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, export=True, local=False,
-            walk=F.FMM_WALK_PHANTOM):
+            walk=F.FMM_WALK_PHANTOM, expansion=F.FMM_EXPANSION_PHANTOM):
     """build -> moments -> forces on the GPU; returns (a, export dict, info)."""
     import torch
 
     X, Mt, H = to_dev(x, m, h)
-    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision, walk=walk)
+    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision, walk=walk,
+                         expansion=expansion)
     t = F.fmm_build_tree(X, p)
     try:
         F.fmm_moments(t, X, Mt, H)
@@ -47,14 +48,16 @@ def eta(a, ref):
     return float(np.sqrt(((a - ref) ** 2).sum() / (ref ** 2).sum()))
 
 
-def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repeat=1):
+def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repeat=1,
+            expansion=F.FMM_EXPANSION_PHANTOM):
     """build -> moments -> forces -> VJP on the GPU; returns (a, [(xbar, mbar)] * repeat)."""
     import torch
 
     X, Mt, H = to_dev(x, m, h)
     dt = torch.float32 if precision == F.FMM_FP32 else torch.float64
     AB = torch.from_numpy(np.ascontiguousarray(abar)).to("cuda").to(dt)
-    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision)
+    p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision,
+                         expansion=expansion)
     t = F.fmm_build_tree(X, p)
     out = []
     try:

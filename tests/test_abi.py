@@ -21,8 +21,10 @@ def test_library_exports_header_functions():
 
 def test_default_params():
     p = F.default_params()
-    assert (p.theta, p.r_kern, p.G, p.leaf_size, p.walk, p.precision, p.reserved) == (
-        0.5, 2.0, 1.0, 8, F.FMM_WALK_PHANTOM, F.FMM_FP64, 0)
+    assert (p.theta, p.r_kern, p.G, p.leaf_size, p.walk, p.precision, p.expansion) == (
+        0.5, 2.0, 1.0, 8, F.FMM_WALK_PHANTOM, F.FMM_FP64, F.FMM_EXPANSION_PHANTOM)
+    with pytest.raises(TypeError):
+        F.default_params(reserved=0)
     assert C.sizeof(F.fmm_stats) == 16 * 8
 
 
@@ -34,7 +36,7 @@ def _build(p, n=10, x=C.c_void_p(16), tree=None):
 @pytest.mark.parametrize("field,value", [
     ("theta", -0.1), ("theta", 1.5), ("theta", float("nan")), ("r_kern", 0.0),
     ("r_kern", float("inf")), ("G", float("nan")), ("leaf_size", 0), ("leaf_size", 65),
-    ("walk", 7), ("precision", 2), ("reserved", 1)])
+    ("walk", 7), ("precision", 2), ("expansion", 2), ("expansion", -1)])
 def test_bad_params_rejected_on_host(field, value):
     p = F.default_params()
     setattr(p, field, value)
