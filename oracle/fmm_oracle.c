@@ -876,3 +876,106 @@ ORC_API void orc_stats(int64_t n, const double *x, const double *v, const double
     }
     out[15] = 0.0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Asymmetric cell pairs and the total-force estimates of Sec. 4 (eq. (33))  */
+/* and Sec. 6 (eq. (46)).                                                    */
+/*                                                                           */
+/* A pair "a receives the field of b" (b in the far list of sink a) is       */
+/* asymmetric when the reverse pair (a in the far list of b) is absent.  For  */
+/* a cell v with at least two leaves, v1 is its lightest leaf (smallest mass; */
+/* among equal masses the one farthest from c_v, the "lightest distant        */
+/* cell"), l_v = |c_v1 - c_v|, and                                           */
+/*   T(v) = M_v1 l_v^3 / (M_v - M_v1) (1 - M_v1 / (M_v - M_v1));             */
+/* T(v) = 0 for a leaf (zero size).  Per asymmetric pair, eq. (33) adds      */
+/*   4 M_a M_b / r^5 (T(a) + T(b)),   r = |c_a - c_b|,                       */
+/* and eq. (46), with N_v the number of leaves of v and m_leaf the mean leaf  */
+/* mass, adds                                                                */
+/*   4 m_leaf^2 N_a N_b / r^5 (U(a) + U(b)),                                 */
+/*   U(v) = s_v^3 (N_v - 2) / (N_v - 1)^2 for N_v >= 2, 0 for a leaf.        */
+/* out[0] = eq. (33) sum, out[1] = eq. (46) sum, out[2] = number of          */
+/* asymmetric pairs, out[3] = those of them with a cell of >= 2 leaves.      */
+/* Sums in sink order, then list order.  Pinned by: the two-leaf super-cell   */
+/* of Sec. 4 (eq. (33) reduces to eq. (32)), equal leaf masses (eq. (33)     */
+/* with l = s equals eq. (46)), brute-force lightest leaves and reverse-pair  */
+/* checks on small trees, and zero for the mutual walk's lists.              */
+/* ------------------------------------------------------------------------ */
+static void asym_leaves(const int32_t *left, const int32_t *right, int32_t v, int32_t *out,
+                        int32_t *k)
+{
+    if (left[v] < 0) {
+        out[(*k)++] = v;
+        return;
+    }
+    asym_leaves(left, right, left[v], out, k);
+    asym_leaves(left, right, right[v], out, k);
+}
+
+static int asym_has(const int32_t *far_off, const int32_t *far_src, int32_t a, int32_t b)
+{
+    for (int32_t e = far_off[a]; e < far_off[a + 1]; ++e)
+        if (far_src[e] == b)
+            return 1;
+    return 0;
+}
+
+ORC_API void orc_asym_estimate(int32_t nnodes, const int32_t *left, const int32_t *right,
+                               const double *M, const double *c, const double *s,
+                               const int32_t *far_off, const int32_t *far_src, double m_leaf,
+                               double *out)
+{
+    double *T = (double *)calloc((size_t)nnodes, sizeof(double));
+    double *U = (double *)calloc((size_t)nnodes, sizeof(double));
+    double *N = (double *)calloc((size_t)nnodes, sizeof(double));
+    int32_t *lv = (int32_t *)malloc((size_t)nnodes * sizeof(int32_t));
+    for (int32_t v = 0; v < nnodes; ++v) {
+        int32_t k = 0;
+        asym_leaves(left, right, v, lv, &k);
+        N[v] = (double)k;
+        if (k < 2)
+            continue;
+        double m1 = M[lv[0]];
+        for (int32_t j = 1; j < k; ++j)
+            if (M[lv[j]] < m1)
+                m1 = M[lv[j]];
+        double d2 = -1.0;
+        for (int32_t j = 0; j < k; ++j) {
+            int32_t u = lv[j];
+            if (M[u] != m1)
+                continue;
+            double dx = c[3 * u] - c[3 * v], dy = c[3 * u + 1] - c[3 * v + 1],
+                   dz = c[3 * u + 2] - c[3 * v + 2];
+            double e = dx * dx + dy * dy + dz * dz;
+            if (e > d2)
+                d2 = e;
+        }
+        double l = sqrt(d2);
+        double rest = M[v] - m1;
+        T[v] = m1 * l * l * l / rest * (1.0 - m1 / rest);
+        U[v] = s[v] * s[v] * s[v] * (N[v] - 2.0) / ((N[v] - 1.0) * (N[v] - 1.0));
+    }
+    double f33 = 0.0, f46 = 0.0, nasym = 0.0, nsuper = 0.0;
+    for (int32_t a = 0; a < nnodes; ++a)
+        for (int32_t e = far_off[a]; e < far_off[a + 1]; ++e) {
+            int32_t b = far_src[e];
+            if (asym_has(far_off, far_src, b, a))
+                continue;
+            nasym += 1.0;
+            if (N[a] >= 2.0 || N[b] >= 2.0)
+                nsuper += 1.0;
+            double dx = c[3 * a] - c[3 * b], dy = c[3 * a + 1] - c[3 * b + 1],
+                   dz = c[3 * a + 2] - c[3 * b + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            double r5 = r2 * r2 * sqrt(r2);
+            f33 += 4.0 * M[a] * M[b] / r5 * (T[a] + T[b]);
+            f46 += 4.0 * m_leaf * m_leaf * N[a] * N[b] / r5 * (U[a] + U[b]);
+        }
+    out[0] = f33;
+    out[1] = f46;
+    out[2] = nasym;
+    out[3] = nsuper;
+    free(T);
+    free(U);
+    free(N);
+    free(lv);
+}

@@ -83,6 +83,7 @@ def lib():
         L.orc_near_and_l2p.argtypes = [I64, _d, _d, _d, _i32, I32, _i32, _i32, _i32, _d, _d,
                                        _i32, _i32, D, _d]
         L.orc_stats.argtypes = [I64, _d, _opt(_d), _d, _d, _d]
+        L.orc_asym_estimate.argtypes = [I32, _i32, _i32, _d, _d, _d, _i32, _i32, D, _d]
         _lib = L
     return _lib
 
@@ -321,6 +322,19 @@ def stats(x, v, m, a):
     o = stats_raw(x, v, m, a)
     return {"sumF": o[0:3], "sumAbsF": o[3], "ratio": o[4], "mass": o[5], "xcom": o[6:9],
             "P": o[9:12], "L": o[12:15]}
+
+
+def asym_estimate(tree: Tree, mom: Moments, lists: Lists, m_leaf=None) -> dict:
+    """Asymmetric pairs of the lists and the total-force estimates eq. (33)
+    and eq. (46) (m_leaf: mean leaf mass unless given)."""
+    nn = tree.nnodes
+    if m_leaf is None:
+        m_leaf = float(mom.M[0]) / int((tree.left < 0).sum())
+    fs = lists.far_src if len(lists.far_src) else np.zeros(1, np.int32)
+    out = np.empty(4)
+    lib().orc_asym_estimate(nn, tree.left, tree.right, mom.M, mom.c, mom.s, lists.far_off,
+                            np.ascontiguousarray(fs, np.int32), float(m_leaf), out)
+    return {"F33": out[0], "F46": out[1], "n_asym": int(out[2]), "n_asym_super": int(out[3])}
 
 
 def kdk(x, v, m, h, dt, steps, force):
