@@ -350,6 +350,155 @@ ORC_API int32_t orc_build_tree(int64_t n, const double *x, int32_t leaf_size, in
 }
 
 /* ------------------------------------------------------------------------ */
+/* kd-tree cut through the centre of mass (Sec. 2 as written: cells are cut  */
+/* through their centres of mass, across the longest axis, until a cell      */
+/* holds no more than leaf_size particles).                                  */
+/* Reading: positions are quantised on a grid of 2^32 steps over the largest */
+/* extent of the global bounding box, q = floor((x - lo) 2^32 / ext) clamped  */
+/* to 2^32 - 1 (the Morton quantisation with 32 bits), and masses to weights  */
+/* w = floor(m / m_max 2^24) clamped to [1, 2^24] (all w = 1 without masses). */
+/* Per cell: the longest axis d of the quantised bounding box (ties -> lowest */
+/* axis); the cut is the weighted centre of mass of q_d, taken exactly in     */
+/* integer arithmetic: a particle goes left iff q_d sum(w) < sum(w q_d).  So  */
+/* the partition does not depend on any summation order.  A cell whose        */
+/* particles share one grid point along d (then along every axis) is halved   */
+/* in tree order (left: the first ceil(n/2)).  Both children keep the        */
+/* parent's order (ascending Morton rank at the root); node ids are DFS       */
+/* pre-order.  Pinned by: an exact big-integer re-implementation on small     */
+/* inputs and the cut lying at the FP64 centre of mass to within the grid.    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t *q;  /* [3][n] quantised coordinates by caller index */
+    uint32_t *w;  /* [n] weights by caller index */
+    int64_t n;
+    int32_t *order, *tmp;
+    int32_t leaf_size, nn;
+    int32_t *first, *count, *left, *right, *axis;
+} comtree_ctx;
+
+static int32_t build_com_node(comtree_ctx *t, int32_t lo, int32_t n)
+{
+    int32_t id = t->nn++;
+    t->first[id] = lo;
+    t->count[id] = n;
+    t->left[id] = t->right[id] = -1;
+    t->axis[id] = -1;
+    if (n <= t->leaf_size)
+        return id;
+    uint32_t mn[3], mx[3];
+    for (int d = 0; d < 3; ++d)
+        mn[d] = mx[d] = t->q[d * t->n + t->order[lo]];
+    for (int32_t k = 0; k < n; ++k)
+        for (int d = 0; d < 3; ++d) {
+            uint32_t v = t->q[d * t->n + t->order[lo + k]];
+            if (v < mn[d])
+                mn[d] = v;
+            if (v > mx[d])
+                mx[d] = v;
+        }
+    int ax = 0;
+    for (int d = 1; d < 3; ++d)
+        if (mx[d] - mn[d] > mx[ax] - mn[ax])
+            ax = d;
+    t->axis[id] = ax;
+    int32_t nl;
+    if (mx[ax] == mn[ax]) {
+        nl = (n + 1) / 2; /* one grid point: halve in tree order */
+    } else {
+        uint64_t sw = 0;
+        unsigned __int128 swq = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            int32_t i = t->order[lo + k];
+            sw += t->w[i];
+            swq += (unsigned __int128)t->w[i] * t->q[ax * t->n + i];
+        }
+        int32_t w = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            int32_t i = t->order[lo + k];
+            if ((unsigned __int128)t->q[ax * t->n + i] * sw < swq)
+                t->tmp[w++] = i;
+        }
+        nl = w;
+        for (int32_t k = 0; k < n; ++k) {
+            int32_t i = t->order[lo + k];
+            if (!((unsigned __int128)t->q[ax * t->n + i] * sw < swq))
+                t->tmp[w++] = i;
+        }
+        memcpy(t->order + lo, t->tmp, (size_t)n * sizeof(int32_t));
+    }
+    int32_t l = build_com_node(t, lo, nl);
+    int32_t r = build_com_node(t, lo + nl, n - nl);
+    t->left[id] = l;
+    t->right[id] = r;
+    return id;
+}
+
+/* m may be NULL (equal weights).  Node arrays must hold 2n entries.
+ * Returns the number of nodes. */
+ORC_API int32_t orc_build_tree_com(int64_t n, const double *x, const double *m, int32_t leaf_size,
+                                   int32_t *perm, int32_t *first, int32_t *count, int32_t *left,
+                                   int32_t *right, int32_t *axis)
+{
+    comtree_ctx t;
+    memset(&t, 0, sizeof t);
+    t.n = n;
+    t.q = (uint32_t *)malloc((size_t)(3 * n) * sizeof(uint32_t));
+    t.w = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    t.tmp = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    t.order = perm;
+    t.leaf_size = leaf_size;
+    t.first = first;
+    t.count = count;
+    t.left = left;
+    t.right = right;
+    t.axis = axis;
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d)
+        lo[d] = hi[d] = x[d];
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double v = x[3 * i + d];
+            if (v < lo[d])
+                lo[d] = v;
+            if (v > hi[d])
+                hi[d] = v;
+        }
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d)
+        if (hi[d] - lo[d] > ext)
+            ext = hi[d] - lo[d];
+    if (ext == 0.0)
+        ext = 1.0;
+    double scale = 4294967296.0 / ext;
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double v = floor((x[3 * i + d] - lo[d]) * scale);
+            t.q[d * n + i] = v >= 4294967295.0 ? 4294967295u : (uint32_t)v;
+        }
+    double mmax = 0.0;
+    if (m)
+        for (int64_t i = 0; i < n; ++i)
+            if (m[i] > mmax)
+                mmax = m[i];
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t w = 1;
+        if (m && mmax > 0.0) {
+            double v = floor(m[i] / mmax * 16777216.0);
+            w = v >= 1.0 ? (v <= 16777216.0 ? (uint32_t)v : 16777216u) : 1u;
+        }
+        t.w[i] = w;
+    }
+    uint64_t *key = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    orc_morton(n, x, key, perm); /* root order: ascending Morton rank */
+    build_com_node(&t, 0, (int32_t)n);
+    free(key);
+    free(t.q);
+    free(t.w);
+    free(t.tmp);
+    return t.nn;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Cell properties (Sec. 2): mass M, centre of mass c, size s = radius of    */
 /* the smallest sphere about c holding all the cell's particles, h_max, and  */
 /* the quadrupole of eq. (7) about c (per-particle masses).                  */

@@ -71,6 +71,9 @@ def lib():
         L.orc_morton.argtypes = [I64, _d, _u64, _i32]
         L.orc_build_tree.restype = I32
         L.orc_build_tree.argtypes = [I64, _d, I32, _i32, _i32, _i32, _i32, _i32, _i32]
+        L.orc_build_tree_com.argtypes = [I64, _d, _opt(_d), I32, _i32, _i32, _i32, _i32, _i32,
+                                         _i32]
+        L.orc_build_tree_com.restype = I32
         L.orc_moments.argtypes = [I64, _d, _d, _d, _i32, I32, _i32, _i32, _i32, _i32,
                                   _d, _d, _d, _d, _d]
         L.orc_p2m.argtypes = [I64, _d, _d, _d, _d, _d]
@@ -167,6 +170,23 @@ def build_tree(x, leaf_size=8) -> Tree:
     arrs = [np.empty(cap, np.int32) for _ in range(5)]
     nn = lib().orc_build_tree(n, x, int(leaf_size), perm, *arrs)
     return Tree(perm, *[a[:nn].copy() for a in arrs])
+
+
+def build_tree_com(x, m=None, leaf_size=10) -> Tree:
+    """kd-tree cut through the centre of mass (Sec. 2 as written); m=None:
+    equal weights."""
+    x = _f64(x)
+    n = x.shape[0]
+    cap = max(2 * n, 1)
+    perm = np.empty(n, np.int32)
+    arrs = [np.empty(cap, np.int32) for _ in range(5)]
+    nn = lib().orc_build_tree_com(n, x, None if m is None else _f64(m), int(leaf_size), perm,
+                                  *arrs)
+    return Tree(perm, *[a[:nn].copy() for a in arrs])
+
+
+MEDIAN_TREE = 0  # count-median cut (the reading used by default)
+COM_TREE = 1     # cut through the centre of mass
 
 
 @dataclass
@@ -288,9 +308,9 @@ class FmmResult:
 
 
 def fmm(x, m, h, theta=0.5, r_kern=2.0, G=1.0, leaf_size=8, policy=PHANTOM,
-        form=PHANTOM_FORM) -> FmmResult:
+        form=PHANTOM_FORM, tree_kind=MEDIAN_TREE) -> FmmResult:
     """Serial kd-tree FMM: build, moments, walk, M2L (+L2L), L2P + near field."""
-    tree = build_tree(x, leaf_size)
+    tree = build_tree(x, leaf_size) if tree_kind == MEDIAN_TREE else build_tree_com(x, m, leaf_size)
     mom = moments(x, m, h, tree)
     lists = walk(tree, mom, theta, r_kern, policy)
     L = far_field(tree, mom, lists, policy, form)
