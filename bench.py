@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--forms", action="store_true",
                     help="only compare the two M2L expansion forms (momentum, accuracy, far-field "
                          "time) for both walks and three theta on the workload, and exit")
+    ap.add_argument("--trees", action="store_true",
+                    help="only compare the count-median tree with the centre-of-mass tree "
+                         "(momentum, accuracy, shape, stage times) on the workload, and exit")
     ap.add_argument("--vjp-reps", type=int, default=5,
                     help="timed VJP calls at the final state (0 = skip)")
     ap.add_argument("--mutual-steps", type=int, default=5,
@@ -300,7 +303,8 @@ def sigma_sweep(args):
     sizes = [1 << k for k in range(args.sweep_min_log2, args.sweep_max_log2 + 1)]
     thetas = [0.2, 0.3, 0.5, 0.7]
     seeds = [101 + k for k in range(args.sweep_seeds)]
-    res = {th: {} for th in thetas}
+    keys = ("sumF", "F33", "F46", "n_asym", "n_asym_super")
+    res = {th: {k: {} for k in keys} for th in thetas}
     for n in sizes:
         for sd in seeds:
             x_np, m_np, h_np = W.polytrope_single(n, sd)
@@ -311,18 +315,30 @@ def sigma_sweep(args):
                 g = F.GravityFMM(theta=th)
                 a = g.forces(x, m, h)
                 st = F.fmm_momentum_stats(x, None, m, a)
+                est = F.fmm_asymmetry_estimate(g.tree)   # eqs. (33), (46) on these lists
                 g.free()
-                res[th].setdefault(n, []).append(float(np.linalg.norm(st["sumF"])))
+                rec = dict(est, sumF=float(np.linalg.norm(st["sumF"])))
+                for k in keys:
+                    res[th][k].setdefault(n, []).append(rec[k])
             log(f"[sweep] n={n} seed={sd}: " + ", ".join(
-                f"theta {th}: |sumF| {res[th][n][-1]:.3e}" for th in thetas))
-    out = {"sweep": "polytrope n=1, M=R=1, 58-neighbour h, leaf<-cell walk, FP64",
+                f"theta {th}: |sumF| {res[th]['sumF'][n][-1]:.3e} eq33 {res[th]['F33'][n][-1]:.3e} "
+                f"eq46 {res[th]['F46'][n][-1]:.3e} pairs {res[th]['n_asym_super'][n][-1]}"
+                for th in thetas))
+    out = {"sweep": "polytrope n=1, M=R=1, 58-neighbour h, leaf<-cell walk, FP64; eq. (33) and "
+                    "eq. (46) from the same lists (mean leaf mass)",
            "sizes": sizes, "seeds": seeds, "theta": {}}
     for th in thetas:
-        mean = np.array([np.mean(res[th][n]) for n in sizes])
-        sig, c = np.polyfit(np.log(sizes), np.log(mean), 1)
-        out["theta"][str(th)] = {"sumF_mean": [float(v) for v in mean],
-                                 "sumF_all": [res[th][n] for n in sizes], "sigma": float(sig)}
-        log(f"[sweep] theta {th}: sigma = {sig:.3f}")
+        rec = {}
+        for k in keys:
+            mean = np.array([np.mean(res[th][k][n]) for n in sizes])
+            rec[k + "_mean"] = [float(v) for v in mean]
+            rec[k + "_all"] = [res[th][k][n] for n in sizes]
+            if len(sizes) > 1 and (mean > 0).all():
+                rec[k + "_exponent"] = float(np.polyfit(np.log(sizes), np.log(mean), 1)[0])
+        rec["sigma"] = rec.get("sumF_exponent")
+        out["theta"][str(th)] = rec
+        log(f"[sweep] theta {th}: exponents " + ", ".join(
+            f"{k} {rec.get(k + '_exponent', float('nan')):.3f}" for k in keys))
     print(json.dumps(out), flush=True)
 
 
@@ -372,6 +388,59 @@ def forms_compare(args):
           flush=True)
 
 
+def trees_compare(args):
+    """Count-median cuts (the default reading) against cuts through the
+    centre of mass (Sec. 2 as written), leaf sizes 8 and 10, at theta 0.3,
+    0.5, 0.7: |sum F| / sum |F|, eta against the FP64 direct sum on sampled
+    sinks, the asymmetric-pair census, tree shape and stage times (FP64,
+    leaf <- cell walk, static configuration)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_01496_amd import fmm as F
+    from paper_2502_01496_amd import workloads as W
+
+    x_np, m_np, h_np, _ = W.config(args.workload)
+    n = len(m_np)
+    x = torch.from_numpy(x_np).cuda()
+    m = torch.from_numpy(m_np).cuda()
+    h = torch.from_numpy(h_np).cuda()
+    rng = np.random.default_rng(123)
+    sinks = torch.from_numpy(rng.choice(n, size=min(args.accuracy_sinks, n), replace=False)).cuda()
+    ref = direct_reference(x, m, h, sinks)
+    rows = []
+    for th in (0.3, 0.5, 0.7):
+        for shape, leaf in ((F.FMM_TREE_MEDIAN, 8), (F.FMM_TREE_MEDIAN, 10), (F.FMM_TREE_COM, 8),
+                            (F.FMM_TREE_COM, 10)):
+            g = F.GravityFMM(theta=th, leaf_size=leaf, tree_shape=shape)
+            a = g.forces(x, m, h)
+            F.fmm_set_timing(g.tree, True)
+            for _ in range(5):
+                g.forces(x, m, h, out=a)
+            torch.cuda.synchronize()
+            st_ms = F.fmm_stage_times(g.tree)
+            F.fmm_set_timing(g.tree, False)
+            st = F.fmm_momentum_stats(x, None, m, a)
+            est = F.fmm_asymmetry_estimate(g.tree)
+            info = F.fmm_tree_info(g.tree)
+            got = a[sinks]
+            eta = float(torch.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum()))
+            g.free()
+            row = {"theta": th, "tree": "com" if shape else "median", "leaf": leaf,
+                   "ratio": st["ratio"], "sumF": float(np.linalg.norm(st["sumF"])), "eta": eta,
+                   "nodes": info["nodes"], "leaves": info["leaves"], "depth": info["depth"],
+                   "far": info["n_far"], "near_leaf_pairs": info["n_near"],
+                   "stages_ms": {k: round(v, 4) for k, v in st_ms.items()}, **est}
+            rows.append(row)
+            log(f"[trees] theta {th} {row['tree']:6s} leaf {leaf:2d}: |sumF|/sum|F| "
+                f"{st['ratio']:.3e}  eta {eta:.3e}  nodes {info['nodes']} depth {info['depth']} "
+                f"far {info['n_far']} near {info['n_near']}  eq33 {est['F33']:.3e}  build "
+                f"{st_ms['build']:.3f} walk {st_ms['walk']:.3f} far {st_ms['far']:.3f} near "
+                f"{st_ms['near']:.3f} ms")
+    print(json.dumps({"trees": f"{args.workload}: n={n}, FP64, static", "rows": rows}),
+          flush=True)
+
+
 def copy_calibration(mib):
     """A plain copy of mib MiB (reads and writes mib MiB each time)."""
     import torch
@@ -395,6 +464,9 @@ def main():
         return
     if args.forms:
         forms_compare(args)
+        return
+    if args.trees:
+        trees_compare(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

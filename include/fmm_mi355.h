@@ -78,6 +78,23 @@ enum { FMM_WALK_PHANTOM = 0, FMM_WALK_MUTUAL = 1 };
  * the leaf <- cell lists. */
 enum { FMM_EXPANSION_PHANTOM = 0, FMM_EXPANSION_DEHNEN = 1 };
 
+/* Tree shape (Sec. 2).
+ * FMM_TREE_MEDIAN: each cell is cut across its longest axis at the count
+ *   median (the reading documented at fmm_build_tree); the shape depends on
+ *   n and leaf_size only.
+ * FMM_TREE_COM: each cell is cut across its longest axis through its centre
+ *   of mass, as Sec. 2 describes (PHANTOM: leaf_size 10).  Positions are
+ *   quantised on a grid of 2^32 steps over the largest extent of the global
+ *   bounding box, q = floor((x - lo) 2^32 / ext), masses to weights
+ *   w = floor(m / m_max 2^24) in [1, 2^24] (all 1 without masses); the axis
+ *   is the longest of the quantised bounding box (ties -> lowest) and a
+ *   particle goes left iff q_d sum(w) < sum(w q_d), exactly, in integer
+ *   arithmetic.  A cell whose particles share one grid point is halved in
+ *   tree order.  Children keep ascending Morton rank.  The shape depends on
+ *   the data: node-sized buffers are allocated for the largest possible tree
+ *   (2n - 1 nodes), and the build synchronises the stream once per level. */
+enum { FMM_TREE_MEDIAN = 0, FMM_TREE_COM = 1 };
+
 /* fmm_forces flags */
 enum { FMM_REWALK = 1 /* rebuild the interaction lists even if present */ };
 
@@ -89,6 +106,8 @@ typedef struct fmm_params {
     int32_t walk;      /* FMM_WALK_* (default PHANTOM) */
     int32_t precision; /* FMM_FP64 or FMM_FP32 (default FP64) */
     int32_t expansion; /* FMM_EXPANSION_* (default PHANTOM) */
+    int32_t tree;      /* FMM_TREE_* (default MEDIAN) */
+    int32_t reserved;  /* must be 0 */
 } fmm_params;
 
 /* Momentum diagnostics of Secs. 5-6, accumulated in FP64.
@@ -129,6 +148,14 @@ void fmm_default_params(fmm_params *p);
 fmm_status fmm_build_tree(const double *x, int64_t n, const fmm_params *p, void *stream,
                           fmm_tree **tree);
 
+/* fmm_build_tree with particle masses, which the centre-of-mass cut
+ * (FMM_TREE_COM) weighs the positions with:
+ *   m  device, double[n], or NULL (equal weights); read during the call's
+ *      stream work only; unused by FMM_TREE_MEDIAN.
+ * A reused tree must also keep its tree shape (FMM_ERR_INVALID otherwise). */
+fmm_status fmm_build_tree_weighted(const double *x, const double *m, int64_t n,
+                                   const fmm_params *p, void *stream, fmm_tree **tree);
+
 /* Cell properties for the current tree membership (Sec. 2): mass M, centre of
  * mass c, size s (radius of the smallest sphere about c that holds all the
  * cell's particles), the largest smoothing length h_max, and the quadrupole
@@ -163,6 +190,28 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream);
  * Errors: FMM_ERR_STATE (no prior fmm_forces on this tree state). */
 fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *m_bar,
                           void *stream);
+
+/* Census of the asymmetric cell pairs of the current interaction lists and the
+ * total-force estimates built on them: Sec. 4, eq. (33), and Sec. 6, eq. (46).
+ * A pair (sink a receives the field of source b) is asymmetric when the lists
+ * lack the reverse pair.  For a cell v with N_v >= 2 leaves, v1 is its lightest
+ * leaf (ties: the one farthest from c_v), l = |c_v1 - c_v|,
+ *   T(v) = M_v1 l^3 / (M_v - M_v1) (1 - M_v1 / (M_v - M_v1)),
+ *   U(v) = s_v^3 (N_v - 2) / (N_v - 1)^2   (T = U = 0 for a leaf);
+ * per asymmetric pair eq. (33) adds 4 M_a M_b (T(a) + T(b)) / r^5 and
+ * eq. (46) adds 4 m_leaf^2 N_a N_b (U(a) + U(b)) / r^5, r = |c_a - c_b|.
+ *   m_leaf  the leaf mass M_l of eq. (46); <= 0 selects the mean leaf mass
+ *           (total mass / number of leaves);
+ *   out     HOST double[4]: eq. (33) sum, eq. (46) sum, number of asymmetric
+ *           pairs, number of those with a cell of >= 2 leaves; written before
+ *           the call returns (synchronises stream).
+ * Works on the lists of either walk (the mutual walk's are symmetric by
+ * construction: all four outputs 0).  With the leaf <- cell lists it builds
+ * the transposed far lists (kept until the next walk, shared with the VJP).
+ * Sums in a fixed order (bitwise reproducible).
+ * Errors: FMM_ERR_STATE (no lists for the current moments), FMM_ERR_INVALID,
+ * FMM_ERR_HIP. */
+fmm_status fmm_asymmetry_estimate(fmm_tree *tree, double m_leaf, double *out, void *stream);
 
 /* Momentum diagnostics (Secs. 5-6) in FP64 with a fixed reduction order
  * (bitwise reproducible run to run):

@@ -123,6 +123,9 @@ void build_topology(int64_t n, int leaf_size, Topology &T)
         T.int_nodes.insert(T.int_nodes.end(), byl[l].begin(), byl[l].end());
         T.lvl_int_off.push_back((int32_t)T.int_nodes.size());
     }
+    T.nbig = (int)T.big_nodes.size();
+    T.node_cap = T.nnodes;
+    T.leaf_cap = T.nleaves;
 }
 
 template <typename P>
@@ -151,6 +154,11 @@ static void release(Tree *t)
 {
     (void)hipDeviceSynchronize();
     release_vjp(*t);
+    release_asym(*t);
+    if (t->s2part)
+        (void)hipFree(t->s2part);
+    if (t->cw.h_ctl)
+        (void)hipHostFree(t->cw.h_ctl);
     for (auto &b : t->owned)
         (void)hipFree(b.p);
     t->owned.clear();
@@ -190,28 +198,75 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     // pair buffers exercise their overflow-and-retry path.
     if (const char *e = std::getenv("FMM_MI355_MW_CAP"))
         t->mw_init_cap = std::max<int64_t>(1, std::atoll(e));
-    build_topology(n, p.leaf_size, t->topo);
-    const Topology &T = t->topo;
-    const int64_t nn = T.nnodes;
-    const int64_t nblk = (n + RS_TILE - 1) / RS_TILE;
     hipError_t e = hipSuccess;
 #define A(expr)                \
     if (e == hipSuccess)       \
         e = (expr);
-    A(upload(*t, &t->first, T.first));
-    A(upload(*t, &t->count, T.count));
-    A(upload(*t, &t->left, T.left));
-    A(upload(*t, &t->right, T.right));
-    A(upload(*t, &t->parent, T.parent));
-    A(upload(*t, &t->level, T.level));
-    A(upload(*t, &t->leaf_node, T.leaf_node));
-    A(upload(*t, &t->node_leaf, T.node_leaf));
-    A(upload(*t, &t->blk_node, T.blk_node));
-    A(upload(*t, &t->blk_start, T.blk_start));
-    A(upload(*t, &t->blk_end, T.blk_end));
-    A(upload(*t, &t->blk_first, T.blk_first));
-    A(upload(*t, &t->sub_root, T.sub_root));
-    A(upload(*t, &t->int_nodes, T.int_nodes));
+    if (p.tree == FMM_TREE_COM) {
+        // shape set by each build; node-sized buffers for the largest tree
+        Topology &T = t->topo;
+        T = Topology();
+        T.n = n;
+        T.leaf_size = p.leaf_size;
+        T.com = true;
+        T.node_cap = 2 * n - 1;
+        T.leaf_cap = n;
+        const int64_t nc = T.node_cap;
+        A(dalloc(*t, &t->first, nc));
+        A(dalloc(*t, &t->count, nc));
+        A(dalloc(*t, &t->left, nc));
+        A(dalloc(*t, &t->right, nc));
+        A(dalloc(*t, &t->parent, nc));
+        A(dalloc(*t, &t->level, nc));
+        A(dalloc(*t, &t->leaf_node, T.leaf_cap));
+        A(dalloc(*t, &t->node_leaf, nc));
+        A(dalloc(*t, &t->int_nodes, nc));
+        A(dalloc(*t, &t->big_nodes, nc));
+        Tree::ComWork &W = t->cw;
+        W.cap_a = n / (p.leaf_size + 1) + 2;
+        W.cap_c = (n + COM_CHUNK - 1) / COM_CHUNK + W.cap_a + 2;
+        A(dalloc(*t, &W.q, 4 * n));
+        A(dalloc(*t, &W.q_tmp, 4 * n));
+        A(dalloc(*t, &W.perm_tmp, n));
+        A(dalloc(*t, &W.node, 8 * nc));
+        A(dalloc(*t, &W.ren, 4 * nc));
+        for (int k = 0; k < 2; ++k) {
+            A(dalloc(*t, &W.act[k], W.cap_a));
+            A(dalloc(*t, &W.act_choff[k], W.cap_a + 1));
+            A(dalloc(*t, &W.chk[k], 3 * W.cap_c));
+        }
+        A(dalloc(*t, &W.cpart, 16 * W.cap_c));
+        A(dalloc(*t, &W.cleft, W.cap_c));
+        A(dalloc(*t, &W.cbase, W.cap_c));
+        A(dalloc(*t, &W.split, 4 * W.cap_a));
+        A(dalloc(*t, &W.nl, W.cap_a));
+        A(dalloc(*t, &W.big, nc));
+        A(dalloc(*t, &W.ctl, 8));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&W.h_ctl, 8 * sizeof(int64_t), hipHostMallocDefault);
+    } else {
+        build_topology(n, p.leaf_size, t->topo);
+        const Topology &T = t->topo;
+        A(upload(*t, &t->first, T.first));
+        A(upload(*t, &t->count, T.count));
+        A(upload(*t, &t->left, T.left));
+        A(upload(*t, &t->right, T.right));
+        A(upload(*t, &t->parent, T.parent));
+        A(upload(*t, &t->level, T.level));
+        A(upload(*t, &t->leaf_node, T.leaf_node));
+        A(upload(*t, &t->node_leaf, T.node_leaf));
+        A(upload(*t, &t->blk_node, T.blk_node));
+        A(upload(*t, &t->blk_start, T.blk_start));
+        A(upload(*t, &t->blk_end, T.blk_end));
+        A(upload(*t, &t->blk_first, T.blk_first));
+        A(upload(*t, &t->sub_root, T.sub_root));
+        A(upload(*t, &t->int_nodes, T.int_nodes));
+        A(upload(*t, &t->big_nodes, T.big_nodes));
+    }
+    const Topology &T = t->topo;
+    const int64_t nn = T.node_cap;
+    const int64_t nblk = (n + RS_TILE - 1) / RS_TILE;
+    t->s2part_depth = T.com ? 64 : T.depth;
     A(dalloc(*t, &t->axis, nn));
     A(dalloc(*t, &t->keys0, 3 * n));
     A(dalloc(*t, &t->keys1, 3 * n));
@@ -238,8 +293,10 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->recQ, NREC * nn));
     A(dalloc(*t, &t->recF, NREC * nn));
     A(dalloc(*t, &t->s2bits, nn));
-    A(dalloc(*t, &t->s2part, (size_t)T.depth * ((n + 63) / 64)));
-    A(upload(*t, &t->big_nodes, T.big_nodes));
+    // per-level partial maxima of s^2: grown by deeper centre-of-mass trees,
+    // so kept apart from the fixed allocations
+    A(hipMalloc((void **)&t->s2part,
+                std::max<size_t>((size_t)t->s2part_depth * ((n + 63) / 64), 32) * sizeof(uint64_t)));
     A(dalloc(*t, &t->upcnt, nn));
     A(dalloc(*t, &t->far_cnt, nn));
     A(dalloc(*t, &t->near_cnt, nn));
@@ -288,6 +345,10 @@ static fmm_status check_params(const fmm_params *p)
         return fail(FMM_ERR_INVALID, "unknown precision %d", p->precision);
     if (p->expansion != FMM_EXPANSION_PHANTOM && p->expansion != FMM_EXPANSION_DEHNEN)
         return fail(FMM_ERR_INVALID, "unknown expansion form %d", p->expansion);
+    if (p->tree != FMM_TREE_MEDIAN && p->tree != FMM_TREE_COM)
+        return fail(FMM_ERR_INVALID, "unknown tree shape %d", p->tree);
+    if (p->reserved != 0)
+        return fail(FMM_ERR_INVALID, "reserved must be 0");
     return FMM_OK;
 }
 
@@ -339,8 +400,9 @@ static fmm_status ensure_slots(Tree &t, int64_t cap_far, int64_t cap_near)
         int64_t want;
     } w[2] = {{&t.far_buf, &t.far_src, &t.cap_far, cap_far},
               {&t.near_buf, &t.near_src, &t.cap_near, cap_near}};
+    const bool more_leaves = nl > t.slots_nl;
     for (auto &x : w) {
-        if (x.b->p && *x.cap == x.want)
+        if (x.b->p && *x.cap == x.want && !more_leaves)
             continue;
         if (x.b->p) {
             HIP_TRY(hipDeviceSynchronize());
@@ -355,6 +417,7 @@ static fmm_status ensure_slots(Tree &t, int64_t cap_far, int64_t cap_near)
         *x.ptr = (int32_t *)p;
         *x.cap = x.want;
     }
+    t.slots_nl = std::max(t.slots_nl, nl);
     return FMM_OK;
 }
 
@@ -396,11 +459,11 @@ static fmm_status ensure_mutual(Tree &t, int64_t cap_task, int64_t cap_far, int6
         if ((st = mw_alloc(M.owned, &p, MW_CNT * sizeof(unsigned long long))) != FMM_OK)
             return st;
         M.cnt = (unsigned long long *)p;
-        if ((st = mw_alloc(M.owned, &p, 2 * (size_t)T.nnodes * sizeof(int64_t))) != FMM_OK)
+        if ((st = mw_alloc(M.owned, &p, 2 * (size_t)T.node_cap * sizeof(int64_t))) != FMM_OK)
             return st;
         M.fstart = (int64_t *)p;
-        M.fend = M.fstart + T.nnodes;
-        if ((st = mw_alloc(M.owned, &p, (size_t)T.nleaves * sizeof(int64_t))) != FMM_OK)
+        M.fend = M.fstart + T.node_cap;
+        if ((st = mw_alloc(M.owned, &p, (size_t)T.leaf_cap * sizeof(int64_t))) != FMM_OK)
             return st;
         M.nstart = (int64_t *)p;
         if ((st = mw_alloc(M.owned, &p, (size_t)RS_PASSES * 256 * sizeof(uint32_t))) != FMM_OK)
@@ -411,13 +474,13 @@ static fmm_status ensure_mutual(Tree &t, int64_t cap_task, int64_t cap_far, int6
     }
     if (t.p.precision == FMM_FP64 && !M.Lown) {
         void *p = nullptr;
-        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.nnodes * sizeof(double))) != FMM_OK)
+        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.node_cap * sizeof(double))) != FMM_OK)
             return st;
         M.Lown = (double *)p;
     }
     if (t.p.precision == FMM_FP32 && !M.Lownf) {
         void *p = nullptr;
-        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.nnodes * sizeof(float))) != FMM_OK)
+        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.node_cap * sizeof(float))) != FMM_OK)
             return st;
         M.Lownf = (float *)p;
     }
@@ -581,12 +644,20 @@ void fmm_default_params(fmm_params *p)
     p->walk = FMM_WALK_PHANTOM;
     p->precision = FMM_FP64;
     p->expansion = FMM_EXPANSION_PHANTOM;
+    p->tree = FMM_TREE_MEDIAN;
+    p->reserved = 0;
 }
 
 const char *fmm_last_error(void) { return g_err.c_str(); }
 
 fmm_status fmm_build_tree(const double *x, int64_t n, const fmm_params *p, void *stream,
                           fmm_tree **tree)
+{
+    return fmm_build_tree_weighted(x, nullptr, n, p, stream, tree);
+}
+
+fmm_status fmm_build_tree_weighted(const double *x, const double *m, int64_t n,
+                                   const fmm_params *p, void *stream, fmm_tree **tree)
 {
     if (!x || !tree)
         return fail(FMM_ERR_INVALID, "x and tree must not be NULL");
@@ -602,6 +673,8 @@ fmm_status fmm_build_tree(const double *x, int64_t n, const fmm_params *p, void 
         t = reinterpret_cast<Tree *>(*tree);
         if (t->topo.n != n || t->topo.leaf_size != p->leaf_size)
             return fail(FMM_ERR_INVALID, "a reused tree must keep n and leaf_size");
+        if (t->p.tree != p->tree)
+            return fail(FMM_ERR_INVALID, "a reused tree must keep its tree shape");
         t->p = *p;
     } else {
         st = create_tree(n, *p, &t);
@@ -610,7 +683,31 @@ fmm_status fmm_build_tree(const double *x, int64_t n, const fmm_params *p, void 
     }
     hipStream_t s = (hipStream_t)stream;
     StageTimer tm(*t, s, 0);
-    hipError_t e = launch_build(*t, x, s);
+    hipError_t e = t->p.tree == FMM_TREE_COM ? launch_build_com(*t, x, m, s)
+                                             : launch_build(*t, x, s);
+    if (e == hipSuccess && t->topo.depth > COM_MAX_DEPTH) {
+        // the walks' stacks hold a bounded number of levels
+        const int d = t->topo.depth;
+        t->has_tree = t->has_moments = t->has_lists = t->has_forces = false;
+        if (!*tree)
+            release(t);
+        return fail(FMM_ERR_INVALID,
+                    "the centre-of-mass tree has %d levels (at most %d are supported): the "
+                    "particles are too strongly clustered for this tree shape",
+                    d, COM_MAX_DEPTH);
+    }
+    if (e == hipSuccess && t->topo.depth > t->s2part_depth) {
+        // a deeper centre-of-mass tree: grow the per-level s^2 partials
+        e = hipStreamSynchronize(s);
+        if (e == hipSuccess)
+            e = hipFree(t->s2part);
+        t->s2part = nullptr;
+        const int64_t d = t->topo.depth + 16;
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&t->s2part, (size_t)d * ((n + 63) / 64) * sizeof(uint64_t));
+        if (e == hipSuccess)
+            t->s2part_depth = d;
+    }
     if (e != hipSuccess) {
         if (!*tree)
             release(t);
@@ -657,8 +754,9 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
     const bool walk = !t.has_lists || (flags & FMM_REWALK) || t.lists_policy != t.p.walk;
     if (t.p.walk == FMM_WALK_MUTUAL)
         return forces_mutual(t, a, walk, s);
-    if (walk && !t.far_buf.p) {
-        fmm_status st = ensure_slots(t, 512, 128);
+    if (walk && (!t.far_buf.p || t.slots_nl < t.topo.nleaves)) {
+        fmm_status st = ensure_slots(t, t.far_buf.p ? t.cap_far : 512,
+                                     t.near_buf.p ? t.cap_near : 128);
         if (st != FMM_OK)
             return st;
     }
@@ -742,6 +840,22 @@ fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *
     if (e != hipSuccess)
         return fail(FMM_ERR_HIP, "vjp launch failed: %s", hipGetErrorString(e));
     tm.done();
+    return FMM_OK;
+}
+
+fmm_status fmm_asymmetry_estimate(fmm_tree *tree, double m_leaf, double *out, void *stream)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!out)
+        return fail(FMM_ERR_INVALID, "out must not be NULL");
+    if (!std::isfinite(m_leaf))
+        return fail(FMM_ERR_INVALID, "m_leaf must be finite");
+    Tree &t = *reinterpret_cast<Tree *>(tree);
+    if (!t.has_forces || !t.has_lists)
+        return fail(FMM_ERR_STATE, "no interaction lists for the current moments: call fmm_forces "
+                                   "first");
+    HIP_TRY(launch_asym(t, m_leaf, out, (hipStream_t)stream));
     return FMM_OK;
 }
 
@@ -848,20 +962,25 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
     const Topology &T = t.topo;
     const int64_t nn = T.nnodes;
     HIP_TRY(hipDeviceSynchronize());
+    // the topology as the device holds it (the centre-of-mass tree has no
+    // host copy)
+    std::vector<int32_t> hl(nn), hnl(nn);
+    HIP_TRY(hipMemcpy(hl.data(), t.left, nn * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hnl.data(), t.node_leaf, nn * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (perm)
         HIP_TRY(hipMemcpy(perm, t.perm, T.n * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (first)
-        std::memcpy(first, T.first.data(), nn * sizeof(int32_t));
+        HIP_TRY(hipMemcpy(first, t.first, nn * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (count)
-        std::memcpy(count, T.count.data(), nn * sizeof(int32_t));
+        HIP_TRY(hipMemcpy(count, t.count, nn * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (left)
-        std::memcpy(left, T.left.data(), nn * sizeof(int32_t));
+        std::memcpy(left, hl.data(), nn * sizeof(int32_t));
     if (right)
-        std::memcpy(right, T.right.data(), nn * sizeof(int32_t));
+        HIP_TRY(hipMemcpy(right, t.right, nn * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (axis) {
         HIP_TRY(hipMemcpy(axis, t.axis, nn * sizeof(int32_t), hipMemcpyDeviceToHost));
         for (int64_t v = 0; v < nn; ++v)
-            if (T.left[v] < 0)
+            if (hl[v] < 0)
                 axis[v] = -1;
     }
     if (rec) {
@@ -899,7 +1018,7 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
             if (off)
                 off[0] = 0;
             for (int64_t v = 0; v < nn; ++v) {
-                int lf = T.node_leaf[v];
+                int lf = hnl[v];
                 if (lf >= 0) {
                     if (src)
                         std::memcpy(src + o, slots.data() + (size_t)lf * cap,
@@ -921,7 +1040,8 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
             const MutualLists &M = t.mw;
             std::vector<int64_t> se(2 * nn);
             std::vector<uint64_t> keys(M.n_far);
-            HIP_TRY(hipMemcpy(se.data(), M.fstart, se.size() * sizeof(int64_t),
+            HIP_TRY(hipMemcpy(se.data(), M.fstart, nn * sizeof(int64_t), hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(se.data() + nn, M.fend, nn * sizeof(int64_t),
                               hipMemcpyDeviceToHost));
             if (M.n_far)
                 HIP_TRY(hipMemcpy(keys.data(), M.far_sorted, keys.size() * sizeof(uint64_t),
@@ -947,7 +1067,7 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
         HIP_TRY(hipMemcpy(Lh.data(), t.L, Lh.size() * sizeof(double), hipMemcpyDeviceToHost));
         for (int64_t v = 0; v < nn; ++v)
             for (int k = 0; k < 19; ++k)
-                local[19 * v + k] = (t.has_forces && T.left[v] < 0) ? Lh[NLOC * v + k] : 0.0;
+                local[19 * v + k] = (t.has_forces && hl[v] < 0) ? Lh[NLOC * v + k] : 0.0;
     }
     return FMM_OK;
 }

@@ -928,17 +928,26 @@ __global__ __launch_bounds__(SUBTREE_THREADS) void k_subtree(
 }
 
 // ---------------------------------------------------------------- driver
-hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
+// Bounding box (with the non-finite check) and the Morton order: sorted keys
+// in keys0, caller indices in ascending Morton rank in vals0.
+hipError_t launch_morton_order(Tree &t, const double *x, hipStream_t s)
 {
-    const Topology &T = t.topo;
-    const int64_t n = T.n;
+    const int64_t n = t.topo.n;
     const int gs = (int)std::min<int64_t>((n + 255) / 256, 2048);
     k_bbox_init<<<1, 64, 0, s>>>(t.bbox, t.err);
     k_bbox<<<(int)std::min<int64_t>((n + 255) / 256, 256), 256, 0, s>>>(x, n, t.bbox, t.err);
     // Morton keys in (keys1, vals1) -> sorted into (keys0, vals0)
     k_morton<<<gs, 256, 0, s>>>(x, n, t.bbox, t.keys1, t.vals1);
-    hipError_t e = sort_by_halves(t.keys1, t.vals1, t.keys0, t.vals0, n, 1, t.rs_hist, t.rs_tot,
-                                  t.run_cnt, t.run_list, t.err, s);
+    return sort_by_halves(t.keys1, t.vals1, t.keys0, t.vals0, n, 1, t.rs_hist, t.rs_tot,
+                          t.run_cnt, t.run_list, t.err, s);
+}
+
+hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const int64_t n = T.n;
+    const int gs = (int)std::min<int64_t>((n + 255) / 256, 2048);
+    hipError_t e = launch_morton_order(t, x, s);
     if (e != hipSuccess)
         return e;
     // lists buffer 0: axis lists 0..2 and the rank list 3

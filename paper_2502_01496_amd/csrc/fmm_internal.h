@@ -28,6 +28,8 @@ constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
 constexpr int RS_SCAN_THREADS = 256;
 constexpr int RS_PASSES = 8;
 constexpr int MAX_LEAF = 64;
+constexpr int COM_CHUNK = 4096;  // particles per chunk of the centre-of-mass build
+constexpr int COM_MAX_DEPTH = 64; // deepest centre-of-mass tree accepted (walk stacks)
 constexpr int NREC = 8;   // doubles per node record (geometry / quadrupole)
 constexpr int NLOC = 20;  // doubles per local expansion (19 used)
 
@@ -76,6 +78,12 @@ struct Topology {
     int64_t n = 0;
     int leaf_size = 0;
     int nnodes = 0, nleaves = 0, depth = 0;
+    // capacities of the node- and leaf-sized buffers: the sizes themselves for
+    // the median tree; 2n - 1 and n for the centre-of-mass tree, whose shape
+    // depends on the data
+    int64_t node_cap = 0, leaf_cap = 0;
+    bool com = false;
+    int nbig = 0;                      // nodes of at least 64 particles
     std::vector<int32_t> first, count, left, right, parent, level, leaf_node, node_leaf;
     // level-synchronous partition of the nodes larger than SUBTREE_MAX
     int nlevels_up = 0;
@@ -213,6 +221,33 @@ struct Tree {
     MutualLists mw;
     int64_t mw_init_cap = 0;        // test hook: FMM_MI355_MW_CAP sets small first capacities
 
+    // centre-of-mass tree build (FMM_TREE_COM)
+    struct ComWork {
+        uint32_t *q = nullptr, *q_tmp = nullptr;   // [4][n]: q0, q1, q2, w in tree order
+        int32_t *perm_tmp = nullptr;
+        int32_t *node = nullptr;   // [8][node_cap] BFS: first, count, parent, level, axis,
+                                   // left, right, internal rank
+        int32_t *ren = nullptr;    // [4][node_cap] subtree nodes, leaves, pre-order id, leaf offset
+        int32_t *act[2] = {nullptr, nullptr};     // active BFS ids per level
+        int64_t *act_choff[2] = {nullptr, nullptr};
+        int32_t *chk[2] = {nullptr, nullptr};     // [3][cap_c]: active index, start, end
+        uint64_t *cpart = nullptr;                 // 16 per chunk
+        int32_t *cleft = nullptr;                  // left count per chunk, then its base
+        int32_t *cbase = nullptr;                  // right base per chunk
+        uint64_t *split = nullptr;                 // 4 per active node: axis|flag, sw, swq lo, hi
+        int32_t *nl = nullptr;                     // left count per active node
+        int32_t *big = nullptr;                    // BFS ids of nodes of >= 64 particles
+        int64_t *ctl = nullptr, *h_ctl = nullptr;  // next level's A, C; big count; m_max bits
+        int64_t cap_a = 0, cap_c = 0;
+        std::vector<int32_t> lev_off;              // BFS id range per level
+    } cw;
+    int64_t s2part_depth = 0;       // levels the s^2 partial buffer holds
+    int64_t slots_nl = 0;           // leaves the list slots were allocated for
+
+    // asymmetric-pair census: T, U, N per node, then partial sums per sink
+    double *asym = nullptr;
+    double *h_asym = nullptr;       // pinned, 4
+
     bool has_tree = false, has_moments = false, has_lists = false, has_forces = false;
     int lists_policy = -1;
 
@@ -229,6 +264,8 @@ hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
 
 // launchers (return hipError_t of the last launch / runtime call)
 hipError_t launch_build(Tree &t, const double *x, hipStream_t s);
+hipError_t launch_morton_order(Tree &t, const double *x, hipStream_t s);
+hipError_t launch_build_com(Tree &t, const double *x, const double *m, hipStream_t s);
 hipError_t launch_moments(Tree &t, const double *x, const double *m, const double *h,
                           hipStream_t s);
 hipError_t launch_walk(Tree &t, hipStream_t s);
@@ -244,7 +281,10 @@ hipError_t launch_mutual_walk(Tree &t, hipStream_t s);
 hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream_t s);
 hipError_t launch_far_mutual(Tree &t, hipStream_t s);
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s);
+hipError_t ensure_transposed(Tree &t, hipStream_t s);
 void release_vjp(Tree &t);
+hipError_t launch_asym(Tree &t, double m_leaf, double *out, hipStream_t s);
+void release_asym(Tree &t);
 hipError_t launch_kick_drift(double *x, double *v, const void *a, int a_fp32, int64_t n,
                              double kick, double drift, hipStream_t s);
 

@@ -276,7 +276,7 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
     const int64_t nwaves = (n + 63) / 64;
     k_node_s2<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, t.first, t.count, t.left,
                                                      t.right, t.s2bits, t.s2part, nwaves);
-    const int nbig = (int)T.big_nodes.size();
+    const int nbig = T.nbig;
     if (nbig > 0)
         k_node_s2_fold<<<(nbig + 3) / 4, 256, 0, s>>>(t.big_nodes, nbig, t.first, t.count,
                                                       t.level, t.s2part, nwaves, t.s2bits);

@@ -337,7 +337,7 @@ hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream
     if (e != hipSuccess)
         return e;
     const uint64_t *ns = (pn & 1) ? M.nkeys[1] : M.nkeys[0];
-    k_mw_fill64<<<256, 256, 0, s>>>(M.fstart, 2 * (int64_t)T.nnodes);
+    k_mw_fill64<<<256, 256, 0, s>>>(M.fstart, 2 * T.node_cap);  // fstart and fend
     if (n_far > 0)
         k_mw_far_bounds<<<(int)((n_far + 255) / 256), 256, 0, s>>>(M.far_sorted, n_far, bits,
                                                                    M.fstart, M.fend);

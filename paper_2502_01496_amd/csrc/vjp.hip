@@ -1034,20 +1034,20 @@ static hipError_t ensure_vjp_base(Tree &t)
     if (t.abt)
         return hipSuccess;
     const Topology &T = t.topo;
-    const int64_t n = T.n, nn = T.nnodes;
+    const int64_t n = T.n, nc = T.node_cap;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = valloc(t, &t.abt, 3 * (n + 1));  // + null record
     if (e == hipSuccess) e = valloc(t, &t.xbt, 3 * n);
     if (e == hipSuccess) e = valloc(t, &t.mbt, n);
-    if (e == hipSuccess) e = valloc(t, &t.Lbar, NLOC * nn);
-    if (e == hipSuccess) e = valloc(t, &t.nadj, 16 * nn);
-    if (e == hipSuccess) e = valloc(t, &t.pair_off, T.nleaves + 1);
-    if (e == hipSuccess) e = valloc(t, &t.vscan, T.nleaves / SCAN_TILE + 2);
-    if (e == hipSuccess) e = valloc(t, &t.farT.off, nn + 1);
-    if (e == hipSuccess) e = valloc(t, &t.pcnt, nn);
-    if (e == hipSuccess) e = valloc(t, &t.poff, nn + 1);
-    if (e == hipSuccess) e = valloc(t, &t.pscan, nn / SCAN_TILE + 2);
-    if (e == hipSuccess) e = valloc(t, &t.nearT.off, nn + 1);
+    if (e == hipSuccess) e = valloc(t, &t.Lbar, NLOC * nc);
+    if (e == hipSuccess) e = valloc(t, &t.nadj, 16 * nc);
+    if (e == hipSuccess) e = valloc(t, &t.pair_off, T.leaf_cap + 1);
+    if (e == hipSuccess) e = valloc(t, &t.vscan, T.leaf_cap / SCAN_TILE + 2);
+    if (e == hipSuccess) e = valloc(t, &t.farT.off, nc + 1);
+    if (e == hipSuccess) e = valloc(t, &t.pcnt, nc);
+    if (e == hipSuccess) e = valloc(t, &t.poff, nc + 1);
+    if (e == hipSuccess) e = valloc(t, &t.pscan, nc / SCAN_TILE + 2);
+    if (e == hipSuccess) e = valloc(t, &t.nearT.off, nc + 1);
     if (e == hipSuccess) e = hipHostMalloc((void **)&t.h_pairs, 4 * sizeof(int64_t), hipHostMallocDefault);
     return e;
 }
@@ -1118,7 +1118,8 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
             return e;
     }
     out.npairs = np;
-    e = hipMemcpyAsync(out.src, vs, np * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (np > 0)
+        e = hipMemcpyAsync(out.src, vs, np * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
     return e;
 }
 
@@ -1172,24 +1173,29 @@ static void vjp_m2l(Tree &t, hipStream_t s)
             t.recA, t.recQ, t.farT.off, t.farT.src, t.Lbar, t.pnode, t.poff, t.npieces, t.ppart);
 }
 
+hipError_t ensure_transposed(Tree &t, hipStream_t s)
+{
+    hipError_t e = ensure_vjp_base(t);
+    if (e != hipSuccess || t.has_transposed)
+        return e;
+    e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, t.farT, s);
+    if (e == hipSuccess)
+        e = build_m2lt_pieces(t, s);
+    if (e == hipSuccess)
+        e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, t.nearT, s);
+    if (e == hipSuccess)
+        t.has_transposed = true;
+    return e;
+}
+
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s)
 {
     const Topology &T = t.topo;
     const int64_t n = T.n;
     const int nl = T.nleaves;
-    hipError_t e = ensure_vjp_base(t);
+    hipError_t e = ensure_transposed(t, s);
     if (e != hipSuccess)
         return e;
-    if (!t.has_transposed) {
-        e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, t.farT, s);
-        if (e == hipSuccess)
-            e = build_m2lt_pieces(t, s);
-        if (e == hipSuccess)
-            e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, t.nearT, s);
-        if (e != hipSuccess)
-            return e;
-        t.has_transposed = true;
-    }
     const bool fp32 = t.p.precision == FMM_FP32;
     if (fp32) {
         // the reverse pass runs in FP64: form the FP64 local expansions

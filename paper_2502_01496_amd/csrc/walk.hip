@@ -20,6 +20,8 @@
 namespace fmm {
 
 constexpr int WALK_STACK = 96;
+// a DFS holds at most depth + 1 entries
+static_assert(COM_MAX_DEPTH + 2 <= WALK_STACK, "narrow walk stack shorter than the deepest tree");
 constexpr int WIDE_STACK = 1024;
 
 __device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, double sa, double ha,

@@ -24,6 +24,7 @@ FMM_OK, FMM_ERR_INVALID, FMM_ERR_ALLOC, FMM_ERR_CAPACITY, FMM_ERR_HIP, FMM_ERR_S
 FMM_FP64, FMM_FP32 = 0, 1
 FMM_WALK_PHANTOM, FMM_WALK_MUTUAL = 0, 1
 FMM_EXPANSION_PHANTOM, FMM_EXPANSION_DEHNEN = 0, 1
+FMM_TREE_MEDIAN, FMM_TREE_COM = 0, 1
 FMM_REWALK = 1
 
 _STATUS = {0: "FMM_OK", -1: "FMM_ERR_INVALID", -2: "FMM_ERR_ALLOC", -3: "FMM_ERR_CAPACITY",
@@ -39,7 +40,7 @@ class FmmError(RuntimeError):
 class fmm_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("r_kern", C.c_double), ("G", C.c_double),
                 ("leaf_size", C.c_int32), ("walk", C.c_int32), ("precision", C.c_int32),
-                ("expansion", C.c_int32)]
+                ("expansion", C.c_int32), ("tree", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fmm_stats(C.Structure):
@@ -68,12 +69,17 @@ def lib() -> C.CDLL:
     L.fmm_last_error.restype = C.c_char_p
     L.fmm_build_tree.argtypes = [_vp, C.c_int64, C.POINTER(fmm_params), _vp, C.POINTER(_vp)]
     L.fmm_build_tree.restype = st
+    L.fmm_build_tree_weighted.argtypes = [_vp, _vp, C.c_int64, C.POINTER(fmm_params), _vp,
+                                          C.POINTER(_vp)]
+    L.fmm_build_tree_weighted.restype = st
     L.fmm_moments.argtypes = [_vp, _vp, _vp, _vp, _vp]
     L.fmm_moments.restype = st
     L.fmm_forces.argtypes = [_vp, _vp, C.c_int32, _vp]
     L.fmm_forces.restype = st
     L.fmm_forces_vjp.argtypes = [_vp, _vp, _vp, _vp, _vp]
     L.fmm_forces_vjp.restype = st
+    L.fmm_asymmetry_estimate.argtypes = [_vp, C.c_double, _vp, _vp]
+    L.fmm_asymmetry_estimate.restype = st
     L.fmm_momentum_stats.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_int64,
                                      C.POINTER(fmm_stats), _vp]
     L.fmm_momentum_stats.restype = st
@@ -148,14 +154,20 @@ def fmm_last_error() -> str:
 
 
 # --------------------------------------------------------------------- calls
-def fmm_build_tree(x, params: fmm_params, stream=None, tree=None):
-    """Build (or rebuild in place) the kd-tree of x (n x 3, float64, GPU)."""
+def fmm_build_tree(x, params: fmm_params, stream=None, tree=None, m=None):
+    """Build (or rebuild in place) the kd-tree of x (n x 3, float64, GPU); m
+    (n, float64, GPU) weighs the centre-of-mass cut of FMM_TREE_COM."""
     import torch
 
     n = x.shape[0]
     h = C.c_void_p(tree) if tree else C.c_void_p(None)
-    _check(lib().fmm_build_tree(_ptr(x, torch.float64, (n, 3), "x"), n, C.byref(params),
-                                _stream(stream), C.byref(h)))
+    if m is None:
+        _check(lib().fmm_build_tree(_ptr(x, torch.float64, (n, 3), "x"), n, C.byref(params),
+                                    _stream(stream), C.byref(h)))
+    else:
+        _check(lib().fmm_build_tree_weighted(_ptr(x, torch.float64, (n, 3), "x"),
+                                             _ptr(m, torch.float64, (n,), "m"), n,
+                                             C.byref(params), _stream(stream), C.byref(h)))
     return h.value
 
 
@@ -194,6 +206,16 @@ def fmm_momentum_stats(x, v, m, a, stream=None) -> dict:
     return {"sumF": np.array(out.sumF), "sumAbsF": out.sumAbsF, "ratio": out.ratio,
             "mass": out.mass, "xcom": np.array(out.xcom), "P": np.array(out.P),
             "L": np.array(out.L)}
+
+
+def fmm_asymmetry_estimate(tree, m_leaf: float = 0.0, stream=None) -> dict:
+    """Asymmetric pairs of the current lists and the total-force estimates
+    eq. (33) and eq. (46) (m_leaf <= 0: mean leaf mass)."""
+    out = np.empty(4)
+    _check(lib().fmm_asymmetry_estimate(C.c_void_p(tree), float(m_leaf),
+                                        out.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return {"F33": float(out[0]), "F46": float(out[1]), "n_asym": int(out[2]),
+            "n_asym_super": int(out[3])}
 
 
 def fmm_kick_drift(x, v, a, kick: float, drift: float, stream=None):
@@ -278,25 +300,28 @@ class GravityFMM:
     walk: int = FMM_WALK_PHANTOM
     precision: int = FMM_FP64
     expansion: int = FMM_EXPANSION_PHANTOM
+    tree_shape: int = FMM_TREE_MEDIAN
     tree: int | None = None
     n: int = 0
 
     def params(self) -> fmm_params:
         return default_params(theta=self.theta, r_kern=self.r_kern, G=self.G,
                               leaf_size=self.leaf_size, walk=self.walk,
-                              precision=self.precision, expansion=self.expansion)
+                              precision=self.precision, expansion=self.expansion,
+                              tree=self.tree_shape)
 
-    def build(self, x, stream=None):
+    def build(self, x, stream=None, m=None):
         if self.tree is not None and x.shape[0] != self.n:
             self.free()
-        self.tree = fmm_build_tree(x, self.params(), stream, self.tree)
+        self.tree = fmm_build_tree(x, self.params(), stream, self.tree,
+                                   m if self.tree_shape == FMM_TREE_COM else None)
         self.n = x.shape[0]
 
     def forces(self, x, m, h, out=None, stream=None, rebuild: bool = True):
         import torch
 
         if rebuild or self.tree is None:
-            self.build(x, stream)
+            self.build(x, stream, m)
         fmm_moments(self.tree, x, m, h, stream)
         if out is None:
             dt = torch.float32 if self.precision == FMM_FP32 else torch.float64

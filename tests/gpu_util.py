@@ -16,14 +16,15 @@ def to_dev(*arrs):
 
 
 def gpu_run(x, m, h, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, export=True, local=False,
-            walk=F.FMM_WALK_PHANTOM, expansion=F.FMM_EXPANSION_PHANTOM):
+            walk=F.FMM_WALK_PHANTOM, expansion=F.FMM_EXPANSION_PHANTOM,
+            tree_shape=F.FMM_TREE_MEDIAN):
     """build -> moments -> forces on the GPU; returns (a, export dict, info)."""
     import torch
 
     X, Mt, H = to_dev(x, m, h)
     p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision, walk=walk,
-                         expansion=expansion)
-    t = F.fmm_build_tree(X, p)
+                         expansion=expansion, tree=tree_shape)
+    t = F.fmm_build_tree(X, p, m=Mt if tree_shape == F.FMM_TREE_COM else None)
     try:
         F.fmm_moments(t, X, Mt, H)
         dt = torch.float32 if precision == F.FMM_FP32 else torch.float64
@@ -49,7 +50,7 @@ def eta(a, ref):
 
 
 def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repeat=1,
-            expansion=F.FMM_EXPANSION_PHANTOM):
+            expansion=F.FMM_EXPANSION_PHANTOM, tree_shape=F.FMM_TREE_MEDIAN):
     """build -> moments -> forces -> VJP on the GPU; returns (a, [(xbar, mbar)] * repeat)."""
     import torch
 
@@ -57,8 +58,8 @@ def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repea
     dt = torch.float32 if precision == F.FMM_FP32 else torch.float64
     AB = torch.from_numpy(np.ascontiguousarray(abar)).to("cuda").to(dt)
     p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision,
-                         expansion=expansion)
-    t = F.fmm_build_tree(X, p)
+                         expansion=expansion, tree=tree_shape)
+    t = F.fmm_build_tree(X, p, m=Mt if tree_shape == F.FMM_TREE_COM else None)
     out = []
     try:
         F.fmm_moments(t, X, Mt, H)

@@ -13,7 +13,7 @@ def test_library_exports_header_functions():
     names = F.header_functions()
     assert len(names) >= 12
     for n in ("fmm_build_tree", "fmm_moments", "fmm_forces", "fmm_forces_vjp",
-              "fmm_momentum_stats"):
+              "fmm_momentum_stats", "fmm_asymmetry_estimate"):
         assert n in names
     missing = [n for n in names if not hasattr(L, n)]
     assert missing == []
@@ -23,8 +23,9 @@ def test_default_params():
     p = F.default_params()
     assert (p.theta, p.r_kern, p.G, p.leaf_size, p.walk, p.precision, p.expansion) == (
         0.5, 2.0, 1.0, 8, F.FMM_WALK_PHANTOM, F.FMM_FP64, F.FMM_EXPANSION_PHANTOM)
+    assert (p.tree, p.reserved) == (F.FMM_TREE_MEDIAN, 0)
     with pytest.raises(TypeError):
-        F.default_params(reserved=0)
+        F.default_params(thetta=0.3)
     assert C.sizeof(F.fmm_stats) == 16 * 8
 
 
@@ -36,7 +37,8 @@ def _build(p, n=10, x=C.c_void_p(16), tree=None):
 @pytest.mark.parametrize("field,value", [
     ("theta", -0.1), ("theta", 1.5), ("theta", float("nan")), ("r_kern", 0.0),
     ("r_kern", float("inf")), ("G", float("nan")), ("leaf_size", 0), ("leaf_size", 65),
-    ("walk", 7), ("precision", 2), ("expansion", 2), ("expansion", -1)])
+    ("walk", 7), ("precision", 2), ("expansion", 2), ("expansion", -1), ("tree", 2),
+    ("reserved", 1)])
 def test_bad_params_rejected_on_host(field, value):
     p = F.default_params()
     setattr(p, field, value)

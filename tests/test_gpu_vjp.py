@@ -17,8 +17,9 @@ from tests.gpu_util import gpu_vjp, say
 pytestmark = pytest.mark.gpu
 
 
-def fd_check(orc, x, m, h, abar, xb, mb, theta, leaf, ndir=4, eps=1e-4, seed=0, form=0):
-    ref = orc.fmm(x, m, h, theta=theta, leaf_size=leaf, form=form)
+def fd_check(orc, x, m, h, abar, xb, mb, theta, leaf, ndir=4, eps=1e-4, seed=0, form=0,
+             tree_kind=0):
+    ref = orc.fmm(x, m, h, theta=theta, leaf_size=leaf, form=form, tree_kind=tree_kind)
     tree, lists = ref.tree, ref.lists
     phi = lambda xx, mm: float((orc.fmm_frozen(xx, mm, h, tree, lists, form=form) * abar).sum())
     rng = np.random.default_rng(seed)
