@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="binary_2x2^18")
     ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--leaf-size", type=int, default=8)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--accuracy-sinks", type=int, default=2048)
@@ -176,7 +177,7 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
     h = torch.from_numpy(h_np).to(dev)
     v = torch.zeros_like(x)
     adt = torch.float32 if prec == F.FMM_FP32 else torch.float64
-    g = F.GravityFMM(theta=args.theta, precision=prec, walk=walk)
+    g = F.GravityFMM(theta=args.theta, precision=prec, walk=walk, leaf_size=args.leaf_size)
     steps = args.steps if steps is None else steps
     a = torch.empty((n, 3), dtype=adt, device=dev)
     dt = args.dt
@@ -504,7 +505,7 @@ def main():
         "vs_baseline": None,
         "dtype": rec["dtype"],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: n={n}, theta={args.theta}, leaf 8, "
+        "config": {"workload": f"{args.workload}: n={n}, theta={args.theta}, leaf {args.leaf_size}, "
                                f"KDK dt={args.dt}, walk=leaf<-cell", "n": n, "theta": args.theta,
                    "precision": args.precision},
         "rel_err": rec["rel_err"],

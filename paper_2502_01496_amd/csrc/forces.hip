@@ -309,6 +309,40 @@ __device__ __forceinline__ int close_first_slot(bool act, bool close, int &front
     return pos;
 }
 
+// Stage list position k of a chunk of the near list (list entries c0 / nsub
+// onward, nsub blocks of at most 8 particles per leaf): its block goes to the
+// close or the far group, or is dropped when empty (a leaf of at most 8 u
+// particles has no block u).
+__device__ __forceinline__ void stage_block(const int32_t *__restrict__ nl, int c0, int k, int nc,
+                                            int nsub, const int32_t *__restrict__ first,
+                                            const int32_t *__restrict__ count,
+                                            const double *__restrict__ recA, const double *rv,
+                                            double r_kern, int2 *R, int &front, int &back)
+{
+    int2 r = make_int2(0, 0);
+    bool close = false;
+    if (k < nc) {
+        const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
+        const int bn = nl[e];
+        r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
+        const double *rb = recA + (int64_t)NREC * bn;
+        const double dx = rv[0] - rb[0], dy = rv[1] - rb[1], dz = rv[2] - rb[2];
+        const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
+        close = dx * dx + dy * dy + dz * dz < CLOSE_FRAC2 * t5 * t5;
+    }
+    const bool keep = r.y > 0;
+    const int pos = close_first_slot(keep, close, front, back);
+    if (keep)
+        R[pos] = r;
+}
+
+// Block of step position k: the close blocks [0, front), then the far ones
+// after the gap left by the dropped blocks.
+__device__ __forceinline__ int skip_gap(int k, int front, int gap)
+{
+    return k < front ? k : k + gap;
+}
+
 // Missing sources read the null record at index n (far away, zero mass,
 // zero smoothing length), so they add exactly zero.
 __device__ __forceinline__ void load_src(const double4 *__restrict__ pm,
@@ -359,7 +393,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     int64_t nnull, double *aout)
 {
     constexpr int NS = 4;
-    __shared__ int2 rng[4][P2P_RANGES];
+    __shared__ int2 rng[4][P2P_RANGES + 8];
     const int w = threadIdx.x >> 6;
     const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
@@ -394,37 +428,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             acc[q] = 0.0;
         for (int c0 = 0; c0 < nb; c0 += P2P_RANGES) {
             const int nc = min(nb - c0, P2P_RANGES);
-            // stage the source blocks of this chunk (padded to a multiple of
-            // 8), close leaves first
+            // stage the source blocks of this chunk, close leaves first
             int front = 0, back = nc;
-            for (int k0 = 0; k0 < ((nc + 7) & ~7); k0 += 64) {
-                const int k = k0 + lane;
-                const bool act = k < nc;
-                int2 r = make_int2(0, 0);
-                bool close = false;
-                if (act) {
-                    const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
-                    const int bn = nl[e];
-                    r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
-                    const double *rb = recA + (int64_t)NREC * bn;
-                    const double dx = rv[0] - rb[0], dy = rv[1] - rb[1], dz = rv[2] - rb[2];
-                    const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
-                    close = dx * dx + dy * dy + dz * dz < CLOSE_FRAC2 * t5 * t5;
-                }
-                const int pos = close_first_slot(act, close, front, back);
-                if (act)
-                    R[pos] = r;
-                else if (k < ((nc + 7) & ~7))
-                    R[k] = r;
-            }
+            for (int k0 = 0; k0 < nc; k0 += 64)
+                stage_block(nl, c0, k0 + lane, nc, nsub, first, count, recA, rv, r_kern, R,
+                            front, back);
+            // the dropped (empty) blocks leave a gap between the close and the
+            // far ones; eight empty blocks follow the last one
+            front = __builtin_amdgcn_readfirstlane(front);
+            const int gap = __builtin_amdgcn_readfirstlane(back - front), ne = nc - gap;
+            if (lane < 8)
+                R[nc + lane] = make_int2(0, 0);
             __builtin_amdgcn_wave_barrier();
             // the next step's sources load while the current step computes
             double4 xj, hj;
-            load_src(pm, ph, nnull, R[grp], slot, xj, hj);
-            for (int kb = 0; kb < nc; kb += 8) {
+            load_src(pm, ph, nnull, R[skip_gap(grp, front, gap)], slot, xj, hj);
+            for (int kb = 0; kb < ne; kb += 8) {
                 double4 xn = xj, hn = hj;
-                if (kb + 8 < nc)
-                    load_src(pm, ph, nnull, R[kb + 8 + grp], slot, xn, hn);
+                if (kb + 8 < ne)
+                    load_src(pm, ph, nnull, R[skip_gap(kb + 8 + grp, front, gap)], slot, xn,
+                             hn);
                 p2p_step_f64<NS>(sx, sy, sz, shi, sh3, sh4, xj, hj, acc);
                 xj = xn;
                 hj = hn;
@@ -564,8 +587,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
 {
     constexpr int NS = 8;
     constexpr int NR = P2P_RANGES / 2;
-    __shared__ int2 rng[4][NR];
-    __shared__ float4 dcs[4][NR];
+    __shared__ int2 rng[4][NR + 8];
+    __shared__ float4 dcs[4][NR + 8];
     const int w = threadIdx.x >> 6;
     const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
@@ -605,14 +628,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             // stage the source blocks of this chunk (padded to a multiple of 8):
             // their particle range and the leaf-centre difference c_a - c_b,
             // formed in FP64 and rounded to FP32; close leaves first
+            // (empty blocks dropped; eight empty blocks after the last one)
             int front = 0, back = nc;
-            for (int k0 = 0; k0 < ((nc + 7) & ~7); k0 += 64) {
+            for (int k0 = 0; k0 < nc; k0 += 64) {
                 const int k = k0 + lane;
-                const bool act = k < nc;
                 int2 r = make_int2(0, 0);
                 float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
                 bool close = false;
-                if (act) {
+                if (k < nc) {
                     const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
                     const int bn = nl[e];
                     r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
@@ -622,21 +645,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                     const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
                     close = dx * dx + dy * dy + dz * dz < CLOSE_FRAC2 * t5 * t5;
                 }
-                const int pos = close_first_slot(act, close, front, back);
-                if (act) {
+                const bool keep = r.y > 0;
+                const int pos = close_first_slot(keep, close, front, back);
+                if (keep) {
                     R[pos] = r;
                     D[pos] = d;
-                } else if (k < ((nc + 7) & ~7)) {
-                    R[k] = r;
-                    D[k] = d;
                 }
             }
+            front = __builtin_amdgcn_readfirstlane(front);
+            const int gap = __builtin_amdgcn_readfirstlane(back - front), ne = nc - gap;
+            if (lane < 8) {
+                R[nc + lane] = make_int2(0, 0);
+                D[nc + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
             __builtin_amdgcn_wave_barrier();
-            for (int kb = 0; kb < nc; kb += 8) {
-                const int2 rg = R[kb + grp];
-                const float4 dc = D[kb + grp];
+            for (int kb = 0; kb < ne; kb += 8) {
+                const int kk = skip_gap(kb + grp, front, gap);
+                const int2 rg = R[kk];
+                const float4 dc = D[kk];
+                // a missing source reads particle 0 (an empty block's start
+                // may be one past the last particle) and is then replaced by
+                // a far, massless one
                 const bool valid = slot < rg.y;
-                const int64_t j = (int64_t)rg.x + (valid ? slot : 0);
+                const int64_t j = valid ? (int64_t)rg.x + slot : 0;
                 float4 yj = pf[j];
                 float4 hj = pfh[j];
                 if (!valid) {

@@ -607,21 +607,24 @@ constexpr int VJP_RANGES = 256;
 constexpr double VJP_CLOSE_FRAC2 = 0.49;  // close leaf: |c_a - c_b| < 0.7 x the bound of eq. (5)
 
 // Stage the source blocks of list entries [c0, c0 + nc) (each list entry,
-// a node id, stands for nsub blocks of at most 8 particles) in R, padded to a
-// multiple of 8 with empty blocks; blocks of leaves within the close radius
-// of the wavefront's own leaf rv come first, each group in list order, so
-// that steps whose pairs are all Newtonian are gathered at the end.
+// a node id, stands for nsub blocks of at most 8 particles) in R: blocks of
+// leaves within the close radius of the wavefront's own leaf rv first, each
+// group in list order, so that steps whose pairs are all Newtonian are
+// gathered at the end; empty blocks are dropped, leaving a gap [front,
+// front + gap) between the groups, and eight empty blocks follow position
+// nc.  Returns the number of staged blocks.
 template <typename IX>
-__device__ __forceinline__ void stage_blocks(const IX *__restrict__ lst, int c0, int nc, int nsub,
-                                             const int32_t *__restrict__ first,
-                                             const int32_t *__restrict__ count,
-                                             const double *__restrict__ recA, const double *rv,
-                                             double r_kern, int lane, int2 *R)
+__device__ __forceinline__ int stage_blocks(const IX *__restrict__ lst, int c0, int nc, int nsub,
+                                            const int32_t *__restrict__ first,
+                                            const int32_t *__restrict__ count,
+                                            const double *__restrict__ recA, const double *rv,
+                                            double r_kern, int lane, int2 *R, int &front,
+                                            int &gap)
 {
-    int front = 0, back = nc;
-    const int ncp = (nc + 7) & ~7;
+    front = 0;
+    int back = nc;
     const uint64_t lt = lanemask_lt();
-    for (int k0 = 0; k0 < ncp; k0 += 64) {
+    for (int k0 = 0; k0 < nc; k0 += 64) {
         const int k = k0 + lane;
         const bool act = k < nc;
         int2 r = make_int2(0, 0);
@@ -635,16 +638,26 @@ __device__ __forceinline__ void stage_blocks(const IX *__restrict__ lst, int c0,
             const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
             close = dx * dx + dy * dy + dz * dz < VJP_CLOSE_FRAC2 * t5 * t5;
         }
-        const uint64_t mc = __ballot(act && close), mf = __ballot(act && !close);
+        const bool keep = r.y > 0;
+        const uint64_t mc = __ballot(keep && close), mf = __ballot(keep && !close);
         const int nf = __popcll(mf);
         const int pos = close ? front + __popcll(mc & lt) : back - nf + __popcll(mf & lt);
         front += __popcll(mc);
         back -= nf;
-        if (act)
+        if (keep)
             R[pos] = r;
-        else if (k < ncp)
-            R[k] = r;
     }
+    if (lane < 8)
+        R[nc + lane] = make_int2(0, 0);
+    front = __builtin_amdgcn_readfirstlane(front);
+    gap = __builtin_amdgcn_readfirstlane(back - front);
+    return nc - gap;
+}
+
+// Block of step position k (close blocks, then the far ones after the gap).
+__device__ __forceinline__ int skip_gap(int k, int front, int gap)
+{
+    return k < front ? k : k + gap;
 }
 
 // Particle index of this lane in a staged block; missing particles read the
@@ -688,7 +701,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     int nsub, const double *__restrict__ recA, double r_kern, int64_t nnull, double *xbt)
 {
     constexpr int NS = 4;
-    __shared__ int2 rng[4][VJP_RANGES];
+    __shared__ int2 rng[4][VJP_RANGES + 8];
     const int w = threadIdx.x >> 6;
     const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
@@ -721,15 +734,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             acc[q] = 0.0;
         for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
             const int nc = min(nb - c0, VJP_RANGES);
-            stage_blocks(nl, c0, nc, nsub, first, count, recA, rv, r_kern, lane, R);
+            int front, gap;
+            const int ne = stage_blocks(nl, c0, nc, nsub, first, count, recA, rv, r_kern, lane,
+                                        R, front, gap);
             __builtin_amdgcn_wave_barrier();
-            int64_t j = block_particle(R[grp], slot, nnull);
+            int64_t j = block_particle(R[skip_gap(grp, front, gap)], slot, nnull);
             double4 xj = pm[j], hj = ph[j];
-            for (int kb = 0; kb < nc; kb += 8) {
+            for (int kb = 0; kb < ne; kb += 8) {
                 int64_t jn = j;
                 double4 xn = xj, hn = hj;
-                if (kb + 8 < nc) {
-                    jn = block_particle(R[kb + 8 + grp], slot, nnull);
+                if (kb + 8 < ne) {
+                    jn = block_particle(R[skip_gap(kb + 8 + grp, front, gap)], slot, nnull);
                     xn = pm[jn];
                     hn = ph[jn];
                 }
@@ -771,7 +786,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const double *__restrict__ recA, double r_kern, int64_t nnull, double *xbt, double *mbt)
 {
     constexpr int NS = 4;
-    __shared__ int2 rng[4][VJP_RANGES];
+    __shared__ int2 rng[4][VJP_RANGES + 8];
     const int w = threadIdx.x >> 6;
     const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
     if (leaf >= nleaves)
@@ -800,16 +815,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             acc[q] = 0.0;
         for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
             const int nc = min(nb - c0, VJP_RANGES);
-            stage_blocks(tsrc + e0, c0, nc, nsub, first, count, recA, rv, r_kern, lane, R);
+            int front, gap;
+            const int ne = stage_blocks(tsrc + e0, c0, nc, nsub, first, count, recA, rv, r_kern,
+                                        lane, R, front, gap);
             __builtin_amdgcn_wave_barrier();
-            int64_t i = block_particle(R[grp], slot, nnull);
+            int64_t i = block_particle(R[skip_gap(grp, front, gap)], slot, nnull);
             double4 xi = pm[i], hi = ph[i];
-            for (int kb = 0; kb < nc; kb += 8) {
+            for (int kb = 0; kb < ne; kb += 8) {
                 const double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
                 int64_t in = i;
                 double4 xn = xi, hn = hi;
-                if (kb + 8 < nc) {
-                    in = block_particle(R[kb + 8 + grp], slot, nnull);
+                if (kb + 8 < ne) {
+                    in = block_particle(R[skip_gap(kb + 8 + grp, front, gap)], slot, nnull);
                     xn = pm[in];
                     hn = ph[in];
                 }

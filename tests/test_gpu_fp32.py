@@ -58,3 +58,18 @@ def test_fp32_accuracy_vs_direct(orc):
     e32, e64 = eta(a32, d), eta(a64, d)
     say(f"    eta vs direct: fp32 {e32:.3e}, fp64 {e64:.3e}")
     assert e32 <= 1.01 * e64 + 1e-6
+
+
+def test_fp32_leaf10_page_aligned_binary():
+    # Regression: with leaf size 10 every leaf has a second source block, empty
+    # for leaves of at most 8 particles; the last leaf's empty block starts one
+    # past the last particle, which for n = 2^19 is the first byte after the
+    # page-aligned FP32 particle arrays.  The FP32 form must not read there
+    # and must agree with the FP64 form.
+    x, m, h = W.polytrope_binary(1 << 18, 2)
+    say("[gpu fp32] binary 2 x 2^18, leaf 10: FP32 form against FP64 on the GPU")
+    a32, _, _ = gpu_run(x, m, h, leaf=10, precision=F.FMM_FP32, export=False)
+    a64, _, _ = gpu_run(x, m, h, leaf=10, export=False)
+    e = eta(a32, a64)
+    say(f"    eta FP32 vs FP64 {e:.2e}")
+    assert e <= 1e-5
