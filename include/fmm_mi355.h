@@ -182,12 +182,15 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream);
 
 /* Vector-Jacobian product of the accelerations of the last fmm_forces call
  * with respect to the positions and masses, with the tree membership and the
- * interaction lists held fixed (the moments do depend on x and m).  Lists of
- * the leaf <- cell walk only (FMM_ERR_STATE after a mutual walk):
+ * interaction lists held fixed (the moments do depend on x and m), for the
+ * lists of either walk (after a mutual walk the reverse pass also runs the
+ * L2L chain backwards).  The reverse pass is FP64 for both precisions:
  *   a_bar  device, [n][3] cotangent of a (double or float per precision);
  *   x_bar  device, [n][3] output, same precision;
  *   m_bar  device, [n] output, same precision.
- * Errors: FMM_ERR_STATE (no prior fmm_forces on this tree state). */
+ * Synchronises `stream` on the first call after a walk (sizes the transposed
+ * lists).  Errors: FMM_ERR_STATE (no prior fmm_forces on this tree state),
+ * FMM_ERR_ALLOC, FMM_ERR_HIP. */
 fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *m_bar,
                           void *stream);
 

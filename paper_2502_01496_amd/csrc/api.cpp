@@ -832,8 +832,14 @@ fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *
         return fail(FMM_ERR_STATE, "fmm_forces must run on this tree state before the VJP");
     if (!t.has_lists)
         return fail(FMM_ERR_STATE, "no interaction lists: call fmm_forces first");
-    if (t.lists_policy != FMM_WALK_PHANTOM)
-        return fail(FMM_ERR_STATE, "the VJP is available for the leaf <- cell walk only");
+    if (t.lists_policy == FMM_WALK_MUTUAL && !t.mw.Lown) {
+        // the reverse pass of an FP32 tree recomputes the M2L sums in FP64
+        void *p = nullptr;
+        fmm_status st = mw_alloc(t.mw.owned, &p, (size_t)NLOC * t.topo.node_cap * sizeof(double));
+        if (st != FMM_OK)
+            return st;
+        t.mw.Lown = (double *)p;
+    }
     hipStream_t s = (hipStream_t)stream;
     StageTimer tm(t, s, 5);
     hipError_t e = launch_vjp(t, a_bar, x_bar, m_bar, s);

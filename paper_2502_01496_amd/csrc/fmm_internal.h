@@ -59,6 +59,46 @@ __device__ __forceinline__ double rsqrt_pos(double x)
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// L2P, eq. (8)
+template <typename T>
+__device__ __forceinline__ void l2p(const T *L, T y0, T y1, T y2, T &a0, T &a1, T &a2)
+{
+    const T h = T(0.5);
+    a0 = L[0] + L[3] * y0 + L[4] * y1 + L[5] * y2 +
+         h * (L[9] * y0 * y0 + L[12] * y1 * y1 + L[14] * y2 * y2) +
+         (L[10] * y0 * y1 + L[11] * y0 * y2 + L[13] * y1 * y2);
+    a1 = L[1] + L[4] * y0 + L[6] * y1 + L[7] * y2 +
+         h * (L[10] * y0 * y0 + L[15] * y1 * y1 + L[17] * y2 * y2) +
+         (L[12] * y0 * y1 + L[13] * y0 * y2 + L[16] * y1 * y2);
+    a2 = L[2] + L[5] * y0 + L[7] * y1 + L[8] * y2 +
+         h * (L[11] * y0 * y0 + L[16] * y1 * y1 + L[18] * y2 * y2) +
+         (L[13] * y0 * y1 + L[14] * y0 * y2 + L[17] * y1 * y2);
+}
+
+// L2L: re-expansion of the quadratic field about a point shifted by d (exact):
+//   L1' = L1 + L2 d + 1/2 L3 : d d,  L2' = L2 + L3 d,  L3' = L3.
+template <typename T>
+__device__ __forceinline__ void l2l_shift(T *L, T d0, T d1, T d2)
+{
+    T a0, a1, a2;
+    l2p<T>(L, d0, d1, d2, a0, a1, a2);
+    const T s3 = L[3] + L[9] * d0 + L[10] * d1 + L[11] * d2;
+    const T s4 = L[4] + L[10] * d0 + L[12] * d1 + L[13] * d2;
+    const T s5 = L[5] + L[11] * d0 + L[13] * d1 + L[14] * d2;
+    const T s6 = L[6] + L[12] * d0 + L[15] * d1 + L[16] * d2;
+    const T s7 = L[7] + L[13] * d0 + L[16] * d1 + L[17] * d2;
+    const T s8 = L[8] + L[14] * d0 + L[17] * d1 + L[18] * d2;
+    L[0] = a0;
+    L[1] = a1;
+    L[2] = a2;
+    L[3] = s3;
+    L[4] = s4;
+    L[5] = s5;
+    L[6] = s6;
+    L[7] = s7;
+    L[8] = s8;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  This bijection of [0, nblocks) gives XCD x a contiguous range of
 // logical block indices, so neighbouring leaves (which share most of their
@@ -280,6 +320,7 @@ int mutual_iterations(const Tree &t);
 hipError_t launch_mutual_walk(Tree &t, hipStream_t s);
 hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream_t s);
 hipError_t launch_far_mutual(Tree &t, hipStream_t s);
+hipError_t launch_l2l_internal(Tree &t, hipStream_t s);
 hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStream_t s);
 hipError_t ensure_transposed(Tree &t, hipStream_t s);
 void release_vjp(Tree &t);

@@ -151,22 +151,6 @@ __device__ __forceinline__ void m2l_acc(T rx, T ry, T rz, T M, const T *Q, T *L)
              b3 * (T(3) * rz * Qzz);
 }
 
-// L2P, eq. (8)
-template <typename T>
-__device__ __forceinline__ void l2p(const T *L, T y0, T y1, T y2, T &a0, T &a1, T &a2)
-{
-    const T h = T(0.5);
-    a0 = L[0] + L[3] * y0 + L[4] * y1 + L[5] * y2 +
-         h * (L[9] * y0 * y0 + L[12] * y1 * y1 + L[14] * y2 * y2) +
-         (L[10] * y0 * y1 + L[11] * y0 * y2 + L[13] * y1 * y2);
-    a1 = L[1] + L[4] * y0 + L[6] * y1 + L[7] * y2 +
-         h * (L[10] * y0 * y0 + L[15] * y1 * y1 + L[17] * y2 * y2) +
-         (L[12] * y0 * y1 + L[13] * y0 * y2 + L[16] * y1 * y2);
-    a2 = L[2] + L[5] * y0 + L[7] * y1 + L[8] * y2 +
-         h * (L[11] * y0 * y0 + L[16] * y1 * y1 + L[18] * y2 * y2) +
-         (L[13] * y0 * y1 + L[14] * y0 * y2 + L[17] * y1 * y2);
-}
-
 // ---------------------------------------------------------------- M2L, FP64
 // 16 lanes per sink leaf, 4 sinks per wave; lanes stride the far list, then a
 // butterfly sum over the 16 lanes (fixed order: deterministic).
@@ -786,45 +770,22 @@ __global__ __launch_bounds__(256) void k_m2l_node(const double *__restrict__ rec
     }
 }
 
-// L2L: re-expansion of the quadratic field about a point shifted by d (exact):
-//   L1' = L1 + L2 d + 1/2 L3 : d d,  L2' = L2 + L3 d,  L3' = L3.
-template <typename T>
-__device__ __forceinline__ void l2l_shift(T *L, T d0, T d1, T d2)
-{
-    T a0, a1, a2;
-    l2p<T>(L, d0, d1, d2, a0, a1, a2);
-    const T s3 = L[3] + L[9] * d0 + L[10] * d1 + L[11] * d2;
-    const T s4 = L[4] + L[10] * d0 + L[12] * d1 + L[13] * d2;
-    const T s5 = L[5] + L[11] * d0 + L[13] * d1 + L[14] * d2;
-    const T s6 = L[6] + L[12] * d0 + L[15] * d1 + L[16] * d2;
-    const T s7 = L[7] + L[13] * d0 + L[16] * d1 + L[17] * d2;
-    const T s8 = L[8] + L[14] * d0 + L[17] * d1 + L[18] * d2;
-    L[0] = a0;
-    L[1] = a1;
-    L[2] = a2;
-    L[3] = s3;
-    L[4] = s4;
-    L[5] = s5;
-    L[6] = s6;
-    L[7] = s7;
-    L[8] = s8;
-}
-
-// One thread per leaf: descend from the root (pre-order ids: the leaf lies in
-// the left subtree of v iff its id is below right[v]), at each step shifting
-// the parent's total expansion to the child's centre of mass and adding the
-// child's own M2L sum.  Only the leaves' totals are needed (for L2P).
+// One thread per listed cell: descend from the root (pre-order ids: a cell
+// lies in the left subtree of v iff its id is below right[v]), at each step
+// shifting the parent's total expansion to the child's centre of mass and
+// adding the child's own M2L sum.  The forces need the leaves' totals (for
+// L2P); the reverse pass also lists the internal cells.
 template <typename T>
 __global__ __launch_bounds__(256) void k_l2l_chain(const double *__restrict__ recA,
                                                    const int32_t *__restrict__ left,
                                                    const int32_t *__restrict__ right,
-                                                   const int32_t *__restrict__ leaf_node,
-                                                   int nleaves, const T *__restrict__ Lown, T *Lout)
+                                                   const int32_t *__restrict__ nodes, int count,
+                                                   const T *__restrict__ Lown, T *Lout)
 {
     const int g = blockIdx.x * 256 + threadIdx.x;
-    if (g >= nleaves)
+    if (g >= count)
         return;
-    const int u = leaf_node[g];
+    const int u = nodes[g];
     T L[19];
 #pragma unroll
     for (int k = 0; k < 19; ++k)
@@ -853,14 +814,14 @@ __global__ __launch_bounds__(256) void k_l2l_chain(const double *__restrict__ re
 }
 
 template <int FORM>
-static void far_mutual(Tree &t, hipStream_t s)
+static void far_mutual(Tree &t, bool fp64, hipStream_t s)
 {
     const Topology &T = t.topo;
     const MutualLists &M = t.mw;
     const uint64_t mask = (1ull << mutual_key_bits(t)) - 1ull;
     const int gm = (int)(((int64_t)T.nnodes * 16 + 255) / 256);
     const int gl = (T.nleaves + 255) / 256;
-    if (t.p.precision == FMM_FP64) {
+    if (fp64) {
         k_m2l_node<double, FORM><<<gm, 256, 0, s>>>(t.recA, t.recQ, t.recF, T.nnodes, M.fstart,
                                                     M.fend, M.far_sorted, mask, M.Lown);
         k_l2l_chain<double><<<gl, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, T.nleaves,
@@ -873,12 +834,28 @@ static void far_mutual(Tree &t, hipStream_t s)
     }
 }
 
-hipError_t launch_far_mutual(Tree &t, hipStream_t s)
+static hipError_t far_mutual_form(Tree &t, bool fp64, hipStream_t s)
 {
     if (t.p.expansion == FMM_EXPANSION_DEHNEN)
-        far_mutual<FMM_EXPANSION_DEHNEN>(t, s);
+        far_mutual<FMM_EXPANSION_DEHNEN>(t, fp64, s);
     else
-        far_mutual<FMM_EXPANSION_PHANTOM>(t, s);
+        far_mutual<FMM_EXPANSION_PHANTOM>(t, fp64, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_mutual(Tree &t, hipStream_t s)
+{
+    return far_mutual_form(t, t.p.precision == FMM_FP64, s);
+}
+
+// FP64 totals of the internal cells from the FP64 M2L sums (mutual walk).
+hipError_t launch_l2l_internal(Tree &t, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const int n_int = T.nnodes - T.nleaves;
+    if (n_int > 0)
+        k_l2l_chain<double><<<(n_int + 255) / 256, 256, 0, s>>>(t.recA, t.left, t.right,
+                                                               t.int_nodes, n_int, t.mw.Lown, t.L);
     return hipGetLastError();
 }
 
@@ -909,7 +886,10 @@ hipError_t launch_far(Tree &t, hipStream_t s)
     return far_leaves(t, t.p.precision == FMM_FP64, s);
 }
 
-hipError_t launch_far_f64(Tree &t, hipStream_t s) { return far_leaves(t, true, s); }
+hipError_t launch_far_f64(Tree &t, hipStream_t s)
+{
+    return t.lists_policy == FMM_WALK_MUTUAL ? far_mutual_form(t, true, s) : far_leaves(t, true, s);
+}
 
 hipError_t launch_near(Tree &t, void *a, hipStream_t s)
 {

@@ -599,6 +599,141 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_src_fold(const int32_t *__restr
         na[0] = na[1] = na[2] = 0.0;
 }
 
+// 2c. Mutual walk.  There the far field of a leaf is the sum, over the cells
+// v on its root path, of the M2L sum into v shifted down to the leaf (L2L),
+// so the reverse pass first carries Lbar up the tree: per level (deepest
+// first), each internal cell v with children a, b takes
+//   Lbar_v = S(d_a)^T Lbar_a + S(d_b)^T Lbar_b,   d_ch = c_ch - c_v,
+// where S(d) is the L2L shift; the derivative of <Lbar_ch, S(d) L_v> in d
+// (L_v: the forward total of v) is added to cbar_ch and taken from cbar_v.
+// Lbar_v is then also the cotangent of v's own M2L sum.
+__global__ __launch_bounds__(256) void k_vjp_l2l_level(const int32_t *__restrict__ nodes, int cnt,
+                                                       const int32_t *__restrict__ left,
+                                                       const int32_t *__restrict__ right,
+                                                       const double *__restrict__ recA,
+                                                       const double *__restrict__ Ltot,
+                                                       double *Lbar, double *nadj)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= cnt)
+        return;
+    const int v = nodes[g];
+    const double *rv = recA + (int64_t)NREC * v;
+    const double *Lf = Ltot + (int64_t)NLOC * v;
+    double L[19], Lb[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+        L[k] = Lf[k];
+        Lb[k] = 0.0;
+    }
+    double ds0 = 0.0, ds1 = 0.0, ds2 = 0.0;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int ch = side == 0 ? left[v] : right[v];
+        const double *rc = recA + (int64_t)NREC * ch;
+        const double d0 = rc[0] - rv[0], d1 = rc[1] - rv[1], d2 = rc[2] - rv[2];
+        const double *B = Lbar + (int64_t)NLOC * ch;
+        const double B0 = B[0], B1 = B[1], B2 = B[2];
+        // first order: L1' = L2P(L, d)
+        l2p_vjp_L(B0, B1, B2, d0, d1, d2, Lb);
+        double e0, e1, e2;
+        l2p_vjp_y(L, B0, B1, B2, d0, d1, d2, e0, e1, e2);
+        // second order: L2' = L2 + L3 d (stored xx, xy, xz, yy, yz, zz)
+        const double B3 = B[3], B4 = B[4], B5 = B[5], B6 = B[6], B7 = B[7], B8 = B[8];
+        e0 += B3 * L[9] + B4 * L[10] + B5 * L[11] + B6 * L[12] + B7 * L[13] + B8 * L[14];
+        e1 += B3 * L[10] + B4 * L[12] + B5 * L[13] + B6 * L[15] + B7 * L[16] + B8 * L[17];
+        e2 += B3 * L[11] + B4 * L[13] + B5 * L[14] + B6 * L[16] + B7 * L[17] + B8 * L[18];
+#pragma unroll
+        for (int k = 3; k < 9; ++k)
+            Lb[k] += B[k];
+        Lb[9] += B3 * d0;
+        Lb[10] += B3 * d1 + B4 * d0;
+        Lb[11] += B3 * d2 + B5 * d0;
+        Lb[12] += B4 * d1 + B6 * d0;
+        Lb[13] += B4 * d2 + B5 * d1 + B7 * d0;
+        Lb[14] += B5 * d2 + B8 * d0;
+        Lb[15] += B6 * d1;
+        Lb[16] += B6 * d2 + B7 * d1;
+        Lb[17] += B7 * d2 + B8 * d1;
+        Lb[18] += B8 * d2;
+        // third order: L3' = L3
+#pragma unroll
+        for (int k = 9; k < 19; ++k)
+            Lb[k] += B[k];
+        double *nc = nadj + 16 * (int64_t)ch;
+        nc[0] += e0;
+        nc[1] += e1;
+        nc[2] += e2;
+        ds0 += e0;
+        ds1 += e1;
+        ds2 += e2;
+    }
+    double *o = Lbar + (int64_t)NLOC * v;
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        o[k] = Lb[k];
+    double *na = nadj + 16 * (int64_t)v;
+    na[0] = -ds0;
+    na[1] = -ds1;
+    na[2] = -ds2;
+}
+
+// M2L^T of the mutual pairs: the pair list is symmetric (v takes b iff b
+// takes v), so the cells that took v as source are v's own partners and one
+// pass over the CSR range of v does both sides: cbar_v += rbar of (v <- b)
+// with Lbar_v, and Mbar_v, Qbar_v, cbar_v -= rbar of (b <- v) with Lbar_b.
+// 16 lanes per cell, all cells.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_vjp_m2l_mutual(
+    const double *__restrict__ recA, const double *__restrict__ recQ, int nnodes,
+    const int64_t *__restrict__ fstart, const int64_t *__restrict__ fend,
+    const uint64_t *__restrict__ keys, uint64_t mask, const double *__restrict__ Lbar,
+    double *nadj)
+{
+    const int v = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    const bool valid = v < nnodes;
+    const int vv = valid ? v : 0;
+    const double *rv = recA + (int64_t)NREC * vv;
+    const double *Qv = recQ + (int64_t)NREC * vv;
+    const double Mv = rv[3];
+    double Lb[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        Lb[k] = Lbar[(int64_t)NLOC * vv + k];
+    double rs[3] = {0.0, 0.0, 0.0}, rt[3] = {0.0, 0.0, 0.0}, Mb = 0.0,
+           Qb[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t e0 = valid ? fstart[v] : 0, e1 = valid ? fend[v] : 0;
+    for (int64_t k = e0 + sub; k < e1; k += 16) {
+        const int b = (int)(keys[k] & mask);
+        const double *rb = recA + (int64_t)NREC * b;
+        const double r[3] = {rv[0] - rb[0], rv[1] - rb[1], rv[2] - rb[2]};
+        double Mx = 0.0, Qx[6] = {0, 0, 0, 0, 0, 0};
+        m2l_vjp<FORM>(r, rb[3], recQ + (int64_t)NREC * b, Lb, rs, Mx, Qx);
+        const double q[3] = {-r[0], -r[1], -r[2]};
+        m2l_vjp<FORM>(q, Mv, Qv, Lbar + (int64_t)NLOC * b, rt, Mb, Qb);
+    }
+    double acc[13] = {rs[0], rs[1], rs[2], rt[0], rt[1], rt[2], Mb,
+                      Qb[0], Qb[1], Qb[2], Qb[3], Qb[4], Qb[5]};
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 13; ++k)
+            acc[k] += __shfl_xor(acc[k], off);
+    if (valid && sub == 0) {
+        double *na = nadj + 16 * (int64_t)v;
+        na[0] += acc[0];
+        na[1] += acc[1];
+        na[2] += acc[2];
+        na[3] = -acc[3];
+        na[4] = -acc[4];
+        na[5] = -acc[5];
+#pragma unroll
+        for (int k = 6; k < 13; ++k)
+            na[k] = acc[k];
+    }
+}
+
 // 3a. P2P^T, sink side: like the forward near field (source per lane, four
 // wave-uniform sinks per pass, source blocks of the close leaves staged
 // first, the next step's sources loaded while the current one computes),
@@ -1190,14 +1325,46 @@ static void vjp_m2l(Tree &t, hipStream_t s)
             t.recA, t.recQ, t.farT.off, t.farT.src, t.Lbar, t.pnode, t.poff, t.npieces, t.ppart);
 }
 
+// Mutual walk: forward totals of the internal cells, L2L^T level by level
+// (deepest first), then M2L^T of the symmetric pairs.
+static hipError_t vjp_mutual_far(Tree &t, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    hipError_t e = launch_l2l_internal(t, s);
+    if (e != hipSuccess)
+        return e;
+    for (int l = T.depth - 2; l >= 0; --l) {
+        const int o = T.lvl_int_off[l], cnt = T.lvl_int_off[l + 1] - o;
+        if (cnt > 0)
+            k_vjp_l2l_level<<<(cnt + 255) / 256, 256, 0, s>>>(t.int_nodes + o, cnt, t.left,
+                                                              t.right, t.recA, t.L, t.Lbar,
+                                                              t.nadj);
+    }
+    const MutualLists &M = t.mw;
+    const uint64_t mask = (1ull << mutual_key_bits(t)) - 1ull;
+    const int g = (int)(((int64_t)T.nnodes * 16 + 255) / 256);
+    if (t.p.expansion == FMM_EXPANSION_DEHNEN)
+        k_vjp_m2l_mutual<FMM_EXPANSION_DEHNEN><<<g, 256, 0, s>>>(
+            t.recA, t.recQ, T.nnodes, M.fstart, M.fend, M.far_sorted, mask, t.Lbar, t.nadj);
+    else
+        k_vjp_m2l_mutual<FMM_EXPANSION_PHANTOM><<<g, 256, 0, s>>>(
+            t.recA, t.recQ, T.nnodes, M.fstart, M.fend, M.far_sorted, mask, t.Lbar, t.nadj);
+    return hipGetLastError();
+}
+
+// The mutual walk's far pairs are symmetric and need no transposition (its
+// near lists are symmetric too, but the source side of P2P^T reads the CSR
+// form).
 hipError_t ensure_transposed(Tree &t, hipStream_t s)
 {
     hipError_t e = ensure_vjp_base(t);
     if (e != hipSuccess || t.has_transposed)
         return e;
-    e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, t.farT, s);
-    if (e == hipSuccess)
-        e = build_m2lt_pieces(t, s);
+    if (t.lists_policy != FMM_WALK_MUTUAL) {
+        e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, t.farT, s);
+        if (e == hipSuccess)
+            e = build_m2lt_pieces(t, s);
+    }
     if (e == hipSuccess)
         e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, t.nearT, s);
     if (e == hipSuccess)
@@ -1227,12 +1394,18 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
         k_vjp_prep<double><<<gs, 256, 0, s>>>((const double *)abar, n, t.perm, t.p.G, t.abt);
     k_vjp_l2p<<<(nl + 255) / 256, 256, 0, s>>>(t.pm, t.abt, t.leaf_node, nl, t.first, t.count,
                                                t.recA, t.L, t.Lbar, t.xbt, t.nadj);
-    if (t.p.expansion == FMM_EXPANSION_DEHNEN)
-        vjp_m2l<FMM_EXPANSION_DEHNEN>(t, s);
-    else
-        vjp_m2l<FMM_EXPANSION_PHANTOM>(t, s);
-    k_vjp_m2l_src_fold<<<(T.nnodes + 255) / 256, 256, 0, s>>>(t.left, T.nnodes, t.poff, t.ppart,
-                                                              t.nadj);
+    if (t.lists_policy == FMM_WALK_MUTUAL) {
+        e = vjp_mutual_far(t, s);
+        if (e != hipSuccess)
+            return e;
+    } else {
+        if (t.p.expansion == FMM_EXPANSION_DEHNEN)
+            vjp_m2l<FMM_EXPANSION_DEHNEN>(t, s);
+        else
+            vjp_m2l<FMM_EXPANSION_PHANTOM>(t, s);
+        k_vjp_m2l_src_fold<<<(T.nnodes + 255) / 256, 256, 0, s>>>(t.left, T.nnodes, t.poff,
+                                                                  t.ppart, t.nadj);
+    }
     const int nsub = (T.leaf_size + 7) / 8;
     k_vjp_p2p_sink<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
                                                 nl, t.near_cnt, t.near_src, (int)t.cap_near,

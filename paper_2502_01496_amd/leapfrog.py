@@ -29,15 +29,18 @@ from . import fmm as F
 class ForceField:
     """One tree reused for every evaluation at a fixed particle count."""
 
-    def __init__(self, theta=0.5, leaf_size=8, G=1.0, precision=F.FMM_FP64, r_kern=2.0):
+    def __init__(self, theta=0.5, leaf_size=8, G=1.0, precision=F.FMM_FP64, r_kern=2.0,
+                 walk=F.FMM_WALK_PHANTOM, expansion=F.FMM_EXPANSION_PHANTOM,
+                 tree_shape=F.FMM_TREE_MEDIAN):
         self.g = F.GravityFMM(theta=theta, leaf_size=leaf_size, G=G, precision=precision,
-                              r_kern=r_kern)
+                              r_kern=r_kern, walk=walk, expansion=expansion,
+                              tree_shape=tree_shape)
         self.generation = 0          # bumped by every build
         self.dtype = torch.float32 if precision == F.FMM_FP32 else torch.float64
 
     def forces(self, x, m, h, out=None):
         """Build the tree at x, then moments, walk and forces."""
-        self.g.build(x)
+        self.g.build(x, m=m)
         self.generation += 1
         F.fmm_moments(self.g.tree, x, m, h)
         if out is None:

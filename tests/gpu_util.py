@@ -50,7 +50,8 @@ def eta(a, ref):
 
 
 def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repeat=1,
-            expansion=F.FMM_EXPANSION_PHANTOM, tree_shape=F.FMM_TREE_MEDIAN):
+            expansion=F.FMM_EXPANSION_PHANTOM, tree_shape=F.FMM_TREE_MEDIAN,
+            walk=F.FMM_WALK_PHANTOM):
     """build -> moments -> forces -> VJP on the GPU; returns (a, [(xbar, mbar)] * repeat)."""
     import torch
 
@@ -58,7 +59,7 @@ def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repea
     dt = torch.float32 if precision == F.FMM_FP32 else torch.float64
     AB = torch.from_numpy(np.ascontiguousarray(abar)).to("cuda").to(dt)
     p = F.default_params(theta=theta, leaf_size=leaf, G=G, precision=precision,
-                         expansion=expansion, tree=tree_shape)
+                         expansion=expansion, tree=tree_shape, walk=walk)
     t = F.fmm_build_tree(X, p, m=Mt if tree_shape == F.FMM_TREE_COM else None)
     out = []
     try:

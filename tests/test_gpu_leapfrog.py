@@ -17,17 +17,17 @@ from tests.gpu_util import say, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def oracle_kdk(orc, x0, v0, m, h, dt, steps, structs=None, theta=0.5):
+def oracle_kdk(orc, x0, v0, m, h, dt, steps, structs=None, theta=0.5, policy=0):
     """KDK with the oracle; records (tree, lists) per visited position unless
     given, in which case they are held fixed."""
     rec = [] if structs is None else None
 
     def force(x, k):
         if structs is None:
-            r = orc.fmm(x, m, h, theta=theta)
+            r = orc.fmm(x, m, h, theta=theta, policy=policy)
             rec.append((r.tree, r.lists))
             return r.a
-        return orc.fmm_frozen(x, m, h, *structs[k])
+        return orc.fmm_frozen(x, m, h, *structs[k], policy=policy)
 
     x, v = x0.copy(), v0.copy()
     a = force(x, 0)
@@ -39,7 +39,8 @@ def oracle_kdk(orc, x0, v0, m, h, dt, steps, structs=None, theta=0.5):
     return x, v, rec
 
 
-def test_leapfrog_adjoint_matches_finite_differences(orc):
+@pytest.mark.parametrize("walk", [F.FMM_WALK_PHANTOM, F.FMM_WALK_MUTUAL])
+def test_leapfrog_adjoint_matches_finite_differences(orc, walk):
     x0, m, h = W.polytrope_binary(1024, 2, cache=False)
     n = len(m)
     rng = np.random.default_rng(5)
@@ -47,8 +48,9 @@ def test_leapfrog_adjoint_matches_finite_differences(orc):
     dt, steps = 1e-3, 4
     w = rng.standard_normal((n, 3))
     u = rng.standard_normal((n, 3))
-    say(f"[gpu leapfrog] adjoint vs frozen-structure finite differences, n={n}, steps={steps}")
-    field = LF.ForceField(theta=0.5)
+    say(f"[gpu leapfrog] adjoint vs frozen-structure finite differences, n={n}, steps={steps}, "
+        f"walk={walk}")
+    field = LF.ForceField(theta=0.5, walk=walk)
     X0, V0, Mt, H = to_dev(x0, v0, m, h)
     try:
         xT, vT, ckpt = LF.kdk_forward(X0, V0, Mt, H, dt, steps, field)
@@ -57,10 +59,13 @@ def test_leapfrog_adjoint_matches_finite_differences(orc):
         field.free()
     xbar, vbar, mbar = (t.cpu().numpy() for t in (xbar, vbar, mbar))
     # the GPU trajectory equals the oracle's
-    xr, vr, structs = oracle_kdk(orc, x0, v0, m, h, dt, steps)
+    xr, vr, structs = oracle_kdk(orc, x0, v0, m, h, dt, steps, policy=walk)
     assert np.abs(xT.cpu().numpy() - xr).max() < 1e-12
-    J = lambda xx, vv, mm: float((w * oracle_kdk(orc, xx, vv, mm, h, dt, steps, structs)[0]).sum()
-                                 + (u * oracle_kdk(orc, xx, vv, mm, h, dt, steps, structs)[1]).sum())
+
+    def J(xx, vv, mm):
+        xt, vt, _ = oracle_kdk(orc, xx, vv, mm, h, dt, steps, structs, policy=walk)
+        return float((w * xt).sum() + (u * vt).sum())
+
     eps = 1e-4
     for _ in range(3):
         e = rng.standard_normal((n, 3))
@@ -87,6 +92,45 @@ def test_com_drift_gradient_runs_and_is_consistent():
         field.free()
     assert L > 0.0 and np.isfinite(L)
     assert torch.isfinite(gx).all() and torch.isfinite(gm).all()
+
+
+def test_com_drift_gradient_closed_form_with_mutual_walk():
+    # With the mutual walk sum_i m_i a_i = 0 for any x and m, so KDK moves the
+    # centre of mass at constant velocity: D = X_T - X_0 = T dt V, V = sum m v_0 / M,
+    # and L = |D|^2 has dL/dx_0 = 0, dL/dv_0,j = 2 T dt m_j D / M and
+    # dL/dm_j = 2 T dt D . (v_0,j - V) / M.  The checkpointed reverse sweep must
+    # give these through the force VJPs; the leaf <- cell walk moves the
+    # centre of mass through its force asymmetry and does not.
+    x0, m, h = W.polytrope_binary(2048, 2, cache=False)
+    rng = np.random.default_rng(9)
+    n = len(m)
+    m = m * (0.5 + rng.random(n))  # unequal masses
+    v0 = 0.1 * rng.standard_normal((n, 3)) + np.array([0.3, -0.2, 0.1])
+    dt, steps = 1e-2, 5
+    M = m.sum()
+    V = (m[:, None] * v0).sum(0) / M
+    D = steps * dt * V
+    gv_ref = 2 * steps * dt * m[:, None] * D[None, :] / M
+    gm_ref = 2 * steps * dt * ((v0 - V) @ D) / M
+    say(f"[gpu leapfrog] centre-of-mass drift gradient in closed form, mutual walk, n={n}")
+    out = {}
+    for walk in (F.FMM_WALK_MUTUAL, F.FMM_WALK_PHANTOM):
+        X0, V0, Mt, H = to_dev(x0, v0, m, h)
+        field = LF.ForceField(theta=0.5, walk=walk)
+        try:
+            L, gx, gm, gv = LF.com_drift_gradient(X0, V0, Mt, H, dt, steps, field)
+        finally:
+            field.free()
+        out[walk] = (L, gx.cpu().numpy(), gm.cpu().numpy(), gv.cpu().numpy())
+    L, gx, gm, gv = out[F.FMM_WALK_MUTUAL]
+    scale_x = np.abs(gv_ref).max() / (steps * dt)  # |dL/dx_T|
+    rx = np.abs(gx).max() / scale_x
+    rx_leaf = np.abs(out[F.FMM_WALK_PHANTOM][1]).max() / scale_x
+    say(f"    mutual: |gx| / |dL/dx_T| {rx:.1e}; leaf <- cell {rx_leaf:.1e}")
+    assert L == pytest.approx(float(D @ D), rel=1e-12)
+    assert rx <= 1e-12 and rx_leaf >= 1e3 * max(rx, 1e-16)
+    assert np.abs(gv - gv_ref).max() <= 1e-12 * np.abs(gv_ref).max()
+    assert np.abs(gm - gm_ref).max() <= 1e-10 * np.abs(gm_ref).max()
 
 
 def test_autograd_function_matches_vjp_and_rebuilds():

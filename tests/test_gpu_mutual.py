@@ -11,7 +11,7 @@ import pytest
 from oracle import oracle as O
 from paper_2502_01496_amd import fmm as F
 from paper_2502_01496_amd import workloads as W
-from tests.gpu_util import eta, force_err, gpu_run, say, to_dev
+from tests.gpu_util import eta, force_err, gpu_run, gpu_vjp, say, to_dev
 from tests.test_gpu_parity import _case, sorted_by_sink
 
 pytestmark = pytest.mark.gpu
@@ -109,31 +109,37 @@ def test_policy_switch_on_one_tree(orc):
     import torch
 
     x, m, h = W.plummer(4096, 1)
-    say("[gpu mutual] leaf<-cell -> mutual -> leaf<-cell on one tree")
+    say("[gpu mutual] leaf<-cell -> mutual -> leaf<-cell -> mutual on one tree, with VJPs")
     X, Mt, H = to_dev(x, m, h)
     A = torch.empty((len(m), 3), dtype=torch.float64, device="cuda")
+    AB = torch.from_numpy(W.cotangent(len(m), 38)).to("cuda")
+    XB = torch.empty_like(A)
+    MB = torch.empty_like(Mt)
     t = F.fmm_build_tree(X, F.default_params())
+    walks = (F.FMM_WALK_PHANTOM, F.FMM_WALK_MUTUAL, F.FMM_WALK_PHANTOM, F.FMM_WALK_MUTUAL)
     try:
-        out = []
-        for walk in (F.FMM_WALK_PHANTOM, F.FMM_WALK_MUTUAL, F.FMM_WALK_PHANTOM):
+        out, vjp = [], []
+        for walk in walks:
             t = F.fmm_build_tree(X, F.default_params(walk=walk), tree=t)
             F.fmm_moments(t, X, Mt, H)
             F.fmm_forces(t, A)
+            F.fmm_forces_vjp(t, AB, XB, MB)
             torch.cuda.synchronize()
             out.append(A.cpu().numpy().copy())
+            vjp.append((XB.cpu().numpy().copy(), MB.cpu().numpy().copy()))
         # frozen lists: forces again without a walk
         F.fmm_forces(t, A)
         torch.cuda.synchronize()
         out.append(A.cpu().numpy().copy())
-        with pytest.raises(F.FmmError):
-            t = F.fmm_build_tree(X, F.default_params(walk=F.FMM_WALK_MUTUAL), tree=t)
-            F.fmm_moments(t, X, Mt, H)
-            F.fmm_forces(t, A)
-            F.fmm_forces_vjp(t, A, torch.empty_like(A), torch.empty_like(Mt))
     finally:
         F.fmm_tree_free(t)
     ref_p = orc.fmm(x, m, h).a
     ref_m = orc.fmm(x, m, h, policy=O.MUTUAL).a
     assert force_err(out[0], ref_p) <= 1e-12
     assert force_err(out[1], ref_m) <= 1e-12
-    assert np.array_equal(out[0], out[2]) and np.array_equal(out[2], out[3])
+    assert np.array_equal(out[0], out[2]) and np.array_equal(out[1], out[3])
+    assert np.array_equal(out[3], out[4])
+    # the reverse pass on a reused tree equals that on a fresh one, per walk
+    for k, walk in enumerate(walks):
+        _, [(xf, mf)] = gpu_vjp(x, m, h, W.cotangent(len(m), 38), walk=walk)
+        assert np.array_equal(vjp[k][0], xf) and np.array_equal(vjp[k][1], mf)
