@@ -218,7 +218,7 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
     # reverse pass at the final state (tree and lists of the last step), timed
     # by the library's events: VJP of the accelerations for a normal cotangent
     vjp_ms = None
-    if walk == F.FMM_WALK_PHANTOM and args.vjp_reps > 0:
+    if args.vjp_reps > 0:
         abar = torch.randn((n, 3), dtype=adt, device=dev, generator=torch.Generator(dev).manual_seed(7))
         xb = torch.empty((n, 3), dtype=adt, device=dev)
         mb = torch.empty(n, dtype=adt, device=dev)
@@ -523,7 +523,7 @@ def main():
         mut = run_one(args, x_np, m_np, h_np, F.FMM_FP64, census=False, walk=F.FMM_WALK_MUTUAL,
                       steps=args.mutual_steps)
         out["mutual_fp64"] = {k: mut[k] for k in ("value", "ms_per_step", "rel_err", "sumF_ratio",
-                                                  "com_drift", "stages_ms", "forces_only",
+                                                  "com_drift", "stages_ms", "vjp_ms", "forces_only",
                                                   "lists")}
         out["mutual_fp64"]["steps"] = args.mutual_steps
     if not args.no_cpu_baseline:
