@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--trees", action="store_true",
                     help="only compare the count-median tree with the centre-of-mass tree "
                          "(momentum, accuracy, shape, stage times) on the workload, and exit")
+    ap.add_argument("--full-configs", action="store_true",
+                    help="only measure the larger workloads (clumpy 2^22 in both precision "
+                         "forms, Plummer 2^20 FP32 forward + VJP, binary 2 x 2^23 FP32 forward "
+                         "and checkpointed backward through 10 KDK steps) and exit")
     ap.add_argument("--vjp-reps", type=int, default=5,
                     help="timed VJP calls at the final state (0 = skip)")
     ap.add_argument("--mutual-steps", type=int, default=5,
@@ -442,6 +446,151 @@ def trees_compare(args):
           flush=True)
 
 
+def _median_ms(fn, reps, warm=2):
+    """Median wall time of fn() in ms, each call bracketed by device syncs."""
+    import statistics
+
+    import torch
+
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(1e3 * (time.perf_counter() - t0))
+    return statistics.median(ts)
+
+
+def full_configs(args):
+    """The larger workloads: clumpy cube 2^22 in both precision forms (one
+    force evaluation = build + moments + walk + forces, median of 10), the
+    FP32 forward + VJP on Plummer 2^20 (median of 10), and the FP32 forward
+    through 10 KDK steps with position checkpoints plus the checkpointed
+    backward pass of |x_com(T) - x_com(0)|^2 on the binary 2 x 2^23 (3
+    repeats), with the peak device memory (torch's high-water mark plus the
+    library's tree)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_01496_amd import fmm as F
+    from paper_2502_01496_amd import leapfrog as LF
+    from paper_2502_01496_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    out = {}
+
+    # clumpy cube 2^22: FP32 form against FP64 (the FP64 path equals the
+    # oracle FMM to 1e-12 in the parity tests), both against the direct sum
+    t0 = time.perf_counter()
+    x_np, m_np, h_np = W.clumpy_cube(1 << 22, 3)
+    n = len(m_np)
+    log(f"[bench full] clumpy 2^22: n={n}, setup {time.perf_counter() - t0:.1f}s")
+    X, Mt, H = (torch.from_numpy(a).to(dev) for a in (x_np, m_np, h_np))
+    rng = np.random.default_rng(123)
+    sinks = torch.from_numpy(rng.choice(n, size=4096, replace=False)).to(dev)
+    ref = direct_reference(X, Mt, H, sinks, chunk=16)
+    res, acc = {}, {}
+    for prec, tag in ((F.FMM_FP64, "fp64"), (F.FMM_FP32, "fp32")):
+        g = F.GravityFMM(theta=0.5, precision=prec)
+        A = torch.empty((n, 3), dtype=torch.float32 if prec else torch.float64, device=dev)
+        ms = _median_ms(lambda: g.forces(X, Mt, H, out=A), 10)
+        F.fmm_set_timing(g.tree, True)
+        g.forces(X, Mt, H, out=A)
+        stages = F.fmm_stage_times(g.tree)
+        st = F.fmm_momentum_stats(X, None, Mt, A)
+        got = A[sinks].double()
+        eta_d = float(torch.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum()))
+        acc[tag] = A.double().clone()
+        res[tag] = {"ms_per_eval": round(ms, 3), "value": n / (ms * 1e-3),
+                    "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+                    "sumF_ratio": st["ratio"], "eta_vs_direct_4096_sinks": eta_d}
+        log(f"[bench full] clumpy 2^22 {tag}: {ms:.2f} ms per evaluation, "
+            f"{n / (ms * 1e-3):.4e} particle-forces/s, ratio {st['ratio']:.3e}, "
+            f"eta vs direct {eta_d:.3e}")
+        g.free()
+    d = acc["fp32"] - acc["fp64"]
+    rel = (torch.linalg.norm(d, dim=1) /
+           torch.linalg.norm(acc["fp64"], dim=1).clamp_min(1e-300)).cpu().numpy()
+    res["fp32_vs_fp64"] = {"eta": float(torch.sqrt((d ** 2).sum() / (acc["fp64"] ** 2).sum())),
+                           "median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
+                           "max": float(rel.max())}
+    log(f"[bench full] clumpy 2^22 FP32 vs FP64: {res['fp32_vs_fp64']}")
+    out["clumpy_2^22"] = res
+    del acc, d, X, Mt, H, ref
+    torch.cuda.empty_cache()
+
+    # Plummer 2^20: FP32 forward (build, moments, walk, forces) and the VJP
+    x_np, m_np, h_np = W.plummer(1 << 20, 4)
+    n = len(m_np)
+    log(f"[bench full] Plummer 2^20: n={n}")
+    X, Mt, H = (torch.from_numpy(a).to(dev) for a in (x_np, m_np, h_np))
+    AB = torch.from_numpy(W.cotangent(n, 41)).to(dev).float()
+    g = F.GravityFMM(theta=0.5, precision=F.FMM_FP32)
+    A = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    XB = torch.empty_like(A)
+    MB = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def fwd_vjp():
+        g.forces(X, Mt, H, out=A)
+        F.fmm_forces_vjp(g.tree, AB, XB, MB)
+
+    fwd = _median_ms(lambda: g.forces(X, Mt, H, out=A), 10)
+    both = _median_ms(fwd_vjp, 10)
+    out["plummer_2^20"] = {"fwd_ms": round(fwd, 3), "fwd_vjp_ms": round(both, 3),
+                           "value": n / (both * 1e-3), "unit": "particle-forces/s (forward + VJP)",
+                           "precision": "fp32 forward, fp64 reverse pass"}
+    log(f"[bench full] Plummer 2^20: forward {fwd:.2f} ms, forward + VJP {both:.2f} ms, "
+        f"{n / (both * 1e-3):.4e} particle-forces/s")
+    g.free()
+    del X, Mt, H, AB, A, XB, MB
+    torch.cuda.empty_cache()
+
+    # binary 2 x 2^23: FP32 forward through 10 KDK steps, checkpointed backward
+    t0 = time.perf_counter()
+    x_np, m_np, h_np = W.polytrope_binary(1 << 23, 5)
+    n = len(m_np)
+    log(f"[bench full] binary 2x2^23: n={n}, setup {time.perf_counter() - t0:.1f}s")
+    X0, Mt, H = (torch.from_numpy(a).to(dev) for a in (x_np, m_np, h_np))
+    V0 = torch.zeros_like(X0)
+    dt, steps = 1e-3, 10
+    field = LF.ForceField(theta=0.5, precision=F.FMM_FP32)
+    runs = []
+    try:
+        LF.kdk_forward(X0, V0, Mt, H, dt, 1, field, keep=False)   # allocations, capacities
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        for rep in range(3):
+            t0 = time.perf_counter()
+            xT, vT, ckpt = LF.kdk_forward(X0, V0, Mt, H, dt, steps, field)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L, gxT, gx0, gm = LF.com_drift_loss_grad(X0, xT, Mt)
+            xbar, _, mbar = LF.kdk_backward(ckpt, Mt, H, dt, field, gxT, torch.zeros_like(vT))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            runs.append((t1 - t0, t2 - t1))
+            log(f"[bench full] binary 2x2^23 repeat {rep}: forward {t1 - t0:.3f} s, "
+                f"backward {t2 - t1:.3f} s, loss {L:.3e}")
+            del ckpt, xT, vT, xbar, mbar
+        peak = torch.cuda.max_memory_allocated() + F.fmm_tree_device_bytes(field.g.tree)
+    finally:
+        field.free()
+    tf = sorted(r[0] for r in runs)[1]
+    tb = sorted(r[1] for r in runs)[1]
+    out["binary_2x2^23"] = {"fwd_s": round(tf, 4), "bwd_s": round(tb, 4),
+                            "value": n * steps / (tf + tb),
+                            "unit": "particle-forces/s (N x 10 / (t_fwd + t_bwd))",
+                            "peak_device_bytes": int(peak), "steps": steps,
+                            "precision": "fp32 forces, fp64 state and reverse pass"}
+    log(f"[bench full] binary 2x2^23: {n * steps / (tf + tb):.4e} particle-forces/s "
+        f"(forward + backward), peak device memory {peak / 2**30:.2f} GiB")
+    print(json.dumps({"full_configs": out}), flush=True)
+
+
 def copy_calibration(mib):
     """A plain copy of mib MiB (reads and writes mib MiB each time)."""
     import torch
@@ -468,6 +617,9 @@ def main():
         return
     if args.trees:
         trees_compare(args)
+        return
+    if args.full_configs:
+        full_configs(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

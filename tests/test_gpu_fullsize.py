@@ -9,7 +9,8 @@ capacities, leaf size 8).
 * clumpy cube 2^22: FP64 against the oracle FMM on every particle, FP32
   against FP64, both against the direct sum on sampled sinks;
 * Plummer 2^20: FP32 forward with the tree fixed, VJP against central finite
-  differences of the FP64 frozen-list forces;
+  differences of the FP64 frozen-list forces; its first 4096 particles as
+  their own system against the oracle's direct-sum adjoint;
 * binary 2 x 2^23: FP32 forward through 10 KDK steps and the checkpointed
   backward pass of |x_com(T) - x_com(0)|^2, against central finite
   differences with every step's tree and lists held at the forward pass's."""
@@ -22,7 +23,7 @@ import torch
 from paper_2502_01496_amd import fmm as F
 from paper_2502_01496_amd import leapfrog as LF
 from paper_2502_01496_amd import workloads as W
-from tests.gpu_util import eta, force_err, gpu_run, say, to_dev
+from tests.gpu_util import eta, force_err, gpu_run, gpu_vjp, say, to_dev
 from tests.test_gpu_parity import sorted_by_sink
 
 pytestmark = pytest.mark.gpu
@@ -171,6 +172,26 @@ def test_plummer_2e20_vjp_fp32_forward():
         F.fmm_tree_free(t64)
     say(f"    worst |FD - VJP| / |grad| over 4 x and 4 m directions: {worst:.3e}")
     assert worst <= 1e-5
+
+
+def test_plummer_2e20_subset_direct_adjoint(orc):
+    # the first 4096 particles of the Plummer 2^20 set as their own system
+    # (m = 1/4096): the VJP of the FP32-forward tree against the oracle's
+    # direct-sum adjoint, which it matches up to the FMM truncation (at most
+    # ten times the forward error eta of the same tree)
+    x, _, h = W.plummer(1 << 20, 4)
+    x, h = x[:4096].copy(), h[:4096].copy()
+    m = np.full(4096, 1.0 / 4096)
+    abar = W.cotangent(1 << 20, 41)[:4096].copy()
+    say("[gpu full] Plummer 2^20, first 4096 particles: VJP vs the direct-sum adjoint")
+    a, [(xb, mb)] = gpu_vjp(x, m, h, abar, precision=F.FMM_FP32)
+    d = orc.direct(x, m, h)
+    eta_fwd = eta(a, d)
+    xr, mr = orc.direct_vjp(x, m, h, abar)
+    ex = np.linalg.norm(xb - xr) / np.linalg.norm(xr)
+    em = np.linalg.norm(mb - mr) / np.linalg.norm(mr)
+    say(f"    forward eta {eta_fwd:.2e}; relative difference: xbar {ex:.2e}, mbar {em:.2e}")
+    assert ex <= 10 * eta_fwd and em <= 10 * eta_fwd
 
 
 @pytest.mark.timeout(900)
