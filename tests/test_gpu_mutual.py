@@ -93,6 +93,18 @@ def test_mutual_deterministic():
     assert np.array_equal(a1, a2)
 
 
+def test_mutual_lists_ascending(orc):
+    # every far and near list holds distinct source ids in ascending order
+    x, m, h = W.clumpy_cube(20000, 3, cache=False)
+    say("[gpu mutual] list order, clumpy_20000")
+    _, ex, _ = gpu_run(x, m, h, walk=F.FMM_WALK_MUTUAL)
+    for off, src in (("far_off", "far_src"), ("near_off", "near_src")):
+        o, sv = ex[off], ex[src]
+        for v in range(len(o) - 1):
+            seg = sv[o[v]:o[v + 1]]
+            assert (np.diff(seg) > 0).all(), (off, v)
+
+
 def test_mutual_buffer_regrowth(orc, monkeypatch):
     # first capacities of 256 entries: frontier, far and near buffers all
     # overflow and are grown over several walks; the lists must not change
