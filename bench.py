@@ -135,10 +135,10 @@ def pair_census(x, h, ex, leaf_size):
     return total, soft
 
 
-def profile_traffic(kernel_tag):
-    """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter runs, valid only while the kernel source is unchanged."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def _profile_record(name, kernel_tag):
+    """A kernel's record from a committed rocprofv3 counter summary, valid only
+    while the kernel source is unchanged (sha1 of the source file)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
@@ -151,7 +151,20 @@ def profile_traffic(kernel_tag):
     digest = hashlib.sha1(open(src, "rb").read()).hexdigest()
     if digest != rec.get("source_sha1"):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def profile_traffic(kernel_tag):
+    """HBM bytes per launch of the dominant kernel (FETCH_SIZE, WRITE_SIZE)."""
+    rec = _profile_record("traffic.json", kernel_tag)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def profile_counted_flop(kernel_tag):
+    """Floating-point operations per launch the hardware counters saw
+    (64 x (add + mul + transcendental + 2 fma) wave instructions)."""
+    rec = _profile_record("valu.json", kernel_tag)
+    return rec.get("flop_per_launch") if rec else None
 
 
 def cpu_baseline(x, m, h, theta):
@@ -274,6 +287,12 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
         others = {k: {"achieved": round(kv[0] / 1e12, 3), "frac": round(kv[0] / peak, 4),
                       "kernel_ms": round(kv[1], 4)} for k, kv in kern.items() if k != dom}
         roof["other_kernels"] = others
+        cf = profile_counted_flop(ktag)
+        roof["counted"] = None if cf is None else {
+            "flop_per_launch": cf, "achieved": round(cf / (kern[dom][1] * 1e-3) / 1e12, 3),
+            "frac": round(cf / (kern[dom][1] * 1e-3) / peak, 4),
+            "what": "executed FLOP from rocprofv3 SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA} counters "
+                    "(profiles/valu_forces_binary_2x2e18.md) over the same launch time"}
     xc = np.array(xcom)
     fo_ms = stages["walk"] + stages["far"] + stages["near"]
     rec = {
