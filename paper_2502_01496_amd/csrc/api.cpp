@@ -198,6 +198,9 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     // pair buffers exercise their overflow-and-retry path.
     if (const char *e = std::getenv("FMM_MI355_MW_CAP"))
         t->mw_init_cap = std::max<int64_t>(1, std::atoll(e));
+    // Test hook: the full-key Morton sort from the first build on.
+    if (const char *e = std::getenv("FMM_MI355_MORTON_FULL"))
+        t->morton_full = std::atoi(e) != 0;
     hipError_t e = hipSuccess;
 #define A(expr)                \
     if (e == hipSuccess)       \
@@ -274,7 +277,7 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->vals1, 3 * n));
     A(dalloc(*t, &t->rs_hist, 3 * 256 * nblk));
     A(dalloc(*t, &t->rs_tot, (size_t)RS_PASSES * 3 * 256));
-    A(dalloc(*t, &t->run_cnt, 1));
+    A(dalloc(*t, &t->run_cnt, 4));  // axis sorts: [0..1], Morton sort: [2..3]
     A(dalloc(*t, &t->run_list, 3 * (n / 65 + 1)));
     A(dalloc(*t, &t->r2o, n));
     A(dalloc(*t, &t->xr, 3 * n));
@@ -512,6 +515,15 @@ static fmm_status ensure_mutual(Tree &t, int64_t cap_task, int64_t cap_far, int6
     return FMM_OK;
 }
 
+// After a readback that included the Morton sort's long-run entry count
+// (h_flags[6]): data whose keys mostly share their high halves switches the
+// tree's later builds to the full-key sort.
+static void note_long_runs(Tree &t)
+{
+    if (!t.morton_full && (uint32_t)t.h_flags[6] > (uint64_t)t.topo.n / 16)
+        t.morton_full = true;
+}
+
 static fmm_status bad_input(uint32_t errbits)
 {
     if (!(errbits & 7u))
@@ -550,7 +562,10 @@ static fmm_status forces_mutual(Tree &t, void *a, bool walk, hipStream_t s)
             HIP_TRY(hipMemcpyAsync(M.h_cnt, M.cnt, (MW_IT + nit + 1) * sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(t.h_flags + 4, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(t.h_flags + 5, t.run_cnt + 2, 2 * sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            note_long_runs(t);
             const uint32_t errbits = (uint32_t)t.h_flags[4];
             if (errbits) {
                 t.has_lists = false;
@@ -782,7 +797,10 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             break;
         HIP_TRY(hipMemcpyAsync(t.h_flags, t.walk_flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(t.h_flags + 4, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(t.h_flags + 5, t.run_cnt + 2, 2 * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        note_long_runs(t);
         uint32_t errbits = (uint32_t)t.h_flags[4];
         if (errbits) {
             t.has_lists = false;

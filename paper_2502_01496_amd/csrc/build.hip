@@ -8,7 +8,9 @@
 // Steps (all on the caller's stream):
 //   1. global bounding box (ordered-bit atomics, order-free);
 //   2. 63-bit Morton keys of positions quantised to 2^21 per axis;
-//   3. stable LSD radix sort by key -> Morton rank order;
+//   3. stable LSD radix sort by key -> Morton rank order (by halves, see
+//      sort_by_halves; a tree whose earlier builds met long runs of equal
+//      high halves sorts all eight digits instead);
 //   4. three stable radix sorts by ordered coordinate bits, from rank order,
 //      giving per axis the particles sorted by (x_d, rank);
 //   5. for cells larger than SUBTREE_MAX, one level at a time: the median of
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(256) void k_run_fix(const uint64_t *__restrict__ ki
 // between the run's segments of the input and output arrays.
 __global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t *vin,
                                                          uint64_t *kout, uint32_t *vout, int64_t n,
-                                                         const uint32_t *__restrict__ long_cnt,
+                                                         uint32_t *long_cnt,
                                                          const int64_t *__restrict__ long_list,
                                                          int64_t long_cap)
 {
@@ -468,6 +470,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t
                 break;
         }
         const int64_t L = end_sh - a;
+        if (t == 0)
+            atomicAdd(&long_cnt[1], (uint32_t)L);  // entries in long runs, for the host
         for (int pass = 0; pass < 8; ++pass) {
             const int src = pass & 1, dst = src ^ 1;
             const uint64_t *ks = K[src] + a;
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t
 
 // Sort B arrays of (key, position) pairs held in (k0, v0); the result lands
 // in (k1, v1).  work: B * (n / (RUN_SHORT + 1) + 1) int64 for the long-run
-// list plus one counter word.
+// list; long_cnt[0] counts the long runs, long_cnt[1] their entries.
 hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
                           int B, uint32_t *hist, uint32_t *tot, uint32_t *long_cnt,
                           int64_t *long_list, uint32_t *err, hipStream_t s)
@@ -546,7 +550,7 @@ hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
         return hipSuccess;
     const int64_t long_cap = (int64_t)B * (n / (RUN_SHORT + 1) + 1);
     k_rs_zero<<<64, 256, 0, s>>>(tot, (int64_t)4 * B * 256);
-    k_rs_zero<<<1, 64, 0, s>>>(long_cnt, 1);
+    k_rs_zero<<<1, 64, 0, s>>>(long_cnt, 2);
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 32 + 8 * pass;
         uint64_t *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
@@ -938,8 +942,20 @@ hipError_t launch_morton_order(Tree &t, const double *x, hipStream_t s)
     k_bbox<<<(int)std::min<int64_t>((n + 255) / 256, 256), 256, 0, s>>>(x, n, t.bbox, t.err);
     // Morton keys in (keys1, vals1) -> sorted into (keys0, vals0)
     k_morton<<<gs, 256, 0, s>>>(x, n, t.bbox, t.keys1, t.vals1);
+    if (t.morton_full) {
+        // concentrated data with distant outliers: most keys share their high
+        // half, so the run fix would sort long runs one workgroup each; all
+        // eight digits device-wide give the same (key, position) order
+        hipError_t e = radix_sort_u64(t.keys1, t.vals1, t.keys0, t.vals0, n, 1, 8, t.rs_hist,
+                                      t.rs_tot, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(t.keys0, t.keys1, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(t.vals0, t.vals1, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        return e;
+    }
     return sort_by_halves(t.keys1, t.vals1, t.keys0, t.vals0, n, 1, t.rs_hist, t.rs_tot,
-                          t.run_cnt, t.run_list, t.err, s);
+                          t.run_cnt + 2, t.run_list, t.err, s);
 }
 
 hipError_t launch_build(Tree &t, const double *x, hipStream_t s)

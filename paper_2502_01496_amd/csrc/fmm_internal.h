@@ -260,6 +260,7 @@ struct Tree {
 
     MutualLists mw;
     int64_t mw_init_cap = 0;        // test hook: FMM_MI355_MW_CAP sets small first capacities
+    bool morton_full = false;       // Morton keys sorted on all eight digits
 
     // centre-of-mass tree build (FMM_TREE_COM)
     struct ComWork {

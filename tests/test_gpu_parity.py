@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 from paper_2502_01496_amd import workloads as W
-from tests.gpu_util import force_err, gpu_run, say
+from paper_2502_01496_amd import fmm as F
+from tests.gpu_util import force_err, gpu_run, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -181,3 +182,39 @@ def test_narrow_stack_fallback(orc, monkeypatch):
     x, m, h = W.plummer(20000, 13)
     say("[gpu parity] narrow-stack walk fallback, plummer_20000")
     _check_lists_and_forces(orc, x, m, h, 0.5, 8)
+
+
+@pytest.mark.parametrize("name", ["plummer_4096", "ties_3000", "clumpy_20000_lognormal",
+                                  "plummer_100003_ragged"])
+def test_full_key_morton_sort(orc, monkeypatch, name):
+    # the Morton order by all eight key digits (used once a tree has met
+    # concentrated data) gives the same (key, position) order as the sort by
+    # halves: tree, records, lists and forces as in the parity test
+    monkeypatch.setenv("FMM_MI355_MORTON_FULL", "1")
+    test_fp64_parity(orc, name)
+
+
+def test_morton_sort_switch_keeps_the_tree():
+    # a Plummer sphere whose halo sets the bounding box: most Morton keys of
+    # the core share their high half, the first forces call switches the
+    # tree to the full-key sort, and the rebuilt tree is the same
+    import torch
+
+    x, m, h = W.plummer(1 << 18, 21)
+    say("[gpu parity] Morton sort switch on concentrated data, plummer_2^18")
+    X, Mt, H = to_dev(x, m, h)
+    A = torch.empty((len(m), 3), dtype=torch.float64, device="cuda")
+    t = F.fmm_build_tree(X, F.default_params())
+    try:
+        exs = []
+        for _ in range(2):
+            t = F.fmm_build_tree(X, F.default_params(), tree=t)
+            F.fmm_moments(t, X, Mt, H)
+            F.fmm_forces(t, A, F.FMM_REWALK)
+            torch.cuda.synchronize()
+            exs.append(F.fmm_debug_export(t, lists=False))
+    finally:
+        F.fmm_tree_free(t)
+    for k in ("perm", "first", "count", "left", "right", "axis"):
+        assert np.array_equal(exs[0][k], exs[1][k]), k
+
