@@ -66,6 +66,10 @@ def parse():
                     help="only measure the larger workloads (clumpy 2^22 in both precision "
                          "forms, Plummer 2^20 FP32 forward + VJP, binary 2 x 2^23 FP32 forward "
                          "and checkpointed backward through 10 KDK steps) and exit")
+    ap.add_argument("--kdk-series", action="store_true",
+                    help="only run 100 FP64 KDK steps of the workload at theta = 0.3, 0.5, 0.7 "
+                         "(leaf <- cell walk) and 0.5 (mutual walk), print the per-step momentum "
+                         "statistics, and exit")
     ap.add_argument("--vjp-reps", type=int, default=5,
                     help="timed VJP calls at the final state (0 = skip)")
     ap.add_argument("--mutual-steps", type=int, default=5,
@@ -234,20 +238,24 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
         f"{value:.4e} particle-forces/s; stages (ms/call) {stages}")
     # reverse pass at the final state (tree and lists of the last step), timed
     # by the library's events: VJP of the accelerations for a normal cotangent
-    vjp_ms = None
+    vjp_ms = vjp_first_ms = None
     if args.vjp_reps > 0:
         abar = torch.randn((n, 3), dtype=adt, device=dev, generator=torch.Generator(dev).manual_seed(7))
         xb = torch.empty((n, 3), dtype=adt, device=dev)
         mb = torch.empty(n, dtype=adt, device=dev)
+        F.fmm_set_timing(g.tree, True)
         F.fmm_forces_vjp(g.tree, abar, xb, mb)        # builds the transposed lists
         torch.cuda.synchronize()
+        vjp_first_ms = F.fmm_stage_times(g.tree)["vjp"]
+        F.fmm_set_timing(g.tree, False)
         F.fmm_set_timing(g.tree, True)
         for _ in range(args.vjp_reps):
             F.fmm_forces_vjp(g.tree, abar, xb, mb)
         torch.cuda.synchronize()
         vjp_ms = F.fmm_stage_times(g.tree)["vjp"]
         F.fmm_set_timing(g.tree, False)
-        log(f"[bench {tag}] VJP {vjp_ms:.3f} ms per call (transposed lists reused)")
+        log(f"[bench {tag}] VJP {vjp_ms:.3f} ms per call (transposed lists reused), "
+            f"{vjp_first_ms:.3f} ms for the first call after a walk (lists transposed)")
 
     info = F.fmm_tree_info(g.tree)
     ex = F.fmm_debug_export(g.tree, lists=True)
@@ -303,6 +311,7 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
         "com_drift": float(np.linalg.norm(xc[-1] - st0["xcom"])),
         "stages_ms": {k: round(v_, 4) for k, v_ in stages.items()},
         "vjp_ms": round(vjp_ms, 4) if vjp_ms is not None else None,
+        "vjp_first_ms": round(vjp_first_ms, 4) if vjp_first_ms is not None else None,
         "forces_only": {"value": n / (fo_ms * 1e-3) if fo_ms > 0 else None,
                         "unit": "particle-forces/s", "stages": "walk + M2L + P2P/L2P"},
         "lists": {"far": info["n_far"], "near_leaf_pairs": info["n_near"], "p2p_pairs": pairs,
@@ -463,6 +472,60 @@ def trees_compare(args):
                 f"{st_ms['near']:.3f} ms")
     print(json.dumps({"trees": f"{args.workload}: n={n}, FP64, static", "rows": rows}),
           flush=True)
+
+
+def kdk_series(args, steps=100):
+    """Per-step momentum diagnostics of a KDK run from rest (the experiment
+    of Secs. 5-6 with gravity only): |sum F| / sum |F|, |sum F|, the
+    centre-of-mass displacement |x_com(t) - x_com(0)|, |P| and |L| after each
+    step, for each opening parameter with the leaf <- cell lists and for the
+    mutual walk at theta = 0.5."""
+    import numpy as np
+    import torch
+
+    from paper_2502_01496_amd import fmm as F
+    from paper_2502_01496_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    x_np, m_np, h_np, _ = W.config(args.workload)
+    n = len(m_np)
+    dt = args.dt
+    runs = []
+    for theta, walk in ((0.3, F.FMM_WALK_PHANTOM), (0.5, F.FMM_WALK_PHANTOM),
+                        (0.7, F.FMM_WALK_PHANTOM), (0.5, F.FMM_WALK_MUTUAL)):
+        X, Mt, H = (torch.from_numpy(a).to("cuda") for a in (x_np, m_np, h_np))
+        V = torch.zeros_like(X)
+        A = torch.empty_like(X)
+        g = F.GravityFMM(theta=theta, walk=walk, leaf_size=args.leaf_size)
+        t0 = time.perf_counter()
+        g.forces(X, Mt, H, out=A)
+        st = [F.fmm_momentum_stats(X, V, Mt, A)]
+        for _ in range(steps):
+            F.fmm_kick_drift(X, V, A, 0.5 * dt, dt)
+            g.forces(X, Mt, H, out=A)
+            F.fmm_kick_drift(X, V, A, 0.5 * dt, 0.0)
+            st.append(F.fmm_momentum_stats(X, V, Mt, A))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.free()
+        x0 = np.array(st[0]["xcom"])
+        ser = {"ratio": [s_["ratio"] for s_ in st],
+               "sumF": [float(np.linalg.norm(s_["sumF"])) for s_ in st],
+               "xcom_disp": [float(np.linalg.norm(np.array(s_["xcom"]) - x0)) for s_ in st],
+               "P": [float(np.linalg.norm(s_["P"])) for s_ in st],
+               "L": [float(np.linalg.norm(s_["L"])) for s_ in st]}
+        tag = f"theta={theta} " + ("mutual" if walk else "leaf<-cell")
+        summ = {"ratio_mean": float(np.mean(ser["ratio"])), "ratio_last": ser["ratio"][-1],
+                "xcom_disp_last": ser["xcom_disp"][-1], "P_last": ser["P"][-1],
+                "L_last": ser["L"][-1], "seconds": round(el, 3)}
+        log(f"[bench kdk] {tag}: {steps} steps in {el:.2f}s; mean |sumF|/sum|F| "
+            f"{summ['ratio_mean']:.3e}; after {steps} steps |x_com - x_com(0)| "
+            f"{summ['xcom_disp_last']:.3e}, |P| {summ['P_last']:.3e}, |L| {summ['L_last']:.3e}")
+        runs.append({"theta": theta, "walk": "mutual" if walk else "leaf<-cell",
+                     "summary": summ, "every_10th_step": {k: v[::10] + [v[-1]]
+                                                          for k, v in ser.items()}})
+    print(json.dumps({"kdk_series": f"{args.workload}: n={n}, FP64, dt={dt}, {steps} steps "
+                                    f"from rest", "runs": runs}), flush=True)
 
 
 def _median_ms(fn, reps, warm=2):
@@ -640,6 +703,9 @@ def main():
     if args.full_configs:
         full_configs(args)
         return
+    if args.kdk_series:
+        kdk_series(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
@@ -684,6 +750,7 @@ def main():
         "com_drift": rec["com_drift"],
         "stages_ms": rec["stages_ms"],
         "vjp_ms": rec["vjp_ms"],
+        "vjp_first_ms": rec["vjp_first_ms"],
         "forces_only": rec["forces_only"],
         "lists": rec["lists"],
         "roofline": rec["roofline"],
@@ -694,7 +761,8 @@ def main():
         mut = run_one(args, x_np, m_np, h_np, F.FMM_FP64, census=False, walk=F.FMM_WALK_MUTUAL,
                       steps=args.mutual_steps)
         out["mutual_fp64"] = {k: mut[k] for k in ("value", "ms_per_step", "rel_err", "sumF_ratio",
-                                                  "com_drift", "stages_ms", "vjp_ms", "forces_only",
+                                                  "com_drift", "stages_ms", "vjp_ms", "vjp_first_ms",
+                                                  "forces_only",
                                                   "lists")}
         out["mutual_fp64"]["steps"] = args.mutual_steps
     if not args.no_cpu_baseline:
