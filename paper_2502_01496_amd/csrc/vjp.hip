@@ -21,6 +21,12 @@
 //      (Qf: the symmetric matrix whose stored entries give Qbar; the dependence
 //      of Q on c cancels because sum m y = 0), evaluated by one thread per
 //      particle walking root -> leaf.
+// With the lists of the mutual walk (Sec. 7), L_a is the sum over the cells
+// v on the leaf's root path of v's own M2L sum shifted down by L2L, and the
+// far pairs are symmetric: step 2 then first carries Lbar up the tree level
+// by level (the adjoint of the shifts, whose centre derivatives go to the
+// child and are taken from the parent), and does the sink and source sides
+// of every cell in one pass over its own pairs (section 2c below).
 // Every accumulator has exactly one owning thread (no floating-point
 // atomics), so the result is bitwise reproducible.  The arithmetic is FP64.
 #include "fmm_internal.h"
