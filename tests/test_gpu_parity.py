@@ -218,3 +218,40 @@ def test_morton_sort_switch_keeps_the_tree():
     for k in ("perm", "first", "count", "left", "right", "axis"):
         assert np.array_equal(exs[0][k], exs[1][k]), k
 
+
+@pytest.mark.parametrize("bad", ["nan_position", "zero_mass", "negative_h"])
+def test_bad_input_data_reported(orc, bad):
+    # data errors are found on the device and reported by fmm_forces
+    # (FMM_ERR_INVALID with the reason); the same tree then takes good data
+    import torch
+
+    x, m, h = W.plummer(4096, 1)
+    xb, mb, hb = x.copy(), m.copy(), h.copy()
+    if bad == "nan_position":
+        xb[17, 1] = np.nan
+        why = "non-finite positions"
+    elif bad == "zero_mass":
+        mb[100] = 0.0
+        why = "masses not positive"
+    else:
+        hb[5] = -0.01
+        why = "smoothing lengths not positive"
+    say(f"[gpu parity] bad input reported: {bad}")
+    A = torch.empty((len(m), 3), dtype=torch.float64, device="cuda")
+    X, Mt, H = to_dev(xb, mb, hb)
+    t = F.fmm_build_tree(X, F.default_params())
+    try:
+        F.fmm_moments(t, X, Mt, H)
+        with pytest.raises(F.FmmError) as ei:
+            F.fmm_forces(t, A)
+        assert why in str(ei.value)
+        X, Mt, H = to_dev(x, m, h)
+        t = F.fmm_build_tree(X, F.default_params(), tree=t)
+        F.fmm_moments(t, X, Mt, H)
+        F.fmm_forces(t, A)
+        torch.cuda.synchronize()
+        a = A.cpu().numpy()
+    finally:
+        F.fmm_tree_free(t)
+    assert force_err(a, orc.fmm(x, m, h).a) <= 1e-12
+
