@@ -56,7 +56,7 @@ __global__ void k_mw_zero(unsigned long long *p, int n)
 __global__ __launch_bounds__(256) void k_mw_init(
     const int32_t *__restrict__ left, const int32_t *__restrict__ right,
     const int32_t *__restrict__ int_nodes, int n_int, const int32_t *__restrict__ leaf_node,
-    int nleaves, int bits, int2 *tout, int64_t cap_task, uint64_t *nkeys, int64_t cap_n,
+    int nleaves, int lbits, int2 *tout, int64_t cap_task, uint64_t *nkeys, int64_t cap_n,
     int32_t *near_cnt, unsigned long long *cnt)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_mw_init(
     if (i < nleaves) {
         near_cnt[i] = 1;
         if (i < cap_n)
-            nkeys[i] = ((uint64_t)i << bits) | (uint64_t)leaf_node[i];
+            nkeys[i] = ((uint64_t)i << lbits) | (uint64_t)i;
     }
     if (i == 0) {
         cnt[MW_IT] = (unsigned long long)n_int;
@@ -128,7 +128,8 @@ __global__ __launch_bounds__(256) void k_mw_step(
     const int2 *__restrict__ tin, int2 *tout, int it, int64_t cap_task,
     const double *__restrict__ recA, const int32_t *__restrict__ left,
     const int32_t *__restrict__ right, const int32_t *__restrict__ node_leaf, double theta2,
-    double r_kern, int bits, uint64_t *fkeys, int64_t cap_f, uint64_t *nkeys, int64_t cap_n,
+    double r_kern, int bits, int lbits, uint64_t *fkeys, int64_t cap_f, uint64_t *nkeys,
+    int64_t cap_n,
     int32_t *near_cnt, unsigned long long *cnt)
 {
     const int64_t nin = min((int64_t)cnt[MW_IT + it], cap_task);
@@ -188,9 +189,9 @@ __global__ __launch_bounds__(256) void k_mw_step(
                 atomicAdd(&near_cnt[fb], 1);
                 const int64_t q = (int64_t)pos[1];
                 if (q < cap_n)
-                    nkeys[q] = ((uint64_t)fa << bits) | (uint64_t)b;
+                    nkeys[q] = ((uint64_t)fa << lbits) | (uint64_t)fb;
                 if (q + 1 < cap_n)
-                    nkeys[q + 1] = ((uint64_t)fb << bits) | (uint64_t)a;
+                    nkeys[q + 1] = ((uint64_t)fb << lbits) | (uint64_t)fa;
                 else
                     ovf |= 4u;
                 pos[1] += 2;
@@ -236,8 +237,9 @@ __global__ __launch_bounds__(256) void k_mw_fill64(int64_t *p, int64_t n)
         p[i] = 0;
 }
 
-// Near pairs sorted by (sink leaf, source): first position of each sink leaf
-// (every leaf has its self pair, so each one is present).
+// Near pairs sorted by (sink leaf, source leaf), both as leaf indices of
+// lbits bits: first position of each sink leaf (every leaf has its self
+// pair, so each one is present).
 __global__ __launch_bounds__(256) void k_mw_near_start(const uint64_t *__restrict__ keys,
                                                        int64_t n, int bits, int64_t *nstart)
 {
@@ -253,6 +255,7 @@ __global__ __launch_bounds__(256) void k_mw_near_start(const uint64_t *__restric
 __global__ __launch_bounds__(256) void k_mw_near_scatter(const uint64_t *__restrict__ keys,
                                                          int64_t n, int bits,
                                                          const int64_t *__restrict__ nstart,
+                                                         const int32_t *__restrict__ leaf_node,
                                                          int32_t *near_src, int64_t cap_near)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(256) void k_mw_near_scatter(const uint64_t *__restr
     const uint64_t s = key >> bits;
     const int64_t k = p - nstart[s];
     if (k < cap_near)
-        near_src[(int64_t)s * cap_near + k] = (int32_t)(key & ((1ull << bits) - 1ull));
+        near_src[(int64_t)s * cap_near + k] = leaf_node[key & ((1ull << bits) - 1ull)];
 }
 
 // Largest near count over the leaves -> cnt[MW_MAXNEAR] (one workgroup).
@@ -302,19 +305,19 @@ hipError_t launch_mutual_walk(Tree &t, hipStream_t s)
 {
     const Topology &T = t.topo;
     const MutualLists &M = t.mw;
-    const int bits = mutual_key_bits(t);
+    const int bits = mutual_key_bits(t), lbits = bit_width(T.nleaves);
     const int nit = mutual_iterations(t);
     const double theta2 = t.p.theta * t.p.theta;
     k_mw_zero<<<1, 256, 0, s>>>(M.cnt, MW_IT + nit + 1);
     const int n_int = T.nnodes - T.nleaves;
     k_mw_init<<<(std::max(n_int, T.nleaves) + 255) / 256, 256, 0, s>>>(
-        t.left, t.right, t.int_nodes, n_int, t.leaf_node, T.nleaves, bits, M.task[0], M.cap_task,
-        M.nkeys[0], M.cap_near, t.near_cnt, M.cnt);
+        t.left, t.right, t.int_nodes, n_int, t.leaf_node, T.nleaves, lbits, M.task[0],
+        M.cap_task, M.nkeys[0], M.cap_near, t.near_cnt, M.cnt);
     for (int it = 0; it < nit; ++it)
         k_mw_step<<<MW_GRID, 256, 0, s>>>(M.task[it & 1], M.task[(it + 1) & 1], it, M.cap_task,
                                           t.recA, t.left, t.right, t.node_leaf, theta2,
-                                          t.p.r_kern, bits, M.fkeys[0], M.cap_far, M.nkeys[0],
-                                          M.cap_near, t.near_cnt, M.cnt);
+                                          t.p.r_kern, bits, lbits, M.fkeys[0], M.cap_far,
+                                          M.nkeys[0], M.cap_near, t.near_cnt, M.cnt);
     k_mw_near_max<<<1, 1024, 0, s>>>(t.near_cnt, T.nleaves, M.cnt);
     return hipGetLastError();
 }
@@ -327,7 +330,8 @@ hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream
     MutualLists &M = t.mw;
     const int bits = mutual_key_bits(t);
     const int pf = (2 * bits + 7) / 8;
-    const int pn = (bit_width(T.nleaves) + bits + 7) / 8;
+    const int lbits = bit_width(T.nleaves);
+    const int pn = (2 * lbits + 7) / 8;  // near keys: (sink leaf, source leaf)
     hipError_t e = radix_sort_u64(M.fkeys[0], nullptr, M.fkeys[1], nullptr, n_far, 1, pf,
                                   M.hist, M.tot, s);
     if (e != hipSuccess)
@@ -343,8 +347,9 @@ hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream
                                                                    M.fstart, M.fend);
     if (n_near > 0) {
         const int g = (int)((n_near + 255) / 256);
-        k_mw_near_start<<<g, 256, 0, s>>>(ns, n_near, bits, M.nstart);
-        k_mw_near_scatter<<<g, 256, 0, s>>>(ns, n_near, bits, M.nstart, t.near_src, t.cap_near);
+        k_mw_near_start<<<g, 256, 0, s>>>(ns, n_near, lbits, M.nstart);
+        k_mw_near_scatter<<<g, 256, 0, s>>>(ns, n_near, lbits, M.nstart, t.leaf_node, t.near_src,
+                                            t.cap_near);
     }
     return hipGetLastError();
 }
