@@ -165,16 +165,17 @@ __global__ void k_rs_zero(uint32_t *p, int64_t cnt)
         p[i] = 0u;
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restrict__ keys,
-                                                        int64_t n, int shift, uint32_t *hist,
-                                                        uint32_t *tot, int nblk)
+template <typename K>
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const K *__restrict__ keys, int64_t n,
+                                                        int shift, uint32_t *hist, uint32_t *tot,
+                                                        int nblk)
 {
     __shared__ uint32_t h[256];
     int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
     if (t < 256)
         h[t] = 0u;
     __syncthreads();
-    const uint64_t *k = keys + (int64_t)b * n;
+    const K *k = keys + (int64_t)b * n;
     int64_t base = (int64_t)blk * RS_TILE;
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -253,11 +254,12 @@ __device__ __forceinline__ uint64_t match_u8(uint32_t d, bool valid)
 // matching; waves in order), place the tile digit-sorted in LDS, then write
 // each digit's run to its global position with consecutive threads on
 // consecutive addresses.
+template <typename K>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
-    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
-    uint32_t *vout, int64_t n, int shift, const uint32_t *__restrict__ hist, int nblk)
+    const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *kout, uint32_t *vout,
+    int64_t n, int shift, const uint32_t *__restrict__ hist, int nblk)
 {
-    __shared__ uint64_t skey[RS_TILE];
+    __shared__ K skey[RS_TILE];
     __shared__ uint32_t sval[RS_TILE];
     __shared__ uint16_t wrun[RS_WAVES][256];
     __shared__ uint32_t loff[256];
@@ -267,19 +269,19 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     for (int i = t; i < RS_WAVES * 256; i += RS_THREADS)
         (&wrun[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t *k = kin + (int64_t)b * n;
+    const K *k = kin + (int64_t)b * n;
     const uint32_t *v = vin ? vin + (int64_t)b * n : nullptr;
     const int64_t tile0 = (int64_t)blk * RS_TILE;
     const int nv = (int)min((int64_t)RS_TILE, n - tile0);
     const int wbase = w * (RS_TILE / RS_WAVES);
-    uint64_t key[RS_ROUNDS];
+    K key[RS_ROUNDS];
     uint32_t val[RS_ROUNDS];
     uint32_t rank[RS_ROUNDS];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const int i = wbase + r * 64 + lane;
-        key[r] = i < nv ? k[tile0 + i] : 0ull;
+        key[r] = i < nv ? k[tile0 + i] : K(0);
         val[r] = (v && i < nv) ? v[tile0 + i] : 0u;
     }
 #pragma unroll
@@ -332,10 +334,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         }
     }
     __syncthreads();
-    uint64_t *ko = kout + (int64_t)b * n;
+    K *ko = kout + (int64_t)b * n;
     uint32_t *vo = vin ? vout + (int64_t)b * n : nullptr;
     for (int j = t; j < nv; j += RS_THREADS) {
-        const uint64_t kk = skey[j];
+        const K kk = skey[j];
         const uint32_t d = (uint32_t)(kk >> shift) & 255u;
         const int64_t gp = (int64_t)gofs[d] + (j - (int)loff[d]);
         ko[gp] = kk;
@@ -345,12 +347,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
 }
 
 // Sort B arrays of n (key, value) pairs by the low 8 * passes key bits
-// (v0 == v1 == nullptr: keys only).  The
-// result ends in (k0, v0) after an even number of passes, in (k1, v1) after
-// an odd one.  hist needs B * 256 * ceil(n / RS_TILE) words, tot
-// passes * B * 256.
-hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
-                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
+// (v0 == v1 == nullptr: keys only).  The result ends in (k0, v0) after an
+// even number of passes, in (k1, v1) after an odd one.  hist needs
+// B * 256 * ceil(n / RS_TILE) words, tot passes * B * 256.
+template <typename K>
+static hipError_t radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int B,
+                             int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
 {
     int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
     if (nblk == 0)
@@ -358,15 +360,28 @@ hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
     k_rs_zero<<<64, 256, 0, s>>>(tot, (int64_t)passes * B * 256);
     for (int pass = 0; pass < passes; ++pass) {
         int shift = 8 * pass;
-        uint64_t *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
+        K *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
         uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
         uint32_t *tp = tot + (int64_t)pass * B * 256;
         dim3 g(nblk, B);
-        k_rs_hist<<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
+        k_rs_hist<K><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
         k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
+        k_rs_scatter<K><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
     }
     return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
+{
+    return radix_sort<uint64_t>(k0, v0, k1, v1, n, B, passes, hist, tot, s);
+}
+
+// 32-bit keys (at most four passes): half the key traffic of the 64-bit sort.
+hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
+{
+    return radix_sort<uint32_t>(k0, v0, k1, v1, n, B, passes, hist, tot, s);
 }
 
 // ---------------------------------------------------------------- (key, value) by halves
@@ -557,9 +572,9 @@ hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
         uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
         uint32_t *tp = tot + (int64_t)pass * B * 256;
         dim3 g(nblk, B);
-        k_rs_hist<<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
+        k_rs_hist<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
         k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
+        k_rs_scatter<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
     }
     const int gf = (int)std::min<int64_t>((n + 255) / 256, 4096);
     k_run_fix<<<dim3(gf, B), 256, 0, s>>>(k0, v0, k1, v1, n, long_cnt, long_list, long_cap, err);

@@ -240,7 +240,7 @@ struct Tree {
     bool has_transposed = false;
     std::vector<DevBuf> vjp_owned;
     int64_t vjp_pair_cap = 0;
-    uint64_t *vk0 = nullptr, *vk1 = nullptr;
+    uint32_t *vk0 = nullptr, *vk1 = nullptr;
     uint32_t *vv0 = nullptr, *vv1 = nullptr, *vhist = nullptr, *vtot = nullptr;
     int64_t *pair_off = nullptr;   // nleaves + 1 offsets of the compacted pairs
     int64_t *vscan = nullptr;
@@ -301,6 +301,8 @@ struct Tree {
 };
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s);
+hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                           int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s);
 
 // launchers (return hipError_t of the last launch / runtime call)

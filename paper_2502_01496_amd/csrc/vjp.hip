@@ -1144,20 +1144,20 @@ __global__ __launch_bounds__(256) void k_cnt_write(const int32_t *cnt, int cap, 
 // (target, sink) pairs in sink-major order: key = target node, value = sink node
 __global__ void k_pairs_write(const int32_t *__restrict__ cnt, const int32_t *__restrict__ slots,
                               int cap, int nl, const int32_t *__restrict__ leaf_node,
-                              const int64_t *__restrict__ off, uint64_t *keys, uint32_t *vals)
+                              const int64_t *__restrict__ off, uint32_t *keys, uint32_t *vals)
 {
     const int lf = blockIdx.x;
     const int c = max(0, min(cnt[lf], cap));
     const int64_t o = off[lf];
     const uint32_t sink = (uint32_t)leaf_node[lf];
     for (int k = threadIdx.x; k < c; k += blockDim.x) {
-        keys[o + k] = (uint64_t)(uint32_t)slots[(int64_t)lf * cap + k];
+        keys[o + k] = (uint32_t)slots[(int64_t)lf * cap + k];
         vals[o + k] = sink;
     }
 }
 
 // CSR offsets over targets from the sorted keys: off[b] = first index with key >= b
-__global__ void k_lower_bound(const uint64_t *__restrict__ keys, int64_t np, int nnodes,
+__global__ void k_lower_bound(const uint32_t *__restrict__ keys, int64_t np, int nnodes,
                               int64_t *off)
 {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= nnodes;
@@ -1165,7 +1165,7 @@ __global__ void k_lower_bound(const uint64_t *__restrict__ keys, int64_t np, int
         int64_t lo = 0, hi = np;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
-            if (keys[mid] < (uint64_t)b)
+            if (keys[mid] < (uint32_t)b)
                 lo = mid + 1;
             else
                 hi = mid;
@@ -1244,8 +1244,8 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
                 (void)hipFree(pp);
         const int64_t cp = np + np / 4 + 1024;
         const int64_t nblk = (cp + RS_TILE - 1) / RS_TILE;
-        e = hipMalloc((void **)&t.vk0, cp * sizeof(uint64_t));
-        if (e == hipSuccess) e = hipMalloc((void **)&t.vk1, cp * sizeof(uint64_t));
+        e = hipMalloc((void **)&t.vk0, cp * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&t.vk1, cp * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc((void **)&t.vv0, cp * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc((void **)&t.vv1, cp * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc((void **)&t.vhist, 256 * nblk * sizeof(uint32_t));
@@ -1258,10 +1258,10 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
         k_pairs_write<<<nl, 64, 0, s>>>(cnt, slots, (int)cap, nl, t.leaf_node, t.pair_off, t.vk0,
                                         t.vv0);
     const int passes = key_passes(T.nnodes);
-    e = radix_sort_u64(t.vk0, t.vv0, t.vk1, t.vv1, np, 1, passes, t.vhist, t.vtot, s);
+    e = radix_sort_u32(t.vk0, t.vv0, t.vk1, t.vv1, np, 1, passes, t.vhist, t.vtot, s);
     if (e != hipSuccess)
         return e;
-    uint64_t *ks = (passes & 1) ? t.vk1 : t.vk0;
+    uint32_t *ks = (passes & 1) ? t.vk1 : t.vk0;
     uint32_t *vs = (passes & 1) ? t.vv1 : t.vv0;
     k_lower_bound<<<(T.nnodes + 256) / 256, 256, 0, s>>>(ks, np, T.nnodes, out.off);
     // keep the sorted values
