@@ -177,12 +177,15 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const K *__restrict__ ke
     __syncthreads();
     const K *k = keys + (int64_t)b * n;
     int64_t base = (int64_t)blk * RS_TILE;
+    // all loads first (indices past the end re-read key n - 1, not counted)
+    K kr[RS_ROUNDS];
 #pragma unroll
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-        int64_t i = base + r * RS_THREADS + t;
-        if (i < n)
-            atomicAdd(&h[(uint32_t)(k[i] >> shift) & 255u], 1u);
-    }
+    for (int r = 0; r < RS_ROUNDS; ++r)
+        kr[r] = k[min(base + r * RS_THREADS + t, n - 1)];
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r)
+        if (base + r * RS_THREADS + t < n)
+            atomicAdd(&h[(uint32_t)(kr[r] >> shift) & 255u], 1u);
     __syncthreads();
     if (t < 256) {
         uint32_t c = h[t];
@@ -284,6 +287,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         key[r] = i < nv ? k[tile0 + i] : K(0);
         val[r] = (v && i < nv) ? v[tile0 + i] : 0u;
     }
+    // this tile's global digit offsets, loaded while the keys are in flight
+    const uint32_t gofs_t = t < 256 ? hist[((int64_t)b * 256 + t) * nblk + blk] : 0u;
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const bool valid = wbase + r * 64 + lane < nv;
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
             wrun[i][t] = (uint16_t)cnt;
             cnt += c;
         }
-        gofs[t] = hist[((int64_t)b * 256 + t) * nblk + blk];
+        gofs[t] = gofs_t;
         uint32_t inc = cnt;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -409,8 +414,17 @@ __global__ __launch_bounds__(256) void k_run_fix(const uint64_t *__restrict__ ki
     uint32_t *vo = vout + (int64_t)b * n;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * 256) {
+        // a run of one entry (nearly all of them) is decided by the two
+        // neighbours, loaded together with the entry
         const uint64_t kp = k[p];
+        const uint64_t kprev = k[p > 0 ? p - 1 : 0], knext = k[p + 1 < n ? p + 1 : p];
+        const uint32_t vp = v[p];
         const uint32_t hp = hi32(kp);
+        if ((p == 0 || hi32(kprev) != hp) && (p + 1 == n || hi32(knext) != hp)) {
+            ko[p] = kp;
+            vo[p] = vp;
+            continue;
+        }
         int64_t a = p;
         while (a > 0 && p - a < RUN_SHORT && hi32(k[a - 1]) == hp)
             --a;
@@ -429,7 +443,6 @@ __global__ __launch_bounds__(256) void k_run_fix(const uint64_t *__restrict__ ki
             }
             continue;
         }
-        const uint32_t vp = v[p];
         if (e - a == 1) {
             ko[p] = kp;
             vo[p] = vp;
@@ -582,8 +595,6 @@ hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
     return hipGetLastError();
 }
 
-
-
 // ---------------------------------------------------------------- level kernels
 // Longest axis of a node from its three sorted lists (first = min, last = max).
 __device__ __forceinline__ int node_axis(const uint32_t *L, int64_t n, const double *xr,
@@ -637,30 +648,58 @@ __device__ __forceinline__ uint32_t goes_left(const Split &S, const double *xr, 
 }
 
 // Sides of a chunk of one list (also stored per position for the scatter)
-// and the chunk's left count.
+// and the chunk's left count.  A chunk holds at most LVL_CHUNK entries, PER
+// per thread: the entries are loaded before the split is found and the
+// coordinates gathered all at once, so a thread waits for two memory round
+// trips rather than two per entry.
 __global__ __launch_bounds__(LVL_THREADS) void k_lvl_count(
     const uint32_t *__restrict__ L, int64_t n, const double *__restrict__ xr,
     const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
     const int32_t *first, const int32_t *count, int32_t *axis_out, uint8_t *side, int32_t *cnt,
     int stride)
 {
+    constexpr int PER = LVL_CHUNK / LVL_THREADS;
     __shared__ uint32_t sh[8];
-    int b = blockIdx.x, d = blockIdx.y;
+    const int b = blockIdx.x, d = blockIdx.y, t = threadIdx.x;
     const int v = blk_node[b];
-    const Split S = node_split(L, n, xr, first[v], count[v]);
-    if (d == 0 && threadIdx.x == 0 && blk_start[b] == S.f)
-        axis_out[v] = S.ax;
+    const int64_t s0 = blk_start[b], e0 = blk_end[b];
     const uint32_t *Ld = L + d * n;
+    // loads past the chunk's end re-read its last entry (a chunk is never
+    // empty) and are discarded, so that every load is issued unconditionally
+    uint32_t r[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        r[k] = Ld[min(s0 + t + k * LVL_THREADS, e0 - 1)];
+    const Split S = node_split(L, n, xr, first[v], count[v]);
+    if (d == 0 && t == 0 && s0 == S.f)
+        axis_out[v] = S.ax;
+    uint32_t g[PER];
+    if (d == S.ax) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            g[k] = s0 + t + k * LVL_THREADS - S.f < S.nl ? 1u : 0u;
+    } else {
+        uint64_t o[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            o[k] = ordbits(xr[S.ax * n + r[k]]);
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            g[k] = (o[k] < S.ob || (o[k] == S.ob && r[k] <= S.rm)) ? 1u : 0u;
+    }
     uint8_t *sd = side + d * n;
     uint32_t c = 0;
-    for (int64_t p = blk_start[b] + threadIdx.x; p < blk_end[b]; p += LVL_THREADS) {
-        const uint32_t g = goes_left(S, xr, n, d, p, Ld[p]);
-        sd[p] = (uint8_t)g;
-        c += g;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t p = s0 + t + k * LVL_THREADS;
+        if (p < e0) {
+            sd[p] = (uint8_t)g[k];
+            c += g[k];
+        }
     }
     uint32_t total;
     block_excl_scan_u32(c, sh, total);
-    if (threadIdx.x == 0)
+    if (t == 0)
         cnt[d * stride + b] = (int32_t)total;
 }
 
@@ -686,9 +725,28 @@ __global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
     const uint32_t *Ls = Lsrc + d * n + s;
     const uint8_t *sd = side + d * n + s;
     uint32_t *Ld = Ldst + d * n;
-    for (int i = t; i < len; i += LVL_THREADS) {
-        sv[i] = Ls[i];
-        sf[i] = sd[i];
+    uint32_t part = 0;
+    {
+        uint32_t lv[PER];
+        uint8_t lf[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = min(t + k * LVL_THREADS, len - 1);  // len >= 1
+            lv[k] = Ls[i];
+            lf[k] = sd[i];
+        }
+        // left entries of the node before this chunk: the counts of the
+        // node's earlier chunks, loaded while the chunk is in flight
+        for (int j = blk_first[b] + t; j < b; j += LVL_THREADS)
+            part += (uint32_t)cnt[d * stride + j];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = t + k * LVL_THREADS;
+            if (i < len) {
+                sv[i] = lv[k];
+                sf[i] = lf[k];
+            }
+        }
     }
     __syncthreads();
     uint32_t fl[PER];
@@ -711,11 +769,7 @@ __global__ __launch_bounds__(LVL_THREADS) void k_lvl_scatter(
         }
     }
     __syncthreads();
-    // left entries of the node before this chunk (sum of the counts of the
-    // node's earlier chunks), then the two runs
-    uint32_t part = 0;
-    for (int j = blk_first[b] + t; j < b; j += LVL_THREADS)
-        part += (uint32_t)cnt[d * stride + j];
+    // then the two runs
     uint32_t before;
     block_excl_scan_u32(part, sh, before);
     const int64_t nb = (int64_t)before;

@@ -83,24 +83,47 @@ __global__ __launch_bounds__(256) void k_leaf_moments(
     int v = leaf_node[lf];
     int64_t f = first[v];
     int c = count[v];
+    // particles are read U at a time, all loads in flight together (indices
+    // past the leaf re-read its last particle and are not summed); sums run
+    // in particle order.  A leaf of at most U particles stays in registers
+    // for the second pass.
+    constexpr int U = 8;
+    double4 q[U];
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hm = 0.0;
-    for (int k = 0; k < c; ++k) {
-        double4 q = pm[f + k];
-        M += q.w;
-        S0 += q.w * q.x;
-        S1 += q.w * q.y;
-        S2 += q.w * q.z;
-        double hh = hs[f + k];
-        hm = hh > hm ? hh : hm;
+    for (int k0 = 0; k0 < c; k0 += U) {
+        double hh[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = f + min(k0 + j, c - 1);
+            q[j] = pm[i];
+            hh[j] = hs[i];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k0 + j < c) {
+                M += q[j].w;
+                S0 += q[j].w * q[j].x;
+                S1 += q[j].w * q[j].y;
+                S2 += q[j].w * q[j].z;
+                hm = hh[j] > hm ? hh[j] : hm;
+            }
     }
     double c0 = S0 / M, c1 = S1 / M, c2 = S2 / M;
     double Q[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < c; ++k) {
-        double4 q = pm[f + k];
-        double y0 = q.x - c0, y1 = q.y - c1, y2 = q.z - c2;
-        quad_add(Q, q.w, y0, y1, y2);
-        if (want_fp32)
-            pf[f + k] = make_float4((float)y0, (float)y1, (float)y2, (float)q.w);
+    for (int k0 = 0; k0 < c; k0 += U) {
+        if (c > U) {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                q[j] = pm[f + min(k0 + j, c - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k0 + j < c) {
+                double y0 = q[j].x - c0, y1 = q[j].y - c1, y2 = q[j].z - c2;
+                quad_add(Q, q[j].w, y0, y1, y2);
+                if (want_fp32)
+                    pf[f + k0 + j] = make_float4((float)y0, (float)y1, (float)y2, (float)q[j].w);
+            }
     }
     double *ra = recA + (int64_t)NREC * v;
     *(double4 *)ra = make_double4(c0, c1, c2, M);
@@ -152,13 +175,15 @@ __global__ __launch_bounds__(256) void k_combine_level(const int32_t *__restrict
 // At each level, a wavefront whose 64 particles all lie in one node writes
 // its maximum to part[level][wave]; otherwise the lanes of each node reduce
 // with a segmented max and one atomicMax per node run (few lanes per node, so
-// little contention).
+// little contention).  Nodes are numbered in depth-first pre-order, so an
+// internal node's left child is v + 1: the centre, both child ids and the
+// left child's particle range are loaded together, one round trip per level.
 __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm, int64_t n,
                                                  const double *__restrict__ recA,
                                                  const int32_t *__restrict__ first,
                                                  const int32_t *__restrict__ count,
                                                  const int32_t *__restrict__ left,
-                                                 const int32_t *__restrict__ right,
+                                                 const int32_t *__restrict__ right, int nnodes,
                                                  uint64_t *s2bits, uint64_t *part, int64_t nwaves)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -170,8 +195,14 @@ __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm,
     for (int lvl = 0; __ballot(!done) != 0ull; ++lvl) {
         const int key = done ? -1 : v;
         uint64_t val = 0ull;
+        int l = -1, rgt = -1;
+        int64_t bnd = 0;
         if (!done) {
             const double *ra = recA + (int64_t)NREC * v;
+            l = left[v];
+            rgt = right[v];
+            const int vn = min(v + 1, nnodes - 1);  // read only when v is internal
+            bnd = (int64_t)first[vn] + count[vn];
             double dx = xp.x - ra[0], dy = xp.y - ra[1], dz = xp.z - ra[2];
             double d2 = (dx * dx + dy * dy) + dz * dz;
             val = (uint64_t)__double_as_longlong(d2);
@@ -196,11 +227,10 @@ __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm,
                 atomicMax((unsigned long long *)&s2bits[v], (unsigned long long)val);
         }
         if (!done) {
-            int l = left[v];
             if (l < 0)
                 done = true;
             else
-                v = (p < (int64_t)first[l] + count[l]) ? l : right[v];
+                v = p < bnd ? l : rgt;
         }
     }
 }
@@ -223,9 +253,19 @@ __global__ __launch_bounds__(256) void k_node_s2_fold(const int32_t *__restrict_
     const int64_t w1 = ((int64_t)first[v] + count[v]) >> 6;
     const uint64_t *pl = part + (int64_t)level[v] * nwaves;
     uint64_t m = 0ull;
-    for (int64_t wv = w0 + lane_id(); wv < w1; wv += 64) {
-        uint64_t x = pl[wv];
-        m = x > m ? x : m;
+    // eight loads in flight per lane; indices past w1 re-read entry w0, which
+    // belongs to the node and so leaves the maximum unchanged
+    constexpr int U = 8;
+    for (int64_t wb = w0 + lane_id(); wb < w1; wb += 64 * U) {
+        uint64_t x[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t q = wb + 64 * j;
+            x[j] = pl[q < w1 ? q : w0];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            m = x[j] > m ? x[j] : m;
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -275,7 +315,8 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
     }
     const int64_t nwaves = (n + 63) / 64;
     k_node_s2<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, t.first, t.count, t.left,
-                                                     t.right, t.s2bits, t.s2part, nwaves);
+                                                     t.right, T.nnodes, t.s2bits, t.s2part,
+                                                     nwaves);
     const int nbig = T.nbig;
     if (nbig > 0)
         k_node_s2_fold<<<(nbig + 3) / 4, 256, 0, s>>>(t.big_nodes, nbig, t.first, t.count,
