@@ -32,12 +32,25 @@ namespace fmm {
 
 constexpr int MW_GRID = 1024;  // workgroups of a frontier step (grid-stride)
 
-__device__ __forceinline__ bool separated(const double *ra, const double *rb, double theta2,
+// A cell's centre, s and h_max (the fields the criterion reads).
+struct MwCell {
+    double c0, c1, c2, s, h;
+};
+
+__device__ __forceinline__ MwCell load_mw(const double *recA, int v)
+{
+    const double *r = recA + (int64_t)NREC * v;
+    const double2 a = *(const double2 *)r;
+    const double2 q = *(const double2 *)(r + 4);
+    return {a.x, a.y, r[2], q.x, q.y};
+}
+
+__device__ __forceinline__ bool separated(const MwCell &A, const MwCell &B, double theta2,
                                           double r_kern)
 {
-    const double dx = ra[0] - rb[0], dy = ra[1] - rb[1], dz = ra[2] - rb[2];
+    const double dx = A.c0 - B.c0, dy = A.c1 - B.c1, dz = A.c2 - B.c2;
     const double r2 = (dx * dx + dy * dy) + dz * dz;
-    const double sa = ra[4], sb = rb[4], ha = ra[5], hb = rb[5];
+    const double sa = A.s, sb = B.s, ha = A.h, hb = B.h;
     const double ss = sa + sb;
     const bool ok4 = theta2 * r2 >= ss * ss;
     const double tt = ss + r_kern * (ha > hb ? ha : hb);
@@ -122,7 +135,9 @@ __device__ __forceinline__ void block_append3(const uint32_t (&v)[3],
 // A workgroup takes MW_K x 256 consecutive pairs per round: it classifies
 // them (far / near / split A / split B), reserves the outputs of the whole
 // round with one atomic per output buffer, then writes them.
-constexpr int MW_K = 16;
+constexpr int MW_K = 8;
+constexpr int MW_KB = 2;  // pairs whose loads are in flight together (more raise the
+                          // register count and cost occupancy)
 
 __global__ __launch_bounds__(256) void k_mw_step(
     const int2 *__restrict__ tin, int2 *tout, int it, int64_t cap_task,
@@ -137,33 +152,51 @@ __global__ __launch_bounds__(256) void k_mw_step(
     const int t = threadIdx.x;
     for (int64_t r0 = (int64_t)blockIdx.x * (256 * MW_K); r0 < nin;
          r0 += (int64_t)gridDim.x * (256 * MW_K)) {
+        // the round's pairs, then per batch of MW_KB pairs every record and
+        // child id they may need, all loads in flight together (pairs past
+        // the frontier's end re-read its last pair and are classified 0)
         int2 tk[MW_K];
+#pragma unroll
+        for (int k = 0; k < MW_K; ++k)
+            tk[k] = tin[min(r0 + k * 256 + t, nin - 1)];
+        int2 outp[MW_K];  // near: the two leaf indices; split: the split cell's children
         uint64_t code = 0;  // 3 bits per pair: 0 none, 1 far, 2 near, 3 split A, 4 split B
         uint32_t num[3] = {0u, 0u, 0u};
 #pragma unroll
-        for (int k = 0; k < MW_K; ++k) {
-            const int64_t i = r0 + k * 256 + t;
-            tk[k] = make_int2(0, 0);
-            uint32_t c = 0;
-            if (i < nin) {
-                tk[k] = tin[i];
-                const int a = tk[k].x, b = tk[k].y;
-                const double *ra = recA + (int64_t)NREC * a;
-                const double *rb = recA + (int64_t)NREC * b;
-                if (separated(ra, rb, theta2, r_kern)) {
-                    c = 1;
-                } else {
-                    const int la = left[a], lb = left[b];
-                    if (la < 0 && lb < 0)
+        for (int k0 = 0; k0 < MW_K; k0 += MW_KB) {
+            MwCell A[MW_KB], B[MW_KB];
+            int la[MW_KB], ra[MW_KB], lb[MW_KB], rb[MW_KB], fa[MW_KB], fb[MW_KB];
+#pragma unroll
+            for (int j = 0; j < MW_KB; ++j) {
+                const int a = tk[k0 + j].x, b = tk[k0 + j].y;
+                A[j] = load_mw(recA, a);
+                B[j] = load_mw(recA, b);
+                la[j] = left[a];
+                ra[j] = right[a];
+                lb[j] = left[b];
+                rb[j] = right[b];
+                fa[j] = node_leaf[a];
+                fb[j] = node_leaf[b];
+            }
+#pragma unroll
+            for (int j = 0; j < MW_KB; ++j) {
+                const int k = k0 + j;
+                uint32_t c = 0;
+                if (r0 + k * 256 + t < nin) {
+                    if (separated(A[j], B[j], theta2, r_kern))
+                        c = 1;
+                    else if (la[j] < 0 && lb[j] < 0)
                         c = 2;
                     else
-                        c = (lb < 0 || (la >= 0 && ra[4] >= rb[4])) ? 3 : 4;
+                        c = (lb[j] < 0 || (la[j] >= 0 && A[j].s >= B[j].s)) ? 3 : 4;
                 }
+                outp[k] = c == 2 ? make_int2(fa[j], fb[j])
+                                 : (c == 3 ? make_int2(la[j], ra[j]) : make_int2(lb[j], rb[j]));
+                code |= (uint64_t)c << (3 * k);
+                num[0] += c == 1 ? 2u : 0u;
+                num[1] += c == 2 ? 2u : 0u;
+                num[2] += c >= 3 ? 2u : 0u;
             }
-            code |= (uint64_t)c << (3 * k);
-            num[0] += c == 1 ? 2u : 0u;
-            num[1] += c == 2 ? 2u : 0u;
-            num[2] += c >= 3 ? 2u : 0u;
         }
         uint64_t pos[3];
         block_append3(num, ctr, pos);
@@ -184,7 +217,7 @@ __global__ __launch_bounds__(256) void k_mw_step(
                     ovf |= 2u;
                 pos[0] += 2;
             } else if (c == 2) {
-                const int fa = node_leaf[a], fb = node_leaf[b];
+                const int fa = outp[k].x, fb = outp[k].y;
                 atomicAdd(&near_cnt[fa], 1);
                 atomicAdd(&near_cnt[fb], 1);
                 const int64_t q = (int64_t)pos[1];
@@ -197,8 +230,8 @@ __global__ __launch_bounds__(256) void k_mw_step(
                 pos[1] += 2;
             } else if (c >= 3) {
                 const bool sa = c == 3;
-                const int sp = sa ? a : b, o = sa ? b : a;
-                const int c0 = left[sp], c1 = right[sp];
+                const int o = sa ? b : a;
+                const int c0 = outp[k].x, c1 = outp[k].y;
                 const int64_t q = (int64_t)pos[2];
                 if (q < cap_task)
                     tout[q] = sa ? make_int2(c0, o) : make_int2(o, c0);

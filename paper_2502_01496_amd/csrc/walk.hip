@@ -24,11 +24,24 @@ constexpr int WALK_STACK = 96;
 static_assert(COM_MAX_DEPTH + 2 <= WALK_STACK, "narrow walk stack shorter than the deepest tree");
 constexpr int WIDE_STACK = 1024;
 
-__device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, double sa, double ha,
-                                       const double *rb, double theta2, double r_kern)
+// Cell b's centre and size s_b, h_max,b, loaded once per visit.
+struct CellRec {
+    double c0, c1, c2, sb, hb;
+};
+
+__device__ __forceinline__ CellRec load_cell(const double *recA, int b)
 {
-    const double dx = ca0 - rb[0], dy = ca1 - rb[1], dz = ca2 - rb[2];
-    const double sb = rb[4], hb = rb[5];
+    const double *rb = recA + (int64_t)NREC * b;
+    const double4 a = *(const double4 *)rb;
+    const double2 q = *(const double2 *)(rb + 4);
+    return {a.x, a.y, a.z, q.x, q.y};
+}
+
+__device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, double sa, double ha,
+                                       const CellRec &cb, double theta2, double r_kern)
+{
+    const double dx = ca0 - cb.c0, dy = ca1 - cb.c1, dz = ca2 - cb.c2;
+    const double sb = cb.sb, hb = cb.hb;
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     const bool open4 = sb * sb > theta2 * r2;
     const double tt = (sa + sb) + r_kern * (ha > hb ? ha : hb);
@@ -88,13 +101,16 @@ __global__ __launch_bounds__(256) void k_walk_group(
         const int b = act ? stk[w][base + lane] : 0;
         const uint32_t m = act ? msk[w][base + lane] : 0u;
         sp = base;
-        const double *rb = recA + (int64_t)NREC * b;
+        // the record is read once for all leaves of the group (idle lanes
+        // read the root's)
+        const CellRec cb = load_cell(recA, b);
         const int lb = left[b], rgt = right[b];
         uint32_t open = 0;
 #pragma unroll
         for (int g = 0; g < WG; ++g) {
             const bool live = (m >> g) & 1u;
-            const bool op = live && opened(ca0[g], ca1[g], ca2[g], sa[g], ha[g], rb, theta2, r_kern);
+            const bool op =
+                opened(ca0[g], ca1[g], ca2[g], sa[g], ha[g], cb, theta2, r_kern) && live;
             const bool far = live && !op;
             const bool nea = op && lb < 0;
             open |= (op ? 1u : 0u) << g;
@@ -183,10 +199,11 @@ __global__ __launch_bounds__(256) void k_walk_p(
         const int b = __builtin_amdgcn_readfirstlane(stk_node[w][sp]);
         const uint64_t mask = stk_mask[w][sp];
         const int lb = left[b];
+        const CellRec cb = load_cell(recA, b);
         const bool active = (mask >> lane) & 1ull;
         bool descend = false;
         if (active) {
-            if (!opened(ca0, ca1, ca2, sa, ha, recA + (int64_t)NREC * b, theta2, r_kern)) {
+            if (!opened(ca0, ca1, ca2, sa, ha, cb, theta2, r_kern)) {
                 if (nf < cap_far)
                     fo[nf] = b;
                 ++nf;
