@@ -790,21 +790,50 @@ __global__ __launch_bounds__(256) void k_l2l_chain(const double *__restrict__ re
 #pragma unroll
     for (int k = 0; k < 19; ++k)
         L[k] = Lown[k];
-    int v = 0;
     double p0 = recA[0], p1 = recA[1], p2 = recA[2];
-    while (v != u) {
-        const int ch = u < right[v] ? left[v] : right[v];
+    // the next cell on the path and its centre and own sum are loaded while
+    // the current shift computes
+    int ch = 0;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    T lo[19];
+    if (u != 0) {
+        ch = u < right[0] ? left[0] : right[0];
         const double *rc = recA + (int64_t)NREC * ch;
-        const double q0 = rc[0], q1 = rc[1], q2 = rc[2];
+        q0 = rc[0];
+        q1 = rc[1];
+        q2 = rc[2];
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            lo[k] = Lown[(int64_t)NLOC * ch + k];
+    }
+    while (ch != 0) {
+        int nx = 0;
+        double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+        T ln[19];
+        if (ch != u) {
+            nx = u < right[ch] ? left[ch] : right[ch];
+            const double *rc = recA + (int64_t)NREC * nx;
+            n0 = rc[0];
+            n1 = rc[1];
+            n2 = rc[2];
+#pragma unroll
+            for (int k = 0; k < 19; ++k)
+                ln[k] = Lown[(int64_t)NLOC * nx + k];
+        }
         l2l_shift<T>(L, (T)(q0 - p0), (T)(q1 - p1), (T)(q2 - p2));
-        const T *lo = Lown + (int64_t)NLOC * ch;
 #pragma unroll
         for (int k = 0; k < 19; ++k)
             L[k] = lo[k] + L[k];
-        v = ch;
         p0 = q0;
         p1 = q1;
         p2 = q2;
+        ch = nx;
+        q0 = n0;
+        q1 = n1;
+        q2 = n2;
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            lo[k] = ln[k];
     }
     T *o = Lout + (int64_t)NLOC * u;
 #pragma unroll

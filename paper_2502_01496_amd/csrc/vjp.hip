@@ -960,16 +960,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const int ne = stage_blocks(tsrc + e0, c0, nc, nsub, first, count, recA, rv, r_kern,
                                         lane, R, front, gap);
             __builtin_amdgcn_wave_barrier();
+            // the next step's sink particles (position, smoothing, adjoint)
+            // load while the current step computes
             int64_t i = block_particle(R[skip_gap(grp, front, gap)], slot, nnull);
             double4 xi = pm[i], hi = ph[i];
+            double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
             for (int kb = 0; kb < ne; kb += 8) {
-                const double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
                 int64_t in = i;
                 double4 xn = xi, hn = hi;
+                double an0 = ai0, an1 = ai1, an2 = ai2;
                 if (kb + 8 < ne) {
                     in = block_particle(R[skip_gap(kb + 8 + grp, front, gap)], slot, nnull);
                     xn = pm[in];
                     hn = ph[in];
+                    an0 = abt[3 * in];
+                    an1 = abt[3 * in + 1];
+                    an2 = abt[3 * in + 2];
                 }
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
@@ -989,6 +995,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 i = in;
                 xi = xn;
                 hi = hn;
+                ai0 = an0;
+                ai1 = an1;
+                ai2 = an2;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -1006,12 +1015,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 }
 
 // 4. Moments adjoint and output: one thread per particle walks root -> leaf.
+// Cells are numbered in depth-first pre-order (an internal cell's left child
+// is v + 1), so each level's loads -- the cell, its child ids and the left
+// child's particle range -- are issued together.
 template <typename TO>
 __global__ __launch_bounds__(256) void k_vjp_moments(
     const double4 *__restrict__ pm, int64_t n, const double *__restrict__ recA,
     const double *__restrict__ nadj, const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ left,
-    const int32_t *__restrict__ right, const double *__restrict__ xbt,
+    const int32_t *__restrict__ right, int nnodes, const double *__restrict__ xbt,
     const double *__restrict__ mbt, const int32_t *__restrict__ perm, TO *xbar, TO *mbar)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1023,6 +1035,9 @@ __global__ __launch_bounds__(256) void k_vjp_moments(
     while (true) {
         const double *ra = recA + (int64_t)NREC * v;
         const double *na = nadj + 16 * (int64_t)v;
+        const int l = left[v], rgt = right[v];
+        const int vn = min(v + 1, nnodes - 1);  // used only when v is internal
+        const int64_t bnd = (int64_t)first[vn] + count[vn];
         const double M = ra[3];
         const double y0 = x.x - ra[0], y1 = x.y - ra[1], y2 = x.z - ra[2];
         const double c0 = na[0] + na[3], c1 = na[1] + na[4], c2 = na[2] + na[5];
@@ -1039,10 +1054,9 @@ __global__ __launch_bounds__(256) void k_vjp_moments(
         gz += wm * c2 + x.w * (6.0 * Qy2 - 2.0 * tr * y2);
         gm += na[6] + (c0 * y0 + c1 * y1 + c2 * y2) / M +
               3.0 * (y0 * Qy0 + y1 * Qy1 + y2 * Qy2) - (y0 * y0 + y1 * y1 + y2 * y2) * tr;
-        const int l = left[v];
         if (l < 0)
             break;
-        v = (p < (int64_t)first[l] + count[l]) ? l : right[v];
+        v = p < bnd ? l : rgt;
     }
     const int64_t i = perm[p];
     xbar[3 * i] = (TO)gx;
@@ -1421,11 +1435,13 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
                                                t.p.r_kern, n, t.xbt, t.mbt);
     if (fp32)
         k_vjp_moments<float><<<(int)((n + 255) / 256), 256, 0, s>>>(
-            t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, t.xbt, t.mbt, t.perm,
+            t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, T.nnodes, t.xbt, t.mbt,
+            t.perm,
             (float *)xbar, (float *)mbar);
     else
         k_vjp_moments<double><<<(int)((n + 255) / 256), 256, 0, s>>>(
-            t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, t.xbt, t.mbt, t.perm,
+            t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, T.nnodes, t.xbt, t.mbt,
+            t.perm,
             (double *)xbar, (double *)mbar);
     return hipGetLastError();
 }
