@@ -31,6 +31,11 @@ constexpr int MAX_LEAF = 64;
 constexpr int COM_CHUNK = 4096;  // particles per chunk of the centre-of-mass build
 constexpr int COM_MAX_DEPTH = 64; // deepest centre-of-mass tree accepted (walk stacks)
 constexpr int NREC = 8;   // doubles per node record (geometry / quadrupole)
+// Geometry record (recA) of a node: centre of mass 0..2, mass 3, size s 4,
+// h_max 5; slot 6 holds the child ids (left in the low 32 bits, right in the
+// high 32, -1 for a leaf) and slot 7 the leaf index (-1 for an internal
+// node), so that a walk reads one 64-byte record per visited cell.
+constexpr int REC_KIDS = 6, REC_LEAF = 7;
 constexpr int NLOC = 20;  // doubles per local expansion (19 used)
 
 // ------------------------------------------------------------------ device

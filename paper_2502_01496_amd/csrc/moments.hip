@@ -12,7 +12,8 @@
 //                one thread per particle walks root -> leaf; lanes on the same
 //                node reduce with a segmented wave max, then one u64 atomicMax
 //                on the bit pattern (order-free for non-negative doubles).
-//   k_node_final s = sqrt(s^2) and the FP32 mirrors.
+//   k_node_final s = sqrt(s^2), the child ids and leaf index in the record's
+//                topology slots, and the FP32 mirrors.
 //
 // Compiled with -ffp-contract=off: M, c, s and h_max are bit-identical to the
 // serial definition (same operations, same order).
@@ -276,14 +277,18 @@ __global__ __launch_bounds__(256) void k_node_s2_fold(const int32_t *__restrict_
         atomicMax((unsigned long long *)&s2bits[v], (unsigned long long)m);
 }
 
-__global__ void k_node_final(int nnodes, const uint64_t *__restrict__ s2bits, double *recA,
+__global__ void k_node_final(int nnodes, const uint64_t *__restrict__ s2bits,
+                             const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                             const int32_t *__restrict__ node_leaf, double *recA,
                              const double *__restrict__ recQ, int want_fp32, float *recF)
 {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nnodes; v += gridDim.x * blockDim.x) {
         double s2 = __longlong_as_double((long long)s2bits[v]);
         recA[(int64_t)NREC * v + 4] = sqrt(s2);
-        recA[(int64_t)NREC * v + 6] = 0.0;
-        recA[(int64_t)NREC * v + 7] = 0.0;
+        const uint64_t kids = (uint64_t)(uint32_t)left[v] | ((uint64_t)(uint32_t)right[v] << 32);
+        recA[(int64_t)NREC * v + REC_KIDS] = __longlong_as_double((long long)kids);
+        recA[(int64_t)NREC * v + REC_LEAF] =
+            __longlong_as_double((long long)(uint64_t)(uint32_t)node_leaf[v]);
         if (want_fp32) {
             float *rf = recF + (int64_t)NREC * v;
             rf[0] = (float)recA[(int64_t)NREC * v + 3];
@@ -321,7 +326,8 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
     if (nbig > 0)
         k_node_s2_fold<<<(nbig + 3) / 4, 256, 0, s>>>(t.big_nodes, nbig, t.first, t.count,
                                                       t.level, t.s2part, nwaves, t.s2bits);
-    k_node_final<<<(T.nnodes + 255) / 256, 256, 0, s>>>(T.nnodes, t.s2bits, t.recA, t.recQ,
+    k_node_final<<<(T.nnodes + 255) / 256, 256, 0, s>>>(T.nnodes, t.s2bits, t.left, t.right,
+                                                       t.node_leaf, t.recA, t.recQ,
                                                        want32, t.recF);
     return hipGetLastError();
 }

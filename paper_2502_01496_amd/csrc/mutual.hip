@@ -32,9 +32,11 @@ namespace fmm {
 
 constexpr int MW_GRID = 1024;  // workgroups of a frontier step (grid-stride)
 
-// A cell's centre, s and h_max (the fields the criterion reads).
+// A cell's centre, s and h_max (the fields the criterion reads), its child
+// ids (left < 0: leaf) and leaf index, all from its one 64-byte record.
 struct MwCell {
     double c0, c1, c2, s, h;
+    int left, right, leaf;
 };
 
 __device__ __forceinline__ MwCell load_mw(const double *recA, int v)
@@ -42,7 +44,8 @@ __device__ __forceinline__ MwCell load_mw(const double *recA, int v)
     const double *r = recA + (int64_t)NREC * v;
     const double2 a = *(const double2 *)r;
     const double2 q = *(const double2 *)(r + 4);
-    return {a.x, a.y, r[2], q.x, q.y};
+    const int4 t = *(const int4 *)(r + REC_KIDS);  // kids (slot 6), leaf index (slot 7)
+    return {a.x, a.y, r[2], q.x, q.y, t.x, t.y, t.z};
 }
 
 __device__ __forceinline__ bool separated(const MwCell &A, const MwCell &B, double theta2,
@@ -141,11 +144,9 @@ constexpr int MW_KB = 2;  // pairs whose loads are in flight together (more rais
 
 __global__ __launch_bounds__(256) void k_mw_step(
     const int2 *__restrict__ tin, int2 *tout, int it, int64_t cap_task,
-    const double *__restrict__ recA, const int32_t *__restrict__ left,
-    const int32_t *__restrict__ right, const int32_t *__restrict__ node_leaf, double theta2,
-    double r_kern, int bits, int lbits, uint64_t *fkeys, int64_t cap_f, uint64_t *nkeys,
-    int64_t cap_n,
-    int32_t *near_cnt, unsigned long long *cnt)
+    const double *__restrict__ recA, double theta2, double r_kern, int bits, int lbits,
+    uint64_t *fkeys, int64_t cap_f, uint64_t *nkeys, int64_t cap_n, int32_t *near_cnt,
+    unsigned long long *cnt)
 {
     const int64_t nin = min((int64_t)cnt[MW_IT + it], cap_task);
     unsigned long long *const ctr[3] = {&cnt[MW_NFAR], &cnt[MW_NNEAR], &cnt[MW_IT + it + 1]};
@@ -165,18 +166,10 @@ __global__ __launch_bounds__(256) void k_mw_step(
 #pragma unroll
         for (int k0 = 0; k0 < MW_K; k0 += MW_KB) {
             MwCell A[MW_KB], B[MW_KB];
-            int la[MW_KB], ra[MW_KB], lb[MW_KB], rb[MW_KB], fa[MW_KB], fb[MW_KB];
 #pragma unroll
             for (int j = 0; j < MW_KB; ++j) {
-                const int a = tk[k0 + j].x, b = tk[k0 + j].y;
-                A[j] = load_mw(recA, a);
-                B[j] = load_mw(recA, b);
-                la[j] = left[a];
-                ra[j] = right[a];
-                lb[j] = left[b];
-                rb[j] = right[b];
-                fa[j] = node_leaf[a];
-                fb[j] = node_leaf[b];
+                A[j] = load_mw(recA, tk[k0 + j].x);
+                B[j] = load_mw(recA, tk[k0 + j].y);
             }
 #pragma unroll
             for (int j = 0; j < MW_KB; ++j) {
@@ -185,13 +178,14 @@ __global__ __launch_bounds__(256) void k_mw_step(
                 if (r0 + k * 256 + t < nin) {
                     if (separated(A[j], B[j], theta2, r_kern))
                         c = 1;
-                    else if (la[j] < 0 && lb[j] < 0)
+                    else if (A[j].left < 0 && B[j].left < 0)
                         c = 2;
                     else
-                        c = (lb[j] < 0 || (la[j] >= 0 && A[j].s >= B[j].s)) ? 3 : 4;
+                        c = (B[j].left < 0 || (A[j].left >= 0 && A[j].s >= B[j].s)) ? 3 : 4;
                 }
-                outp[k] = c == 2 ? make_int2(fa[j], fb[j])
-                                 : (c == 3 ? make_int2(la[j], ra[j]) : make_int2(lb[j], rb[j]));
+                outp[k] = c == 2 ? make_int2(A[j].leaf, B[j].leaf)
+                                 : (c == 3 ? make_int2(A[j].left, A[j].right)
+                                           : make_int2(B[j].left, B[j].right));
                 code |= (uint64_t)c << (3 * k);
                 num[0] += c == 1 ? 2u : 0u;
                 num[1] += c == 2 ? 2u : 0u;
@@ -348,9 +342,9 @@ hipError_t launch_mutual_walk(Tree &t, hipStream_t s)
         M.cap_task, M.nkeys[0], M.cap_near, t.near_cnt, M.cnt);
     for (int it = 0; it < nit; ++it)
         k_mw_step<<<MW_GRID, 256, 0, s>>>(M.task[it & 1], M.task[(it + 1) & 1], it, M.cap_task,
-                                          t.recA, t.left, t.right, t.node_leaf, theta2,
-                                          t.p.r_kern, bits, lbits, M.fkeys[0], M.cap_far,
-                                          M.nkeys[0], M.cap_near, t.near_cnt, M.cnt);
+                                          t.recA, theta2, t.p.r_kern, bits, lbits,
+                                          M.fkeys[0], M.cap_far, M.nkeys[0], M.cap_near,
+                                          t.near_cnt, M.cnt);
     k_mw_near_max<<<1, 1024, 0, s>>>(t.near_cnt, T.nleaves, M.cnt);
     return hipGetLastError();
 }

@@ -24,17 +24,21 @@ constexpr int WALK_STACK = 96;
 static_assert(COM_MAX_DEPTH + 2 <= WALK_STACK, "narrow walk stack shorter than the deepest tree");
 constexpr int WIDE_STACK = 1024;
 
-// Cell b's centre and size s_b, h_max,b, loaded once per visit.
+// Cell b's centre, size s_b, h_max,b and child ids (left < 0: leaf), read
+// from its one 64-byte record once per visit.
 struct CellRec {
     double c0, c1, c2, sb, hb;
+    int left, right;
 };
 
 __device__ __forceinline__ CellRec load_cell(const double *recA, int b)
 {
     const double *rb = recA + (int64_t)NREC * b;
-    const double4 a = *(const double4 *)rb;
+    const double2 a = *(const double2 *)rb;
+    const double c2 = rb[2];
     const double2 q = *(const double2 *)(rb + 4);
-    return {a.x, a.y, a.z, q.x, q.y};
+    const int2 kids = *(const int2 *)(rb + REC_KIDS);
+    return {a.x, a.y, c2, q.x, q.y, kids.x, kids.y};
 }
 
 __device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, double sa, double ha,
@@ -61,8 +65,7 @@ __device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, doubl
 constexpr int WG = 4;
 
 __global__ __launch_bounds__(256) void k_walk_group(
-    const double *__restrict__ recA, const int32_t *__restrict__ left,
-    const int32_t *__restrict__ right, const int32_t *__restrict__ leaf_node, int nleaves,
+    const double *__restrict__ recA, const int32_t *__restrict__ leaf_node, int nleaves,
     double theta2, double r_kern, int32_t *far_src, int cap_far, int32_t *near_src,
     int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *stack_overflow, int stack_limit)
 {
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(256) void k_walk_group(
         // the record is read once for all leaves of the group (idle lanes
         // read the root's)
         const CellRec cb = load_cell(recA, b);
-        const int lb = left[b], rgt = right[b];
+        const int lb = cb.left, rgt = cb.right;
         uint32_t open = 0;
 #pragma unroll
         for (int g = 0; g < WG; ++g) {
@@ -170,8 +173,7 @@ __global__ __launch_bounds__(256) void k_walk_group(
 // 64 consecutive leaves per wave share one DFS stack whose entries carry the
 // mask of lanes that opened the parent (depth-bounded), writing the same slots.
 __global__ __launch_bounds__(256) void k_walk_p(
-    const double *__restrict__ recA, const int32_t *__restrict__ left,
-    const int32_t *__restrict__ right, const int32_t *__restrict__ leaf_node, int nleaves,
+    const double *__restrict__ recA, const int32_t *__restrict__ leaf_node, int nleaves,
     double theta2, double r_kern, int32_t *far_src, int cap_far, int32_t *near_src,
     int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *maxcnt)
 {
@@ -198,8 +200,8 @@ __global__ __launch_bounds__(256) void k_walk_p(
         --sp;
         const int b = __builtin_amdgcn_readfirstlane(stk_node[w][sp]);
         const uint64_t mask = stk_mask[w][sp];
-        const int lb = left[b];
         const CellRec cb = load_cell(recA, b);
+        const int lb = cb.left;
         const bool active = (mask >> lane) & 1ull;
         bool descend = false;
         if (active) {
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(256) void k_walk_p(
         const uint64_t om = __ballot(descend);
         if (om != 0ull) {
             if (lane == 0) {
-                stk_node[w][sp] = right[b];
+                stk_node[w][sp] = cb.right;
                 stk_mask[w][sp] = om;
                 stk_node[w][sp + 1] = lb;
                 stk_mask[w][sp + 1] = om;
@@ -281,7 +283,7 @@ hipError_t launch_walk(Tree &t, hipStream_t s)
     k_walk_init<<<1, 64, 0, s>>>(t.walk_flags);
     const int groups = (nl + WG - 1) / WG;
     k_walk_group<<<(groups + 3) / 4, 256, 0, s>>>(
-        t.recA, t.left, t.right, t.leaf_node, nl, theta2, t.p.r_kern, t.far_src, (int)t.cap_far,
+        t.recA, t.leaf_node, nl, theta2, t.p.r_kern, t.far_src, (int)t.cap_far,
         t.near_src, (int)t.cap_near, t.far_cnt, t.near_cnt, t.walk_flags + 2,
         std::min(std::max(t.wide_stack_limit, 2), WIDE_STACK));
     k_list_max<<<std::min(LIST_MAX_BLOCKS, (nl + 1023) / 1024), 1024, 0, s>>>(t.far_cnt, t.near_cnt,
@@ -294,7 +296,7 @@ hipError_t launch_walk_fallback(Tree &t, hipStream_t s)
     const Topology &T = t.topo;
     const double theta2 = t.p.theta * t.p.theta;
     const int nl = T.nleaves;
-    k_walk_p<<<(nl + 255) / 256, 256, 0, s>>>(t.recA, t.left, t.right, t.leaf_node, nl, theta2,
+    k_walk_p<<<(nl + 255) / 256, 256, 0, s>>>(t.recA, t.leaf_node, nl, theta2,
                                                t.p.r_kern, t.far_src, (int)t.cap_far, t.near_src,
                                                (int)t.cap_near, t.far_cnt, t.near_cnt,
                                                t.walk_flags);
