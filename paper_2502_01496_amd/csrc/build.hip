@@ -155,9 +155,11 @@ __global__ void k_rank_gather(const double *__restrict__ x, int64_t n, const uin
 // ---------------------------------------------------------------- radix sort
 // Stable LSD radix sort of B independent (key u64, value u32) arrays of
 // length n laid out back to back.  Per 8-bit pass: per-tile digit histograms,
-// a scan per (digit, array) over the tiles, then a stable scatter.  Inside a
-// tile the 16 waves take consecutive sixteenths; a wave ranks its 64 keys of a
-// round with ballot-based digit matching, so rank order = input order.
+// a scan per (digit, array) over the tiles that also stores the digit's
+// total, then a stable scatter that adds the digit bases (a scan of the 256
+// totals in LDS, so no tile updates a shared counter).  Inside a tile the 16
+// waves take consecutive sixteenths; a wave ranks its 64 keys of a round with
+// ballot-based digit matching, so rank order = input order.
 __global__ void k_rs_zero(uint32_t *p, int64_t cnt)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
@@ -167,8 +169,7 @@ __global__ void k_rs_zero(uint32_t *p, int64_t cnt)
 
 template <typename K>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const K *__restrict__ keys, int64_t n,
-                                                        int shift, uint32_t *hist, uint32_t *tot,
-                                                        int nblk)
+                                                        int shift, uint32_t *hist, int nblk)
 {
     __shared__ uint32_t h[256];
     int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
@@ -187,12 +188,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const K *__restrict__ ke
         if (base + r * RS_THREADS + t < n)
             atomicAdd(&h[(uint32_t)(kr[r] >> shift) & 255u], 1u);
     __syncthreads();
-    if (t < 256) {
-        uint32_t c = h[t];
-        hist[((int64_t)b * 256 + t) * nblk + blk] = c;
-        if (c)
-            atomicAdd(&tot[b * 256 + t], c);
-    }
+    if (t < 256)
+        hist[((int64_t)b * 256 + t) * nblk + blk] = h[t];
 }
 
 // Exclusive scan across one block of up to 256 threads (values <= 2^32).
@@ -220,16 +217,15 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *sh
     return wbase + inc - v;
 }
 
-__global__ __launch_bounds__(RS_SCAN_THREADS) void k_rs_scan(uint32_t *hist, const uint32_t *tot,
+// Row (digit d of array b) of the tile histograms -> offsets of the tiles
+// within the digit's output run; the row total goes to tot.
+__global__ __launch_bounds__(RS_SCAN_THREADS) void k_rs_scan(uint32_t *hist, uint32_t *tot,
                                                              int nblk)
 {
     __shared__ uint32_t sh[8];
     int d = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
-    uint32_t mine = t < d ? tot[b * 256 + t] : 0u;
-    uint32_t base;
-    block_excl_scan_u32(mine, sh, base);
     uint32_t *row = hist + ((int64_t)b * 256 + d) * nblk;
-    uint32_t run = base;
+    uint32_t run = 0;
     for (int c0 = 0; c0 < nblk; c0 += RS_SCAN_THREADS) {
         int i = c0 + t;
         uint32_t v = i < nblk ? row[i] : 0u;
@@ -239,6 +235,8 @@ __global__ __launch_bounds__(RS_SCAN_THREADS) void k_rs_scan(uint32_t *hist, con
             row[i] = run + ex;
         run += total;
     }
+    if (t == 0)
+        tot[b * 256 + d] = run;
 }
 
 __device__ __forceinline__ uint64_t match_u8(uint32_t d, bool valid)
@@ -260,14 +258,15 @@ __device__ __forceinline__ uint64_t match_u8(uint32_t d, bool valid)
 template <typename K>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *kout, uint32_t *vout,
-    int64_t n, int shift, const uint32_t *__restrict__ hist, int nblk)
+    int64_t n, int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
+    int nblk)
 {
     __shared__ K skey[RS_TILE];
     __shared__ uint32_t sval[RS_TILE];
     __shared__ uint16_t wrun[RS_WAVES][256];
     __shared__ uint32_t loff[256];
     __shared__ uint32_t gofs[256];
-    __shared__ uint32_t wtot[4];
+    __shared__ uint32_t wtot[4], wtot2[4];
     const int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = lane_id();
     for (int i = t; i < RS_WAVES * 256; i += RS_THREADS)
         (&wrun[0][0])[i] = 0;
@@ -287,8 +286,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         key[r] = i < nv ? k[tile0 + i] : K(0);
         val[r] = (v && i < nv) ? v[tile0 + i] : 0u;
     }
-    // this tile's global digit offsets, loaded while the keys are in flight
+    // this tile's offsets within the digit runs and the digit totals, loaded
+    // while the keys are in flight
     const uint32_t gofs_t = t < 256 ? hist[((int64_t)b * 256 + t) * nblk + blk] : 0u;
+    const uint32_t dtot = t < 256 ? tot[b * 256 + t] : 0u;
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const bool valid = wbase + r * 64 + lane < nv;
@@ -309,24 +310,33 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
             wrun[i][t] = (uint16_t)cnt;
             cnt += c;
         }
-        gofs[t] = gofs_t;
-        uint32_t inc = cnt;
+        // exclusive scans over the digits: tile-local offsets (of cnt) and
+        // the digit bases (of the totals)
+        uint32_t inc = cnt, inc2 = dtot;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t o = __shfl_up(inc, off);
-            if (lane >= off)
+            const uint32_t o = __shfl_up(inc, off), o2 = __shfl_up(inc2, off);
+            if (lane >= off) {
                 inc += o;
+                inc2 += o2;
+            }
         }
-        if (lane == 63)
+        if (lane == 63) {
             wtot[w] = inc;
+            wtot2[w] = inc2;
+        }
         loff[t] = inc - cnt;
+        gofs[t] = gofs_t + (inc2 - dtot);
     }
     __syncthreads();
     if (t < 256) {
-        uint32_t add = 0;
-        for (int i = 0; i < w; ++i)
+        uint32_t add = 0, add2 = 0;
+        for (int i = 0; i < w; ++i) {
             add += wtot[i];
+            add2 += wtot2[i];
+        }
         loff[t] += add;
+        gofs[t] += add2;
     }
     __syncthreads();
 #pragma unroll
@@ -362,16 +372,15 @@ static hipError_t radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n
     int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
     if (nblk == 0)
         return hipSuccess;
-    k_rs_zero<<<64, 256, 0, s>>>(tot, (int64_t)passes * B * 256);
     for (int pass = 0; pass < passes; ++pass) {
         int shift = 8 * pass;
         K *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
         uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
         uint32_t *tp = tot + (int64_t)pass * B * 256;
         dim3 g(nblk, B);
-        k_rs_hist<K><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
+        k_rs_hist<K><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
         k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<K><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
+        k_rs_scatter<K><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp, nblk);
     }
     return hipGetLastError();
 }
@@ -577,7 +586,6 @@ hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
     if (nblk == 0)
         return hipSuccess;
     const int64_t long_cap = (int64_t)B * (n / (RUN_SHORT + 1) + 1);
-    k_rs_zero<<<64, 256, 0, s>>>(tot, (int64_t)4 * B * 256);
     k_rs_zero<<<1, 64, 0, s>>>(long_cnt, 2);
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 32 + 8 * pass;
@@ -585,9 +593,10 @@ hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
         uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
         uint32_t *tp = tot + (int64_t)pass * B * 256;
         dim3 g(nblk, B);
-        k_rs_hist<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, tp, nblk);
+        k_rs_hist<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
         k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
+        k_rs_scatter<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp,
+                                                         nblk);
     }
     const int gf = (int)std::min<int64_t>((n + 255) / 256, 4096);
     k_run_fix<<<dim3(gf, B), 256, 0, s>>>(k0, v0, k1, v1, n, long_cnt, long_list, long_cap, err);
