@@ -138,7 +138,7 @@ __device__ __forceinline__ void block_append3(const uint32_t (&v)[3],
 // A workgroup takes MW_K x 256 consecutive pairs per round: it classifies
 // them (far / near / split A / split B), reserves the outputs of the whole
 // round with one atomic per output buffer, then writes them.
-constexpr int MW_K = 8;
+constexpr int MW_K = 4;
 constexpr int MW_KB = 2;  // pairs whose loads are in flight together (more raise the
                           // register count and cost occupancy)
 
