@@ -124,6 +124,50 @@ void build_topology(int64_t n, int leaf_size, Topology &T)
         T.lvl_int_off.push_back((int32_t)T.int_nodes.size());
     }
     T.nbig = (int)T.big_nodes.size();
+    // subtree moments: a subtree's nodes are the pre-order ids [r, r + size)
+    // and its leaves a contiguous run of leaf indices
+    T.sub_moments = true;
+    for (int32_t r : T.sub_root) {
+        int32_t lo = r, hi = r;
+        while (T.left[lo] >= 0)
+            lo = T.left[lo];
+        while (T.right[hi] >= 0)
+            hi = T.right[hi];
+        const int32_t size = hi - r + 1;
+        if (size > SM_MAXNODES) {
+            T.sub_moments = false;
+            break;
+        }
+        T.sm_leaf.push_back(T.node_leaf[lo]);
+        T.sm_leaf.push_back(T.node_leaf[hi] + 1);
+        std::vector<std::vector<int32_t>> g(SM_MAXL);
+        for (int32_t v = r; v <= hi; ++v)
+            if (T.left[v] >= 0) {
+                const int d = T.level[v] - T.level[r];
+                if (d >= SM_MAXL) {
+                    T.sub_moments = false;
+                    break;
+                }
+                g[d].push_back(v);
+            }
+        if (!T.sub_moments)
+            break;
+        for (int d = SM_MAXL - 1; d >= 0; --d) {
+            T.sm_lvl.push_back((int32_t)(T.sm_nodes.size() / 2));
+            for (int32_t v : g[d]) {
+                T.sm_nodes.push_back(v);
+                T.sm_nodes.push_back(T.right[v]);
+            }
+        }
+        T.sm_lvl.push_back((int32_t)(T.sm_nodes.size() / 2));
+    }
+    T.top_lvl_off.assign(1, 0);
+    for (int l = 0; l < T.depth; ++l) {
+        for (int32_t v : byl[l])
+            if (T.count[v] > SUBTREE_MAX)
+                T.top_nodes.push_back(v);
+        T.top_lvl_off.push_back((int32_t)T.top_nodes.size());
+    }
     T.node_cap = T.nnodes;
     T.leaf_cap = T.nleaves;
 }
@@ -265,6 +309,10 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
         A(upload(*t, &t->sub_root, T.sub_root));
         A(upload(*t, &t->int_nodes, T.int_nodes));
         A(upload(*t, &t->big_nodes, T.big_nodes));
+        A(upload(*t, &t->sm_leaf, T.sm_leaf));
+        A(upload(*t, &t->sm_lvl, T.sm_lvl));
+        A(upload(*t, &t->sm_nodes, T.sm_nodes));
+        A(upload(*t, &t->top_nodes, T.top_nodes));
     }
     const Topology &T = t->topo;
     const int64_t nn = T.node_cap;

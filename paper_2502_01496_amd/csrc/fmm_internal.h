@@ -17,6 +17,8 @@ namespace fmm {
 constexpr int SUBTREE_MAX = 2048;
 constexpr int SUBTREE_MAXSEG = SUBTREE_MAX / 2;
 constexpr int SUBTREE_THREADS = 1024;
+constexpr int SM_MAXNODES = 1024;  // nodes of a subtree whose moments are combined in LDS
+constexpr int SM_MAXL = 16;        // internal levels of such a subtree
 // Positions handled by one workgroup in the per-level partition kernels.
 constexpr int LVL_CHUNK = 2048;
 constexpr int LVL_THREADS = 256;
@@ -140,6 +142,16 @@ struct Topology {
     std::vector<int32_t> lvl_int_off;  // depth + 1
     std::vector<int32_t> int_nodes;
     std::vector<int32_t> big_nodes;    // nodes of at least 64 particles
+    // moments of the LDS subtrees in one launch (sub_moments): per subtree
+    // its leaf range, its internal nodes as (node, right child) grouped by
+    // level, deepest first (group k of subtree s starts at
+    // sm_lvl[s * (SM_MAXL + 1) + k]), and the nodes above the subtrees by
+    // level; sub_moments is false when a subtree has more than SM_MAXNODES
+    // nodes
+    bool sub_moments = false;
+    std::vector<int32_t> sm_leaf, sm_lvl, sm_nodes;
+    std::vector<int32_t> top_lvl_off;  // depth + 1
+    std::vector<int32_t> top_nodes;
 };
 
 void build_topology(int64_t n, int leaf_size, Topology &t);
@@ -185,6 +197,7 @@ struct Tree {
     int32_t *parent = nullptr, *level = nullptr, *leaf_node = nullptr, *node_leaf = nullptr;
     int32_t *blk_node = nullptr, *blk_start = nullptr, *blk_end = nullptr, *blk_first = nullptr;
     int32_t *sub_root = nullptr, *axis = nullptr, *int_nodes = nullptr;
+    int32_t *sm_leaf = nullptr, *sm_lvl = nullptr, *sm_nodes = nullptr, *top_nodes = nullptr;
 
     // build workspace
     uint64_t *keys0 = nullptr, *keys1 = nullptr;  // 3n each (batched sorts)

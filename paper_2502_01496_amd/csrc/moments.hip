@@ -72,16 +72,15 @@ __device__ __forceinline__ void quad_add(double *Q, double w, double y0, double 
     Q[5] += w * (3.0 * y2 * y2 - yy);
 }
 
-// P2M at the leaves: one thread per leaf.
-__global__ __launch_bounds__(256) void k_leaf_moments(
-    const double4 *__restrict__ pm, const double *__restrict__ hs,
-    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ first,
-    const int32_t *__restrict__ count, double *recA, double *recQ, int want_fp32, float4 *pf)
+// P2M of leaf v (node id): M, c, h_max and the quadrupole about c, written to
+// its records; the values are also returned for a caller that combines them.
+__device__ __forceinline__ void leaf_p2m(const double4 *__restrict__ pm,
+                                         const double *__restrict__ hs, int v,
+                                         const int32_t *__restrict__ first,
+                                         const int32_t *__restrict__ count, double *recA,
+                                         double *recQ, int want_fp32, float4 *pf, double *outA,
+                                         double *outQ)
 {
-    int lf = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lf >= nleaves)
-        return;
-    int v = leaf_node[lf];
     int64_t f = first[v];
     int c = count[v];
     // particles are read U at a time, all loads in flight together (indices
@@ -132,26 +131,39 @@ __global__ __launch_bounds__(256) void k_leaf_moments(
     double *rq = recQ + (int64_t)NREC * v;
     for (int k = 0; k < 6; ++k)
         rq[k] = Q[k];
+    outA[0] = c0;
+    outA[1] = c1;
+    outA[2] = c2;
+    outA[3] = M;
+    outA[4] = hm;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        outQ[k] = Q[k];
+}
+
+// P2M at the leaves: one thread per leaf.
+__global__ __launch_bounds__(256) void k_leaf_moments(
+    const double4 *__restrict__ pm, const double *__restrict__ hs,
+    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ first,
+    const int32_t *__restrict__ count, double *recA, double *recQ, int want_fp32, float4 *pf)
+{
+    int lf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves)
+        return;
+    double a[5], q[6];
+    leaf_p2m(pm, hs, leaf_node[lf], first, count, recA, recQ, want_fp32, pf, a, q);
 }
 
 // M2M for the internal nodes of one level (children were done by the
 // previous launch): M = M_L + M_R, c = (M_L c_L + M_R c_R) / M, quadrupole by
 // the parallel-axis shift of both children, h_max = max of the children.
-__global__ __launch_bounds__(256) void k_combine_level(const int32_t *__restrict__ nodes, int cnt,
-                                                       const int32_t *__restrict__ left,
-                                                       const int32_t *__restrict__ right,
-                                                       double *recA, double *recQ)
+// Parent from its two children: al / ar = (c0, c1, c2, M, h_max), ql / qr the
+// quadrupoles; the parent's record is written to pa (5 values) and pq.
+__device__ __forceinline__ void combine2(const double *al, const double *ql, const double *ar,
+                                         const double *qr, double *pa, double *pq)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= cnt)
-        return;
-    const int p = nodes[k];
-    const int l = left[p], r = right[p];
-    const double *al = recA + (int64_t)NREC * l, *ar = recA + (int64_t)NREC * r;
-    const double *ql = recQ + (int64_t)NREC * l, *qr = recQ + (int64_t)NREC * r;
-    const double4 A = *(const double4 *)al, B = *(const double4 *)ar;
-    const double Ml = A.w, Mr = B.w;
-    const double cl[3] = {A.x, A.y, A.z}, cr[3] = {B.x, B.y, B.z};
+    const double Ml = al[3], Mr = ar[3];
+    const double cl[3] = {al[0], al[1], al[2]}, cr[3] = {ar[0], ar[1], ar[2]};
     const double Mp = Ml + Mr;
     double cp[3];
     for (int d = 0; d < 3; ++d)
@@ -163,13 +175,84 @@ __global__ __launch_bounds__(256) void k_combine_level(const int32_t *__restrict
     for (int j = 0; j < 6; ++j)
         Qp[j] += qr[j];
     quad_add(Qp, Mr, cr[0] - cp[0], cr[1] - cp[1], cr[2] - cp[2]);
-    const double hl = al[5], hr = ar[5];
-    double *pa = recA + (int64_t)NREC * p;
-    *(double4 *)pa = make_double4(cp[0], cp[1], cp[2], Mp);
-    pa[5] = hl > hr ? hl : hr;
-    double *pq = recQ + (int64_t)NREC * p;
+    const double hl = al[4], hr = ar[4];
+    pa[0] = cp[0];
+    pa[1] = cp[1];
+    pa[2] = cp[2];
+    pa[3] = Mp;
+    pa[4] = hl > hr ? hl : hr;
     for (int j = 0; j < 6; ++j)
         pq[j] = Qp[j];
+}
+
+__device__ __forceinline__ void store_rec(double *recA, double *recQ, int p, const double *a,
+                                          const double *q)
+{
+    double *ra = recA + (int64_t)NREC * p;
+    *(double4 *)ra = make_double4(a[0], a[1], a[2], a[3]);
+    ra[5] = a[4];
+    double *rq = recQ + (int64_t)NREC * p;
+    for (int j = 0; j < 6; ++j)
+        rq[j] = q[j];
+}
+
+__global__ __launch_bounds__(256) void k_combine_level(const int32_t *__restrict__ nodes, int cnt,
+                                                       const int32_t *__restrict__ left,
+                                                       const int32_t *__restrict__ right,
+                                                       double *recA, double *recQ)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= cnt)
+        return;
+    const int p = nodes[k];
+    const int l = left[p], r = right[p];
+    const double *ral = recA + (int64_t)NREC * l, *rar = recA + (int64_t)NREC * r;
+    const double4 A = *(const double4 *)ral, B = *(const double4 *)rar;
+    const double al[5] = {A.x, A.y, A.z, A.w, ral[5]}, ar[5] = {B.x, B.y, B.z, B.w, rar[5]};
+    double ql[6], qr[6];
+    for (int j = 0; j < 6; ++j) {
+        ql[j] = recQ[(int64_t)NREC * l + j];
+        qr[j] = recQ[(int64_t)NREC * r + j];
+    }
+    double pa[5], pq[6];
+    combine2(al, ql, ar, qr, pa, pq);
+    store_rec(recA, recQ, p, pa, pq);
+}
+
+// All moments of one LDS subtree (cells of at most SUBTREE_MAX particles)
+// per workgroup: P2M of its leaves, then its internal cells level by level,
+// deepest first, the children read from LDS (a subtree's cells are the
+// pre-order ids [r, r + size), at most SM_MAXNODES of them).  The same
+// operations in the same order as k_leaf_moments and k_combine_level.
+__global__ __launch_bounds__(256) void k_sub_moments(
+    const double4 *__restrict__ pm, const double *__restrict__ hs,
+    const int32_t *__restrict__ leaf_node, const int32_t *__restrict__ first,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ sub_root,
+    const int32_t *__restrict__ sm_leaf, const int32_t *__restrict__ sm_lvl,
+    const int2 *__restrict__ sm_nodes, double *recA, double *recQ, int want_fp32, float4 *pf)
+{
+    __shared__ double sA[SM_MAXNODES][5];
+    __shared__ double sQ[SM_MAXNODES][6];
+    const int s = blockIdx.x, t = threadIdx.x;
+    const int r = sub_root[s];
+    const int lf0 = sm_leaf[2 * s], lf1 = sm_leaf[2 * s + 1];
+    for (int lf = lf0 + t; lf < lf1; lf += 256) {
+        const int v = leaf_node[lf];
+        leaf_p2m(pm, hs, v, first, count, recA, recQ, want_fp32, pf, sA[v - r], sQ[v - r]);
+    }
+    const int32_t *g = sm_lvl + s * (SM_MAXL + 1);
+    for (int k = 0; k < SM_MAXL; ++k) {
+        const int g0 = g[k], g1 = g[k + 1];
+        if (g0 == g1)
+            continue;
+        __syncthreads();
+        for (int i = g0 + t; i < g1; i += 256) {
+            const int2 e = sm_nodes[i];
+            const int p = e.x, l = p + 1, rr = e.y;  // pre-order: left child = p + 1
+            combine2(sA[l - r], sQ[l - r], sA[rr - r], sQ[rr - r], sA[p - r], sQ[p - r]);
+            store_rec(recA, recQ, p, sA[p - r], sQ[p - r]);
+        }
+    }
 }
 
 // Exact s^2 per node, phase 1: one thread per particle walks root -> leaf.
@@ -309,14 +392,26 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
     int want32 = t.p.precision == FMM_FP32;
     k_gather<<<gs, 256, 0, s>>>(x, m, h, n, t.perm, t.pm, t.hs, t.ph, t.err, T.nnodes, t.s2bits,
                                 t.upcnt, want32, t.pfh);
-    k_leaf_moments<<<(T.nleaves + 255) / 256, 256, 0, s>>>(t.pm, t.hs, t.leaf_node, T.nleaves,
-                                                           t.first, t.count, t.recA, t.recQ,
-                                                           want32, t.pf);
-    for (int l = T.depth - 2; l >= 0; --l) {
-        int o = T.lvl_int_off[l], cnt = T.lvl_int_off[l + 1] - o;
-        if (cnt > 0)
-            k_combine_level<<<(cnt + 255) / 256, 256, 0, s>>>(t.int_nodes + o, cnt, t.left,
-                                                              t.right, t.recA, t.recQ);
+    if (!T.com && T.sub_moments) {
+        // the subtrees in one launch, then the cells above them level by level
+        k_sub_moments<<<(int)T.sub_root.size(), 256, 0, s>>>(
+            t.pm, t.hs, t.leaf_node, t.first, t.count, t.sub_root, t.sm_leaf, t.sm_lvl,
+            (const int2 *)t.sm_nodes, t.recA, t.recQ, want32, t.pf);
+        for (int l = T.depth - 2; l >= 0; --l) {
+            int o = T.top_lvl_off[l], cnt = T.top_lvl_off[l + 1] - o;
+            if (cnt > 0)
+                k_combine_level<<<(cnt + 255) / 256, 256, 0, s>>>(t.top_nodes + o, cnt, t.left,
+                                                                  t.right, t.recA, t.recQ);
+        }
+    } else {
+        k_leaf_moments<<<(T.nleaves + 255) / 256, 256, 0, s>>>(
+            t.pm, t.hs, t.leaf_node, T.nleaves, t.first, t.count, t.recA, t.recQ, want32, t.pf);
+        for (int l = T.depth - 2; l >= 0; --l) {
+            int o = T.lvl_int_off[l], cnt = T.lvl_int_off[l + 1] - o;
+            if (cnt > 0)
+                k_combine_level<<<(cnt + 255) / 256, 256, 0, s>>>(t.int_nodes + o, cnt, t.left,
+                                                                  t.right, t.recA, t.recQ);
+        }
     }
     const int64_t nwaves = (n + 63) / 64;
     k_node_s2<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, t.first, t.count, t.left,
