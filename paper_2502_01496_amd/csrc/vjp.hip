@@ -960,22 +960,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const int ne = stage_blocks(tsrc + e0, c0, nc, nsub, first, count, recA, rv, r_kern,
                                         lane, R, front, gap);
             __builtin_amdgcn_wave_barrier();
-            // the next step's sink particles (position, smoothing, adjoint)
-            // load while the current step computes
             int64_t i = block_particle(R[skip_gap(grp, front, gap)], slot, nnull);
             double4 xi = pm[i], hi = ph[i];
-            double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
             for (int kb = 0; kb < ne; kb += 8) {
+                const double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
                 int64_t in = i;
                 double4 xn = xi, hn = hi;
-                double an0 = ai0, an1 = ai1, an2 = ai2;
                 if (kb + 8 < ne) {
                     in = block_particle(R[skip_gap(kb + 8 + grp, front, gap)], slot, nnull);
                     xn = pm[in];
                     hn = ph[in];
-                    an0 = abt[3 * in];
-                    an1 = abt[3 * in + 1];
-                    an2 = abt[3 * in + 2];
                 }
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
@@ -995,9 +989,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 i = in;
                 xi = xn;
                 hi = hn;
-                ai0 = an0;
-                ai1 = an1;
-                ai2 = an2;
             }
             __builtin_amdgcn_wave_barrier();
         }
