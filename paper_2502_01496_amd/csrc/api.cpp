@@ -168,6 +168,37 @@ void build_topology(int64_t n, int leaf_size, Topology &T)
                 T.top_nodes.push_back(v);
         T.top_lvl_off.push_back((int32_t)T.top_nodes.size());
     }
+    {
+        const size_t nslots = T.sub_root.size() + T.top_nodes.size();
+        T.top_fused = T.sub_moments && nslots <= (size_t)SM_MAXNODES;
+        if (T.top_fused) {
+            std::vector<int32_t> slot(T.nnodes, -1);
+            for (int32_t r : T.sub_root) {
+                slot[r] = (int32_t)T.top_slot_node.size();
+                T.top_slot_node.push_back(r);
+            }
+            for (int l = T.depth - 1; l >= 0; --l)
+                for (int k = T.top_lvl_off[l]; k < T.top_lvl_off[l + 1]; ++k) {
+                    slot[T.top_nodes[k]] = (int32_t)T.top_slot_node.size();
+                    T.top_slot_node.push_back(T.top_nodes[k]);
+                }
+            for (int l = T.depth - 1; l >= 0; --l) {
+                if (T.top_lvl_off[l + 1] == T.top_lvl_off[l])
+                    continue;
+                T.top_grp.push_back((int32_t)(T.top_task.size() / 3));
+                for (int k = T.top_lvl_off[l]; k < T.top_lvl_off[l + 1]; ++k) {
+                    const int32_t v = T.top_nodes[k];
+                    // a child is either above the subtrees or a subtree root
+                    if (slot[T.left[v]] < 0 || slot[T.right[v]] < 0)
+                        T.top_fused = false;
+                    T.top_task.push_back(v);
+                    T.top_task.push_back(slot[T.left[v]]);
+                    T.top_task.push_back(slot[T.right[v]]);
+                }
+            }
+            T.top_grp.push_back((int32_t)(T.top_task.size() / 3));
+        }
+    }
     T.node_cap = T.nnodes;
     T.leaf_cap = T.nleaves;
 }
@@ -313,6 +344,9 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
         A(upload(*t, &t->sm_lvl, T.sm_lvl));
         A(upload(*t, &t->sm_nodes, T.sm_nodes));
         A(upload(*t, &t->top_nodes, T.top_nodes));
+        A(upload(*t, &t->top_slot_node, T.top_slot_node));
+        A(upload(*t, &t->top_task, T.top_task));
+        A(upload(*t, &t->top_grp, T.top_grp));
     }
     const Topology &T = t->topo;
     const int64_t nn = T.node_cap;

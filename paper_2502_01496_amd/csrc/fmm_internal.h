@@ -152,6 +152,15 @@ struct Topology {
     std::vector<int32_t> sm_leaf, sm_lvl, sm_nodes;
     std::vector<int32_t> top_lvl_off;  // depth + 1
     std::vector<int32_t> top_nodes;
+    // the cells above the subtrees combined by one workgroup through LDS
+    // (when the subtree roots and those cells fit SM_MAXNODES slots): slots
+    // [0, nsub) hold the subtree roots, then the cells above them deepest
+    // level first; per such cell (node, left slot, right slot), grouped by
+    // level (top_grp offsets)
+    bool top_fused = false;
+    std::vector<int32_t> top_slot_node;  // node id per slot
+    std::vector<int32_t> top_task;       // (node, left slot, right slot) per cell
+    std::vector<int32_t> top_grp;        // group offsets into top_task / 3
 };
 
 void build_topology(int64_t n, int leaf_size, Topology &t);
@@ -198,6 +207,7 @@ struct Tree {
     int32_t *blk_node = nullptr, *blk_start = nullptr, *blk_end = nullptr, *blk_first = nullptr;
     int32_t *sub_root = nullptr, *axis = nullptr, *int_nodes = nullptr;
     int32_t *sm_leaf = nullptr, *sm_lvl = nullptr, *sm_nodes = nullptr, *top_nodes = nullptr;
+    int32_t *top_slot_node = nullptr, *top_task = nullptr, *top_grp = nullptr;
 
     // build workspace
     uint64_t *keys0 = nullptr, *keys1 = nullptr;  // 3n each (batched sorts)

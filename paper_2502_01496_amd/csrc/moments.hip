@@ -255,6 +255,40 @@ __global__ __launch_bounds__(256) void k_sub_moments(
     }
 }
 
+// The cells above the LDS subtrees in one workgroup: the subtree roots'
+// records (from k_sub_moments) are loaded into LDS slots [0, nroots), then
+// the cells are combined level by level, deepest first, cell k of the task
+// list into slot nroots + k (the same operations as k_combine_level).
+__global__ __launch_bounds__(1024) void k_top_moments(const int32_t *__restrict__ slot_node,
+                                                      int nroots, const int32_t *__restrict__ task,
+                                                      const int32_t *__restrict__ grp, int ngrp,
+                                                      double *recA, double *recQ)
+{
+    __shared__ double sA[SM_MAXNODES][5];
+    __shared__ double sQ[SM_MAXNODES][6];
+    const int t = threadIdx.x;
+    for (int i = t; i < nroots; i += 1024) {
+        const int v = slot_node[i];
+        const double *ra = recA + (int64_t)NREC * v;
+        sA[i][0] = ra[0];
+        sA[i][1] = ra[1];
+        sA[i][2] = ra[2];
+        sA[i][3] = ra[3];
+        sA[i][4] = ra[5];
+        for (int j = 0; j < 6; ++j)
+            sQ[i][j] = recQ[(int64_t)NREC * v + j];
+    }
+    for (int g = 0; g < ngrp; ++g) {
+        __syncthreads();
+        const int k1 = grp[g + 1];
+        for (int k = grp[g] + t; k < k1; k += 1024) {
+            const int p = task[3 * k], ls = task[3 * k + 1], rs = task[3 * k + 2];
+            combine2(sA[ls], sQ[ls], sA[rs], sQ[rs], sA[nroots + k], sQ[nroots + k]);
+            store_rec(recA, recQ, p, sA[nroots + k], sQ[nroots + k]);
+        }
+    }
+}
+
 // Exact s^2 per node, phase 1: one thread per particle walks root -> leaf.
 // At each level, a wavefront whose 64 particles all lie in one node writes
 // its maximum to part[level][wave]; otherwise the lanes of each node reduce
@@ -397,11 +431,18 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
         k_sub_moments<<<(int)T.sub_root.size(), 256, 0, s>>>(
             t.pm, t.hs, t.leaf_node, t.first, t.count, t.sub_root, t.sm_leaf, t.sm_lvl,
             (const int2 *)t.sm_nodes, t.recA, t.recQ, want32, t.pf);
-        for (int l = T.depth - 2; l >= 0; --l) {
-            int o = T.top_lvl_off[l], cnt = T.top_lvl_off[l + 1] - o;
-            if (cnt > 0)
-                k_combine_level<<<(cnt + 255) / 256, 256, 0, s>>>(t.top_nodes + o, cnt, t.left,
-                                                                  t.right, t.recA, t.recQ);
+        if (T.top_fused) {
+            if (!T.top_nodes.empty())
+                k_top_moments<<<1, 1024, 0, s>>>(t.top_slot_node, (int)T.sub_root.size(),
+                                                 t.top_task, t.top_grp,
+                                                 (int)T.top_grp.size() - 1, t.recA, t.recQ);
+        } else {
+            for (int l = T.depth - 2; l >= 0; --l) {
+                int o = T.top_lvl_off[l], cnt = T.top_lvl_off[l + 1] - o;
+                if (cnt > 0)
+                    k_combine_level<<<(cnt + 255) / 256, 256, 0, s>>>(
+                        t.top_nodes + o, cnt, t.left, t.right, t.recA, t.recQ);
+            }
         }
     } else {
         k_leaf_moments<<<(T.nleaves + 255) / 256, 256, 0, s>>>(
