@@ -8,6 +8,12 @@
 //   k_combine_level one launch per tree level, deepest first: parents from
 //                their two children -- M = M_L + M_R, c = (M_L c_L + M_R c_R) / M,
 //                Q by the parallel-axis shift, h_max = max.
+//   k_sub_moments / k_top_moments  the same two steps for the median-split
+//                tree in two launches: one workgroup per subtree of at most
+//                SUBTREE_MAX particles (its leaves, then its levels through
+//                LDS), then one workgroup for the cells above the subtrees
+//                when they fit LDS (per-level launches otherwise); the
+//                centre-of-mass tree takes k_leaf_moments + k_combine_level.
 //   k_node_s2    s^2 = max over the node's particles of |x - c|^2, exactly:
 //                one thread per particle walks root -> leaf; lanes on the same
 //                node reduce with a segmented wave max, then one u64 atomicMax
