@@ -333,18 +333,24 @@ __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm,
         }
         const int k0 = __shfl(key, 0);
         const bool uniform = __ballot(key == k0 && key >= 0) == ~0ull;
-        // segmented inclusive max over runs of equal key (runs are contiguous)
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            uint64_t ov = __shfl_up(val, off);
-            int ok = __shfl_up(key, off);
-            if (lane >= off && ok == key)
-                val = ov > val ? ov : val;
-        }
         if (uniform) {
+            // one node for the whole wavefront: a butterfly max
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const uint64_t ov = __shfl_xor(val, off);
+                val = ov > val ? ov : val;
+            }
             if (lane == 63)
                 part[(int64_t)lvl * nwaves + wave] = val;
         } else {
+            // segmented inclusive max over runs of equal key (runs are contiguous)
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                uint64_t ov = __shfl_up(val, off);
+                int ok = __shfl_up(key, off);
+                if (lane >= off && ok == key)
+                    val = ov > val ? ov : val;
+            }
             int nk = __shfl_down(key, 1);
             bool tail = (lane == 63) || (nk != key);
             if (!done && tail)
