@@ -993,14 +993,21 @@ __global__ __launch_bounds__(SUBTREE_THREADS) void k_subtree(
         nseg = nseg_sh[cur];
     }
 
-    // leaves: members in ascending local id (= ascending Morton rank)
+    // leaves: members in ascending local id (= ascending Morton rank).  The
+    // leaf holding position p follows from the split rule alone (the left
+    // child takes the first ceil(c / 2) positions; a cell of more than
+    // leaf_size particles splits), so it is found without memory reads.
     for (int p = t; p < n0; p += SUBTREE_THREADS) {
-        int v = root;
-        while (left[v] >= 0) {
-            int l = left[v];
-            v = (f0 + p < first[l] + count[l]) ? l : right[v];
+        int lf = 0, ln = n0;
+        while (ln > leaf_size) {
+            const int nl = (ln + 1) >> 1;
+            if (p < lf + nl) {
+                ln = nl;
+            } else {
+                lf += nl;
+                ln -= nl;
+            }
         }
-        int lf = (int)(first[v] - f0), ln = count[v];
         uint16_t me = lst[cur][0][p];
         int rank = 0;
         for (int q = 0; q < ln; ++q)
