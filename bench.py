@@ -208,11 +208,18 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
         F.fmm_moments(g.tree, x, m, h)
         F.fmm_forces(g.tree, a, F.FMM_REWALK)
 
-    def step():
+    # momentum statistics of every timed step, gathered on the device and
+    # read once after the timed region
+    stats_buf = torch.zeros((max(steps, 1), 16), dtype=torch.float64, device=dev)
+
+    def step(i=None):
         F.fmm_kick_drift(x, v, a, 0.5 * dt, dt)
         forces()
         F.fmm_kick_drift(x, v, a, 0.5 * dt, 0.0)
-        return F.fmm_momentum_stats(x, v, m, a)
+        if i is None:
+            return F.fmm_momentum_stats(x, v, m, a)
+        F.fmm_momentum_stats_async(x, v, m, a, stats_buf[i])
+        return None
 
     forces()
     st0 = F.fmm_momentum_stats(x, v, m, a)
@@ -220,15 +227,15 @@ def run_one(args, x_np, m_np, h_np, prec, census=True, walk=0, steps=None):
         step()
     torch.cuda.synchronize()
     F.fmm_set_timing(g.tree, True)
-    ratios, xcom = [], []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(steps):
-        st = step()
-        ratios.append(st["ratio"])
-        xcom.append(st["xcom"])
+    for i in range(steps):
+        step(i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
+    sb = stats_buf[:steps].cpu().numpy()
+    ratios = [float(r) for r in sb[:, 4]]
+    xcom = [sb[k, 6:9].copy() for k in range(steps)]
     stages = F.fmm_stage_times(g.tree)
     F.fmm_set_timing(g.tree, False)
     ms_step = 1e3 * elapsed / steps

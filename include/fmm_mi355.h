@@ -224,6 +224,19 @@ fmm_status fmm_asymmetry_estimate(fmm_tree *tree, double m_leaf, double *out, vo
 fmm_status fmm_momentum_stats(const double *x, const double *v, const double *m, const void *a,
                               int32_t a_precision, int64_t n, fmm_stats *out, void *stream);
 
+/* The same statistics written to DEVICE memory without waiting (Secs. 5-6),
+ * for callers that gather them every step and read them once at the end.
+ *   out  device pointer to one fmm_stats (16 doubles, caller-owned), written
+ *        when the stream reaches the call; the values equal those of
+ *        fmm_momentum_stats bit for bit.
+ * The partial sums use a per-device library buffer: calls on one stream run
+ * in order, calls on different streams of one device must not overlap.
+ * Errors: FMM_ERR_INVALID for NULL x, m, a, out, n < 1 or an unknown
+ * precision (nothing is launched); FMM_ERR_HIP for a failed launch. */
+fmm_status fmm_momentum_stats_async(const double *x, const double *v, const double *m,
+                                    const void *a, int32_t a_precision, int64_t n,
+                                    fmm_stats *out, void *stream);
+
 /* Leapfrog update for kick-drift-kick time stepping with fixed dt:
  *   v += kick * a;  then  x += drift * v      (elementwise, FP64 state)
  * A KDK step is fmm_kick_drift(kick = dt/2, drift = dt), new forces, then

@@ -978,9 +978,29 @@ fmm_status fmm_momentum_stats(const double *x, const double *v, const double *m,
     fmm_status st = stats_scratch(&dev, &host);
     if (st != FMM_OK)
         return st;
-    HIP_TRY(launch_stats(x, v, m, a, a_precision == FMM_FP32, n, dev, host, (hipStream_t)stream));
+    HIP_TRY(launch_stats(x, v, m, a, a_precision == FMM_FP32, n, dev, nullptr, host,
+                         (hipStream_t)stream));
     static_assert(sizeof(fmm_stats) == 16 * sizeof(double), "fmm_stats layout");
     std::memcpy(out, host, sizeof(fmm_stats));
+    return FMM_OK;
+}
+
+fmm_status fmm_momentum_stats_async(const double *x, const double *v, const double *m,
+                                    const void *a, int32_t a_precision, int64_t n,
+                                    fmm_stats *out, void *stream)
+{
+    if (!x || !m || !a || !out)
+        return fail(FMM_ERR_INVALID, "x, m, a and out must not be NULL");
+    if (n < 1)
+        return fail(FMM_ERR_INVALID, "n must be positive");
+    if (a_precision != FMM_FP64 && a_precision != FMM_FP32)
+        return fail(FMM_ERR_INVALID, "unknown precision %d", a_precision);
+    double *dev = nullptr, *host = nullptr;
+    fmm_status st = stats_scratch(&dev, &host);
+    if (st != FMM_OK)
+        return st;
+    HIP_TRY(launch_stats(x, v, m, a, a_precision == FMM_FP32, n, dev, (double *)out, nullptr,
+                         (hipStream_t)stream));
     return FMM_OK;
 }
 

@@ -102,8 +102,12 @@ __global__ __launch_bounds__(ST_THREADS) void k_stats_final(const double *__rest
     }
 }
 
+// Partial sums in red + 16; the 16 results to d_out (device) if given, else
+// to red, then copied to h_out with the stream synchronised.  With h_out ==
+// nullptr nothing waits.
 hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,
-                        int a_fp32, int64_t n, double *red, double *h_out, hipStream_t s)
+                        int a_fp32, int64_t n, double *red, double *d_out, double *h_out,
+                        hipStream_t s)
 {
     int nb = (int)std::min<int64_t>((n + ST_THREADS - 1) / ST_THREADS, ST_MAX_BLOCKS);
     double *part = red + 16;
@@ -111,7 +115,9 @@ hipError_t launch_stats(const double *x, const double *v, const double *m, const
         k_stats_partial<float><<<nb, ST_THREADS, 0, s>>>(x, v, m, (const float *)a, n, part);
     else
         k_stats_partial<double><<<nb, ST_THREADS, 0, s>>>(x, v, m, (const double *)a, n, part);
-    k_stats_final<<<1, ST_THREADS, 0, s>>>(part, nb, red);
+    k_stats_final<<<1, ST_THREADS, 0, s>>>(part, nb, d_out ? d_out : red);
+    if (!h_out)
+        return hipGetLastError();
     hipError_t e = hipMemcpyAsync(h_out, red, 16 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess)
         return e;

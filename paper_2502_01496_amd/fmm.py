@@ -83,6 +83,8 @@ def lib() -> C.CDLL:
     L.fmm_momentum_stats.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_int64,
                                      C.POINTER(fmm_stats), _vp]
     L.fmm_momentum_stats.restype = st
+    L.fmm_momentum_stats_async.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_int64, _vp, _vp]
+    L.fmm_momentum_stats_async.restype = st
     L.fmm_kick_drift.argtypes = [_vp, _vp, _vp, C.c_int32, C.c_int64, C.c_double, C.c_double,
                                  _vp]
     L.fmm_kick_drift.restype = st
@@ -206,6 +208,21 @@ def fmm_momentum_stats(x, v, m, a, stream=None) -> dict:
     return {"sumF": np.array(out.sumF), "sumAbsF": out.sumAbsF, "ratio": out.ratio,
             "mass": out.mass, "xcom": np.array(out.xcom), "P": np.array(out.P),
             "L": np.array(out.L)}
+
+
+def fmm_momentum_stats_async(x, v, m, a, out, stream=None):
+    """The statistics of fmm_momentum_stats into out, a float64 device tensor
+    of 16 elements (sumF[3], sumAbsF, ratio, mass, xcom[3], P[3], L[3], pad),
+    without waiting for the stream."""
+    import torch
+
+    n = x.shape[0]
+    prec = FMM_FP32 if a.dtype == torch.float32 else FMM_FP64
+    _check(lib().fmm_momentum_stats_async(
+        _ptr(x, torch.float64, (n, 3), "x"),
+        _ptr(v, torch.float64, (n, 3), "v") if v is not None else None,
+        _ptr(m, torch.float64, (n,), "m"), _ptr(a, a.dtype, (n, 3), "a"), prec, n,
+        _ptr(out, torch.float64, (16,), "out"), _stream(stream)))
 
 
 def fmm_asymmetry_estimate(tree, m_leaf: float = 0.0, stream=None) -> dict:

@@ -78,6 +78,11 @@ def test_stats_argument_checks():
     assert L.fmm_momentum_stats(v, None, v, v, 0, 0, C.byref(out), None) == F.FMM_ERR_INVALID
     assert L.fmm_momentum_stats(v, None, v, v, 5, 10, C.byref(out), None) == F.FMM_ERR_INVALID
     assert L.fmm_momentum_stats(v, None, v, v, 0, 10, None, None) == F.FMM_ERR_INVALID
+    # the device-output form rejects the same arguments before launching anything
+    assert L.fmm_momentum_stats_async(None, None, v, v, 0, 10, v, None) == F.FMM_ERR_INVALID
+    assert L.fmm_momentum_stats_async(v, None, v, v, 0, 0, v, None) == F.FMM_ERR_INVALID
+    assert L.fmm_momentum_stats_async(v, None, v, v, 5, 10, v, None) == F.FMM_ERR_INVALID
+    assert L.fmm_momentum_stats_async(v, None, v, v, 0, 10, None, None) == F.FMM_ERR_INVALID
 
 
 def test_binding_refuses_host_tensors():
