@@ -98,6 +98,15 @@ enum { FMM_TREE_MEDIAN = 0, FMM_TREE_COM = 1 };
 /* fmm_forces flags */
 enum { FMM_REWALK = 1 /* rebuild the interaction lists even if present */ };
 
+/* Device allocator hooks (fmm_params.dev_alloc / dev_free): every byte of
+ * device memory a tree holds is taken with dev_alloc(bytes, alloc_ctx) and
+ * returned with dev_free(ptr, alloc_ctx); NULL hooks use hipMalloc/hipFree.
+ * dev_alloc returns NULL when it cannot serve the request, and the library
+ * call then fails with FMM_ERR_ALLOC.  Pinned host staging buffers (a few
+ * bytes per tree) are not device memory and do not go through the hooks. */
+typedef void *(*fmm_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*fmm_free_fn)(void *ptr, void *ctx);
+
 typedef struct fmm_params {
     double theta;      /* opening parameter of eq. (4), 0 <= theta <= 1 (default 0.5) */
     double r_kern;     /* kernel support radius in units of h, eq. (5); M4: 2 (default) */
@@ -108,6 +117,21 @@ typedef struct fmm_params {
     int32_t expansion; /* FMM_EXPANSION_* (default PHANTOM) */
     int32_t tree;      /* FMM_TREE_* (default MEDIAN) */
     int32_t reserved;  /* must be 0 */
+    /* Interaction-list capacity per sink list, in entries.  0 (default): the
+     * per-sink slots grow on demand (a walk that overflows them is redone
+     * with larger slots).  > 0: every sink list holds at most this many
+     * cells; a walk that needs more returns FMM_ERR_CAPACITY and leaves the
+     * tree without lists (its moments stay valid). */
+    int64_t list_capacity;
+    /* Upper bound on the device memory the tree may hold, in bytes (the
+     * figure fmm_tree_device_bytes reports).  0 (default): no bound.  A call
+     * whose allocation would exceed it returns FMM_ERR_ALLOC; memory the
+     * failing call had taken for the same purpose is returned first, so the
+     * tree holds what it held before the call. */
+    int64_t device_bytes_limit;
+    fmm_alloc_fn dev_alloc; /* NULL: hipMalloc (default) */
+    fmm_free_fn dev_free;   /* NULL: hipFree; must be set iff dev_alloc is */
+    void *alloc_ctx;        /* passed to both hooks */
 } fmm_params;
 
 /* Momentum diagnostics of Secs. 5-6, accumulated in FP64.
@@ -143,8 +167,11 @@ void fmm_default_params(fmm_params *p);
  *          tree (built earlier with the same n and leaf_size) is rebuilt in
  *          place, reusing its memory.  Rebuilding invalidates the moments and
  *          the interaction lists.
- * Errors: FMM_ERR_INVALID (n, p out of range, NULL pointers, n/leaf_size
- * differing from the reused tree's), FMM_ERR_ALLOC, FMM_ERR_HIP. */
+ * A reused tree keeps its allocator: dev_alloc, dev_free, alloc_ctx and
+ * device_bytes_limit must equal those it was created with.
+ * Errors: FMM_ERR_INVALID (n, p out of range, NULL pointers, n/leaf_size or
+ * the allocator differing from the reused tree's), FMM_ERR_ALLOC (nothing is
+ * kept: a failed new tree returns all it took), FMM_ERR_HIP. */
 fmm_status fmm_build_tree(const double *x, int64_t n, const fmm_params *p, void *stream,
                           fmm_tree **tree);
 
@@ -175,9 +202,13 @@ fmm_status fmm_moments(fmm_tree *tree, const double *x, const double *m, const d
  * flags & FMM_REWALK, then evaluates M2L (eq. (6)), L2L (mutual walk only),
  * L2P (eq. (8)) and the softened near field, and writes
  *   a  device, double[n][3] (FMM_FP64) or float[n][3] (FMM_FP32), caller order.
- * Synchronises `stream` once to size the interaction lists when it walks.
+ * Synchronises `stream` once: to size the interaction lists when it walks,
+ * else to read the data checks of the last fmm_moments.
  * Errors: FMM_ERR_STATE (no moments), FMM_ERR_INVALID (bad input data found
- * on the device), FMM_ERR_ALLOC, FMM_ERR_HIP. */
+ * on the device by the last fmm_moments: non-finite positions, masses or
+ * smoothing lengths not positive and finite; the lists are then dropped),
+ * FMM_ERR_CAPACITY (a sink list needs more than params.list_capacity
+ * entries), FMM_ERR_ALLOC, FMM_ERR_HIP. */
 fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream);
 
 /* Vector-Jacobian product of the accelerations of the last fmm_forces call
@@ -257,6 +288,11 @@ const char *fmm_last_error(void);
  * near entries, list sinks, has_lists. */
 fmm_status fmm_tree_info(const fmm_tree *tree, int64_t *info);
 
+/* The parameters a tree was last built with and its particle count, to host
+ * memory (*p, *n; either may be NULL).  Never touches the device: callers use
+ * it to check the shapes and precision of their buffers before a call. */
+fmm_status fmm_tree_params(const fmm_tree *tree, fmm_params *p, int64_t *n);
+
 /* Device memory the library holds for a tree (its topology, workspace,
  * interaction lists and VJP workspace), in bytes, to *bytes (host).  Memory
  * the caller owns (inputs, outputs) is not included. */
@@ -279,6 +315,35 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
                             int32_t *left, int32_t *right, int32_t *axis, double *rec,
                             int64_t *far_off, int32_t *far_src, int64_t *near_off,
                             int32_t *near_src, double *local);
+
+/* Replace a tree's particle order, cell records and interaction lists with
+ * given ones (test and bring-up aid, the inverse of fmm_debug_export), so that
+ * the far field (M2L, eq. (6)), its Taylor evaluation (L2P, eq. (8)) and the
+ * near field (Sec. 3, eqs. (12)-(15)) can be checked on structures that did
+ * not come from this library's build, moments and walk.  Synchronises.
+ *   tree         built with FMM_TREE_MEDIAN and FMM_WALK_PHANTOM;
+ *   x, m, h      DEVICE, caller order, as for fmm_moments (the data checks of
+ *                fmm_moments apply and are reported by the next fmm_forces);
+ *   perm         HOST int32[n], tree position -> caller index (a permutation);
+ *   first, count, left, right   HOST int32[nodes]: must equal the tree's own
+ *                topology (FMM_ERR_INVALID otherwise; for a median-split tree
+ *                the shape depends on n and leaf_size only);
+ *   rec          HOST double[nodes][12], the layout of fmm_debug_export;
+ *   far_off, near_off   HOST int64[nodes+1], far_src, near_src HOST int32:
+ *                CSR over sink node ids, sinks are leaves; near entries are
+ *                leaves, far entries any cell (may be NULL when empty).
+ * After the call the tree holds moments and lists: fmm_forces without
+ * FMM_REWALK evaluates M2L, L2P and the near field on exactly these, with
+ * the tree's params (G, precision, expansion form); fmm_moments or a walk
+ * replaces them again, and the imported perm stays until the next build.
+ * Errors: FMM_ERR_STATE (no tree), FMM_ERR_INVALID (shape, permutation or
+ * list checks fail; nothing is changed), FMM_ERR_CAPACITY (a list longer than
+ * params.list_capacity), FMM_ERR_ALLOC, FMM_ERR_HIP. */
+fmm_status fmm_debug_import(fmm_tree *tree, const double *x, const double *m, const double *h,
+                            const int32_t *perm, const int32_t *first, const int32_t *count,
+                            const int32_t *left, const int32_t *right, const double *rec,
+                            const int64_t *far_off, const int32_t *far_src,
+                            const int64_t *near_off, const int32_t *near_src, void *stream);
 
 /* Stage timing.  fmm_set_timing(tree, 1) starts recording a pair of HIP
  * events around each stage on the caller's stream (no added synchronisation;

@@ -908,25 +908,32 @@ ORC_API void orc_l2l(const double *L, const double *delta, double *out)
  * far list, in list order; with the mutual walk also the L2L pass from each
  * node into its children, parents first (pre-order).  L is nnodes x 19, zero
  * for nodes without a far field. */
+/* M2L sum of one sink cell v over its far list src[0 .. nsrc), in list order. */
+static void sink_far(int32_t form, int32_t v, const double *M, const double *c, const double *Q,
+                     const int32_t *src, int64_t nsrc, double *Lv)
+{
+    double t[19];
+    for (int k = 0; k < 19; ++k)
+        Lv[k] = 0.0;
+    for (int64_t e = 0; e < nsrc; ++e) {
+        int32_t b = src[e];
+        double rv[3] = {c[3 * v] - c[3 * b], c[3 * v + 1] - c[3 * b + 1],
+                        c[3 * v + 2] - c[3 * b + 2]};
+        orc_m2l(form, rv, M[b], Q + 6 * b, t);
+        for (int k = 0; k < 19; ++k)
+            Lv[k] += t[k];
+    }
+}
+
 ORC_API void orc_far_field(int32_t policy, int32_t form, int32_t nnodes, const int32_t *left,
                            const int32_t *right, const double *M, const double *c,
                            const double *Q, const int32_t *far_off, const int32_t *far_src,
                            double *L)
 {
     double t[19];
-    for (int32_t v = 0; v < nnodes; ++v) {
-        double *Lv = L + 19 * v;
-        for (int k = 0; k < 19; ++k)
-            Lv[k] = 0.0;
-        for (int32_t e = far_off[v]; e < far_off[v + 1]; ++e) {
-            int32_t b = far_src[e];
-            double rv[3] = {c[3 * v] - c[3 * b], c[3 * v + 1] - c[3 * b + 1],
-                            c[3 * v + 2] - c[3 * b + 2]};
-            orc_m2l(form, rv, M[b], Q + 6 * b, t);
-            for (int k = 0; k < 19; ++k)
-                Lv[k] += t[k];
-        }
-    }
+    for (int32_t v = 0; v < nnodes; ++v)
+        sink_far(form, v, M, c, Q, far_src + far_off[v], far_off[v + 1] - far_off[v],
+                 L + 19 * v);
     if (policy == 1) {
         for (int32_t v = 0; v < nnodes; ++v) {
             if (left[v] < 0)
@@ -947,6 +954,41 @@ ORC_API void orc_far_field(int32_t policy, int32_t form, int32_t nnodes, const i
 /* L2P plus the near field for every particle, written in caller order:
  *   a_i = G (L2P(L_leaf, x_i - c_leaf)
  *            - sum_{b in near(leaf)} sum_{j in b, j != i} m_j G_ij (x_i - x_j)). */
+/* L2P and the near field for the particles of leaf v, near list
+ * src[0 .. nsrc), written in caller order:
+ *   a_i = G (L2P(L_v, x_i - c_v) - sum_{b} sum_{j in b, j != i} m_j G_ij (x_i - x_j)). */
+static void leaf_near_l2p(const double *x, const double *m, const double *h,
+                          const int32_t *perm, const int32_t *first, const int32_t *count,
+                          const double *c, int32_t v, const double *Lv, const int32_t *src,
+                          int64_t nsrc, double G, double *a)
+{
+    for (int32_t k = 0; k < count[v]; ++k) {
+        int32_t i = perm[first[v] + k];
+        double y[3] = {x[3 * i] - c[3 * v], x[3 * i + 1] - c[3 * v + 1],
+                       x[3 * i + 2] - c[3 * v + 2]};
+        double af[3];
+        orc_l2p(Lv, y, af);
+        double an[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = 0; e < nsrc; ++e) {
+            int32_t b = src[e];
+            for (int32_t kk = 0; kk < count[b]; ++kk) {
+                int32_t j = perm[first[b] + kk];
+                if (j == i)
+                    continue;
+                double dx = x[3 * i] - x[3 * j], dy = x[3 * i + 1] - x[3 * j + 1],
+                       dz = x[3 * i + 2] - x[3 * j + 2];
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                double f = m[j] * pair_g(r, h[i], h[j]);
+                an[0] -= f * dx;
+                an[1] -= f * dy;
+                an[2] -= f * dz;
+            }
+        }
+        for (int d = 0; d < 3; ++d)
+            a[3 * i + d] = G * (af[d] + an[d]);
+    }
+}
+
 ORC_API void orc_near_and_l2p(int64_t n, const double *x, const double *m, const double *h,
                               const int32_t *perm, int32_t nnodes, const int32_t *first,
                               const int32_t *count, const int32_t *left, const double *c,
@@ -954,35 +996,82 @@ ORC_API void orc_near_and_l2p(int64_t n, const double *x, const double *m, const
                               double G, double *a)
 {
     (void)n;
-    for (int32_t v = 0; v < nnodes; ++v) {
-        if (left[v] >= 0)
-            continue;
-        for (int32_t k = 0; k < count[v]; ++k) {
-            int32_t i = perm[first[v] + k];
-            double y[3] = {x[3 * i] - c[3 * v], x[3 * i + 1] - c[3 * v + 1],
-                           x[3 * i + 2] - c[3 * v + 2]};
-            double af[3];
-            orc_l2p(L + 19 * v, y, af);
-            double an[3] = {0.0, 0.0, 0.0};
-            for (int32_t e = near_off[v]; e < near_off[v + 1]; ++e) {
-                int32_t b = near_src[e];
-                for (int32_t kk = 0; kk < count[b]; ++kk) {
-                    int32_t j = perm[first[b] + kk];
-                    if (j == i)
-                        continue;
-                    double dx = x[3 * i] - x[3 * j], dy = x[3 * i + 1] - x[3 * j + 1],
-                           dz = x[3 * i + 2] - x[3 * j + 2];
-                    double r = sqrt(dx * dx + dy * dy + dz * dz);
-                    double f = m[j] * pair_g(r, h[i], h[j]);
-                    an[0] -= f * dx;
-                    an[1] -= f * dy;
-                    an[2] -= f * dz;
-                }
-            }
-            for (int d = 0; d < 3; ++d)
-                a[3 * i + d] = G * (af[d] + an[d]);
+    for (int32_t v = 0; v < nnodes; ++v)
+        if (left[v] < 0)
+            leaf_near_l2p(x, m, h, perm, first, count, c, v, L + 19 * v,
+                          near_src + near_off[v], near_off[v + 1] - near_off[v], G, a);
+}
+
+/* The leaf <- cell FMM (policy 0) for a chosen set of sink leaves only: for
+ * each listed leaf, its own walk (the same DFS and criteria (4), (5) as
+ * orc_walk), its M2L sum (eq. (6), orc_far_field's order) and L2P plus the
+ * near field for its particles (orc_near_and_l2p's order).  The accelerations
+ * of those particles are therefore identical to the full evaluation's; the
+ * other rows of a are not written.  Lets a test or a timing run reach single
+ * leaves of trees too large for the full O(N) list storage.
+ *   leaves  node ids of leaf cells, nsel of them;
+ *   counts  NULL or int64[2 nsel]: far and near list lengths per listed leaf.
+ * Re-entrant: calls on disjoint leaf sets may run on several threads. */
+ORC_API void orc_fmm_leaves(int64_t n, const double *x, const double *m, const double *h,
+                            const int32_t *perm, int32_t nnodes, const int32_t *first,
+                            const int32_t *count, const int32_t *left, const int32_t *right,
+                            const double *M, const double *c, const double *s,
+                            const double *hmax, const double *Q, double theta, double r_kern,
+                            double G, int32_t form, int64_t nsel, const int32_t *leaves,
+                            double *a, int64_t *counts)
+{
+    (void)n;
+    walk_ctx w;
+    w.nnodes = nnodes;
+    w.left = left;
+    w.right = right;
+    w.c = c;
+    w.s = s;
+    w.hmax = hmax;
+    w.theta2 = theta * theta;
+    w.r_kern = r_kern;
+    w.far_cnt = (int32_t *)calloc((size_t)nnodes, sizeof(int32_t));
+    w.near_cnt = (int32_t *)calloc((size_t)nnodes, sizeof(int32_t));
+    /* one sink at a time: its lists start at offset 0 */
+    int32_t *zero_off = (int32_t *)calloc((size_t)nnodes + 1, sizeof(int32_t));
+    w.far_off = zero_off;
+    w.near_off = zero_off;
+    int64_t cap_f = 0, cap_n = 0;
+    int32_t *fs = NULL, *ns = NULL;
+    double Lv[19];
+    for (int64_t q = 0; q < nsel; ++q) {
+        int32_t v = leaves[q];
+        w.far_cnt[v] = w.near_cnt[v] = 0;
+        w.far_src = w.near_src = NULL;
+        walk_leaf(&w, v);
+        int64_t nf = w.far_cnt[v], nn = w.near_cnt[v];
+        if (nf > cap_f) {
+            free(fs);
+            cap_f = nf;
+            fs = (int32_t *)malloc((size_t)cap_f * sizeof(int32_t));
         }
+        if (nn > cap_n) {
+            free(ns);
+            cap_n = nn;
+            ns = (int32_t *)malloc((size_t)cap_n * sizeof(int32_t));
+        }
+        w.far_cnt[v] = w.near_cnt[v] = 0;
+        w.far_src = fs;
+        w.near_src = ns;
+        walk_leaf(&w, v);
+        sink_far(form, v, M, c, Q, fs, nf, Lv);
+        leaf_near_l2p(x, m, h, perm, first, count, c, v, Lv, ns, nn, G, a);
+        if (counts) {
+            counts[2 * q] = nf;
+            counts[2 * q + 1] = nn;
+        }
+        w.far_cnt[v] = w.near_cnt[v] = 0;
     }
+    free(fs);
+    free(ns);
+    free(zero_off);
+    free(w.far_cnt);
+    free(w.near_cnt);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -87,6 +87,9 @@ def lib():
                                        _i32, _i32, D, _d]
         L.orc_stats.argtypes = [I64, _d, _opt(_d), _d, _d, _d]
         L.orc_asym_estimate.argtypes = [I32, _i32, _i32, _d, _d, _d, _i32, _i32, D, _d]
+        L.orc_fmm_leaves.argtypes = [I64, _d, _d, _d, _i32, I32, _i32, _i32, _i32, _i32,
+                                     _d, _d, _d, _d, _d, D, D, D, I32, I64, _i32, _d,
+                                     _opt(_i64)]
         _lib = L
     return _lib
 
@@ -316,6 +319,23 @@ def fmm(x, m, h, theta=0.5, r_kern=2.0, G=1.0, leaf_size=8, policy=PHANTOM,
     L = far_field(tree, mom, lists, policy, form)
     a = near_and_l2p(x, m, h, tree, mom, L, lists, G)
     return FmmResult(a, tree, mom, lists, L)
+
+
+def fmm_leaves(x, m, h, tree: Tree, mom: Moments, leaves, theta=0.5, r_kern=2.0, G=1.0,
+               form=PHANTOM_FORM, a=None, counts=False):
+    """The leaf <- cell FMM for the listed sink leaves (node ids) only: their
+    walks, M2L sums, L2P and near fields, identical to fmm()'s rows for their
+    particles.  Rows of other particles are left as they are in `a` (zeros if
+    a is None).  counts=True also returns the far and near list lengths."""
+    x, m, h = _f64(x), _f64(m), _f64(h)
+    if a is None:
+        a = np.zeros_like(x)
+    lv = np.ascontiguousarray(leaves, dtype=np.int32)
+    cnt = np.zeros(2 * len(lv), np.int64) if counts else None
+    lib().orc_fmm_leaves(len(m), x, m, h, tree.perm, tree.nnodes, tree.first, tree.count,
+                         tree.left, tree.right, mom.M, mom.c, mom.s, mom.hmax, mom.Q,
+                         float(theta), float(r_kern), float(G), int(form), len(lv), lv, a, cnt)
+    return (a, cnt.reshape(-1, 2)) if counts else a
 
 
 def fmm_frozen(x, m, h, tree: Tree, lists: Lists, G=1.0, policy=PHANTOM, form=PHANTOM_FORM):

@@ -203,15 +203,54 @@ void build_topology(int64_t n, int leaf_size, Topology &T)
     T.leaf_cap = T.nleaves;
 }
 
+hipError_t tree_malloc(Tree &t, void **p, size_t bytes)
+{
+    *p = nullptr;
+    bytes = std::max<size_t>(bytes, 256);
+    if (t.p.device_bytes_limit > 0 &&
+        t.held_bytes + (int64_t)bytes > t.p.device_bytes_limit)
+        return hipErrorOutOfMemory;
+    void *q = nullptr;
+    if (t.p.dev_alloc) {
+        q = t.p.dev_alloc(bytes, t.p.alloc_ctx);
+        if (!q)
+            return hipErrorOutOfMemory;
+    } else {
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess)
+            return e;
+    }
+    t.held.push_back({q, bytes});
+    t.held_bytes += (int64_t)bytes;
+    *p = q;
+    return hipSuccess;
+}
+
+void tree_free(Tree &t, void *p)
+{
+    if (!p)
+        return;
+    for (size_t k = 0; k < t.held.size(); ++k)
+        if (t.held[k].first == p) {
+            t.held_bytes -= (int64_t)t.held[k].second;
+            t.held[k] = t.held.back();
+            t.held.pop_back();
+            if (t.p.dev_free)
+                t.p.dev_free(p, t.p.alloc_ctx);
+            else
+                (void)hipFree(p);
+            return;
+        }
+}
+
 template <typename P>
 static hipError_t dalloc(Tree &t, P **out, size_t elems)
 {
     void *p = nullptr;
-    size_t bytes = std::max<size_t>(elems * sizeof(P), 256);
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = tree_malloc(t, &p, elems * sizeof(P));
     if (e != hipSuccess)
         return e;
-    t.owned.push_back({p, bytes});
+    t.owned.push_back({p, std::max<size_t>(elems * sizeof(P), 256)});
     *out = (P *)p;
     return hipSuccess;
 }
@@ -230,24 +269,15 @@ static void release(Tree *t)
     (void)hipDeviceSynchronize();
     release_vjp(*t);
     release_asym(*t);
-    if (t->s2part)
-        (void)hipFree(t->s2part);
     if (t->cw.h_ctl)
         (void)hipHostFree(t->cw.h_ctl);
-    for (auto &b : t->owned)
-        (void)hipFree(b.p);
     t->owned.clear();
-    for (DevBuf *b : {&t->mw.b_task, &t->mw.b_fkeys, &t->mw.b_nkeys, &t->mw.b_hist})
-        if (b->p)
-            (void)hipFree(b->p);
-    for (auto &b : t->mw.owned)
-        (void)hipFree(b.p);
+    t->mw.owned.clear();
+    // every device allocation still held, newest first
+    while (!t->held.empty())
+        tree_free(*t, t->held.back().first);
     if (t->mw.h_cnt)
         (void)hipHostFree(t->mw.h_cnt);
-    if (t->far_buf.p)
-        (void)hipFree(t->far_buf.p);
-    if (t->near_buf.p)
-        (void)hipFree(t->near_buf.p);
     if (t->h_flags)
         (void)hipHostFree(t->h_flags);
     if (t->h_red)
@@ -380,8 +410,8 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->s2bits, nn));
     // per-level partial maxima of s^2: grown by deeper centre-of-mass trees,
     // so kept apart from the fixed allocations
-    A(hipMalloc((void **)&t->s2part,
-                std::max<size_t>((size_t)t->s2part_depth * ((n + 63) / 64), 32) * sizeof(uint64_t)));
+    A(tree_malloc(*t, (void **)&t->s2part,
+                  std::max<size_t>((size_t)t->s2part_depth * ((n + 63) / 64), 32) * sizeof(uint64_t)));
     A(dalloc(*t, &t->upcnt, nn));
     A(dalloc(*t, &t->far_cnt, nn));
     A(dalloc(*t, &t->near_cnt, nn));
@@ -390,7 +420,7 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->Lf, NLOC * nn));
     A(dalloc(*t, &t->red, 16 + 16 * 512));
     if (e == hipSuccess)
-        e = hipHostMalloc((void **)&t->h_flags, 8 * sizeof(int32_t), hipHostMallocDefault);
+        e = hipHostMalloc((void **)&t->h_flags, 16 * sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&t->h_red, 16 * sizeof(double), hipHostMallocDefault);
     for (int k = 0; k < 8 && e == hipSuccess; ++k)
@@ -434,6 +464,12 @@ static fmm_status check_params(const fmm_params *p)
         return fail(FMM_ERR_INVALID, "unknown tree shape %d", p->tree);
     if (p->reserved != 0)
         return fail(FMM_ERR_INVALID, "reserved must be 0");
+    if (p->list_capacity < 0)
+        return fail(FMM_ERR_INVALID, "list_capacity must be >= 0");
+    if (p->device_bytes_limit < 0)
+        return fail(FMM_ERR_INVALID, "device_bytes_limit must be >= 0");
+    if ((p->dev_alloc == nullptr) != (p->dev_free == nullptr))
+        return fail(FMM_ERR_INVALID, "dev_alloc and dev_free must be given together");
     return FMM_OK;
 }
 
@@ -474,10 +510,14 @@ struct StageTimer {
     }
 };
 
-// (Re)allocate the per-leaf list slots for capacities cap_far / cap_near.
+// (Re)allocate the per-leaf list slots for capacities cap_far / cap_near
+// (both fixed at params.list_capacity when that is set).  Slots that are
+// reallocated lose their lists; on failure the tree is left without lists.
 static fmm_status ensure_slots(Tree &t, int64_t cap_far, int64_t cap_near)
 {
     const int64_t nl = t.topo.nleaves;
+    if (t.p.list_capacity > 0)
+        cap_far = cap_near = t.p.list_capacity;
     struct Want {
         DevBuf *b;
         int32_t **ptr;
@@ -491,12 +531,22 @@ static fmm_status ensure_slots(Tree &t, int64_t cap_far, int64_t cap_near)
             continue;
         if (x.b->p) {
             HIP_TRY(hipDeviceSynchronize());
-            HIP_TRY(hipFree(x.b->p));
+            tree_free(t, x.b->p);
             x.b->p = nullptr;
+            x.b->bytes = 0;
+            *x.ptr = nullptr;
+            *x.cap = 0;
+            t.has_lists = false;
         }
         size_t bytes = (size_t)std::max<int64_t>(1, nl * x.want) * sizeof(int32_t);
         void *p = nullptr;
-        HIP_TRY(hipMalloc(&p, bytes));
+        hipError_t e = tree_malloc(t, &p, bytes);
+        if (e != hipSuccess) {
+            t.has_lists = false;
+            return fail(e == hipErrorOutOfMemory ? FMM_ERR_ALLOC : FMM_ERR_HIP,
+                        "interaction-list slots of %lld bytes: %s", (long long)bytes,
+                        hipGetErrorString(e));
+        }
         x.b->p = p;
         x.b->bytes = bytes;
         *x.ptr = (int32_t *)p;
@@ -506,29 +556,47 @@ static fmm_status ensure_slots(Tree &t, int64_t cap_far, int64_t cap_near)
     return FMM_OK;
 }
 
+// Release the per-leaf list slots (and with them the lists).
+static fmm_status drop_slots(Tree &t)
+{
+    if (!t.far_buf.p && !t.near_buf.p)
+        return FMM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    for (DevBuf *b : {&t.far_buf, &t.near_buf}) {
+        tree_free(t, b->p);
+        b->p = nullptr;
+        b->bytes = 0;
+    }
+    t.far_src = t.near_src = nullptr;
+    t.cap_far = t.cap_near = 0;
+    t.slots_nl = 0;
+    t.has_lists = t.has_forces = false;
+    return FMM_OK;
+}
+
 static int64_t round_cap(int64_t need) { return ((need + need / 4 + 64) + 63) / 64 * 64; }
 
 // (Re)allocate a growable device buffer to at least `bytes` (contents lost).
-static fmm_status grow(DevBuf &b, size_t bytes)
+static fmm_status grow(Tree &t, DevBuf &b, size_t bytes)
 {
     if (b.p && b.bytes >= bytes)
         return FMM_OK;
     if (b.p) {
         HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipFree(b.p));
+        tree_free(t, b.p);
         b.p = nullptr;
         b.bytes = 0;
     }
-    HIP_TRY(hipMalloc(&b.p, std::max<size_t>(bytes, 256)));
+    HIP_TRY(tree_malloc(t, &b.p, bytes));
     b.bytes = std::max<size_t>(bytes, 256);
     return FMM_OK;
 }
 
-static fmm_status mw_alloc(std::vector<DevBuf> &owned, void **out, size_t bytes)
+static fmm_status mw_alloc(Tree &t, void **out, size_t bytes)
 {
     void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, std::max<size_t>(bytes, 256)));
-    owned.push_back({p, bytes});
+    HIP_TRY(tree_malloc(t, &p, bytes));
+    t.mw.owned.push_back({p, bytes});
     *out = p;
     return FMM_OK;
 }
@@ -541,17 +609,17 @@ static fmm_status ensure_mutual(Tree &t, int64_t cap_task, int64_t cap_far, int6
     fmm_status st = FMM_OK;
     if (!M.cnt) {
         void *p = nullptr;
-        if ((st = mw_alloc(M.owned, &p, MW_CNT * sizeof(unsigned long long))) != FMM_OK)
+        if ((st = mw_alloc(t, &p, MW_CNT * sizeof(unsigned long long))) != FMM_OK)
             return st;
         M.cnt = (unsigned long long *)p;
-        if ((st = mw_alloc(M.owned, &p, 2 * (size_t)T.node_cap * sizeof(int64_t))) != FMM_OK)
+        if ((st = mw_alloc(t, &p, 2 * (size_t)T.node_cap * sizeof(int64_t))) != FMM_OK)
             return st;
         M.fstart = (int64_t *)p;
         M.fend = M.fstart + T.node_cap;
-        if ((st = mw_alloc(M.owned, &p, (size_t)T.leaf_cap * sizeof(int64_t))) != FMM_OK)
+        if ((st = mw_alloc(t, &p, (size_t)T.leaf_cap * sizeof(int64_t))) != FMM_OK)
             return st;
         M.nstart = (int64_t *)p;
-        if ((st = mw_alloc(M.owned, &p, (size_t)RS_PASSES * 256 * sizeof(uint32_t))) != FMM_OK)
+        if ((st = mw_alloc(t, &p, (size_t)RS_PASSES * 256 * sizeof(uint32_t))) != FMM_OK)
             return st;
         M.tot = (uint32_t *)p;
         HIP_TRY(hipHostMalloc((void **)&M.h_cnt, MW_CNT * sizeof(unsigned long long),
@@ -559,39 +627,48 @@ static fmm_status ensure_mutual(Tree &t, int64_t cap_task, int64_t cap_far, int6
     }
     if (t.p.precision == FMM_FP64 && !M.Lown) {
         void *p = nullptr;
-        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.node_cap * sizeof(double))) != FMM_OK)
+        if ((st = mw_alloc(t, &p, (size_t)NLOC * T.node_cap * sizeof(double))) != FMM_OK)
             return st;
         M.Lown = (double *)p;
     }
     if (t.p.precision == FMM_FP32 && !M.Lownf) {
         void *p = nullptr;
-        if ((st = mw_alloc(M.owned, &p, (size_t)NLOC * T.node_cap * sizeof(float))) != FMM_OK)
+        if ((st = mw_alloc(t, &p, (size_t)NLOC * T.node_cap * sizeof(float))) != FMM_OK)
             return st;
         M.Lownf = (float *)p;
     }
     if (cap_task > M.cap_task) {
-        if ((st = grow(M.b_task, 2 * (size_t)cap_task * sizeof(int2))) != FMM_OK)
+        M.task[0] = M.task[1] = nullptr;
+        M.cap_task = 0;
+        if ((st = grow(t, M.b_task, 2 * (size_t)cap_task * sizeof(int2))) != FMM_OK)
             return st;
         M.task[0] = (int2 *)M.b_task.p;
         M.task[1] = M.task[0] + cap_task;
         M.cap_task = cap_task;
     }
     if (cap_far > M.cap_far) {
-        if ((st = grow(M.b_fkeys, 2 * (size_t)cap_far * sizeof(uint64_t))) != FMM_OK)
+        M.fkeys[0] = M.fkeys[1] = nullptr;
+        M.far_sorted = nullptr;
+        M.cap_far = 0;
+        t.has_lists = false;
+        if ((st = grow(t, M.b_fkeys, 2 * (size_t)cap_far * sizeof(uint64_t))) != FMM_OK)
             return st;
         M.fkeys[0] = (uint64_t *)M.b_fkeys.p;
         M.fkeys[1] = M.fkeys[0] + cap_far;
         M.cap_far = cap_far;
     }
     if (cap_near > M.cap_near) {
-        if ((st = grow(M.b_nkeys, 2 * (size_t)cap_near * sizeof(uint64_t))) != FMM_OK)
+        M.nkeys[0] = M.nkeys[1] = nullptr;
+        M.cap_near = 0;
+        if ((st = grow(t, M.b_nkeys, 2 * (size_t)cap_near * sizeof(uint64_t))) != FMM_OK)
             return st;
         M.nkeys[0] = (uint64_t *)M.b_nkeys.p;
         M.nkeys[1] = M.nkeys[0] + cap_near;
         M.cap_near = cap_near;
     }
     const int64_t tiles = (std::max(M.cap_far, M.cap_near) + RS_TILE - 1) / RS_TILE;
-    if ((st = grow(M.b_hist, (size_t)256 * tiles * sizeof(uint32_t))) != FMM_OK)
+    M.hist = nullptr;
+    if ((st = grow(t, M.b_hist, (size_t)256 * tiles * sizeof(uint32_t))) != FMM_OK)
         return st;
     M.hist = (uint32_t *)M.b_hist.p;
     return FMM_OK;
@@ -606,6 +683,15 @@ static void note_long_runs(Tree &t)
         t.morton_full = true;
 }
 
+// Enqueue the readback of both data-check words (build, moments) to
+// h_flags[8..9]; their OR after the stream has synchronised.
+static hipError_t read_err_async(Tree &t, hipStream_t s)
+{
+    return hipMemcpyAsync(t.h_flags + 8, t.err, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+}
+
+static uint32_t err_bits(const Tree &t) { return (uint32_t)t.h_flags[8] | (uint32_t)t.h_flags[9]; }
+
 static fmm_status bad_input(uint32_t errbits)
 {
     if (!(errbits & 7u))
@@ -616,6 +702,21 @@ static fmm_status bad_input(uint32_t errbits)
                 (errbits & 4) ? " smoothing lengths not positive and finite" : "");
 }
 
+// Forces on kept lists: the data checks of the last moments call are read
+// back (one synchronisation); bad data drops the lists.
+static fmm_status check_data_after(Tree &t, hipStream_t s)
+{
+    HIP_TRY(read_err_async(t, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t errbits = err_bits(t);
+    if (errbits) {
+        t.has_lists = t.has_forces = false;
+        return bad_input(errbits);
+    }
+    t.has_forces = true;
+    return FMM_OK;
+}
+
 // fmm_forces for the mutual walk: walk (one readback of the pair counts,
 // buffers grown and the walk redone if they overflowed), sort into lists,
 // then M2L + L2L and the near field.
@@ -624,6 +725,8 @@ static fmm_status forces_mutual(Tree &t, void *a, bool walk, hipStream_t s)
     MutualLists &M = t.mw;
     const Topology &T = t.topo;
     if (walk) {
+        // the lists are replaced: none until the walk has succeeded
+        t.has_lists = t.has_forces = false;
         // first capacities: above the frontier and pair counts of theta = 0.5
         // with 58-neighbour smoothing lengths (grown on overflow, then kept)
         const int64_t c0 = t.mw_init_cap;
@@ -643,12 +746,12 @@ static fmm_status forces_mutual(Tree &t, void *a, bool walk, hipStream_t s)
             HIP_TRY(launch_mutual_walk(t, s));
             HIP_TRY(hipMemcpyAsync(M.h_cnt, M.cnt, (MW_IT + nit + 1) * sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(t.h_flags + 4, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(read_err_async(t, s));
             HIP_TRY(hipMemcpyAsync(t.h_flags + 5, t.run_cnt + 2, 2 * sizeof(uint32_t),
                                    hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             note_long_runs(t);
-            const uint32_t errbits = (uint32_t)t.h_flags[4];
+            const uint32_t errbits = err_bits(t);
             if (errbits) {
                 t.has_lists = false;
                 return bad_input(errbits);
@@ -669,6 +772,10 @@ static fmm_status forces_mutual(Tree &t, void *a, bool walk, hipStream_t s)
             if (M.h_cnt[MW_IT + nit] != 0)
                 return fail(FMM_ERR_CAPACITY, "mutual walk did not finish in %d levels", nit);
             const int64_t mx = (int64_t)M.h_cnt[MW_MAXNEAR];
+            if (t.p.list_capacity > 0 && mx > t.p.list_capacity)
+                return fail(FMM_ERR_CAPACITY,
+                            "a near list needs %lld entries; list_capacity is %lld",
+                            (long long)mx, (long long)t.p.list_capacity);
             if (mx > t.cap_near && (st = ensure_slots(t, t.cap_far, round_cap(mx))) != FMM_OK)
                 return st;
             HIP_TRY(launch_mutual_lists(t, nf, nn, s));
@@ -743,6 +850,11 @@ void fmm_default_params(fmm_params *p)
     p->expansion = FMM_EXPANSION_PHANTOM;
     p->tree = FMM_TREE_MEDIAN;
     p->reserved = 0;
+    p->list_capacity = 0;
+    p->device_bytes_limit = 0;
+    p->dev_alloc = nullptr;
+    p->dev_free = nullptr;
+    p->alloc_ctx = nullptr;
 }
 
 const char *fmm_last_error(void) { return g_err.c_str(); }
@@ -772,6 +884,15 @@ fmm_status fmm_build_tree_weighted(const double *x, const double *m, int64_t n,
             return fail(FMM_ERR_INVALID, "a reused tree must keep n and leaf_size");
         if (t->p.tree != p->tree)
             return fail(FMM_ERR_INVALID, "a reused tree must keep its tree shape");
+        if (t->p.dev_alloc != p->dev_alloc || t->p.dev_free != p->dev_free ||
+            t->p.alloc_ctx != p->alloc_ctx || t->p.device_bytes_limit != p->device_bytes_limit)
+            return fail(FMM_ERR_INVALID, "a reused tree must keep its allocator and byte limit");
+        if (t->p.list_capacity != p->list_capacity) {
+            // the slots are sized for the old capacity: drop them with the lists
+            fmm_status st = drop_slots(*t);
+            if (st != FMM_OK)
+                return st;
+        }
         t->p = *p;
     } else {
         st = create_tree(n, *p, &t);
@@ -796,19 +917,24 @@ fmm_status fmm_build_tree_weighted(const double *x, const double *m, int64_t n,
     if (e == hipSuccess && t->topo.depth > t->s2part_depth) {
         // a deeper centre-of-mass tree: grow the per-level s^2 partials
         e = hipStreamSynchronize(s);
-        if (e == hipSuccess)
-            e = hipFree(t->s2part);
-        t->s2part = nullptr;
+        if (e == hipSuccess) {
+            tree_free(*t, t->s2part);
+            t->s2part = nullptr;
+            t->s2part_depth = 0;
+        }
         const int64_t d = t->topo.depth + 16;
         if (e == hipSuccess)
-            e = hipMalloc((void **)&t->s2part, (size_t)d * ((n + 63) / 64) * sizeof(uint64_t));
+            e = tree_malloc(*t, (void **)&t->s2part, (size_t)d * ((n + 63) / 64) * sizeof(uint64_t));
         if (e == hipSuccess)
             t->s2part_depth = d;
     }
     if (e != hipSuccess) {
         if (!*tree)
             release(t);
-        return fail(FMM_ERR_HIP, "tree build launch failed: %s", hipGetErrorString(e));
+        else
+            t->has_tree = t->has_moments = t->has_lists = t->has_forces = false;
+        return fail(e == hipErrorOutOfMemory ? FMM_ERR_ALLOC : FMM_ERR_HIP,
+                    "tree build failed: %s", hipGetErrorString(e));
     }
     tm.done();
     t->has_tree = true;
@@ -849,13 +975,21 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
         return fail(FMM_ERR_STATE, "fmm_moments must run before fmm_forces");
     hipStream_t s = (hipStream_t)stream;
     const bool walk = !t.has_lists || (flags & FMM_REWALK) || t.lists_policy != t.p.walk;
-    if (t.p.walk == FMM_WALK_MUTUAL)
-        return forces_mutual(t, a, walk, s);
-    if (walk && (!t.far_buf.p || t.slots_nl < t.topo.nleaves)) {
-        fmm_status st = ensure_slots(t, t.far_buf.p ? t.cap_far : 512,
-                                     t.near_buf.p ? t.cap_near : 128);
-        if (st != FMM_OK)
+    if (t.p.walk == FMM_WALK_MUTUAL) {
+        fmm_status st = forces_mutual(t, a, walk, s);
+        if (st != FMM_OK || walk)
             return st;
+        return check_data_after(t, s);
+    }
+    if (walk) {
+        // the lists are replaced: none until the walk has succeeded
+        t.has_lists = t.has_forces = false;
+        if (!t.far_buf.p || t.slots_nl < t.topo.nleaves) {
+            fmm_status st = ensure_slots(t, t.far_buf.p ? t.cap_far : 512,
+                                         t.near_buf.p ? t.cap_near : 128);
+            if (st != FMM_OK)
+                return st;
+        }
     }
     // Optimistic order: walk, M2L, P2P, then one readback of the list maxima;
     // if a slot overflowed, grow the slots and do it again.
@@ -876,14 +1010,14 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             tm.done();
         }
         if (!walk)
-            break;
+            return check_data_after(t, s);
         HIP_TRY(hipMemcpyAsync(t.h_flags, t.walk_flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(t.h_flags + 4, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(read_err_async(t, s));
         HIP_TRY(hipMemcpyAsync(t.h_flags + 5, t.run_cnt + 2, 2 * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         note_long_runs(t);
-        uint32_t errbits = (uint32_t)t.h_flags[4];
+        uint32_t errbits = err_bits(t);
         if (errbits) {
             t.has_lists = false;
             return bad_input(errbits);
@@ -896,6 +1030,10 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             HIP_TRY(hipStreamSynchronize(s));
         }
         const int64_t mf = t.h_flags[0], mn = t.h_flags[1];
+        if (t.p.list_capacity > 0 && (mf > t.cap_far || mn > t.cap_near))
+            return fail(FMM_ERR_CAPACITY,
+                        "a sink list needs %lld entries (far) / %lld (near); list_capacity is %lld",
+                        (long long)mf, (long long)mn, (long long)t.p.list_capacity);
         if (mf <= t.cap_far && mn <= t.cap_near) {
             if (t.h_flags[2]) {  // lists were completed by the fallback: evaluate again
                 HIP_TRY(launch_far(t, s));
@@ -914,10 +1052,7 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
         if (st != FMM_OK)
             return st;
     }
-    if (walk)
-        return fail(FMM_ERR_CAPACITY, "interaction lists did not fit after resizing");
-    t.has_forces = true;
-    return FMM_OK;
+    return fail(FMM_ERR_CAPACITY, "interaction lists did not fit after resizing");
 }
 
 fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *m_bar,
@@ -935,7 +1070,7 @@ fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *
     if (t.lists_policy == FMM_WALK_MUTUAL && !t.mw.Lown) {
         // the reverse pass of an FP32 tree recomputes the M2L sums in FP64
         void *p = nullptr;
-        fmm_status st = mw_alloc(t.mw.owned, &p, (size_t)NLOC * t.topo.node_cap * sizeof(double));
+        fmm_status st = mw_alloc(t, &p, (size_t)NLOC * t.topo.node_cap * sizeof(double));
         if (st != FMM_OK)
             return st;
         t.mw.Lown = (double *)p;
@@ -944,7 +1079,8 @@ fmm_status fmm_forces_vjp(fmm_tree *tree, const void *a_bar, void *x_bar, void *
     StageTimer tm(t, s, 5);
     hipError_t e = launch_vjp(t, a_bar, x_bar, m_bar, s);
     if (e != hipSuccess)
-        return fail(FMM_ERR_HIP, "vjp launch failed: %s", hipGetErrorString(e));
+        return fail(e == hipErrorOutOfMemory ? FMM_ERR_ALLOC : FMM_ERR_HIP,
+                    "reverse pass failed: %s", hipGetErrorString(e));
     tm.done();
     return FMM_OK;
 }
@@ -961,7 +1097,7 @@ fmm_status fmm_asymmetry_estimate(fmm_tree *tree, double m_leaf, double *out, vo
     if (!t.has_forces || !t.has_lists)
         return fail(FMM_ERR_STATE, "no interaction lists for the current moments: call fmm_forces "
                                    "first");
-    HIP_TRY(launch_asym(t, m_leaf, out, (hipStream_t)stream));
+    HIP_TRY(launch_asym(t, m_leaf, out, (hipStream_t)stream));  // out of memory -> FMM_ERR_ALLOC
     return FMM_OK;
 }
 
@@ -1062,18 +1198,19 @@ fmm_status fmm_tree_device_bytes(const fmm_tree *tree, int64_t *bytes)
         return fail(FMM_ERR_STATE, "unknown or freed tree handle");
     if (!bytes)
         return fail(FMM_ERR_INVALID, "bytes must not be NULL");
+    *bytes = reinterpret_cast<const Tree *>(tree)->held_bytes;
+    return FMM_OK;
+}
+
+fmm_status fmm_tree_params(const fmm_tree *tree, fmm_params *p, int64_t *n)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
     const Tree &t = *reinterpret_cast<const Tree *>(tree);
-    int64_t b = 0;
-    for (const auto &d : t.owned)
-        b += (int64_t)d.bytes;
-    for (const auto &d : t.vjp_owned)
-        b += (int64_t)d.bytes;
-    for (const auto &d : t.mw.owned)
-        b += (int64_t)d.bytes;
-    for (const DevBuf *d : {&t.far_buf, &t.near_buf, &t.mw.b_task, &t.mw.b_fkeys, &t.mw.b_nkeys,
-                            &t.mw.b_hist})
-        b += (int64_t)d->bytes;
-    *bytes = b;
+    if (p)
+        *p = t.p;
+    if (n)
+        *n = t.topo.n;
     return FMM_OK;
 }
 
@@ -1195,6 +1332,112 @@ fmm_status fmm_debug_export(const fmm_tree *tree, int32_t *perm, int32_t *first,
             for (int k = 0; k < 19; ++k)
                 local[19 * v + k] = (t.has_forces && hl[v] < 0) ? Lh[NLOC * v + k] : 0.0;
     }
+    return FMM_OK;
+}
+
+fmm_status fmm_debug_import(fmm_tree *tree, const double *x, const double *m, const double *h,
+                            const int32_t *perm, const int32_t *first, const int32_t *count,
+                            const int32_t *left, const int32_t *right, const double *rec,
+                            const int64_t *far_off, const int32_t *far_src,
+                            const int64_t *near_off, const int32_t *near_src, void *stream)
+{
+    if (!tree_ok(tree))
+        return fail(FMM_ERR_STATE, "unknown or freed tree handle");
+    if (!x || !m || !h || !perm || !first || !count || !left || !right || !rec || !far_off ||
+        !near_off)
+        return fail(FMM_ERR_INVALID, "x, m, h, perm, topology, rec and the list offsets must "
+                                     "not be NULL");
+    Tree &t = *reinterpret_cast<Tree *>(tree);
+    if (!t.has_tree)
+        return fail(FMM_ERR_STATE, "the tree has not been built");
+    if (t.p.tree != FMM_TREE_MEDIAN || t.p.walk != FMM_WALK_PHANTOM)
+        return fail(FMM_ERR_INVALID, "import needs a median-split tree with the leaf <- cell walk");
+    const Topology &T = t.topo;
+    const int64_t n = T.n, nn = T.nnodes, nl = T.nleaves;
+    // the imported tree must have this tree's shape (node ids in the same order)
+    for (int64_t v = 0; v < nn; ++v)
+        if (first[v] != T.first[v] || count[v] != T.count[v] || left[v] != T.left[v] ||
+            right[v] != T.right[v])
+            return fail(FMM_ERR_INVALID, "imported topology differs from the tree's at node %lld",
+                        (long long)v);
+    {
+        std::vector<uint8_t> seen(n, 0);
+        for (int64_t p = 0; p < n; ++p) {
+            const int32_t i = perm[p];
+            if (i < 0 || i >= n || seen[i])
+                return fail(FMM_ERR_INVALID, "perm is not a permutation of [0, n)");
+            seen[i] = 1;
+        }
+    }
+    int64_t mf = 0, mnr = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t *off = pass ? near_off : far_off;
+        const int32_t *src = pass ? near_src : far_src;
+        if (off[0] != 0)
+            return fail(FMM_ERR_INVALID, "list offsets must start at 0");
+        for (int64_t v = 0; v < nn; ++v) {
+            const int64_t c = off[v + 1] - off[v];
+            if (c < 0 || (c > 0 && (T.left[v] >= 0 || !src)))
+                return fail(FMM_ERR_INVALID, "lists must be CSR over leaf sinks (node %lld)",
+                            (long long)v);
+            for (int64_t k = off[v]; k < off[v + 1]; ++k)
+                if (src[k] < 0 || src[k] >= nn || (pass && T.left[src[k]] >= 0))
+                    return fail(FMM_ERR_INVALID, "list entry %lld of node %lld is not a valid %s",
+                                (long long)k, (long long)v, pass ? "leaf" : "cell");
+            (pass ? mnr : mf) = std::max(pass ? mnr : mf, c);
+        }
+    }
+    if (t.p.list_capacity > 0 && (mf > t.p.list_capacity || mnr > t.p.list_capacity))
+        return fail(FMM_ERR_CAPACITY, "imported lists need %lld / %lld entries; list_capacity is "
+                    "%lld", (long long)mf, (long long)mnr, (long long)t.p.list_capacity);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    t.has_moments = t.has_lists = t.has_forces = false;
+    fmm_status st = ensure_slots(t, std::max<int64_t>(mf, 1), std::max<int64_t>(mnr, 1));
+    if (st != FMM_OK)
+        return st;
+    // host images of the slots, counts and records
+    std::vector<int32_t> fs((size_t)nl * t.cap_far, 0), ns((size_t)nl * t.cap_near, 0);
+    std::vector<int32_t> fc(nl), nc(nl);
+    int64_t tf = 0, tn = 0;
+    for (int64_t lf = 0; lf < nl; ++lf) {
+        const int32_t v = T.leaf_node[lf];
+        fc[lf] = (int32_t)(far_off[v + 1] - far_off[v]);
+        nc[lf] = (int32_t)(near_off[v + 1] - near_off[v]);
+        for (int32_t k = 0; k < fc[lf]; ++k)
+            fs[(size_t)lf * t.cap_far + k] = far_src[far_off[v] + k];
+        for (int32_t k = 0; k < nc[lf]; ++k)
+            ns[(size_t)lf * t.cap_near + k] = near_src[near_off[v] + k];
+        tf += fc[lf];
+        tn += nc[lf];
+    }
+    void *rdev = nullptr;
+    HIP_TRY(tree_malloc(t, &rdev, (size_t)nn * 12 * sizeof(double)));
+    hipError_t e = hipMemcpy(rdev, rec, (size_t)nn * 12 * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t.perm, perm, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t.far_src, fs.data(), fs.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t.near_src, ns.data(), ns.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t.far_cnt, fc.data(), fc.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t.near_cnt, nc.data(), nc.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_import(t, x, m, h, (const double *)rdev, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    tree_free(t, rdev);
+    if (e != hipSuccess)
+        return fail(FMM_ERR_HIP, "import failed: %s", hipGetErrorString(e));
+    t.has_moments = true;
+    t.has_lists = true;
+    t.has_transposed = false;
+    t.lists_policy = FMM_WALK_PHANTOM;
+    t.nsinks = (int)nl;
+    t.n_far = tf;
+    t.n_near = tn;
     return FMM_OK;
 }
 

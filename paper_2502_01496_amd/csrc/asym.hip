@@ -228,11 +228,14 @@ hipError_t launch_asym(Tree &t, double m_leaf, double *out, hipStream_t s)
     if (!t.asym) {
         // T, U, N per node; four sums per sink (nodes >= leaves); four totals
         const size_t nc = (size_t)T.node_cap;
-        e = hipMalloc((void **)&t.asym, (3 * nc + 4 * nc + 4) * sizeof(double));
-        if (e == hipSuccess)
+        e = tree_malloc(t, (void **)&t.asym, (3 * nc + 4 * nc + 4) * sizeof(double));
+        if (e == hipSuccess && !t.h_asym)
             e = hipHostMalloc((void **)&t.h_asym, 4 * sizeof(double), hipHostMallocDefault);
-        if (e != hipSuccess)
+        if (e != hipSuccess) {
+            tree_free(t, t.asym);
+            t.asym = nullptr;
             return e;
+        }
     }
     double *tun = t.asym, *part = t.asym + 3 * (size_t)T.node_cap,
            *dout = part + 4 * (size_t)T.node_cap;
@@ -270,8 +273,7 @@ hipError_t launch_asym(Tree &t, double m_leaf, double *out, hipStream_t s)
 
 void release_asym(Tree &t)
 {
-    if (t.asym)
-        (void)hipFree(t.asym);
+    tree_free(t, t.asym);
     if (t.h_asym)
         (void)hipHostFree(t.h_asym);
     t.asym = nullptr;

@@ -170,6 +170,15 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+struct Tree;
+// Device memory of a tree.  Every allocation and release of a tree's device
+// memory goes through these two: they apply the caller's allocator hooks and
+// byte limit (fmm_params) and keep the count fmm_tree_device_bytes reports.
+// tree_malloc returns hipErrorOutOfMemory when the limit would be exceeded
+// or a hook returns NULL; tree_free(nullptr) is a no-op.
+hipError_t tree_malloc(Tree &t, void **p, size_t bytes);
+void tree_free(Tree &t, void *p);
+
 // Mutual walk state: pair frontier, far / near pair buffers (sorted by
 // (sink, source) keys), CSR ranges of the far lists, and the counters
 //   cnt[MW_NFAR], cnt[MW_NNEAR]  pairs appended,
@@ -200,6 +209,8 @@ struct Tree {
     fmm_params p{};
     Topology topo;
     std::vector<DevBuf> owned;
+    int64_t held_bytes = 0;         // device memory held (tree_malloc - tree_free)
+    std::vector<std::pair<void *, size_t>> held;  // every live allocation
 
     // topology on the device
     int32_t *first = nullptr, *count = nullptr, *left = nullptr, *right = nullptr;
@@ -221,7 +232,10 @@ struct Tree {
     uint8_t *side = nullptr;      // 4 x n: side of each list entry at the current level
     int32_t *lvl_cnt = nullptr;
     uint64_t *bbox = nullptr;     // ordered bits: min xyz, max xyz
-    uint32_t *err = nullptr;      // device error flags (bit 0 x, bit 1 m, bit 2 h)
+    // device error flags: err[0] from the build (bit 0 non-finite x, bit 3
+    // internal), err[1] from the last moments call (bit 0 x, bit 1 m, bit 2 h;
+    // cleared at the start of every moments call)
+    uint32_t *err = nullptr;
     int32_t *perm = nullptr;      // tree position -> caller index
 
     // particles in tree order
@@ -264,6 +278,7 @@ struct Tree {
         int64_t *off = nullptr;   // nnodes + 1, CSR over target node ids
         uint32_t *src = nullptr;  // sink node ids, ascending per target
         int64_t npairs = 0;
+        int64_t src_cap = 0;      // entries src holds
     } farT, nearT;
     bool has_transposed = false;
     std::vector<DevBuf> vjp_owned;
@@ -339,6 +354,8 @@ hipError_t launch_morton_order(Tree &t, const double *x, hipStream_t s);
 hipError_t launch_build_com(Tree &t, const double *x, const double *m, hipStream_t s);
 hipError_t launch_moments(Tree &t, const double *x, const double *m, const double *h,
                           hipStream_t s);
+hipError_t launch_import(Tree &t, const double *x, const double *m, const double *h,
+                         const double *rec12, hipStream_t s);
 hipError_t launch_walk(Tree &t, hipStream_t s);
 hipError_t launch_walk_fallback(Tree &t, hipStream_t s);
 hipError_t launch_far(Tree &t, hipStream_t s);

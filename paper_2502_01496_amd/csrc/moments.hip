@@ -2,7 +2,9 @@
 // s, h_max; quadrupole eq. (7)).
 //
 //   k_gather     caller-order x, m, h -> tree-order (x, y, z, m), h and
-//                (1/h, 1/h^3, 4 h^2, h); flags bad inputs; clears the s^2 maxima.
+//                (1/h, 1/h^3, 4 h^2, h); flags bad inputs in the call's own
+//                check word (cleared first by k_clear_word); clears the s^2
+//                maxima.
 //   k_leaf_moments  one thread per leaf: M, sum(m x) left to right, c = S / M,
 //                h_max and the quadrupole about c.
 //   k_combine_level one launch per tree level, deepest first: parents from
@@ -26,6 +28,10 @@
 #include "fmm_internal.h"
 
 namespace fmm {
+
+// The moments call's data-check word starts at zero on every call (a kernel,
+// not a memset, so that the call can be captured in a graph).
+__global__ void k_clear_word(uint32_t *w) { *w = 0u; }
 
 __global__ void k_gather(const double *__restrict__ x, const double *__restrict__ m,
                          const double *__restrict__ h, int64_t n, const int32_t *__restrict__ perm,
@@ -428,6 +434,83 @@ __global__ void k_node_final(int nnodes, const uint64_t *__restrict__ s2bits,
     }
 }
 
+// Imported cell records (host layout of fmm_debug_import, 12 doubles per
+// node: M, c[3], s, h_max, Q[6]) into the device records, with the child ids
+// and leaf index from the topology and the FP32 mirror.
+__global__ void k_import_records(int nnodes, const double *__restrict__ rec12,
+                                 const int32_t *__restrict__ left,
+                                 const int32_t *__restrict__ right,
+                                 const int32_t *__restrict__ node_leaf, double *recA, double *recQ,
+                                 int want_fp32, float *recF)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nnodes; v += gridDim.x * blockDim.x) {
+        const double *r = rec12 + 12 * (int64_t)v;
+        double *ra = recA + (int64_t)NREC * v;
+        double *rq = recQ + (int64_t)NREC * v;
+        ra[0] = r[1];
+        ra[1] = r[2];
+        ra[2] = r[3];
+        ra[3] = r[0];
+        ra[4] = r[4];
+        ra[5] = r[5];
+        const uint64_t kids = (uint64_t)(uint32_t)left[v] | ((uint64_t)(uint32_t)right[v] << 32);
+        ra[REC_KIDS] = __longlong_as_double((long long)kids);
+        ra[REC_LEAF] = __longlong_as_double((long long)(uint64_t)(uint32_t)node_leaf[v]);
+        for (int k = 0; k < 6; ++k)
+            rq[k] = r[6 + k];
+        rq[6] = rq[7] = 0.0;
+        if (want_fp32) {
+            float *rf = recF + (int64_t)NREC * v;
+            rf[0] = (float)r[0];
+            for (int k = 0; k < 6; ++k)
+                rf[1 + k] = (float)r[6 + k];
+            rf[7] = 0.0f;
+        }
+    }
+}
+
+// FP32 form: particle offsets from the (imported) centre of mass of their
+// leaf, one thread per leaf.
+__global__ void k_import_offsets(int nleaves, const int32_t *__restrict__ leaf_node,
+                                 const int32_t *__restrict__ first,
+                                 const int32_t *__restrict__ count,
+                                 const double *__restrict__ recA, const double4 *__restrict__ pm,
+                                 float4 *pf)
+{
+    const int lf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves)
+        return;
+    const int v = leaf_node[lf];
+    const double *c = recA + (int64_t)NREC * v;
+    for (int64_t p = first[v]; p < (int64_t)first[v] + count[v]; ++p) {
+        const double4 q = pm[p];
+        pf[p] = make_float4((float)(q.x - c[0]), (float)(q.y - c[1]), (float)(q.z - c[2]),
+                            (float)q.w);
+    }
+}
+
+// fmm_debug_import: tree-order particles from the imported permutation (with
+// the data checks of a moments call), then the imported cell records.
+hipError_t launch_import(Tree &t, const double *x, const double *m, const double *h,
+                         const double *rec12, hipStream_t s)
+{
+    const Topology &T = t.topo;
+    const int64_t n = T.n;
+    const int64_t work = n > T.nnodes ? n : T.nnodes;
+    const int gs = (int)std::min<int64_t>((work + 255) / 256, 4096);
+    const int want32 = t.p.precision == FMM_FP32;
+    k_clear_word<<<1, 1, 0, s>>>(t.err + 1);
+    k_gather<<<gs, 256, 0, s>>>(x, m, h, n, t.perm, t.pm, t.hs, t.ph, t.err + 1, T.nnodes,
+                                t.s2bits, t.upcnt, want32, t.pfh);
+    k_import_records<<<(T.nnodes + 255) / 256, 256, 0, s>>>(T.nnodes, rec12, t.left, t.right,
+                                                           t.node_leaf, t.recA, t.recQ, want32,
+                                                           t.recF);
+    if (want32)
+        k_import_offsets<<<(T.nleaves + 255) / 256, 256, 0, s>>>(T.nleaves, t.leaf_node, t.first,
+                                                                 t.count, t.recA, t.pm, t.pf);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments(Tree &t, const double *x, const double *m, const double *h,
                           hipStream_t s)
 {
@@ -436,7 +519,8 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
     int64_t work = n > T.nnodes ? n : T.nnodes;
     int gs = (int)std::min<int64_t>((work + 255) / 256, 4096);
     int want32 = t.p.precision == FMM_FP32;
-    k_gather<<<gs, 256, 0, s>>>(x, m, h, n, t.perm, t.pm, t.hs, t.ph, t.err, T.nnodes, t.s2bits,
+    k_clear_word<<<1, 1, 0, s>>>(t.err + 1);
+    k_gather<<<gs, 256, 0, s>>>(x, m, h, n, t.perm, t.pm, t.hs, t.ph, t.err + 1, T.nnodes, t.s2bits,
                                 t.upcnt, want32, t.pfh);
     if (!T.com && T.sub_moments) {
         // the subtrees in one launch, then the cells above them level by level

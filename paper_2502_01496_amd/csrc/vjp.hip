@@ -1183,13 +1183,21 @@ template <typename P>
 static hipError_t valloc(Tree &t, P **out, size_t elems)
 {
     void *p = nullptr;
-    size_t bytes = std::max<size_t>(elems * sizeof(P), 256);
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = tree_malloc(t, &p, elems * sizeof(P));
     if (e != hipSuccess)
         return e;
-    t.vjp_owned.push_back({p, bytes});
+    t.vjp_owned.push_back({p, std::max<size_t>(elems * sizeof(P), 256)});
     *out = (P *)p;
     return hipSuccess;
+}
+
+// Free a list of device buffers of the reverse pass and clear the pointers.
+static void vfree(Tree &t, std::initializer_list<void **> ptrs)
+{
+    for (void **pp : ptrs) {
+        tree_free(t, *pp);
+        *pp = nullptr;
+    }
 }
 
 static hipError_t ensure_vjp_base(Tree &t)
@@ -1211,7 +1219,17 @@ static hipError_t ensure_vjp_base(Tree &t)
     if (e == hipSuccess) e = valloc(t, &t.poff, nc + 1);
     if (e == hipSuccess) e = valloc(t, &t.pscan, nc / SCAN_TILE + 2);
     if (e == hipSuccess) e = valloc(t, &t.nearT.off, nc + 1);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&t.h_pairs, 4 * sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess && !t.h_pairs)
+        e = hipHostMalloc((void **)&t.h_pairs, 4 * sizeof(int64_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        // all or nothing: return what this call took
+        for (auto &b : t.vjp_owned)
+            tree_free(t, b.p);
+        t.vjp_owned.clear();
+        t.abt = t.xbt = t.mbt = t.Lbar = t.nadj = nullptr;
+        t.pair_off = t.vscan = t.farT.off = t.poff = t.pscan = t.nearT.off = nullptr;
+        t.pcnt = nullptr;
+    }
     return e;
 }
 
@@ -1243,20 +1261,24 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     if (np > t.vjp_pair_cap) {
         // (re)allocate the pair sort buffers
         e = hipStreamSynchronize(s);
-        for (void *pp : {(void *)t.vk0, (void *)t.vk1, (void *)t.vv0, (void *)t.vv1,
-                         (void *)t.vhist, (void *)t.vtot})
-            if (pp)
-                (void)hipFree(pp);
-        const int64_t cp = np + np / 4 + 1024;
-        const int64_t nblk = (cp + RS_TILE - 1) / RS_TILE;
-        e = hipMalloc((void **)&t.vk0, cp * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc((void **)&t.vk1, cp * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc((void **)&t.vv0, cp * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc((void **)&t.vv1, cp * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc((void **)&t.vhist, 256 * nblk * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc((void **)&t.vtot, 8 * 256 * sizeof(uint32_t));
         if (e != hipSuccess)
             return e;
+        vfree(t, {(void **)&t.vk0, (void **)&t.vk1, (void **)&t.vv0, (void **)&t.vv1,
+                  (void **)&t.vhist, (void **)&t.vtot});
+        t.vjp_pair_cap = 0;
+        const int64_t cp = np + np / 4 + 1024;
+        const int64_t nblk = (cp + RS_TILE - 1) / RS_TILE;
+        e = tree_malloc(t, (void **)&t.vk0, cp * sizeof(uint32_t));
+        if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vk1, cp * sizeof(uint32_t));
+        if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vv0, cp * sizeof(uint32_t));
+        if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vv1, cp * sizeof(uint32_t));
+        if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vhist, 256 * nblk * sizeof(uint32_t));
+        if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vtot, 8 * 256 * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            vfree(t, {(void **)&t.vk0, (void **)&t.vk1, (void **)&t.vv0, (void **)&t.vv1,
+                      (void **)&t.vhist, (void **)&t.vtot});
+            return e;
+        }
         t.vjp_pair_cap = cp;
     }
     if (nl > 0)
@@ -1270,15 +1292,16 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     uint32_t *vs = (passes & 1) ? t.vv1 : t.vv0;
     k_lower_bound<<<(T.nnodes + 256) / 256, 256, 0, s>>>(ks, np, T.nnodes, out.off);
     // keep the sorted values
-    if (out.src && out.npairs < np) {
+    if (out.src && out.src_cap < np) {
         (void)hipStreamSynchronize(s);
-        (void)hipFree(out.src);
-        out.src = nullptr;
+        vfree(t, {(void **)&out.src});
+        out.src_cap = 0;
     }
     if (!out.src) {
-        e = hipMalloc((void **)&out.src, std::max<int64_t>(np, 1) * sizeof(uint32_t));
+        e = tree_malloc(t, (void **)&out.src, std::max<int64_t>(np, 1) * sizeof(uint32_t));
         if (e != hipSuccess)
             return e;
+        out.src_cap = std::max<int64_t>(np, 1);
     }
     out.npairs = np;
     if (np > 0)
@@ -1304,17 +1327,17 @@ static hipError_t build_m2lt_pieces(Tree &t, hipStream_t s)
         return e;
     const int64_t np = t.h_pairs[1];
     if (np > t.piece_cap) {
-        for (void *pp : {(void *)t.pnode, (void *)t.ppart})
-            if (pp)
-                (void)hipFree(pp);
-        t.pnode = nullptr;
-        t.ppart = nullptr;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return e;
+        vfree(t, {(void **)&t.pnode, (void **)&t.ppart});
+        t.piece_cap = 0;
         const int64_t cp = np + np / 4 + 256;
-        e = hipMalloc((void **)&t.pnode, cp * sizeof(int32_t));
+        e = tree_malloc(t, (void **)&t.pnode, cp * sizeof(int32_t));
         if (e == hipSuccess)
-            e = hipMalloc((void **)&t.ppart, 10 * cp * sizeof(double));
+            e = tree_malloc(t, (void **)&t.ppart, 10 * cp * sizeof(double));
         if (e != hipSuccess) {
-            t.piece_cap = 0;
+            vfree(t, {(void **)&t.pnode, (void **)&t.ppart});
             return e;
         }
         t.piece_cap = cp;
@@ -1440,15 +1463,14 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
 void release_vjp(Tree &t)
 {
     for (auto &b : t.vjp_owned)
-        (void)hipFree(b.p);
+        tree_free(t, b.p);
     t.vjp_owned.clear();
-    for (void *pp : {(void *)t.vk0, (void *)t.vk1, (void *)t.vv0, (void *)t.vv1, (void *)t.vhist,
-                     (void *)t.vtot, (void *)t.farT.src, (void *)t.nearT.src, (void *)t.pnode,
-                     (void *)t.ppart})
-        if (pp)
-            (void)hipFree(pp);
+    vfree(t, {(void **)&t.vk0, (void **)&t.vk1, (void **)&t.vv0, (void **)&t.vv1,
+              (void **)&t.vhist, (void **)&t.vtot, (void **)&t.farT.src, (void **)&t.nearT.src,
+              (void **)&t.pnode, (void **)&t.ppart});
     if (t.h_pairs)
         (void)hipHostFree(t.h_pairs);
+    t.h_pairs = nullptr;
 }
 
 }  // namespace fmm

@@ -37,10 +37,16 @@ class FmmError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class fmm_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("r_kern", C.c_double), ("G", C.c_double),
                 ("leaf_size", C.c_int32), ("walk", C.c_int32), ("precision", C.c_int32),
-                ("expansion", C.c_int32), ("tree", C.c_int32), ("reserved", C.c_int32)]
+                ("expansion", C.c_int32), ("tree", C.c_int32), ("reserved", C.c_int32),
+                ("list_capacity", C.c_int64), ("device_bytes_limit", C.c_int64),
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class fmm_stats(C.Structure):
@@ -94,6 +100,10 @@ def lib() -> C.CDLL:
     L.fmm_tree_info.restype = st
     L.fmm_tree_device_bytes.argtypes = [_vp, C.POINTER(C.c_int64)]
     L.fmm_tree_device_bytes.restype = st
+    L.fmm_tree_params.argtypes = [_vp, C.POINTER(fmm_params), C.POINTER(C.c_int64)]
+    L.fmm_tree_params.restype = st
+    L.fmm_debug_import.argtypes = [_vp] * 15
+    L.fmm_debug_import.restype = st
     L.fmm_debug_export.argtypes = [_vp] * 13
     L.fmm_debug_export.restype = st
     L.fmm_set_timing.argtypes = [_vp, C.c_int32]
@@ -125,18 +135,22 @@ def _stream(stream):
 
 
 def _ptr(t, dtype, shape=None, name="tensor"):
+    """Device pointer of t after checking its dtype, shape, layout and device
+    (in that order), so that no kernel is handed a buffer it would overrun."""
     import torch
 
     if t is None:
         return None
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+    if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor on the GPU")
     if t.dtype != dtype:
         raise TypeError(f"{name} must have dtype {dtype} (got {t.dtype})")
-    if not t.is_contiguous():
-        raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
     return C.c_void_p(t.data_ptr())
 
 
@@ -176,23 +190,38 @@ def fmm_build_tree(x, params: fmm_params, stream=None, tree=None, m=None):
 def fmm_moments(tree, x, m, h, stream=None):
     import torch
 
-    n = x.shape[0]
+    _, n = _tree_dtype_n(tree)
     _check(lib().fmm_moments(C.c_void_p(tree), _ptr(x, torch.float64, (n, 3), "x"),
                              _ptr(m, torch.float64, (n,), "m"), _ptr(h, torch.float64, (n,), "h"),
                              _stream(stream)))
 
 
-def fmm_forces(tree, a, flags: int = 0, stream=None):
+def fmm_tree_params(tree):
+    """(params, n) the tree was last built with (host only, no device work)."""
+    p = fmm_params()
+    n = C.c_int64(0)
+    _check(lib().fmm_tree_params(C.c_void_p(tree), C.byref(p), C.byref(n)))
+    return p, int(n.value)
+
+
+def _tree_dtype_n(tree):
+    """dtype of the tree's accelerations and its particle count."""
     import torch
 
-    _check(lib().fmm_forces(C.c_void_p(tree), _ptr(a, a.dtype, None, "a") if a.dtype in
-                            (torch.float32, torch.float64) else None, flags, _stream(stream)))
+    p, n = fmm_tree_params(tree)
+    return (torch.float32 if p.precision == FMM_FP32 else torch.float64), n
+
+
+def fmm_forces(tree, a, flags: int = 0, stream=None):
+    dt, n = _tree_dtype_n(tree)
+    _check(lib().fmm_forces(C.c_void_p(tree), _ptr(a, dt, (n, 3), "a"), flags, _stream(stream)))
 
 
 def fmm_forces_vjp(tree, a_bar, x_bar, m_bar, stream=None):
-    _check(lib().fmm_forces_vjp(C.c_void_p(tree), _ptr(a_bar, a_bar.dtype, None, "a_bar"),
-                                _ptr(x_bar, x_bar.dtype, None, "x_bar"),
-                                _ptr(m_bar, m_bar.dtype, None, "m_bar"), _stream(stream)))
+    dt, n = _tree_dtype_n(tree)
+    _check(lib().fmm_forces_vjp(C.c_void_p(tree), _ptr(a_bar, dt, (n, 3), "a_bar"),
+                                _ptr(x_bar, dt, (n, 3), "x_bar"),
+                                _ptr(m_bar, dt, (n,), "m_bar"), _stream(stream)))
 
 
 def fmm_momentum_stats(x, v, m, a, stream=None) -> dict:
@@ -276,6 +305,30 @@ def fmm_stage_times(tree) -> dict:
     return dict(zip(keys, ms.tolist()))
 
 
+def fmm_debug_import(tree, x, m, h, ex: dict, stream=None):
+    """Replace the tree's particle order, cell records and interaction lists
+    with those of ex (keys as fmm_debug_export returns them: perm, first,
+    count, left, right, rec, far_off, far_src, near_off, near_src); x, m, h
+    are the particles on the GPU (caller order)."""
+    import torch
+
+    _, n = _tree_dtype_n(tree)
+    keep = {}
+
+    def host(k, dt):
+        a = np.ascontiguousarray(ex[k], dtype=dt)
+        keep[k] = a
+        return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+    args = [host("perm", np.int32), host("first", np.int32), host("count", np.int32),
+            host("left", np.int32), host("right", np.int32), host("rec", np.float64),
+            host("far_off", np.int64), host("far_src", np.int32), host("near_off", np.int64),
+            host("near_src", np.int32)]
+    _check(lib().fmm_debug_import(C.c_void_p(tree), _ptr(x, torch.float64, (n, 3), "x"),
+                                  _ptr(m, torch.float64, (n,), "m"),
+                                  _ptr(h, torch.float64, (n,), "h"), *args, _stream(stream)))
+
+
 def fmm_debug_export(tree, lists: bool = True, local: bool = False) -> dict:
     """Copy the tree, cell records and lists to host numpy arrays."""
     info = fmm_tree_info(tree)
@@ -304,6 +357,46 @@ def fmm_debug_export(tree, lists: bool = True, local: bool = False) -> dict:
         out["far_src"] = out["far_src"][: info["n_far"]]
         out["near_src"] = out["near_src"][: info["n_near"]]
     return out
+
+
+class TorchDeviceAllocator:
+    """Allocator hooks (fmm_params.dev_alloc / dev_free) that take a tree's
+    device memory from torch's caching allocator, so that it is counted in
+    torch.cuda.memory_allocated() and reused by torch after fmm_tree_free.
+    `live` maps each pointer the library holds to its size."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.live: dict[int, int] = {}
+        self.calls = 0
+        self._alloc = ALLOC_FN(self._on_alloc)
+        self._free = FREE_FN(self._on_free)
+
+    def allocate(self, nbytes: int):
+        import torch
+
+        return torch.cuda.caching_allocator_alloc(nbytes, device=self.device)
+
+    def _on_alloc(self, nbytes, ctx):
+        self.calls += 1
+        try:
+            ptr = self.allocate(int(nbytes))
+        except Exception:
+            return None
+        if ptr:
+            self.live[int(ptr)] = int(nbytes)
+        return ptr
+
+    def _on_free(self, ptr, ctx):
+        import torch
+
+        self.live.pop(int(ptr))
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    def apply(self, params: fmm_params) -> fmm_params:
+        params.dev_alloc = self._alloc
+        params.dev_free = self._free
+        return params
 
 
 # --------------------------------------------------------------------- convenience

@@ -24,9 +24,14 @@ def test_default_params():
     assert (p.theta, p.r_kern, p.G, p.leaf_size, p.walk, p.precision, p.expansion) == (
         0.5, 2.0, 1.0, 8, F.FMM_WALK_PHANTOM, F.FMM_FP64, F.FMM_EXPANSION_PHANTOM)
     assert (p.tree, p.reserved) == (F.FMM_TREE_MEDIAN, 0)
+    assert (p.list_capacity, p.device_bytes_limit, p.alloc_ctx) == (0, 0, None)
+    assert not p.dev_alloc and not p.dev_free
     with pytest.raises(TypeError):
         F.default_params(thetta=0.3)
     assert C.sizeof(F.fmm_stats) == 16 * 8
+    # the C layout: 3 doubles, 6 int32, 2 int64, 3 pointers
+    assert C.sizeof(F.fmm_params) == 88
+    assert F.fmm_params.list_capacity.offset == 48 and F.fmm_params.alloc_ctx.offset == 80
 
 
 def _build(p, n=10, x=C.c_void_p(16), tree=None):
@@ -38,13 +43,24 @@ def _build(p, n=10, x=C.c_void_p(16), tree=None):
     ("theta", -0.1), ("theta", 1.5), ("theta", float("nan")), ("r_kern", 0.0),
     ("r_kern", float("inf")), ("G", float("nan")), ("leaf_size", 0), ("leaf_size", 65),
     ("walk", 7), ("precision", 2), ("expansion", 2), ("expansion", -1), ("tree", 2),
-    ("reserved", 1)])
+    ("reserved", 1), ("list_capacity", -1), ("device_bytes_limit", -5)])
 def test_bad_params_rejected_on_host(field, value):
     p = F.default_params()
     setattr(p, field, value)
     st, h = _build(p)
     assert st == F.FMM_ERR_INVALID and h is None
     assert F.fmm_last_error() != ""
+
+
+def test_allocator_hooks_must_come_in_pairs():
+    p = F.default_params()
+    p.dev_alloc = F.ALLOC_FN(lambda nbytes, ctx: None)
+    st, h = _build(p)
+    assert st == F.FMM_ERR_INVALID and h is None
+    assert "together" in F.fmm_last_error()
+    p = F.default_params()
+    p.dev_free = F.FREE_FN(lambda ptr, ctx: None)
+    assert _build(p)[0] == F.FMM_ERR_INVALID
 
 
 def test_bad_sizes_and_pointers_rejected():
@@ -67,6 +83,10 @@ def test_unknown_handles_rejected():
     assert L.fmm_forces_vjp(bogus, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == F.FMM_ERR_STATE
     info = (C.c_int64 * 8)()
     assert L.fmm_tree_info(bogus, info) == F.FMM_ERR_STATE
+    assert L.fmm_tree_params(bogus, None, None) == F.FMM_ERR_STATE
+    assert L.fmm_debug_import(bogus, *([C.c_void_p(8)] * 13), None) == F.FMM_ERR_STATE
+    with pytest.raises(F.FmmError):
+        F.fmm_tree_params(None)
     L.fmm_tree_free(bogus)  # no-op
 
 
@@ -90,3 +110,20 @@ def test_binding_refuses_host_tensors():
 
     with pytest.raises((TypeError, RuntimeError)):
         F.fmm_build_tree(torch.zeros(4, 3, dtype=torch.float64), F.default_params())
+
+
+def test_binding_checks_dtype_and_shape_before_the_call():
+    # a buffer of the wrong precision or length would let a kernel write past
+    # it: the binding refuses it before anything reaches the library
+    import torch
+
+    with pytest.raises(TypeError, match="dtype"):
+        F._ptr(torch.zeros(4, 3, dtype=torch.float32), torch.float64, (4, 3), "a")
+    with pytest.raises(ValueError, match="shape"):
+        F._ptr(torch.zeros(3, 3, dtype=torch.float64), torch.float64, (4, 3), "a")
+    with pytest.raises(ValueError, match="shape"):
+        F._ptr(torch.zeros(12, dtype=torch.float64), torch.float64, (4, 3), "a")
+    with pytest.raises(ValueError, match="contiguous"):
+        F._ptr(torch.zeros(3, 4, dtype=torch.float64).t(), torch.float64, (4, 3), "a")
+    with pytest.raises(TypeError, match="GPU"):
+        F._ptr(torch.zeros(4, 3, dtype=torch.float64), torch.float64, (4, 3), "a")

@@ -129,3 +129,26 @@ def test_direct_adjoint_momentum_identity(orc):
     a = orc.direct(x, m, h)
     assert np.abs(xb).max() < 1e-13 * np.abs(a).max() * m.max()
     np.testing.assert_allclose(mb, -(a @ e), rtol=1e-12, atol=1e-14 * np.abs(a).max())
+
+
+@pytest.mark.parametrize("n,leaf,theta", [(1, 8, 0.5), (9, 1, 0.3), (500, 8, 0.5), (777, 3, 0.7),
+                                          (2048, 10, 0.5)])
+def test_fmm_leaves_equals_full_evaluation(orc, n, leaf, theta):
+    # the per-leaf entry point is the full evaluation restricted to chosen
+    # sinks: same lists, same arithmetic order, so the rows are bit-identical
+    x, m, h = W.clumpy_cube(n, 17, n_clumps=4, cache=False) if n >= 64 else W.plummer(n, 3)
+    ref = orc.fmm(x, m, h, theta=theta, leaf_size=leaf)
+    leaves = np.flatnonzero(ref.tree.left < 0)
+    a, cnt = orc.fmm_leaves(x, m, h, ref.tree, ref.mom, leaves, theta=theta, counts=True)
+    np.testing.assert_array_equal(a, ref.a)
+    np.testing.assert_array_equal(cnt[:, 0], np.diff(ref.lists.far_off)[leaves])
+    np.testing.assert_array_equal(cnt[:, 1], np.diff(ref.lists.near_off)[leaves])
+    # a subset writes exactly the rows of its particles
+    sub = leaves[::3]
+    part = orc.fmm_leaves(x, m, h, ref.tree, ref.mom, sub, theta=theta)
+    rows = np.concatenate([ref.tree.perm[ref.tree.first[v]:ref.tree.first[v] + ref.tree.count[v]]
+                           for v in sub])
+    mask = np.zeros(n, bool)
+    mask[rows] = True
+    np.testing.assert_array_equal(part[mask], ref.a[mask])
+    assert (part[~mask] == 0).all()
