@@ -268,6 +268,21 @@ fmm_status fmm_momentum_stats_async(const double *x, const double *v, const doub
                                     const void *a, int32_t a_precision, int64_t n,
                                     fmm_stats *out, void *stream);
 
+/* fmm_momentum_stats_async for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same 16 values, bit for bit, written to DEVICE memory
+ * without waiting; the partial sums live in a fixed 64.1 KiB array of the
+ * library's code object on each device (held until the process ends), so
+ * the call allocates nothing, neither on its first call nor later.
+ *   out  device pointer to one fmm_stats (caller-owned).
+ * Calls that overlap on one device (other streams, other threads) race for
+ * that array; calls on one stream run in order.
+ * Errors: FMM_ERR_INVALID (NULL x, m, a or out, n < 1, unknown precision;
+ * nothing is launched), FMM_ERR_CAPACITY (n above 2^31 - 1), FMM_ERR_HIP. */
+fmm_status fmm_momentum_stats_noalloc(const double *x, const double *v, const double *m,
+                                      const void *a, int32_t a_precision, int64_t n,
+                                      fmm_stats *out, void *stream);
+
 /* Leapfrog update for kick-drift-kick time stepping with fixed dt:
  *   v += kick * a;  then  x += drift * v      (elementwise, FP64 state)
  * A KDK step is fmm_kick_drift(kick = dt/2, drift = dt), new forces, then

@@ -1140,6 +1140,26 @@ fmm_status fmm_momentum_stats_async(const double *x, const double *v, const doub
     return FMM_OK;
 }
 
+fmm_status fmm_momentum_stats_noalloc(const double *x, const double *v, const double *m,
+                                      const void *a, int32_t a_precision, int64_t n,
+                                      fmm_stats *out, void *stream)
+{
+    if (!x || !m || !a || !out)
+        return fail(FMM_ERR_INVALID, "x, m, a and out must not be NULL");
+    if (n < 1)
+        return fail(FMM_ERR_INVALID, "n must be positive");
+    if (n > NOALLOC_MAX_N)
+        return fail(FMM_ERR_CAPACITY, "n = %lld exceeds the %lld particles the no-allocation "
+                    "statistics accept", (long long)n, (long long)NOALLOC_MAX_N);
+    if (a_precision != FMM_FP64 && a_precision != FMM_FP32)
+        return fail(FMM_ERR_INVALID, "unknown precision %d", a_precision);
+    double *scr = nullptr;
+    HIP_TRY(stats_noalloc_scratch(&scr));
+    HIP_TRY(launch_stats(x, v, m, a, a_precision == FMM_FP32, n, scr, (double *)out, nullptr,
+                         (hipStream_t)stream));
+    return FMM_OK;
+}
+
 fmm_status fmm_kick_drift(double *x, double *v, const void *a, int32_t a_precision, int64_t n,
                           double kick, double drift, void *stream)
 {

@@ -363,6 +363,8 @@ hipError_t launch_near(Tree &t, void *a, hipStream_t s);
 hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,
                         int a_fp32, int64_t n, double *red, double *d_out, double *h_out,
                         hipStream_t s);
+hipError_t stats_noalloc_scratch(double **ptr);
+constexpr int64_t NOALLOC_MAX_N = INT32_MAX;  // particles fmm_momentum_stats_noalloc accepts
 hipError_t launch_far_f64(Tree &t, hipStream_t s);
 int mutual_key_bits(const Tree &t);
 int mutual_iterations(const Tree &t);

@@ -4,6 +4,8 @@
 // FP64 throughout (also for FP32 accelerations).  The grid size depends on n
 // only and every reduction runs in a fixed order, so the result is bitwise
 // reproducible from run to run.
+#include <mutex>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -122,6 +124,40 @@ hipError_t launch_stats(const double *x, const double *v, const double *m, const
     if (e != hipSuccess)
         return e;
     return hipStreamSynchronize(s);
+}
+
+// ---------------------------------------------------------------- no-allocation form
+// fmm_momentum_stats_noalloc keeps its partial sums in this array instead of
+// an allocated buffer: 16 doubles of results after 16 x ST_MAX_BLOCKS
+// per-block partials, one copy per device in the library's code object
+// (64.1 KiB, held until the process ends).  Every partial the final
+// reduction reads is written by the same call first, so nothing needs
+// clearing; calls that overlap on one device race for it.
+constexpr int NOALLOC_DOUBLES = 16 + 16 * ST_MAX_BLOCKS;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the host-side name is only a stand-in for the symbol).
+hipError_t stats_noalloc_scratch(double **ptr)
+{
+    static std::mutex mu;
+    static double *addr[64] = {};
+    int d = 0;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess)
+        return e;
+    if (d < 0 || d >= 64)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[d]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[d] = (double *)p;
+    }
+    *ptr = addr[d];
+    return hipSuccess;
 }
 
 }  // namespace fmm

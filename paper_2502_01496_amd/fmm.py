@@ -91,6 +91,8 @@ def lib() -> C.CDLL:
     L.fmm_momentum_stats.restype = st
     L.fmm_momentum_stats_async.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_int64, _vp, _vp]
     L.fmm_momentum_stats_async.restype = st
+    L.fmm_momentum_stats_noalloc.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, C.c_int64, _vp, _vp]
+    L.fmm_momentum_stats_noalloc.restype = st
     L.fmm_kick_drift.argtypes = [_vp, _vp, _vp, C.c_int32, C.c_int64, C.c_double, C.c_double,
                                  _vp]
     L.fmm_kick_drift.restype = st
@@ -248,6 +250,21 @@ def fmm_momentum_stats_async(x, v, m, a, out, stream=None):
     n = x.shape[0]
     prec = FMM_FP32 if a.dtype == torch.float32 else FMM_FP64
     _check(lib().fmm_momentum_stats_async(
+        _ptr(x, torch.float64, (n, 3), "x"),
+        _ptr(v, torch.float64, (n, 3), "v") if v is not None else None,
+        _ptr(m, torch.float64, (n,), "m"), _ptr(a, a.dtype, (n, 3), "a"), prec, n,
+        _ptr(out, torch.float64, (16,), "out"), _stream(stream)))
+
+
+def fmm_momentum_stats_noalloc(x, v, m, a, out, stream=None):
+    """fmm_momentum_stats_async without any device allocation (the partial
+    sums use a fixed array of the library): out is a float64 device tensor of
+    16 elements."""
+    import torch
+
+    n = x.shape[0]
+    prec = FMM_FP32 if a.dtype == torch.float32 else FMM_FP64
+    _check(lib().fmm_momentum_stats_noalloc(
         _ptr(x, torch.float64, (n, 3), "x"),
         _ptr(v, torch.float64, (n, 3), "v") if v is not None else None,
         _ptr(m, torch.float64, (n,), "m"), _ptr(a, a.dtype, (n, 3), "a"), prec, n,
