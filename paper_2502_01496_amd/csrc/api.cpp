@@ -278,6 +278,8 @@ static void release(Tree *t)
         tree_free(*t, t->held.back().first);
     if (t->mw.h_cnt)
         (void)hipHostFree(t->mw.h_cnt);
+    if (t->h_piece)
+        (void)hipHostFree(t->h_piece);
     if (t->h_flags)
         (void)hipHostFree(t->h_flags);
     if (t->h_red)
@@ -303,6 +305,10 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     // pair buffers exercise their overflow-and-retry path.
     if (const char *e = std::getenv("FMM_MI355_MW_CAP"))
         t->mw_init_cap = std::max<int64_t>(1, std::atoll(e));
+    // Test hook: small list pieces (near-field blocks and far-field entries
+    // per piece) put the split evaluation to work on ordinary trees.
+    if (const char *e = std::getenv("FMM_MI355_PIECE"))
+        t->near_piece_blocks = t->far_piece_entries = std::max<int64_t>(1, std::atoll(e));
     // Test hook: the full-key Morton sort from the first build on.
     if (const char *e = std::getenv("FMM_MI355_MORTON_FULL"))
         t->morton_full = std::atoi(e) != 0;
@@ -571,6 +577,7 @@ static fmm_status drop_slots(Tree &t)
     t.cap_far = t.cap_near = 0;
     t.slots_nl = 0;
     t.has_lists = t.has_forces = false;
+    t.pieces_valid = false;
     return FMM_OK;
 }
 
@@ -700,6 +707,94 @@ static fmm_status bad_input(uint32_t errbits)
                 (errbits & 1) ? " non-finite positions" : "",
                 (errbits & 2) ? " masses not positive and finite" : "",
                 (errbits & 4) ? " smoothing lengths not positive and finite" : "");
+}
+
+// Workspace of the list pieces that does not depend on the lists: pieces per
+// leaf, their offsets and the scan workspace (all or nothing).
+static fmm_status ensure_piece_base(Tree &t)
+{
+    if (t.pnear.np)
+        return FMM_OK;
+    const int64_t nl = t.topo.leaf_cap;
+    hipError_t e = hipSuccess;
+    for (Tree::Pieces *P : {&t.pnear, &t.pfar}) {
+        if (e == hipSuccess)
+            e = tree_malloc(t, (void **)&P->np, nl * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = tree_malloc(t, (void **)&P->off, (nl + 1) * sizeof(int64_t));
+        if (e == hipSuccess)
+            e = tree_malloc(t, (void **)&P->tsum, count_scan_workspace((int)nl) * sizeof(int64_t));
+    }
+    if (e == hipSuccess && !t.h_piece)
+        e = hipHostMalloc((void **)&t.h_piece, 2 * sizeof(int64_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        for (Tree::Pieces *P : {&t.pnear, &t.pfar}) {
+            tree_free(t, P->np);
+            tree_free(t, P->off);
+            tree_free(t, P->tsum);
+            P->np = nullptr;
+            P->off = P->tsum = nullptr;
+        }
+        return fail(FMM_ERR_ALLOC, "list pieces: %s", hipGetErrorString(e));
+    }
+    return FMM_OK;
+}
+
+// The piece totals (near, far) to the pinned host buffer.
+static hipError_t read_piece_totals_async(Tree &t, hipStream_t s)
+{
+    const int nl = t.topo.nleaves;
+    hipError_t e = hipMemcpyAsync(t.h_piece, t.pnear.off + nl, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t.h_piece + 1, t.pfar.off + nl, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           s);
+    return e;
+}
+
+// Lay out the pieces of the current lists: counts and offsets (unless the
+// totals were already read back with them, have_totals), buffers for the
+// pieces and their partial sums, and the piece lists.
+static fmm_status build_pieces(Tree &t, hipStream_t s, bool have_totals)
+{
+    fmm_status st = ensure_piece_base(t);
+    if (st != FMM_OK)
+        return st;
+    if (!have_totals) {
+        HIP_TRY(launch_piece_counts(t, s));
+        HIP_TRY(read_piece_totals_async(t, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    const size_t strides[2] = {(size_t)3 * t.topo.leaf_size * sizeof(double),
+                               (size_t)NLOC * sizeof(double)};
+    Tree::Pieces *Ps[2] = {&t.pnear, &t.pfar};
+    for (int k = 0; k < 2; ++k) {
+        Tree::Pieces &P = *Ps[k];
+        const int64_t np = t.h_piece[k];
+        if (np > P.cap) {
+            HIP_TRY(hipStreamSynchronize(s));
+            tree_free(t, P.list);
+            tree_free(t, P.part);
+            P.list = nullptr;
+            P.part = nullptr;
+            P.cap = 0;
+            const int64_t cap = np + np / 4 + 64;
+            hipError_t e = tree_malloc(t, (void **)&P.list, cap * sizeof(int2));
+            if (e == hipSuccess)
+                e = tree_malloc(t, &P.part, cap * strides[k]);
+            if (e != hipSuccess) {
+                tree_free(t, P.list);
+                P.list = nullptr;
+                return fail(FMM_ERR_ALLOC, "list pieces: %s", hipGetErrorString(e));
+            }
+            P.cap = cap;
+        }
+        P.n = np;
+        P.part_stride = strides[k];
+    }
+    HIP_TRY(launch_piece_fill(t, s));
+    t.pieces_valid = true;
+    return FMM_OK;
 }
 
 // Forces on kept lists: the data checks of the last moments call are read
@@ -991,13 +1086,17 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
                 return st;
         }
     }
-    // Optimistic order: walk, M2L, P2P, then one readback of the list maxima;
-    // if a slot overflowed, grow the slots and do it again.
-    for (int attempt = 0; attempt < 4; ++attempt) {
-        if (walk) {
-            StageTimer tm(t, s, 2);
-            HIP_TRY(launch_walk(t, s));
-            tm.done();
+    // Lists are evaluated whole, or split into pieces when the last walk
+    // found lists longer than one piece (the sums are bit-identical either
+    // way; pieces only balance the work).  Whole lists: walk, M2L, P2P, then
+    // one readback of the list maxima.  Split lists: the list lengths are read
+    // back first, then the pieces are laid out and evaluated.  If a slot
+    // overflowed, the slots grow and it is done again.
+    if (!walk) {
+        if (t.split_lists && !t.pieces_valid) {
+            fmm_status st = build_pieces(t, s, false);
+            if (st != FMM_OK)
+                return st;
         }
         {
             StageTimer tm(t, s, 3);
@@ -1009,8 +1108,34 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             HIP_TRY(launch_near(t, a, s));
             tm.done();
         }
-        if (!walk)
-            return check_data_after(t, s);
+        return check_data_after(t, s);
+    }
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        t.pieces_valid = false;
+        {
+            StageTimer tm(t, s, 2);
+            HIP_TRY(launch_walk(t, s));
+            tm.done();
+        }
+        const bool split = t.split_lists;
+        if (split) {
+            fmm_status st = ensure_piece_base(t);
+            if (st != FMM_OK)
+                return st;
+            HIP_TRY(launch_piece_counts(t, s));
+            HIP_TRY(read_piece_totals_async(t, s));
+        } else {
+            {
+                StageTimer tm(t, s, 3);
+                HIP_TRY(launch_far(t, s));
+                tm.done();
+            }
+            {
+                StageTimer tm(t, s, 4);
+                HIP_TRY(launch_near(t, a, s));
+                tm.done();
+            }
+        }
         HIP_TRY(hipMemcpyAsync(t.h_flags, t.walk_flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(read_err_async(t, s));
         HIP_TRY(hipMemcpyAsync(t.h_flags + 5, t.run_cnt + 2, 2 * sizeof(uint32_t),
@@ -1022,7 +1147,8 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             t.has_lists = false;
             return bad_input(errbits);
         }
-        if (t.h_flags[2]) {
+        const bool fallback = t.h_flags[2] != 0;
+        if (fallback) {
             // some leaves overflowed the wide walk's stack: redo those exactly
             HIP_TRY(launch_walk_fallback(t, s));
             HIP_TRY(hipMemcpyAsync(t.h_flags, t.walk_flags, 4 * sizeof(int32_t),
@@ -1035,15 +1161,35 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
                         "a sink list needs %lld entries (far) / %lld (near); list_capacity is %lld",
                         (long long)mf, (long long)mn, (long long)t.p.list_capacity);
         if (mf <= t.cap_far && mn <= t.cap_near) {
-            if (t.h_flags[2]) {  // lists were completed by the fallback: evaluate again
-                HIP_TRY(launch_far(t, s));
-                HIP_TRY(launch_near(t, a, s));
-            }
             t.has_lists = true;
             t.has_transposed = false;
             t.lists_policy = t.p.walk;
             t.nsinks = t.topo.nleaves;
             t.n_far = t.n_near = -1;  // totals computed on demand
+            t.max_far = (int32_t)mf;
+            t.max_near = (int32_t)mn;
+            const int nsub = (t.topo.leaf_size + 7) / 8;
+            t.split_lists = mf > t.far_piece_entries || mn * nsub > t.near_piece_blocks;
+            if (split || fallback) {
+                // evaluate now: on the pieces of these lists (their totals were
+                // read with the maxima unless the fallback changed the lists),
+                // or whole lists again after the fallback completed them
+                if (t.split_lists) {
+                    fmm_status st = build_pieces(t, s, split && !fallback);
+                    if (st != FMM_OK)
+                        return st;
+                }
+                {
+                    StageTimer tm(t, s, 3);
+                    HIP_TRY(launch_far(t, s));
+                    tm.done();
+                }
+                {
+                    StageTimer tm(t, s, 4);
+                    HIP_TRY(launch_near(t, a, s));
+                    tm.done();
+                }
+            }
             t.has_forces = true;
             return FMM_OK;
         }
@@ -1413,6 +1559,8 @@ fmm_status fmm_debug_import(fmm_tree *tree, const double *x, const double *m, co
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
     t.has_moments = t.has_lists = t.has_forces = false;
+    t.pieces_valid = false;
+    t.split_lists = false;
     fmm_status st = ensure_slots(t, std::max<int64_t>(mf, 1), std::max<int64_t>(mnr, 1));
     if (st != FMM_OK)
         return st;

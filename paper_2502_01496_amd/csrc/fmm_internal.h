@@ -117,6 +117,17 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks)
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// Position of piece k of leaf lf in a piece list: the extra pieces (k >= 1)
+// of split leaves come first, leaf by leaf (extra = off[nleaves] - nleaves of
+// them, off the exclusive scan of the pieces per leaf), then the first piece
+// of every leaf at extra + lf.  A leaf with one piece finishes in the kernel
+// that evaluates it; the folds visit the extra entries only.
+__device__ __forceinline__ int64_t piece_pos(const int64_t *__restrict__ off, int64_t extra,
+                                             int lf, int k)
+{
+    return k == 0 ? extra + lf : off[lf] - lf + (k - 1);
+}
+
 // ------------------------------------------------------------------ host
 // Data-independent shape of the median-split tree: with ceil(n/2) / floor(n/2)
 // children, node sizes (and so first/count/left/right) depend on n and the
@@ -332,6 +343,26 @@ struct Tree {
     double *asym = nullptr;
     double *h_asym = nullptr;       // pinned, 4
 
+    // Long interaction lists are split into pieces of bounded work, one
+    // wavefront (near field) or 16-lane group (far field) each, with partial
+    // sums folded per leaf in piece order; used when the last walk found a
+    // list longer than one piece (trees with a few very long lists).
+    struct Pieces {
+        int32_t *np = nullptr;    // pieces per leaf
+        int64_t *off = nullptr;   // nleaves + 1, first piece of each leaf
+        int64_t *tsum = nullptr;  // scan workspace
+        int2 *list = nullptr;     // (leaf, piece index) per piece
+        void *part = nullptr;     // partial sums per piece
+        int64_t cap = 0;          // pieces the list and partial buffers hold
+        int64_t n = 0;            // pieces of the current lists
+        size_t part_stride = 0;   // bytes of partial sums per piece
+    } pnear, pfar, pnearT;  // forward near and far lists; transposed near lists
+    bool split_lists = false;     // the last walk's lists are split (predicted for the next)
+    bool pieces_valid = false;    // pnear / pfar describe the current lists
+    int64_t near_piece_blocks = 512, far_piece_entries = 1024;  // test hook: FMM_MI355_PIECE
+    int32_t max_far = 0, max_near = 0;  // longest lists of the last walk
+    int64_t *h_piece = nullptr;         // pinned: piece totals (near, far)
+
     bool has_tree = false, has_moments = false, has_lists = false, has_forces = false;
     int lists_policy = -1;
 
@@ -348,6 +379,7 @@ hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                           int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s);
 
+
 // launchers (return hipError_t of the last launch / runtime call)
 hipError_t launch_build(Tree &t, const double *x, hipStream_t s);
 hipError_t launch_morton_order(Tree &t, const double *x, hipStream_t s);
@@ -360,6 +392,20 @@ hipError_t launch_walk(Tree &t, hipStream_t s);
 hipError_t launch_walk_fallback(Tree &t, hipStream_t s);
 hipError_t launch_far(Tree &t, hipStream_t s);
 hipError_t launch_near(Tree &t, void *a, hipStream_t s);
+hipError_t launch_count_scan(const int32_t *cnt, int cap, int n, int64_t *tsum, int64_t *off,
+                             hipStream_t s);
+int64_t count_scan_workspace(int n);
+hipError_t launch_piece_counts(Tree &t, hipStream_t s);
+hipError_t launch_piece_fill(Tree &t, hipStream_t s);
+hipError_t launch_piece_table(const int64_t *off, const int32_t *np, int nleaves, int2 *list,
+                              hipStream_t s);
+
+// The forward lists are split into pieces (the last walk found a list
+// longer than one piece, and the piece tables describe the current lists).
+inline bool use_pieces(const Tree &t)
+{
+    return t.split_lists && t.pieces_valid && t.lists_policy == FMM_WALK_PHANTOM;
+}
 hipError_t launch_stats(const double *x, const double *v, const double *m, const void *a,
                         int a_fp32, int64_t n, double *red, double *d_out, double *h_out,
                         hipStream_t s);

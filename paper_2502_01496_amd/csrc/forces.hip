@@ -151,51 +151,147 @@ __device__ __forceinline__ void m2l_acc(T rx, T ry, T rz, T M, const T *Q, T *L)
              b3 * (T(3) * rz * Qzz);
 }
 
-// ---------------------------------------------------------------- M2L, FP64
-// 16 lanes per sink leaf, 4 sinks per wave; lanes stride the far list, then a
-// butterfly sum over the 16 lanes (fixed order: deterministic).
+// ---------------------------------------------------------------- list pieces
+// Pieces per leaf for a list of min(cnt, cap) entries of `mult` work units
+// each: ceil(work / per), at least one.
+__global__ void k_piece_count(const int32_t *__restrict__ cnt, int cap, int nleaves, int mult,
+                              int64_t per, int32_t *np)
+{
+    const int lf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves)
+        return;
+    const int64_t wk = (int64_t)max(0, min(cnt[lf], cap)) * mult;
+    np[lf] = (int32_t)max<int64_t>(1, (wk + per - 1) / per);
+}
+
+__global__ void k_piece_fill(const int64_t *__restrict__ off, const int32_t *__restrict__ np,
+                             int nleaves, int2 *list)
+{
+    const int lf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves)
+        return;
+    const int64_t extra = off[nleaves] - nleaves;
+    for (int k = 0; k < np[lf]; ++k)
+        list[piece_pos(off, extra, lf, k)] = make_int2(lf, k);
+}
+
+// Folding the partial sums of a split leaf's pieces, in piece order: one
+// thread per extra list entry, the one holding piece 1 of its leaf folds it.
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_fold(const int32_t *__restrict__ leaf_node,
+                                                  const int64_t *__restrict__ off,
+                                                  const int2 *__restrict__ list, int extra,
+                                                  const T *__restrict__ part, T *Lout)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= extra || list[e].y != 1)
+        return;
+    const int lf = list[e].x;
+    T L[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        L[k] = T(0);
+    const int np = (int)(off[lf + 1] - off[lf]);
+    for (int q = 0; q < np; ++q) {
+        const T *pp = part + (int64_t)NLOC * piece_pos(off, extra, lf, q);
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            L[k] += pp[k];
+    }
+    T *o = Lout + (int64_t)NLOC * leaf_node[lf];
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        o[k] = L[k];
+    o[19] = T(0);
+}
+
+// ---------------------------------------------------------------- M2L at the leaves
+// One source of the leaf M2L: FP64 records, or the FP32 form (r formed in
+// FP64 and rounded, M and Q from the FP32 mirror of the records, FP32
+// accumulation).
 template <int FORM>
-__global__ __launch_bounds__(256) void k_m2l_leaf_f64(
+__device__ __forceinline__ void m2l_leaf_src(const double *__restrict__ recA,
+                                             const double *__restrict__ recQ, const float *,
+                                             int b, double c0, double c1, double c2, double *L)
+{
+    const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
+    const double *qb = recQ + (int64_t)NREC * b;
+    const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
+                  q45 = *(const double2 *)(qb + 4);
+    const double Q[6] = {q01.x, q01.y, q23.x, q23.y, q45.x, q45.y};
+    m2l_acc<double, FORM>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
+}
+template <int FORM>
+__device__ __forceinline__ void m2l_leaf_src(const double *__restrict__ recA, const double *,
+                                             const float *__restrict__ recF, int b, double c0,
+                                             double c1, double c2, float *L)
+{
+    const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
+    const float4 f0 = *(const float4 *)(recF + (int64_t)NREC * b);
+    const float4 f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
+    const float Q[6] = {f0.y, f0.z, f0.w, f1.x, f1.y, f1.z};
+    m2l_acc<float, FORM>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
+}
+
+// M2L of eq. (6) at the sink leaves.  16 lanes per unit, 4 units per wave;
+// lanes stride the far list, and a butterfly sum over the 16 lanes ends each
+// piece of `per` list entries; piece sums add up in piece order, starting
+// from zero (fixed order: deterministic).  A unit is a leaf (pieces == nullptr: all its pieces in
+// turn, total to Lout) or one entry of the piece list: the only piece of its
+// leaf (total to Lout) or one piece of a split list (its sum to part, added
+// by k_m2l_fold), with bit-identical totals either way.
+template <typename T, int FORM>
+__global__ __launch_bounds__(256) void k_m2l_leaf(
     const double *__restrict__ recA, const double *__restrict__ recQ,
-    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
-    const int32_t *__restrict__ far_src, int cap_far, double *Lout)
+    const float *__restrict__ recF, const int32_t *__restrict__ leaf_node, int nunits,
+    const int32_t *__restrict__ far_cnt, const int32_t *__restrict__ far_src, int cap_far,
+    T *Lout, const int2 *__restrict__ pieces, int per, T *part)
 {
     const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
     const int sub = threadIdx.x & 15;
-    const bool valid = g < nleaves;
-    const int v = valid ? leaf_node[g] : 0;
+    const bool valid = g < nunits;
+    const int2 pc = pieces && valid ? pieces[g] : make_int2(valid ? g : 0, 0);
+    const int lf = pc.x;
+    const int v = valid ? leaf_node[lf] : 0;
     const double *rv = recA + (int64_t)NREC * v;
     const double c0 = rv[0], c1 = rv[1], c2 = rv[2];
-    double L[19];
-#pragma unroll
-    for (int k = 0; k < 19; ++k)
-        L[k] = 0.0;
-    const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
-    const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
-    // the next source's index is loaded one interaction ahead
-    int bn = sub < nk ? fl[sub] : 0;
-    for (int k = sub; k < nk; k += 16) {
-        const int b = bn;
-        if (k + 16 < nk)
-            bn = fl[k + 16];
-        const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
-        const double *qb = recQ + (int64_t)NREC * b;
-        const double2 q01 = *(const double2 *)qb, q23 = *(const double2 *)(qb + 2),
-                      q45 = *(const double2 *)(qb + 4);
-        const double Q[6] = {q01.x, q01.y, q23.x, q23.y, q45.x, q45.y};
-        m2l_acc<double, FORM>(c0 - cb.x, c1 - cb.y, c2 - cb.z, cb.w, Q, L);
-    }
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1)
-#pragma unroll
-        for (int k = 0; k < 19; ++k)
-            L[k] += __shfl_xor(L[k], off);
+    const int nfull = valid ? max(0, min(far_cnt[lf], cap_far)) : 0;
+    const int lo = pieces ? pc.y * per : 0;
+    const int hi = pieces ? min(nfull, lo + per) : nfull;
+    const int32_t *fl = far_src + (int64_t)lf * cap_far;
+    const bool split = pieces && nfull > per;
+    T *o = split ? part + (int64_t)NLOC * g : Lout + (int64_t)NLOC * v;
     if (valid && sub == 0) {
-        double *o = Lout + (int64_t)NLOC * v;
+#pragma unroll
+        for (int k = 0; k < NLOC; ++k)
+            o[k] = T(0);
+    }
+    for (int p0 = lo; p0 < hi; p0 += per) {
+        const int p1 = min(hi, p0 + per);
+        T L[19];
 #pragma unroll
         for (int k = 0; k < 19; ++k)
-            o[k] = L[k];
-        o[19] = 0.0;
+            L[k] = T(0);
+        // the next source's index is loaded one interaction ahead
+        int bn = p0 + sub < p1 ? fl[p0 + sub] : 0;
+        for (int k = p0 + sub; k < p1; k += 16) {
+            const int b = bn;
+            if (k + 16 < p1)
+                bn = fl[k + 16];
+            m2l_leaf_src<FORM>(recA, recQ, recF, b, c0, c1, c2, L);
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+            for (int k = 0; k < 19; ++k)
+                L[k] += __shfl_xor(L[k], off);
+        // the piece sums add up in the output itself (no registers held for a
+        // running total), in piece order: 0 + L_0 + L_1 + ...
+        if (valid && sub == 0) {
+#pragma unroll
+            for (int k = 0; k < 19; ++k)
+                o[k] = o[k] + L[k];
+        }
     }
 }
 
@@ -210,162 +306,143 @@ __device__ __forceinline__ double m4g_f64(double q, double hinv3, double u3)
     return __builtin_unpredictable(q < 1.0) ? p1 : g;
 }
 
-// m / r^3 for finite r2 > 0: hardware reciprocal square root y, refined with
-// the series (1 - e)^(-3/2) = 1 + 3/2 e + 15/8 e^2 + O(e^3), e = 1 - r2 y^2
-// (r^-3 = y^3 (1 - e)^(-3/2)).
+// m / r^3 for finite r2 > 0: the hardware reciprocal square root y refined
+// once with the series (1 - e)^(-1/2) = 1 + e/2 + 3/8 e^2 + O(e^3),
+// e = 1 - r2 y^2, then cubed.
 __device__ __forceinline__ double m_over_r3(double r2, double m)
 {
     const double y = __builtin_amdgcn_rsq(r2);
-    const double t = y * y;
-    const double e = fma(-r2, t, 1.0);
-    const double my3 = m * (t * y);
-    return fma(my3, e * fma(e, 1.875, 1.5), my3);
+    const double e = fma(-(r2 * y), y, 1.0);
+    const double u = fma(y * e, fma(e, 0.375, 0.5), y);
+    return m * ((u * u) * u);
 }
 
-// Reduce-scatter of 12 per-lane doubles over the 64 lanes of a wavefront.
+// Reduce-scatter of 24 per-lane values over the 64 lanes of a wavefront.
 // Each xor step halves the set of values a lane keeps (it sends the other
-// half to its partner); after the steps over lane bits 5..2 a lane holds the
-// partial sum of one value, and two plain butterfly steps finish the sum in
-// each group of four lanes.  Value index held by lane l:
-//   6 b5 + 3 b4 + (2 b3 + b2), valid when (2 b3 + b2) < 3.
-__device__ __forceinline__ double xchg_keep(double keep, double send, int off)
+// half to its partner); after the steps over lane bits 5..1 a lane holds the
+// partial sum of one value, and a last butterfly step finishes it.  Value
+// index held by lane l: 12 b5 + 6 b4 + 3 b3 + (2 b2 + b1), valid when
+// (2 b2 + b1) < 3.
+template <typename T>
+__device__ __forceinline__ T xchg_keep(T keep, T send, int off)
 {
     return keep + __shfl_xor(send, off);
 }
 
-__device__ __forceinline__ double reduce_scatter12(const double *v, int lane, int &idx)
+// Value index a lane holds after reduce_scatter24 (-1: none).
+__device__ __forceinline__ int rs24_index(int lane)
 {
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
-    double a[6];
+    const int sub = 2 * ((lane >> 2) & 1) + ((lane >> 1) & 1);
+    return sub < 3 ? 12 * ((lane >> 5) & 1) + 6 * ((lane >> 4) & 1) + 3 * ((lane >> 3) & 1) + sub
+                   : -1;
+}
+
+template <typename T>
+__device__ __forceinline__ T reduce_scatter24(const T *v, int lane)
+{
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    T a[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        a[k] = xchg_keep<T>(b5 ? v[12 + k] : v[k], b5 ? v[k] : v[12 + k], 32);
+    T b[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-        a[k] = xchg_keep(b5 ? v[6 + k] : v[k], b5 ? v[k] : v[6 + k], 32);
-    double b[3];
+        b[k] = xchg_keep<T>(b4 ? a[6 + k] : a[k], b4 ? a[k] : a[6 + k], 16);
+    T cc[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        b[k] = xchg_keep(b4 ? a[3 + k] : a[k], b4 ? a[k] : a[3 + k], 16);
-    // 3 values -> pad to 4 -> 2 (bit 3)
-    const double c0 = xchg_keep(b3 ? b[2] : b[0], b3 ? b[0] : b[2], 8);
-    const double c1 = xchg_keep(b3 ? 0.0 : b[1], b3 ? b[1] : 0.0, 8);
-    // 2 -> 1 (bit 2)
-    double d = xchg_keep(b2 ? c1 : c0, b2 ? c0 : c1, 4);
-    d += __shfl_xor(d, 2);
-    d += __shfl_xor(d, 1);
-    idx = 6 * (int)b5 + 3 * (int)b4 + (2 * (int)b3 + (int)b2);
-    const bool ok = (2 * (int)b3 + (int)b2) < 3;
-    if (!ok)
-        idx = -1;
-    return d;
+        cc[k] = xchg_keep<T>(b3 ? b[3 + k] : b[k], b3 ? b[k] : b[3 + k], 8);
+    const T d0 = xchg_keep<T>(b2 ? cc[2] : cc[0], b2 ? cc[0] : cc[2], 4);
+    const T d1 = xchg_keep<T>(b2 ? T(0) : cc[1], b2 ? cc[1] : T(0), 4);
+    T e = xchg_keep<T>(b1 ? d1 : d0, b1 ? d0 : d1, 2);
+    e += __shfl_xor(e, 1);
+    return e;
 }
 
-// Near field, source-per-lane form.  One wavefront per sink leaf; a step
-// takes 8 source blocks (a near leaf contributes ceil(leaf_size / 8) blocks of
-// at most 8 particles), lane = 8 g + t holds particle t of the g-th block
-// (loaded once: no redundant traffic), and the sink particles, 4 per pass, are
-// wave-uniform.  The block ranges are staged in LDS once per chunk of the near
-// list, and the sources of the next step are loaded while the current step
-// computes.  Missing sources are placed far away with zero mass, so they add
-// exactly zero.  For each sink, a step whose 64 pairs all lie outside both
-// smoothing supports takes the Newtonian branch only.  The per-lane sums are
-// reduce-scattered so that the lane holding component c of sink s adds L2P
-// and writes G * a.
-constexpr int P2P_RANGES = 512;  // source blocks staged in LDS per wavefront
+// Near field.  One wavefront per sink leaf; P2P_NS sink particles per pass
+// are wave-uniform, and a step takes 8 source blocks (a near leaf gives
+// ceil(leaf_size / 8) blocks of at most 8 particles): lane = 8 g + t holds
+// particle t of the g-th block, loaded once per pass.  The block ranges of
+// a chunk of the near list are staged in LDS (empty blocks dropped), and the
+// next step's sources load while the current step computes.  Missing
+// sources are the null record (far away, zero mass, zero smoothing length),
+// which adds exactly zero.
+//
+// Every pair is first tested against the softening support of eqs. (14)-(15),
+// with the largest 4 h^2 of the pass's sinks standing in for the sink's own:
+// r^2 < max(H4, 4 h_j^2).  Pairs outside it are Newtonian for certain and
+// take the form m / r^3 in the step.  Pairs inside are appended to their
+// sink's queue in LDS (the source's tree position) and evaluated with the M4
+// kernel, which is exact on both sides of the support, 64 at a time, so that
+// the softened form runs with every lane busy instead of stalling a whole
+// step whenever one of its pairs may be softened (a queue is drained each
+// time it has gathered 64 pairs, and at the end of the pass).  The order of
+// all additions depends on the lists only, so results are bitwise
+// reproducible.
+// The per-lane sums are reduce-scattered so that the lane holding component
+// c of sink s adds L2P and writes G * a.
+constexpr int P2P_NS = 8;        // sinks per pass
+constexpr int P2P_QCAP = 128;    // softened pairs a sink's queue holds (a step adds <= 64)
+constexpr int P2P_BLOCKS = 256;  // source blocks staged in LDS per chunk
 
-// While staging a chunk of the near list, source blocks of leaves whose
-// centre lies within CLOSE_FRAC of the softening bound of eq. (5),
-//   |c_a - c_b| < CLOSE_FRAC ((s_a + s_b) + R_kern max(h_a, h_b)),
-// are placed first and the others after them (each group in list order).
-// The softened branch runs for a whole step of eight source blocks if any
-// pair in it is softened, so gathering the close leaves leaves more steps
-// on the Newtonian branch.  Deterministic: the order depends on the list only.
-constexpr double CLOSE_FRAC2 = 0.49;  // CLOSE_FRAC = 0.7, squared
-
-// Position of a block in the partitioned chunk; front / back are the
-// wave-uniform fill positions (front grows from 0, back shrinks from nc).
-__device__ __forceinline__ int close_first_slot(bool act, bool close, int &front, int &back)
+// Stage the non-empty blocks of list entries [c0, c0 + nc) (entry k: block
+// k % nsub of near leaf k / nsub) in list order; returns their number.
+__device__ __forceinline__ int stage_blocks_in_order(const int32_t *__restrict__ nl, int c0, int nc,
+                                                     int nsub, const int32_t *__restrict__ first,
+                                                     const int32_t *__restrict__ count, int lane,
+                                                     int2 *R)
 {
-    const uint64_t lt = lanemask_lt();
-    const uint64_t mc = __ballot(act && close), mf = __ballot(act && !close);
-    const int nf = __popcll(mf);
-    const int pos = close ? front + __popcll(mc & lt) : back - nf + __popcll(mf & lt);
-    front += __popcll(mc);
-    back -= nf;
-    return pos;
-}
-
-// Stage list position k of a chunk of the near list (list entries c0 / nsub
-// onward, nsub blocks of at most 8 particles per leaf): its block goes to the
-// close or the far group, or is dropped when empty (a leaf of at most 8 u
-// particles has no block u).
-__device__ __forceinline__ void stage_block(const int32_t *__restrict__ nl, int c0, int k, int nc,
-                                            int nsub, const int32_t *__restrict__ first,
-                                            const int32_t *__restrict__ count,
-                                            const double *__restrict__ recA, const double *rv,
-                                            double r_kern, int2 *R, int &front, int &back)
-{
-    int2 r = make_int2(0, 0);
-    bool close = false;
-    if (k < nc) {
-        const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
-        const int bn = nl[e];
-        r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
-        const double *rb = recA + (int64_t)NREC * bn;
-        const double dx = rv[0] - rb[0], dy = rv[1] - rb[1], dz = rv[2] - rb[2];
-        const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
-        close = dx * dx + dy * dy + dz * dz < CLOSE_FRAC2 * t5 * t5;
-    }
-    const bool keep = r.y > 0;
-    const int pos = close_first_slot(keep, close, front, back);
-    if (keep)
-        R[pos] = r;
-}
-
-// Block of step position k: the close blocks [0, front), then the far ones
-// after the gap left by the dropped blocks.
-__device__ __forceinline__ int skip_gap(int k, int front, int gap)
-{
-    return k < front ? k : k + gap;
-}
-
-// Missing sources read the null record at index n (far away, zero mass,
-// zero smoothing length), so they add exactly zero.
-__device__ __forceinline__ void load_src(const double4 *__restrict__ pm,
-                                         const double4 *__restrict__ ph, int64_t nnull, int2 rg,
-                                         int slot, double4 &xj, double4 &hj)
-{
-    const int64_t j = slot < rg.y ? (int64_t)rg.x + slot : nnull;
-    xj = pm[j];
-    hj = ph[j];
-}
-
-// Pairs of one step: the NS wave-uniform sinks against this lane's source.
-template <int NS>
-__device__ __forceinline__ void p2p_step_f64(const double (&sx)[NS], const double (&sy)[NS],
-                                             const double (&sz)[NS], const double (&shi)[NS],
-                                             const double (&sh3)[NS], const double (&sh4)[NS],
-                                             const double4 xj, const double4 hj,
-                                             double (&acc)[3 * NS])
-{
-    const double mh = 0.5 * xj.w;
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        double fm;
-        if ((__ballot(r2 < hj.z) | __ballot(r2 < sh4[q])) == 0ull) {
-            fm = m_over_r3(r2, xj.w);
-        } else {
-            const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
-            const double r = r2 * u;
-            const double u3 = u * u * u;
-            const double gi = m4g_f64(r * shi[q], sh3[q], u3);
-            const double gj = m4g_f64(r * hj.x, hj.y, u3);
-            fm = mh * (gi + gj);
+    int ne = 0;
+    for (int k0 = 0; k0 < nc; k0 += 64) {
+        const int k = k0 + lane;
+        int2 r = make_int2(0, 0);
+        if (k < nc) {
+            const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
+            const int bn = nl[e];
+            r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
         }
-        acc[3 * q] -= fm * dx;
-        acc[3 * q + 1] -= fm * dy;
-        acc[3 * q + 2] -= fm * dz;
+        const bool keep = r.y > 0;
+        const uint64_t mk = __ballot(keep);
+        if (keep)
+            R[ne + __popcll(mk & lanemask_lt())] = r;
+        ne += __popcll(mk);
     }
+    if (lane < 8)
+        R[ne + lane] = make_int2(0, 0);  // eight empty blocks after the last one
+    return ne;
+}
+
+// Source particle of a lane in block rg (the null record past its end).
+__device__ __forceinline__ int64_t block_src(int2 rg, int slot, int64_t nnull)
+{
+    return slot < rg.y ? (int64_t)rg.x + slot : nnull;
+}
+
+// The softened pairs of sink q: cnt <= 64 entries of its queue from position
+// head, one per lane, with the mean of the two M4 kernels.
+template <int NS>
+__device__ __forceinline__ void p2p_drain_f64(const double4 *__restrict__ pm,
+                                              const double4 *__restrict__ ph,
+                                              const int32_t *Q, int head, int cnt, int lane,
+                                              int64_t nnull, double sx, double sy, double sz,
+                                              double shi, double sh3, double &ax, double &ay,
+                                              double &az)
+{
+    const int64_t j = lane < cnt ? (int64_t)Q[(head + lane) & (P2P_QCAP - 1)] : nnull;
+    const double4 xj = pm[j];
+    const double4 hj = ph[j];
+    const double dx = sx - xj.x, dy = sy - xj.y, dz = sz - xj.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+    const double r = r2 * u;
+    const double u3 = u * u * u;
+    const double gi = m4g_f64(r * shi, sh3, u3);
+    const double gj = m4g_f64(r * hj.x, hj.y, u3);
+    const double fm = 0.5 * xj.w * (gi + gj);
+    ax -= fm * dx;
+    ay -= fm * dy;
+    az -= fm * dz;
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_p2p_src_f64(
@@ -374,74 +451,122 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
     const int32_t *__restrict__ near_src, int cap_near, int nsub, const double *__restrict__ Lloc,
     const double *__restrict__ recA, const int32_t *__restrict__ perm, double G, double r_kern,
-    int64_t nnull, double *aout)
+    int64_t nnull, double *aout, const int2 *__restrict__ pieces, int per, double *part,
+    int part_stride)
 {
-    constexpr int NS = 4;
-    __shared__ int2 rng[4][P2P_RANGES + 8];
+    constexpr int NS = P2P_NS;
+    __shared__ int2 rng[4][P2P_BLOCKS + 8];
+    __shared__ int32_t que[4][NS][P2P_QCAP];
+    __shared__ double2 shh[4][NS];  // 1/h, 1/h^3 of the pass's sinks
+    (void)r_kern;
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
-    if (leaf >= nleaves)
+    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    if (unit >= nleaves)
         return;
     const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
     const int grp = lane >> 3, slot = lane & 7;
+    const int2 pc = pieces ? pieces[unit] : make_int2(unit, 0);
+    const int leaf = pc.x;
     const int v = leaf_node[leaf];
     const int64_t f = first[v];
     const int c = count[v];
-    const int nb = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int nbf = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int b_lo = pieces ? pc.y * per : 0;
+    const int b_hi = pieces ? min(nbf, b_lo + per) : nbf;
     const int32_t *nl = near_src + (int64_t)leaf * cap_near;
     const double *rv = recA + (int64_t)NREC * v;
     const double *Lv = Lloc + (int64_t)NLOC * v;
     int2 *R = rng[w];
     for (int sb = 0; sb < c; sb += NS) {
-        double sx[NS], sy[NS], sz[NS], shi[NS], sh3[NS], sh4[NS];
+        double sx[NS], sy[NS], sz[NS], H4 = 0.0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             const int64_t is = f + min(sb + q, c - 1);
             const double4 x4 = pm[is];
-            const double4 h4 = ph[is];
             sx[q] = x4.x;
             sy[q] = x4.y;
             sz[q] = x4.z;
-            shi[q] = h4.x;
-            sh3[q] = h4.y;
-            sh4[q] = h4.z;
+            const double h4q = ph[is].z;
+            H4 = h4q > H4 ? h4q : H4;
         }
+        if (lane < NS) {
+            const double4 h4 = ph[f + min(sb + lane, c - 1)];
+            shh[w][lane] = make_double2(h4.x, h4.y);
+        }
+        // pieces of `per` source blocks: each ends with its queues drained
+        // and its per-lane sums reduce-scattered, and the piece sums add up
+        // in piece order (the same sums, bit for bit, whether a wavefront
+        // takes all of a leaf's pieces or one piece each)
+        double tot = 0.0;
         double acc[3 * NS];
+        int tail[NS];  // queue fill counts; entries [tail & ~63, tail) are pending
+        auto drain = [&](int q, int head, int cnt) {
+            const double2 hs = shh[w][q];
+            p2p_drain_f64<NS>(pm, ph, que[w][q], head, cnt, lane, nnull, sx[q], sy[q], sz[q],
+                              hs.x, hs.y, acc[3 * q], acc[3 * q + 1], acc[3 * q + 2]);
+        };
+        for (int p0 = b_lo; p0 < b_hi; p0 += per) {
+        const int nb = min(b_hi, p0 + per);
 #pragma unroll
         for (int q = 0; q < 3 * NS; ++q)
             acc[q] = 0.0;
-        for (int c0 = 0; c0 < nb; c0 += P2P_RANGES) {
-            const int nc = min(nb - c0, P2P_RANGES);
-            // stage the source blocks of this chunk, close leaves first
-            int front = 0, back = nc;
-            for (int k0 = 0; k0 < nc; k0 += 64)
-                stage_block(nl, c0, k0 + lane, nc, nsub, first, count, recA, rv, r_kern, R,
-                            front, back);
-            // the dropped (empty) blocks leave a gap between the close and the
-            // far ones; eight empty blocks follow the last one
-            front = __builtin_amdgcn_readfirstlane(front);
-            const int gap = __builtin_amdgcn_readfirstlane(back - front), ne = nc - gap;
-            if (lane < 8)
-                R[nc + lane] = make_int2(0, 0);
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            tail[q] = 0;
+        for (int c0 = p0; c0 < nb; c0 += P2P_BLOCKS) {
+            const int nc = min(nb - c0, P2P_BLOCKS);
+            const int ne = __builtin_amdgcn_readfirstlane(
+                stage_blocks_in_order(nl, c0, nc, nsub, first, count, lane, R));
             __builtin_amdgcn_wave_barrier();
-            // the next step's sources load while the current step computes
-            double4 xj, hj;
-            load_src(pm, ph, nnull, R[skip_gap(grp, front, gap)], slot, xj, hj);
             for (int kb = 0; kb < ne; kb += 8) {
-                double4 xn = xj, hn = hj;
-                if (kb + 8 < ne)
-                    load_src(pm, ph, nnull, R[skip_gap(kb + 8 + grp, front, gap)], slot, xn,
-                             hn);
-                p2p_step_f64<NS>(sx, sy, sz, shi, sh3, sh4, xj, hj, acc);
-                xj = xn;
-                hj = hn;
+                // (the latency of these loads is covered by the other
+                // wavefronts of the SIMD: no registers are held for a prefetch)
+                const int32_t j = (int32_t)block_src(R[kb + grp], slot, nnull);
+                const double4 xj = pm[j];
+                const double hj4 = ph[j].z;
+                const double hmax4 = hj4 > H4 ? hj4 : H4;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    // (every lane is active here: the softened mask is the
+                    // complement of the Newtonian one)
+                    const bool newt = !(r2 < hmax4);
+                    const uint64_t bal = ~__ballot(newt);
+                    const double fm = newt ? m_over_r3(r2, xj.w) : 0.0;
+                    acc[3 * q] -= fm * dx;
+                    acc[3 * q + 1] -= fm * dy;
+                    acc[3 * q + 2] -= fm * dz;
+                    if (bal) {
+                        // possibly softened pairs leave the step for the sink's queue
+                        const int t0 = tail[q];
+                        if (!newt)
+                            que[w][q][(t0 + __popcll(bal & lt)) & (P2P_QCAP - 1)] = j;
+                        tail[q] = t0 + __popcll(bal);
+                        // a queue that has gathered another 64 pairs is evaluated
+                        if ((tail[q] >> 6) != (t0 >> 6)) {
+                            __builtin_amdgcn_wave_barrier();
+                            drain(q, t0 & ~63, 64);
+                        }
+                    }
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
-        int idx;
-        const double tot = reduce_scatter12(acc, lane, idx);
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+            if (tail[q] & 63)
+                drain(q, tail[q] & ~63, tail[q] & 63);
+        __builtin_amdgcn_wave_barrier();
+        tot += reduce_scatter24<double>(acc, lane);
+        }
+        const int idx = rs24_index(lane);
         const int q = idx / 3, comp = idx - 3 * (idx / 3);
-        if (idx >= 0 && (lane & 3) == 0 && sb + q < c) {
+        if (pieces && nbf > per) {
+            if (idx >= 0 && (lane & 1) == 0 && sb + q < c)
+                part[(int64_t)unit * part_stride + 3 * (sb + q) + comp] = tot;
+        } else if (idx >= 0 && (lane & 1) == 0 && sb + q < c) {
             // component comp of eq. (8) at sink q
             double sxq = sx[0], syq = sy[0], szq = sz[0];
 #pragma unroll
@@ -461,57 +586,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             const int64_t o = 3 * (int64_t)perm[f + sb + q] + comp;
             aout[o] = G * (far_c + tot);
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 // ---------------------------------------------------------------- FP32 form
-// M2L in FP32: r = c_sink - c_source is formed in FP64 and rounded, M and Q
-// come from the FP32 mirror of the cell records, and the 19 coefficients are
-// accumulated in FP32.
-template <int FORM>
-__global__ __launch_bounds__(256) void k_m2l_leaf_f32(
-    const double *__restrict__ recA, const float *__restrict__ recF,
-    const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
-    const int32_t *__restrict__ far_src, int cap_far, float *Lout)
-{
-    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
-    const int sub = threadIdx.x & 15;
-    const bool valid = g < nleaves;
-    const int v = valid ? leaf_node[g] : 0;
-    const double *rv = recA + (int64_t)NREC * v;
-    const double c0 = rv[0], c1 = rv[1], c2 = rv[2];
-    float L[19];
-#pragma unroll
-    for (int k = 0; k < 19; ++k)
-        L[k] = 0.0f;
-    const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
-    const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
-    int bn = sub < nk ? fl[sub] : 0;
-    for (int k = sub; k < nk; k += 16) {
-        const int b = bn;
-        if (k + 16 < nk)
-            bn = fl[k + 16];
-        const double4 cb = *(const double4 *)(recA + (int64_t)NREC * b);
-        const float4 f0 = *(const float4 *)(recF + (int64_t)NREC * b);
-        const float4 f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
-        const float Q[6] = {f0.y, f0.z, f0.w, f1.x, f1.y, f1.z};
-        m2l_acc<float, FORM>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q,
-                             L);
-    }
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1)
-#pragma unroll
-        for (int k = 0; k < 19; ++k)
-            L[k] += __shfl_xor(L[k], off);
-    if (valid && sub == 0) {
-        float *o = Lout + (int64_t)NLOC * v;
-#pragma unroll
-        for (int k = 0; k < 19; ++k)
-            o[k] = L[k];
-        o[19] = 0.0f;
-    }
-}
-
 __device__ __forceinline__ float m4g_f32(float q, float hinv3, float u3)
 {
     // both pieces are evaluated and selected (no divergent branches)
@@ -522,67 +601,74 @@ __device__ __forceinline__ float m4g_f32(float q, float hinv3, float u3)
     return __builtin_unpredictable(q < 1.0f) ? p1 : g;
 }
 
-__device__ __forceinline__ float xchg_keep_f(float keep, float send, int off)
-{
-    return keep + __shfl_xor(send, off);
-}
-
-// Reduce-scatter of 24 per-lane floats over the wavefront (same scheme as
-// the 12-value FP64 version, one more halving).  Value index held by lane l:
-//   12 b5 + 6 b4 + 3 b3 + (2 b2 + b1), valid when (2 b2 + b1) < 3.
-__device__ __forceinline__ float reduce_scatter24(const float *v, int lane, int &idx)
-{
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
-    float a[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k)
-        a[k] = xchg_keep_f(b5 ? v[12 + k] : v[k], b5 ? v[k] : v[12 + k], 32);
-    float b[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        b[k] = xchg_keep_f(b4 ? a[6 + k] : a[k], b4 ? a[k] : a[6 + k], 16);
-    float cc[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        cc[k] = xchg_keep_f(b3 ? b[3 + k] : b[k], b3 ? b[k] : b[3 + k], 8);
-    const float d0 = xchg_keep_f(b2 ? cc[2] : cc[0], b2 ? cc[0] : cc[2], 4);
-    const float d1 = xchg_keep_f(b2 ? 0.0f : cc[1], b2 ? cc[1] : 0.0f, 4);
-    float e = xchg_keep_f(b1 ? d1 : d0, b1 ? d0 : d1, 2);
-    e += __shfl_xor(e, 1);
-    const int sub = 2 * (int)b2 + (int)b1;
-    idx = sub < 3 ? 12 * (int)b5 + 6 * (int)b4 + 3 * (int)b3 + sub : -1;
-    return e;
-}
-
 // FP32 near field with leaf-relative offsets: for a sink in leaf a and a
 // source in leaf b, x_i - x_j = (c_a - c_b) + (y_i - y_j) with c_a - c_b formed
 // in FP64 and rounded once per leaf pair, and y = x - c_leaf stored in FP32.
-// Eight sinks per pass (wave-uniform), FP32 accumulation.  pf[p] = (y, m),
-// pfh[p] = (1/h, 1/h^3, 4 h^2, 0), all rounded from FP64.
+// Eight sinks per pass (wave-uniform), source per lane, FP32 accumulation;
+// pf[p] = (y, m), pfh[p] = (1/h, 1/h^3, 4 h^2, 0), all rounded from FP64.
+// A step whose pairs all lie outside both softening supports of eqs.
+// (14)-(15) takes the Newtonian form; otherwise the whole step takes the M4
+// form (exact on both sides of the support).  In FP32 the M4 form costs
+// little more than the Newtonian one, so, unlike the FP64 kernel, no pair is
+// deferred: instead the blocks of a chunk of the near list whose leaves lie
+// within CLOSE_FRAC of the bound of eq. (5),
+//   |c_a - c_b| < CLOSE_FRAC ((s_a + s_b) + R_kern max(h_a, h_b)),
+// are staged first (each group in list order), so that the softened pairs
+// gather in few steps.  The order of all additions depends on the lists
+// only.  Long lists are cut into pieces of `per` blocks as in the FP64
+// kernel.
 __device__ __forceinline__ float rsq_pos_f(float x) { return __builtin_amdgcn_rsqf(x); }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_p2p_src_f32(
+constexpr int P2P_RANGES_F32 = 256;    // blocks staged in LDS per chunk
+constexpr double CLOSE_FRAC2 = 0.49;   // CLOSE_FRAC = 0.7, squared
+
+// Position of a block in the partitioned chunk; front / back are the
+// wave-uniform fill positions (front grows from 0, back shrinks from nc).
+__device__ __forceinline__ int close_first_slot(bool act, bool close, int &front, int &back)
+{
+    const uint64_t lt = lanemask_lt();
+    const uint64_t mc = __ballot(act && close), mf = __ballot(act && !close);
+    const int nf = __popcll(mf);
+    const int pos = close ? front + __popcll(mc & lt) : back - nf + __popcll(mf & lt);
+    front += __popcll(mc);
+    back -= nf;
+    return pos;
+}
+
+// Staged position of step block k (close blocks, then the far ones after the
+// gap left by dropped empty blocks).
+__device__ __forceinline__ int skip_gap(int k, int front, int gap)
+{
+    return k < front ? k : k + gap;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_p2p_src_f32(
     const float4 *__restrict__ pf, const float4 *__restrict__ pfh,
     const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
     const int32_t *__restrict__ near_cnt, const int32_t *__restrict__ near_src, int cap_near,
     int nsub, const float *__restrict__ Lloc, const double *__restrict__ recA,
-    const int32_t *__restrict__ perm, float G, double r_kern, float *aout)
+    const int32_t *__restrict__ perm, float G, double r_kern, float *aout,
+    const int2 *__restrict__ pieces, int per, float *part, int part_stride)
 {
-    constexpr int NS = 8;
-    constexpr int NR = P2P_RANGES / 2;
+    constexpr int NS = P2P_NS;
+    constexpr int NR = P2P_RANGES_F32;
     __shared__ int2 rng[4][NR + 8];
     __shared__ float4 dcs[4][NR + 8];
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
-    if (leaf >= nleaves)
+    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    if (unit >= nleaves)
         return;
     const int lane = lane_id();
     const int grp = lane >> 3, slot = lane & 7;
+    const int2 pc = pieces ? pieces[unit] : make_int2(unit, 0);
+    const int leaf = pc.x;
     const int v = leaf_node[leaf];
     const int64_t f = first[v];
     const int c = count[v];
-    const int nb = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int nbf = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int b_lo = pieces ? pc.y * per : 0;
+    const int b_hi = pieces ? min(nbf, b_lo + per) : nbf;
     const int32_t *nl = near_src + (int64_t)leaf * cap_near;
     const double *rv = recA + (int64_t)NREC * v;
     const double ca0 = rv[0], ca1 = rv[1], ca2 = rv[2];
@@ -603,16 +689,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             sh3[q] = h4.y;
             sh4[q] = h4.z;
         }
+        float tot = 0.0f;
+        for (int p0 = b_lo; p0 < b_hi; p0 += per) {
+        const int nb = min(b_hi, p0 + per);
         float acc[3 * NS];
 #pragma unroll
         for (int q = 0; q < 3 * NS; ++q)
             acc[q] = 0.0f;
-        for (int c0 = 0; c0 < nb; c0 += NR) {
+        for (int c0 = p0; c0 < nb; c0 += NR) {
             const int nc = min(nb - c0, NR);
-            // stage the source blocks of this chunk (padded to a multiple of 8):
-            // their particle range and the leaf-centre difference c_a - c_b,
-            // formed in FP64 and rounded to FP32; close leaves first
-            // (empty blocks dropped; eight empty blocks after the last one)
+            // stage the source blocks of this chunk: their particle range and
+            // the leaf-centre difference c_a - c_b, formed in FP64 and rounded
+            // to FP32; close leaves first, empty blocks dropped, eight empty
+            // blocks after the last one
             int front = 0, back = nc;
             for (int k0 = 0; k0 < nc; k0 += 64) {
                 const int k = k0 + lane;
@@ -682,10 +771,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             }
             __builtin_amdgcn_wave_barrier();
         }
-        int idx;
-        const float tot = reduce_scatter24(acc, lane, idx);
+        tot += reduce_scatter24<float>(acc, lane);
+        }
+        const int idx = rs24_index(lane);
         const int q = idx / 3, comp = idx - 3 * (idx / 3);
-        if (idx >= 0 && (lane & 1) == 0 && sb + q < c) {
+        if (pieces && nbf > per) {
+            if (idx >= 0 && (lane & 1) == 0 && sb + q < c)
+                part[(int64_t)unit * part_stride + 3 * (sb + q) + comp] = tot;
+        } else if (idx >= 0 && (lane & 1) == 0 && sb + q < c) {
             float sxq = sx[0], syq = sy[0], szq = sz[0];
 #pragma unroll
             for (int r = 1; r < NS; ++r)
@@ -704,6 +797,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             const int64_t o = 3 * (int64_t)perm[f + sb + q] + comp;
             aout[o] = G * (far_c + tot);
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -892,13 +986,27 @@ template <int FORM>
 static void far_leaf(Tree &t, bool fp64, hipStream_t s)
 {
     const int nl = t.topo.nleaves;
-    const int g = (nl * 16 + 255) / 256;
-    if (fp64)
-        k_m2l_leaf_f64<FORM><<<g, 256, 0, s>>>(t.recA, t.recQ, t.leaf_node, nl, t.far_cnt,
-                                               t.far_src, (int)t.cap_far, t.L);
-    else
-        k_m2l_leaf_f32<FORM><<<g, 256, 0, s>>>(t.recA, t.recF, t.leaf_node, nl, t.far_cnt,
-                                               t.far_src, (int)t.cap_far, t.Lf);
+    const bool pc = use_pieces(t);
+    const int nu = pc ? (int)t.pfar.n : nl;
+    const int g = (nu * 16 + 255) / 256;
+    const int2 *pl = pc ? t.pfar.list : nullptr;
+    const int per = (int)t.far_piece_entries;
+    const int extra = pc ? nu - nl : 0;
+    if (fp64) {
+        k_m2l_leaf<double, FORM><<<g, 256, 0, s>>>(t.recA, t.recQ, t.recF, t.leaf_node, nu,
+                                                   t.far_cnt, t.far_src, (int)t.cap_far, t.L, pl,
+                                                   per, (double *)t.pfar.part);
+        if (extra > 0)
+            k_m2l_fold<double><<<(extra + 255) / 256, 256, 0, s>>>(
+                t.leaf_node, t.pfar.off, t.pfar.list, extra, (const double *)t.pfar.part, t.L);
+    } else {
+        k_m2l_leaf<float, FORM><<<g, 256, 0, s>>>(t.recA, t.recQ, t.recF, t.leaf_node, nu,
+                                                  t.far_cnt, t.far_src, (int)t.cap_far, t.Lf, pl,
+                                                  per, (float *)t.pfar.part);
+        if (extra > 0)
+            k_m2l_fold<float><<<(extra + 255) / 256, 256, 0, s>>>(
+                t.leaf_node, t.pfar.off, t.pfar.list, extra, (const float *)t.pfar.part, t.Lf);
+    }
 }
 
 static hipError_t far_leaves(Tree &t, bool fp64, hipStream_t s)
@@ -920,21 +1028,120 @@ hipError_t launch_far_f64(Tree &t, hipStream_t s)
     return t.lists_policy == FMM_WALK_MUTUAL ? far_mutual_form(t, true, s) : far_leaves(t, true, s);
 }
 
+// The near field of leaves whose lists were split: each leaf's piece sums
+// in piece order, then L2P (eq. (8)) and the output, exactly as the kernels
+// finish an unsplit leaf.  One wavefront per extra list entry; the one
+// holding piece 1 of its leaf folds it, lanes over the leaf's 3 x count
+// values.
+template <typename T>
+__global__ __launch_bounds__(256) void k_p2p_fold(
+    const int32_t *__restrict__ leaf_node, const int2 *__restrict__ list, int extra,
+    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+    const int64_t *__restrict__ off, const T *__restrict__ part, int stride,
+    const T *__restrict__ Lloc, const double *__restrict__ recA, const double4 *__restrict__ pm,
+    const float4 *__restrict__ pf, const int32_t *__restrict__ perm, T G, T *aout)
+{
+    const int e = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (e >= extra || list[e].y != 1)
+        return;
+    const int lf = list[e].x;
+    const int lane = lane_id();
+    const int v = leaf_node[lf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const int np = (int)(off[lf + 1] - off[lf]);
+    const double *rv = recA + (int64_t)NREC * v;
+    const T *Lv = Lloc + (int64_t)NLOC * v;
+    for (int i3 = lane; i3 < 3 * c; i3 += 64) {
+        T tot = T(0);
+        for (int q = 0; q < np; ++q)
+            tot += part[piece_pos(off, extra, lf, q) * stride + i3];
+        const int i = i3 / 3, comp = i3 - 3 * (i3 / 3);
+        T Lr[19];
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            Lr[k] = Lv[k];
+        T fx, fy, fz;
+        if constexpr (sizeof(T) == 8) {
+            const double4 x4 = pm[f + i];
+            l2p<double>(Lr, x4.x - rv[0], x4.y - rv[1], x4.z - rv[2], fx, fy, fz);
+        } else {
+            const float4 y4 = pf[f + i];
+            l2p<float>(Lr, y4.x, y4.y, y4.z, fx, fy, fz);
+        }
+        const T far_c = comp == 0 ? fx : (comp == 1 ? fy : fz);
+        aout[3 * (int64_t)perm[f + i] + comp] = G * (far_c + tot);
+    }
+}
+
 hipError_t launch_near(Tree &t, void *a, hipStream_t s)
 {
     const Topology &T = t.topo;
     const int nl = T.nleaves;
     const int nsub = (T.leaf_size + 7) / 8;
-    if (t.p.precision == FMM_FP64)
-        k_p2p_src_f64<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node, nl,
+    const bool pc = use_pieces(t);
+    const int nu = pc ? (int)t.pnear.n : nl;
+    const int2 *pl = pc ? t.pnear.list : nullptr;
+    const int per = (int)t.near_piece_blocks;
+    const int stride = 3 * T.leaf_size;
+    const int extra = pc ? nu - nl : 0;
+    if (t.p.precision == FMM_FP64) {
+        k_p2p_src_f64<<<(nu + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node, nu,
                                                    t.near_cnt, t.near_src, (int)t.cap_near, nsub,
                                                    t.L, t.recA, t.perm, t.p.G, t.p.r_kern,
-                                                   T.n, (double *)a);
-    else
-        k_p2p_src_f32<<<(nl + 3) / 4, 256, 0, s>>>(t.pf, t.pfh, t.first, t.count,
-                                                   t.leaf_node, nl, t.near_cnt, t.near_src,
+                                                   T.n, (double *)a, pl, per,
+                                                   (double *)t.pnear.part, stride);
+        if (extra > 0)
+            k_p2p_fold<double><<<(extra + 3) / 4, 256, 0, s>>>(
+                t.leaf_node, t.pnear.list, extra, t.first, t.count, t.pnear.off,
+                (const double *)t.pnear.part, stride, t.L, t.recA, t.pm, t.pf, t.perm, t.p.G,
+                (double *)a);
+    } else {
+        k_p2p_src_f32<<<(nu + 3) / 4, 256, 0, s>>>(t.pf, t.pfh, t.first, t.count,
+                                                   t.leaf_node, nu, t.near_cnt, t.near_src,
                                                    (int)t.cap_near, nsub, t.Lf, t.recA, t.perm,
-                                                   (float)t.p.G, t.p.r_kern, (float *)a);
+                                                   (float)t.p.G, t.p.r_kern, (float *)a, pl, per,
+                                                   (float *)t.pnear.part, stride);
+        if (extra > 0)
+            k_p2p_fold<float><<<(extra + 3) / 4, 256, 0, s>>>(
+                t.leaf_node, t.pnear.list, extra, t.first, t.count, t.pnear.off,
+                (const float *)t.pnear.part, stride, t.Lf, t.recA, t.pm, t.pf, t.perm,
+                (float)t.p.G, (float *)a);
+    }
+    return hipGetLastError();
+}
+
+// Pieces per leaf of the current lists and their offsets (device; the totals
+// sit at off[nleaves]).
+hipError_t launch_piece_counts(Tree &t, hipStream_t s)
+{
+    const int nl = t.topo.nleaves;
+    const int nsub = (t.topo.leaf_size + 7) / 8;
+    const int g = (nl + 255) / 256;
+    k_piece_count<<<g, 256, 0, s>>>(t.near_cnt, (int)t.cap_near, nl, nsub, t.near_piece_blocks,
+                                    t.pnear.np);
+    k_piece_count<<<g, 256, 0, s>>>(t.far_cnt, (int)t.cap_far, nl, 1, t.far_piece_entries,
+                                    t.pfar.np);
+    hipError_t e = launch_count_scan(t.pnear.np, INT32_MAX, nl, t.pnear.tsum, t.pnear.off, s);
+    if (e == hipSuccess)
+        e = launch_count_scan(t.pfar.np, INT32_MAX, nl, t.pfar.tsum, t.pfar.off, s);
+    return e;
+}
+
+hipError_t launch_piece_fill(Tree &t, hipStream_t s)
+{
+    const int nl = t.topo.nleaves;
+    const int g = (nl + 255) / 256;
+    k_piece_fill<<<g, 256, 0, s>>>(t.pnear.off, t.pnear.np, nl, t.pnear.list);
+    k_piece_fill<<<g, 256, 0, s>>>(t.pfar.off, t.pfar.np, nl, t.pfar.list);
+    return hipGetLastError();
+}
+
+hipError_t launch_piece_table(const int64_t *off, const int32_t *np, int nleaves, int2 *list,
+                              hipStream_t s)
+{
+    if (nleaves > 0)
+        k_piece_fill<<<(nleaves + 255) / 256, 256, 0, s>>>(off, np, nleaves, list);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@
 // or a near pair of cells.
 //
 // GPU form: breadth-first expansion of the pair frontier, one launch per
-// level of the recursion with a fixed grid (counts stay on the device), and
+// two levels of the recursion with a fixed grid (counts stay on the device), and
 // wavefront-aggregated appends to the next frontier and to the far / near
 // pair buffers.  The pairs are then sorted by the key (sink, source), which
 // makes the lists independent of the order of the appends: far lists become
@@ -134,13 +134,31 @@ __device__ __forceinline__ void block_append3(const uint32_t (&v)[3],
     __syncthreads();  // wsum / gbase are reused by the next call
 }
 
-// One level of the pair recursion: frontier cnt[MW_IT + it] -> cnt[MW_IT + it + 1].
-// A workgroup takes MW_K x 256 consecutive pairs per round: it classifies
-// them (far / near / split A / split B), reserves the outputs of the whole
-// round with one atomic per output buffer, then writes them.
-constexpr int MW_K = 4;
-constexpr int MW_KB = 2;  // pairs whose loads are in flight together (more raise the
-                          // register count and cost occupancy)
+// Classification of a pair (A, B): 0 none, 1 far, 2 near, 3 split A, 4 split B;
+// op: the two leaf indices (near) or the split cell's children (split).
+__device__ __forceinline__ uint32_t mw_classify(const MwCell &A, const MwCell &B, double theta2,
+                                                double r_kern, int2 &op)
+{
+    uint32_t c;
+    if (separated(A, B, theta2, r_kern))
+        c = 1;
+    else if (A.left < 0 && B.left < 0)
+        c = 2;
+    else
+        c = (B.left < 0 || (A.left >= 0 && A.s >= B.s)) ? 3 : 4;
+    op = c == 2 ? make_int2(A.leaf, B.leaf)
+                : (c == 3 ? make_int2(A.left, A.right) : make_int2(B.left, B.right));
+    return c;
+}
+
+// Two levels of the pair recursion per launch: frontier cnt[MW_IT + it] ->
+// cnt[MW_IT + it + 1].  A thread classifies its pair; if one cell of it is
+// split, it classifies the two child pairs at once (the other cell's record
+// is already loaded), so a pair leaves far / near output and at most four
+// grandchild pairs for the next launch.  A workgroup takes MW_K x 256
+// consecutive pairs per round and reserves the outputs of the whole round
+// with one atomic per output buffer.
+constexpr int MW_K = 2;
 
 __global__ __launch_bounds__(256) void k_mw_step(
     const int2 *__restrict__ tin, int2 *tout, int it, int64_t cap_task,
@@ -153,89 +171,100 @@ __global__ __launch_bounds__(256) void k_mw_step(
     const int t = threadIdx.x;
     for (int64_t r0 = (int64_t)blockIdx.x * (256 * MW_K); r0 < nin;
          r0 += (int64_t)gridDim.x * (256 * MW_K)) {
-        // the round's pairs, then per batch of MW_KB pairs every record and
-        // child id they may need, all loads in flight together (pairs past
-        // the frontier's end re-read its last pair and are classified 0)
-        int2 tk[MW_K];
+        // per input pair k: the pair itself (slot 0) and, when it splits, its
+        // two child pairs (slots 1, 2); pairs past the frontier's end re-read
+        // its last pair and are classified 0
+        int2 pr[MW_K][3], op[MW_K][3];
+        uint32_t cd[MW_K][3];
+        MwCell A[MW_K], B[MW_K];
 #pragma unroll
-        for (int k = 0; k < MW_K; ++k)
-            tk[k] = tin[min(r0 + k * 256 + t, nin - 1)];
-        int2 outp[MW_K];  // near: the two leaf indices; split: the split cell's children
-        uint64_t code = 0;  // 3 bits per pair: 0 none, 1 far, 2 near, 3 split A, 4 split B
-        uint32_t num[3] = {0u, 0u, 0u};
+        for (int k = 0; k < MW_K; ++k) {
+            pr[k][0] = tin[min(r0 + k * 256 + t, nin - 1)];
+            A[k] = load_mw(recA, pr[k][0].x);
+            B[k] = load_mw(recA, pr[k][0].y);
+        }
+        MwCell C0[MW_K], C1[MW_K];
+        bool sa[MW_K];
 #pragma unroll
-        for (int k0 = 0; k0 < MW_K; k0 += MW_KB) {
-            MwCell A[MW_KB], B[MW_KB];
+        for (int k = 0; k < MW_K; ++k) {
+            cd[k][0] = r0 + k * 256 + t < nin ? mw_classify(A[k], B[k], theta2, r_kern, op[k][0])
+                                              : 0u;
+            cd[k][1] = cd[k][2] = 0u;
+            sa[k] = cd[k][0] == 3;
+            // children of the split cell (loads issued for both pairs together)
+            const int c0 = cd[k][0] >= 3 ? op[k][0].x : pr[k][0].x;
+            const int c1 = cd[k][0] >= 3 ? op[k][0].y : pr[k][0].x;
+            C0[k] = load_mw(recA, c0);
+            C1[k] = load_mw(recA, c1);
+        }
 #pragma unroll
-            for (int j = 0; j < MW_KB; ++j) {
-                A[j] = load_mw(recA, tk[k0 + j].x);
-                B[j] = load_mw(recA, tk[k0 + j].y);
-            }
-#pragma unroll
-            for (int j = 0; j < MW_KB; ++j) {
-                const int k = k0 + j;
-                uint32_t c = 0;
-                if (r0 + k * 256 + t < nin) {
-                    if (separated(A[j], B[j], theta2, r_kern))
-                        c = 1;
-                    else if (A[j].left < 0 && B[j].left < 0)
-                        c = 2;
-                    else
-                        c = (B[j].left < 0 || (A[j].left >= 0 && A[j].s >= B[j].s)) ? 3 : 4;
-                }
-                outp[k] = c == 2 ? make_int2(A[j].leaf, B[j].leaf)
-                                 : (c == 3 ? make_int2(A[j].left, A[j].right)
-                                           : make_int2(B[j].left, B[j].right));
-                code |= (uint64_t)c << (3 * k);
-                num[0] += c == 1 ? 2u : 0u;
-                num[1] += c == 2 ? 2u : 0u;
-                num[2] += c >= 3 ? 2u : 0u;
+        for (int k = 0; k < MW_K; ++k) {
+            if (cd[k][0] >= 3) {
+                const int o = sa[k] ? pr[k][0].y : pr[k][0].x;
+                const MwCell &O = sa[k] ? B[k] : A[k];
+                pr[k][1] = sa[k] ? make_int2(op[k][0].x, o) : make_int2(o, op[k][0].x);
+                pr[k][2] = sa[k] ? make_int2(op[k][0].y, o) : make_int2(o, op[k][0].y);
+                cd[k][1] = sa[k] ? mw_classify(C0[k], O, theta2, r_kern, op[k][1])
+                                 : mw_classify(O, C0[k], theta2, r_kern, op[k][1]);
+                cd[k][2] = sa[k] ? mw_classify(C1[k], O, theta2, r_kern, op[k][2])
+                                 : mw_classify(O, C1[k], theta2, r_kern, op[k][2]);
             }
         }
+        uint32_t num[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int k = 0; k < MW_K; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                num[0] += cd[k][j] == 1 ? 2u : 0u;
+                num[1] += cd[k][j] == 2 ? 2u : 0u;
+                num[2] += (j > 0 && cd[k][j] >= 3) ? 2u : 0u;
+            }
         uint64_t pos[3];
         block_append3(num, ctr, pos);
         uint32_t ovf = 0;
 #pragma unroll
-        for (int k = 0; k < MW_K; ++k) {
-            const uint32_t c = (uint32_t)(code >> (3 * k)) & 7u;
-            const int a = tk[k].x, b = tk[k].y;
-            // every reserved slot below a capacity is written, so a consumer
-            // that clamps a count to the capacity reads written entries only
-            if (c == 1) {
-                const int64_t q = (int64_t)pos[0];
-                if (q < cap_f)
-                    fkeys[q] = ((uint64_t)a << bits) | (uint64_t)b;
-                if (q + 1 < cap_f)
-                    fkeys[q + 1] = ((uint64_t)b << bits) | (uint64_t)a;
-                else
-                    ovf |= 2u;
-                pos[0] += 2;
-            } else if (c == 2) {
-                const int fa = outp[k].x, fb = outp[k].y;
-                atomicAdd(&near_cnt[fa], 1);
-                atomicAdd(&near_cnt[fb], 1);
-                const int64_t q = (int64_t)pos[1];
-                if (q < cap_n)
-                    nkeys[q] = ((uint64_t)fa << lbits) | (uint64_t)fb;
-                if (q + 1 < cap_n)
-                    nkeys[q + 1] = ((uint64_t)fb << lbits) | (uint64_t)fa;
-                else
-                    ovf |= 4u;
-                pos[1] += 2;
-            } else if (c >= 3) {
-                const bool sa = c == 3;
-                const int o = sa ? b : a;
-                const int c0 = outp[k].x, c1 = outp[k].y;
-                const int64_t q = (int64_t)pos[2];
-                if (q < cap_task)
-                    tout[q] = sa ? make_int2(c0, o) : make_int2(o, c0);
-                if (q + 1 < cap_task)
-                    tout[q + 1] = sa ? make_int2(c1, o) : make_int2(o, c1);
-                else
-                    ovf |= 1u;
-                pos[2] += 2;
+        for (int k = 0; k < MW_K; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const uint32_t c = cd[k][j];
+                const int a = pr[k][j].x, b = pr[k][j].y;
+                // every reserved slot below a capacity is written, so a consumer
+                // that clamps a count to the capacity reads written entries only
+                if (c == 1) {
+                    const int64_t q = (int64_t)pos[0];
+                    if (q < cap_f)
+                        fkeys[q] = ((uint64_t)a << bits) | (uint64_t)b;
+                    if (q + 1 < cap_f)
+                        fkeys[q + 1] = ((uint64_t)b << bits) | (uint64_t)a;
+                    else
+                        ovf |= 2u;
+                    pos[0] += 2;
+                } else if (c == 2) {
+                    const int fa = op[k][j].x, fb = op[k][j].y;
+                    atomicAdd(&near_cnt[fa], 1);
+                    atomicAdd(&near_cnt[fb], 1);
+                    const int64_t q = (int64_t)pos[1];
+                    if (q < cap_n)
+                        nkeys[q] = ((uint64_t)fa << lbits) | (uint64_t)fb;
+                    if (q + 1 < cap_n)
+                        nkeys[q + 1] = ((uint64_t)fb << lbits) | (uint64_t)fa;
+                    else
+                        ovf |= 4u;
+                    pos[1] += 2;
+                } else if (j > 0 && c >= 3) {
+                    const bool s_a = c == 3;
+                    const int o = s_a ? b : a;
+                    const int g0 = op[k][j].x, g1 = op[k][j].y;
+                    const int64_t q = (int64_t)pos[2];
+                    if (q < cap_task)
+                        tout[q] = s_a ? make_int2(g0, o) : make_int2(o, g0);
+                    if (q + 1 < cap_task)
+                        tout[q + 1] = s_a ? make_int2(g1, o) : make_int2(o, g1);
+                    else
+                        ovf |= 1u;
+                    pos[2] += 2;
+                }
             }
-        }
         if (ovf)
             atomicOr(&cnt[MW_FLAGS], (unsigned long long)ovf);
     }
@@ -326,7 +355,9 @@ static int bit_width(int64_t v)
 
 int mutual_key_bits(const Tree &t) { return bit_width(t.topo.nnodes); }
 
-int mutual_iterations(const Tree &t) { return 2 * t.topo.depth + 2; }
+// Launches of the two-level step: the recursion from the seed pairs ends
+// within 2 depth + 2 levels (each split lowers one cell).
+int mutual_iterations(const Tree &t) { return t.topo.depth + 1; }
 
 hipError_t launch_mutual_walk(Tree &t, hipStream_t s)
 {

@@ -347,50 +347,6 @@ __device__ __forceinline__ double xk(double keep, double send, int off)
     return keep + __shfl_xor(send, off);
 }
 
-// Reduce-scatter of 12 doubles over the wavefront; value index held by lane l
-// is 6 b5 + 3 b4 + (2 b3 + b2) when (2 b3 + b2) < 3 (sum complete in every lane
-// of the group of four).
-__device__ __forceinline__ double rs12(const double *v, int lane, int &idx)
-{
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
-    double a[6], b[3];
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        a[k] = xk(b5 ? v[6 + k] : v[k], b5 ? v[k] : v[6 + k], 32);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        b[k] = xk(b4 ? a[3 + k] : a[k], b4 ? a[k] : a[3 + k], 16);
-    const double c0 = xk(b3 ? b[2] : b[0], b3 ? b[0] : b[2], 8);
-    const double c1 = xk(b3 ? 0.0 : b[1], b3 ? b[1] : 0.0, 8);
-    double d = xk(b2 ? c1 : c0, b2 ? c0 : c1, 4);
-    d += __shfl_xor(d, 2);
-    d += __shfl_xor(d, 1);
-    const int sub = 2 * (int)b3 + (int)b2;
-    idx = sub < 3 ? 6 * (int)b5 + 3 * (int)b4 + sub : -1;
-    return d;
-}
-
-// Reduce-scatter of 16 doubles; lane l holds value 8 b5 + 4 b4 + 2 b3 + b2.
-__device__ __forceinline__ double rs16(const double *v, int lane, int &idx)
-{
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
-    double a[8], b[4], c[2];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        a[k] = xk(b5 ? v[8 + k] : v[k], b5 ? v[k] : v[8 + k], 32);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        b[k] = xk(b4 ? a[4 + k] : a[k], b4 ? a[k] : a[4 + k], 16);
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-        c[k] = xk(b3 ? b[2 + k] : b[k], b3 ? b[k] : b[2 + k], 8);
-    double d = xk(b2 ? c[1] : c[0], b2 ? c[0] : c[1], 4);
-    d += __shfl_xor(d, 2);
-    d += __shfl_xor(d, 1);
-    idx = 8 * (int)b5 + 4 * (int)b4 + 2 * (int)b3 + (int)b2;
-    return d;
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -740,65 +696,58 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_mutual(
     }
 }
 
-// 3a. P2P^T, sink side: like the forward near field (source per lane, four
-// wave-uniform sinks per pass, source blocks of the close leaves staged
-// first, the next step's sources loaded while the current one computes),
-// pair function dbar.  xbt += the sum.
-constexpr int VJP_RANGES = 256;
-constexpr double VJP_CLOSE_FRAC2 = 0.49;  // close leaf: |c_a - c_b| < 0.7 x the bound of eq. (5)
+// 3. P2P^T: the near pairs of eqs. (12)-(15) in reverse.  For a pair (i, j)
+// with d = x_i - x_j, G_ij the mean of the two M4 kernels (r^-3 beyond both
+// supports) and D_ij = (dG_ij / dr) / r, the adjoint of
+// a_i = -sum_j m_j G_ij d gives
+//   sink side:   xbar_i -= sum_j m_j (G_ij abar_i + D_ij (d . abar_i) d),
+//   source side: xbar_j += m_j sum_i (G_ij abar_i + D_ij (d . abar_i) d),
+//                mbar_j  = -sum_i G_ij (d . abar_i),
+// the source side over the sink leaves whose near list holds j's leaf (the
+// transposed lists).  Both kernels take the forward near field's layout: a
+// lane per particle of a staged block (8 blocks a step), VJP_NS particles of
+// the wavefront's own leaf per pass (wave-uniform), block ranges staged in
+// LDS in list order.  A pair with r^2 < max(H4, 4 h^2) -- H4 the largest
+// 4 h^2 of the pass's uniform particles, 4 h^2 the lane's own -- may be
+// softened: it goes to its uniform particle's queue in LDS and is evaluated
+// with the M4 kernels, 64 at a time; every other pair is Newtonian for
+// certain (G = r^-3, D = -3 r^-5).  Two particles at one point have
+// G = (g_i(0) + g_j(0)) / 2 and d = 0; a particle paired with itself adds
+// nothing.  Long lists are cut into pieces of `per` blocks (pieces != null:
+// a unit is one entry of the piece list, and a split leaf's piece sums go to
+// part, folded in piece order); the order of all additions depends on the
+// lists only.
+constexpr int VJP_NS = 8;        // uniform particles per pass
+constexpr int VJP_QCAP = 128;    // softened pairs a queue holds (a step adds <= 64)
+constexpr int VJP_BLOCKS = 256;  // blocks staged in LDS per chunk
 
-// Stage the source blocks of list entries [c0, c0 + nc) (each list entry,
-// a node id, stands for nsub blocks of at most 8 particles) in R: blocks of
-// leaves within the close radius of the wavefront's own leaf rv first, each
-// group in list order, so that steps whose pairs are all Newtonian are
-// gathered at the end; empty blocks are dropped, leaving a gap [front,
-// front + gap) between the groups, and eight empty blocks follow position
-// nc.  Returns the number of staged blocks.
+// Stage the non-empty blocks of list entries [c0, c0 + nc) (entry k: block
+// k % nsub of leaf lst[k / nsub]) in list order, then eight empty blocks;
+// returns the number of staged blocks.
 template <typename IX>
-__device__ __forceinline__ int stage_blocks(const IX *__restrict__ lst, int c0, int nc, int nsub,
-                                            const int32_t *__restrict__ first,
-                                            const int32_t *__restrict__ count,
-                                            const double *__restrict__ recA, const double *rv,
-                                            double r_kern, int lane, int2 *R, int &front,
-                                            int &gap)
+__device__ __forceinline__ int stage_list_blocks(const IX *__restrict__ lst, int c0, int nc,
+                                                 int nsub, const int32_t *__restrict__ first,
+                                                 const int32_t *__restrict__ count, int lane,
+                                                 int2 *R)
 {
-    front = 0;
-    int back = nc;
-    const uint64_t lt = lanemask_lt();
+    int ne = 0;
     for (int k0 = 0; k0 < nc; k0 += 64) {
         const int k = k0 + lane;
-        const bool act = k < nc;
         int2 r = make_int2(0, 0);
-        bool close = false;
-        if (act) {
+        if (k < nc) {
             const int e = (c0 + k) / nsub, u = (c0 + k) - e * nsub;
             const int bn = (int)lst[e];
             r = make_int2(first[bn] + 8 * u, max(0, min(8, count[bn] - 8 * u)));
-            const double *rb = recA + (int64_t)NREC * bn;
-            const double dx = rv[0] - rb[0], dy = rv[1] - rb[1], dz = rv[2] - rb[2];
-            const double t5 = (rv[4] + rb[4]) + r_kern * fmax(rv[5], rb[5]);
-            close = dx * dx + dy * dy + dz * dz < VJP_CLOSE_FRAC2 * t5 * t5;
         }
         const bool keep = r.y > 0;
-        const uint64_t mc = __ballot(keep && close), mf = __ballot(keep && !close);
-        const int nf = __popcll(mf);
-        const int pos = close ? front + __popcll(mc & lt) : back - nf + __popcll(mf & lt);
-        front += __popcll(mc);
-        back -= nf;
+        const uint64_t mk = __ballot(keep);
         if (keep)
-            R[pos] = r;
+            R[ne + __popcll(mk & lanemask_lt())] = r;
+        ne += __popcll(mk);
     }
     if (lane < 8)
-        R[nc + lane] = make_int2(0, 0);
-    front = __builtin_amdgcn_readfirstlane(front);
-    gap = __builtin_amdgcn_readfirstlane(back - front);
-    return nc - gap;
-}
-
-// Block of step position k (close blocks, then the far ones after the gap).
-__device__ __forceinline__ int skip_gap(int k, int front, int gap)
-{
-    return k < front ? k : k + gap;
+        R[ne + lane] = make_int2(0, 0);
+    return ne;
 }
 
 // Particle index of this lane in a staged block; missing particles read the
@@ -809,199 +758,394 @@ __device__ __forceinline__ int64_t block_particle(int2 rg, int slot, int64_t nnu
     return slot < rg.y ? (int64_t)rg.x + slot : nnull;
 }
 
-// G_ij and G'_ij / r of one pair (eq. (3) with the symmetric pair kernel).
-// A step in which no pair of the wavefront lies inside a smoothing support
-// takes the Newtonian branch, G = r^-3, G' / r = -3 r^-5.  Otherwise the
-// spline branch also covers r = 0: two distinct particles at one point have
-// G = (g_i(0) + g_j(0)) / 2 and d = 0; a particle paired with itself (self)
-// gets G = 0, so the pair adds nothing.
-__device__ __forceinline__ void pair_gdg_step(double r2, double4 ha, double4 hb, bool self,
-                                              double &Gp, double &dGr)
+// G_ij and D_ij of a pair that may be softened: each side's M4 kernel
+// (eq. (13) and its derivative) at q = r / h, and their mean.
+__device__ __forceinline__ void pair_gd_soft(double r2, double4 ha, double4 hb, bool self,
+                                             double &Gp, double &Dp)
 {
-    if ((__ballot(r2 < ha.z) | __ballot(r2 < hb.z)) == 0ull) {
-        const double u = rsqrt_pos(r2);
-        const double u2 = u * u;
-        Gp = u2 * u;
-        dGr = -3.0 * (Gp * u2);
-    } else {
-        const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
-        const double r = r2 * u;
-        const double u3 = u * u * u;
-        const double qa = r * ha.x, qb = r * hb.x;
-        Gp = 0.5 * (m4g(qa, ha.y, u3) + m4g(qb, hb.y, u3));
-        dGr = 0.5 * (m4dgr(qa, ha.x, ha.y, ha.w, u) + m4dgr(qb, hb.x, hb.y, hb.w, u));
-        Gp = self ? 0.0 : Gp;
-    }
+    const double u = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+    const double r = r2 * u;
+    const double u3 = u * u * u;
+    const double qa = r * ha.x, qb = r * hb.x;
+    const double g = 0.5 * (m4g(qa, ha.y, u3) + m4g(qb, hb.y, u3));
+    Gp = self ? 0.0 : g;
+    Dp = 0.5 * (m4dgr(qa, ha.x, ha.y, ha.w, u) + m4dgr(qb, hb.x, hb.y, hb.w, u));
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_sink(
+// Reduce-scatter of 32 per-lane values over the wavefront: after xor steps
+// over lane bits 5..1 (each keeps half of its values and sends the other
+// half to its partner) and a last butterfly step, lanes 2v and 2v + 1 hold
+// the sum of value v.
+__device__ __forceinline__ double reduce_scatter32(const double *v, int lane)
+{
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    double a[16], b[8], c[4], d[2];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        a[k] = xk(b5 ? v[16 + k] : v[k], b5 ? v[k] : v[16 + k], 32);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        b[k] = xk(b4 ? a[8 + k] : a[k], b4 ? a[k] : a[8 + k], 16);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        c[k] = xk(b3 ? b[4 + k] : b[k], b3 ? b[k] : b[4 + k], 8);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        d[k] = xk(b2 ? c[2 + k] : c[k], b2 ? c[k] : c[2 + k], 4);
+    double e = xk(b1 ? d[1] : d[0], b1 ? d[0] : d[1], 2);
+    e += __shfl_xor(e, 1);
+    return e;
+}
+
+// 3a. Sink side.  Per sink q the lanes sum S = sum_j m_j G_ij and
+// V = sum_j m_j D_ij (d . abar_i) d; a piece adds -(abar_i S + V) to xbar_i
+// (abar_i is wave-uniform, so the G term needs no per-pair product).  The
+// queues that a step fills past a multiple of 64 are evaluated after the
+// step, when its source data are no longer held.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vjp_p2p_sink(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
-    const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nunits,
     const int32_t *__restrict__ near_cnt, const int32_t *__restrict__ near_src, int cap_near,
-    int nsub, const double *__restrict__ recA, double r_kern, int64_t nnull, double *xbt)
+    int nsub, int64_t nnull, double *xbt, const int2 *__restrict__ pieces, int per, double *part,
+    int part_stride)
 {
-    constexpr int NS = 4;
-    __shared__ int2 rng[4][VJP_RANGES + 8];
+    constexpr int NS = VJP_NS;
+    __shared__ int2 rng[4][VJP_BLOCKS + 8];
+    __shared__ int32_t que[4][NS][VJP_QCAP];
+    __shared__ double4 shx[4][NS];  // positions of the pass's sinks
+    __shared__ double4 sha[4][NS];  // abar of the pass's sinks
+    __shared__ double4 sh3[4][NS];  // -3 abar (the Newtonian D = -3 r^-5 folded in)
+    __shared__ double4 shh[4][NS];  // h data of the pass's sinks
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
-    if (leaf >= nleaves)
+    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    if (unit >= nunits)
         return;
     const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
     const int grp = lane >> 3, slot = lane & 7;
+    const int2 pc = pieces ? pieces[unit] : make_int2(unit, 0);
+    const int leaf = pc.x;
     const int v = leaf_node[leaf];
     const int64_t f = first[v];
     const int c = count[v];
-    const int nb = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int nbf = max(0, min(near_cnt[leaf], cap_near)) * nsub;
+    const int b_lo = pieces ? pc.y * per : 0;
+    const int b_hi = pieces ? min(nbf, b_lo + per) : nbf;
+    const bool split = pieces && nbf > per;
     const int32_t *nl = near_src + (int64_t)leaf * cap_near;
-    const double *rv = recA + (int64_t)NREC * v;
     int2 *R = rng[w];
+    // value 4 q + k of the reduce-scatter (lanes 8 q + 2 k, + 1): k = 0 S, k = 1..3 V_k
+    const int qv = lane >> 3, kv = (lane >> 1) & 3;
     for (int sb = 0; sb < c; sb += NS) {
-        double4 xs[NS], hsn[NS];
-        double as0[NS], as1[NS], as2[NS];
-        int64_t is[NS];
+        double sx[NS], sy[NS], sz[NS], H4 = 0.0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            is[q] = f + min(sb + q, c - 1);
-            xs[q] = pm[is[q]];
-            hsn[q] = ph[is[q]];
-            as0[q] = abt[3 * is[q]];
-            as1[q] = abt[3 * is[q] + 1];
-            as2[q] = abt[3 * is[q] + 2];
+            const int64_t is = f + min(sb + q, c - 1);
+            const double4 x4 = pm[is];
+            sx[q] = x4.x;
+            sy[q] = x4.y;
+            sz[q] = x4.z;
+            const double h4q = ph[is].z;
+            H4 = h4q > H4 ? h4q : H4;
         }
-        double acc[3 * NS];
+        if (lane < NS) {
+            const int64_t is = f + min(sb + lane, c - 1);
+            shx[w][lane] = pm[is];
+            shh[w][lane] = ph[is];
+            const double a0 = abt[3 * is], a1 = abt[3 * is + 1], a2 = abt[3 * is + 2];
+            sha[w][lane] = make_double4(a0, a1, a2, 0.0);
+            sh3[w][lane] = make_double4(-3.0 * a0, -3.0 * a1, -3.0 * a2, 0.0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        double tot = 0.0;
+        double acc[4 * NS];
+        int tail[NS];  // queue fill counts; entries [tail & ~63, tail) are pending
+        // softened pairs of sink q: cnt <= 64 queue entries from position head
+        auto drain = [&](int q, int head, int cnt) {
+            const int64_t j =
+                lane < cnt ? (int64_t)que[w][q][(head + lane) & (VJP_QCAP - 1)] : nnull;
+            const double4 xj = pm[j];
+            const double4 hj = ph[j];
+            const double4 xs = shx[w][q];
+            const double dx = xs.x - xj.x, dy = xs.y - xj.y, dz = xs.z - xj.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            double Gp, Dp;
+            pair_gd_soft(r2, shh[w][q], hj, j == f + min(sb + q, c - 1), Gp, Dp);
+            const double4 a = sha[w][q];
+            const double t = xj.w * Dp * (dx * a.x + dy * a.y + dz * a.z);
+            acc[4 * q] += xj.w * Gp;
+            acc[4 * q + 1] += t * dx;
+            acc[4 * q + 2] += t * dy;
+            acc[4 * q + 3] += t * dz;
+        };
+        for (int p0 = b_lo; p0 < b_hi; p0 += per) {
+            const int nb = min(b_hi, p0 + per);
 #pragma unroll
-        for (int q = 0; q < 3 * NS; ++q)
-            acc[q] = 0.0;
-        for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
-            const int nc = min(nb - c0, VJP_RANGES);
-            int front, gap;
-            const int ne = stage_blocks(nl, c0, nc, nsub, first, count, recA, rv, r_kern, lane,
-                                        R, front, gap);
-            __builtin_amdgcn_wave_barrier();
-            int64_t j = block_particle(R[skip_gap(grp, front, gap)], slot, nnull);
-            double4 xj = pm[j], hj = ph[j];
-            for (int kb = 0; kb < ne; kb += 8) {
-                int64_t jn = j;
-                double4 xn = xj, hn = hj;
-                if (kb + 8 < ne) {
-                    jn = block_particle(R[skip_gap(kb + 8 + grp, front, gap)], slot, nnull);
-                    xn = pm[jn];
-                    hn = ph[jn];
-                }
+            for (int q = 0; q < 4 * NS; ++q)
+                acc[q] = 0.0;
 #pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    const double dx = xs[q].x - xj.x, dy = xs[q].y - xj.y, dz = xs[q].z - xj.z;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    double Gp, dGr;
-                    pair_gdg_step(r2, hsn[q], hj, j == is[q], Gp, dGr);
-                    const double da = dx * as0[q] + dy * as1[q] + dz * as2[q];
-                    const double t = dGr * da;
-                    acc[3 * q] -= xj.w * (Gp * as0[q] + t * dx);
-                    acc[3 * q + 1] -= xj.w * (Gp * as1[q] + t * dy);
-                    acc[3 * q + 2] -= xj.w * (Gp * as2[q] + t * dz);
+            for (int q = 0; q < NS; ++q)
+                tail[q] = 0;
+            for (int c0 = p0; c0 < nb; c0 += VJP_BLOCKS) {
+                const int nc = min(nb - c0, VJP_BLOCKS);
+                const int ne = __builtin_amdgcn_readfirstlane(
+                    stage_list_blocks(nl, c0, nc, nsub, first, count, lane, R));
+                __builtin_amdgcn_wave_barrier();
+                for (int kb = 0; kb < ne; kb += 8) {
+                    uint32_t full = 0u;  // queues that passed a multiple of 64 in this step
+                    {
+                        const int32_t j = (int32_t)block_particle(R[kb + grp], slot, nnull);
+                        const double4 xj = pm[j];
+                        const double hj4 = ph[j].z;
+                        const double hmax4 = hj4 > H4 ? hj4 : H4;
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) {
+                            const double dx = sx[q] - xj.x, dy = sy[q] - xj.y, dz = sz[q] - xj.z;
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            // (every lane is active here: the softened mask is
+                            // the complement of the Newtonian one)
+                            const bool newt = !(r2 < hmax4);
+                            const uint64_t bal = ~__ballot(newt);
+                            if (newt) {
+                                const double u = rsqrt_pos(r2);
+                                const double u2 = u * u;
+                                const double mg = xj.w * (u2 * u);
+                                const double4 a = sh3[w][q];
+                                const double t = (mg * u2) * (dx * a.x + dy * a.y + dz * a.z);
+                                acc[4 * q] += mg;
+                                acc[4 * q + 1] += t * dx;
+                                acc[4 * q + 2] += t * dy;
+                                acc[4 * q + 3] += t * dz;
+                            }
+                            if (bal) {
+                                // possibly softened pairs leave the step for the sink's queue
+                                const int t0 = tail[q];
+                                if (!newt)
+                                    que[w][q][(t0 + __popcll(bal & lt)) & (VJP_QCAP - 1)] = j;
+                                tail[q] = t0 + __popcll(bal);
+                                if ((tail[q] >> 6) != (t0 >> 6))
+                                    full |= 1u << q;
+                            }
+                        }
+                    }
+                    if (full) {
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int q = 0; q < NS; ++q)
+                            if (full & (1u << q))
+                                drain(q, ((tail[q] >> 6) - 1) << 6, 64);
+                    }
                 }
-                j = jn;
-                xj = xn;
-                hj = hn;
+                __builtin_amdgcn_wave_barrier();
             }
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (tail[q] & 63)
+                    drain(q, tail[q] & ~63, tail[q] & 63);
             __builtin_amdgcn_wave_barrier();
+            const double e = reduce_scatter32(acc, lane);
+            const double S = __shfl(e, lane & ~7);
+            const double4 a = sha[w][qv];
+            const double ak = kv == 1 ? a.x : (kv == 2 ? a.y : a.z);
+            tot += -fma(ak, S, e);
         }
-        int idx;
-        const double tot = rs12(acc, lane, idx);
-        const int q = idx / 3, comp = idx - 3 * (idx / 3);
-        if (idx >= 0 && (lane & 3) == 0 && sb + q < c)
-            xbt[3 * (f + sb + q) + comp] += tot;
+        if (kv >= 1 && (lane & 1) == 0 && sb + qv < c) {
+            if (split)
+                part[(int64_t)unit * part_stride + 3 * (sb + qv) + (kv - 1)] = tot;
+            else
+                xbt[3 * (f + sb + qv) + (kv - 1)] += tot;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// 3b. P2P^T, source side: one wavefront per source leaf b over the sink leaves
-// whose near list holds b (transposed, ascending, close leaves staged first);
-// lanes hold sink particles, four source particles of b per pass are
-// wave-uniform.  xbt[j] -= sum dbar, mbt[j] = sum -G_ij (d . abar'_i).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_src(
+// 3b. Source side: the wavefront's own leaf holds the sources (uniform), the
+// lanes the particles of the sink leaves of its transposed list.  Per source
+// q the lanes sum X = sum_i (G_ij abar_i + D_ij (d . abar_i) d) and
+// Y = sum_i G_ij (d . abar_i); a piece adds m_j X to xbar_j and -Y to mbar_j.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vjp_p2p_src(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
-    const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
-    const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc, int nsub,
-    const double *__restrict__ recA, double r_kern, int64_t nnull, double *xbt, double *mbt)
+    const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nunits,
+    const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc, int nsub, int64_t nnull,
+    double *xbt, double *mbt, const int2 *__restrict__ pieces, int per, double *part,
+    int part_stride)
 {
-    constexpr int NS = 4;
-    __shared__ int2 rng[4][VJP_RANGES + 8];
+    constexpr int NS = VJP_NS;
+    __shared__ int2 rng[4][VJP_BLOCKS + 8];
+    __shared__ int32_t que[4][NS][VJP_QCAP];
+    __shared__ double4 shx[4][NS];  // positions of the pass's sources
+    __shared__ double4 shh[4][NS];  // h data of the pass's sources
     const int w = threadIdx.x >> 6;
-    const int leaf = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
-    if (leaf >= nleaves)
+    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    if (unit >= nunits)
         return;
     const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
     const int grp = lane >> 3, slot = lane & 7;
+    const int2 pc = pieces ? pieces[unit] : make_int2(unit, 0);
+    const int leaf = pc.x;
     const int v = leaf_node[leaf];
     const int64_t f = first[v];
     const int c = count[v];
     const int64_t e0 = toff[v];
-    const int nb = (int)(toff[v + 1] - e0) * nsub;
-    const double *rv = recA + (int64_t)NREC * v;
+    const int nbf = (int)(toff[v + 1] - e0) * nsub;
+    const int b_lo = pieces ? pc.y * per : 0;
+    const int b_hi = pieces ? min(nbf, b_lo + per) : nbf;
+    const bool split = pieces && nbf > per;
+    const uint32_t *tl = tsrc + e0;
     int2 *R = rng[w];
+    // value 4 q + k of the reduce-scatter (lanes 8 q + 2 k, + 1): k = 0..2 X_k, k = 3 Y
+    const int qv = lane >> 3, kv = (lane >> 1) & 3;
     for (int sb = 0; sb < c; sb += NS) {
-        double4 xs[NS], hsn[NS];
-        int64_t js[NS];
+        double sx[NS], sy[NS], sz[NS], H4 = 0.0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            js[q] = f + min(sb + q, c - 1);
-            xs[q] = pm[js[q]];
-            hsn[q] = ph[js[q]];
+            const int64_t js = f + min(sb + q, c - 1);
+            const double4 x4 = pm[js];
+            sx[q] = x4.x;
+            sy[q] = x4.y;
+            sz[q] = x4.z;
+            const double h4q = ph[js].z;
+            H4 = h4q > H4 ? h4q : H4;
         }
+        if (lane < NS) {
+            const int64_t js = f + min(sb + lane, c - 1);
+            shx[w][lane] = pm[js];
+            shh[w][lane] = ph[js];
+        }
+        __builtin_amdgcn_wave_barrier();
+        double tot = 0.0;
         double acc[4 * NS];
+        int tail[NS];
+        // softened pairs of source q: cnt <= 64 queued sink particles from head
+        auto drain = [&](int q, int head, int cnt) {
+            const int64_t i =
+                lane < cnt ? (int64_t)que[w][q][(head + lane) & (VJP_QCAP - 1)] : nnull;
+            const double4 xi = pm[i];
+            const double4 hi = ph[i];
+            const double a0 = abt[3 * i], a1 = abt[3 * i + 1], a2 = abt[3 * i + 2];
+            const double4 xs = shx[w][q];
+            const double dx = xi.x - xs.x, dy = xi.y - xs.y, dz = xi.z - xs.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            double Gp, Dp;
+            pair_gd_soft(r2, hi, shh[w][q], i == f + min(sb + q, c - 1), Gp, Dp);
+            const double da = dx * a0 + dy * a1 + dz * a2;
+            const double t = Dp * da;
+            acc[4 * q] += Gp * a0 + t * dx;
+            acc[4 * q + 1] += Gp * a1 + t * dy;
+            acc[4 * q + 2] += Gp * a2 + t * dz;
+            acc[4 * q + 3] += Gp * da;
+        };
+        for (int p0 = b_lo; p0 < b_hi; p0 += per) {
+            const int nb = min(b_hi, p0 + per);
 #pragma unroll
-        for (int q = 0; q < 4 * NS; ++q)
-            acc[q] = 0.0;
-        for (int c0 = 0; c0 < nb; c0 += VJP_RANGES) {
-            const int nc = min(nb - c0, VJP_RANGES);
-            int front, gap;
-            const int ne = stage_blocks(tsrc + e0, c0, nc, nsub, first, count, recA, rv, r_kern,
-                                        lane, R, front, gap);
-            __builtin_amdgcn_wave_barrier();
-            int64_t i = block_particle(R[skip_gap(grp, front, gap)], slot, nnull);
-            double4 xi = pm[i], hi = ph[i];
-            for (int kb = 0; kb < ne; kb += 8) {
-                const double ai0 = abt[3 * i], ai1 = abt[3 * i + 1], ai2 = abt[3 * i + 2];
-                int64_t in = i;
-                double4 xn = xi, hn = hi;
-                if (kb + 8 < ne) {
-                    in = block_particle(R[skip_gap(kb + 8 + grp, front, gap)], slot, nnull);
-                    xn = pm[in];
-                    hn = ph[in];
-                }
+            for (int q = 0; q < 4 * NS; ++q)
+                acc[q] = 0.0;
 #pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    const double dx = xi.x - xs[q].x, dy = xi.y - xs[q].y, dz = xi.z - xs[q].z;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    double Gp, dGr;
-                    pair_gdg_step(r2, hi, hsn[q], i == js[q], Gp, dGr);
-                    const double da = dx * ai0 + dy * ai1 + dz * ai2;
-                    const double t = dGr * da;
-                    const double mj = xs[q].w;
-                    // xbar_j -= dbar = -m_j [G abar_i + t d]
-                    acc[4 * q] += mj * (Gp * ai0 + t * dx);
-                    acc[4 * q + 1] += mj * (Gp * ai1 + t * dy);
-                    acc[4 * q + 2] += mj * (Gp * ai2 + t * dz);
-                    acc[4 * q + 3] -= Gp * da;
+            for (int q = 0; q < NS; ++q)
+                tail[q] = 0;
+            for (int c0 = p0; c0 < nb; c0 += VJP_BLOCKS) {
+                const int nc = min(nb - c0, VJP_BLOCKS);
+                const int ne = __builtin_amdgcn_readfirstlane(
+                    stage_list_blocks(tl, c0, nc, nsub, first, count, lane, R));
+                __builtin_amdgcn_wave_barrier();
+                for (int kb = 0; kb < ne; kb += 8) {
+                    uint32_t full = 0u;
+                    {
+                        const int32_t i = (int32_t)block_particle(R[kb + grp], slot, nnull);
+                        const double4 xi = pm[i];
+                        const double hi4 = ph[i].z;
+                        const double a0 = abt[3 * (int64_t)i], a1 = abt[3 * (int64_t)i + 1],
+                                     a2 = abt[3 * (int64_t)i + 2];
+                        const double hmax4 = hi4 > H4 ? hi4 : H4;
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) {
+                            const double dx = xi.x - sx[q], dy = xi.y - sy[q], dz = xi.z - sz[q];
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            const bool newt = !(r2 < hmax4);
+                            const uint64_t bal = ~__ballot(newt);
+                            if (newt) {
+                                const double u = rsqrt_pos(r2);
+                                const double u2 = u * u;
+                                const double Gp = u2 * u;
+                                const double da = dx * a0 + dy * a1 + dz * a2;
+                                const double t = (-3.0 * (Gp * u2)) * da;
+                                acc[4 * q] += Gp * a0 + t * dx;
+                                acc[4 * q + 1] += Gp * a1 + t * dy;
+                                acc[4 * q + 2] += Gp * a2 + t * dz;
+                                acc[4 * q + 3] += Gp * da;
+                            }
+                            if (bal) {
+                                const int t0 = tail[q];
+                                if (!newt)
+                                    que[w][q][(t0 + __popcll(bal & lt)) & (VJP_QCAP - 1)] = i;
+                                tail[q] = t0 + __popcll(bal);
+                                if ((tail[q] >> 6) != (t0 >> 6))
+                                    full |= 1u << q;
+                            }
+                        }
+                    }
+                    if (full) {
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int q = 0; q < NS; ++q)
+                            if (full & (1u << q))
+                                drain(q, ((tail[q] >> 6) - 1) << 6, 64);
+                    }
                 }
-                i = in;
-                xi = xn;
-                hi = hn;
+                __builtin_amdgcn_wave_barrier();
             }
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (tail[q] & 63)
+                    drain(q, tail[q] & ~63, tail[q] & 63);
             __builtin_amdgcn_wave_barrier();
+            const double e = reduce_scatter32(acc, lane);
+            const double mq = shx[w][qv].w;
+            tot += kv < 3 ? mq * e : -e;
         }
-        int idx;
-        const double tot = rs16(acc, lane, idx);
-        const int q = idx >> 2, comp = idx & 3;
-        if ((lane & 3) == 0 && sb + q < c) {
-            const int64_t jj = f + sb + q;
-            if (comp < 3)
-                xbt[3 * jj + comp] += tot;
+        if ((lane & 1) == 0 && sb + qv < c) {
+            const int64_t jj = f + sb + qv;
+            if (split)
+                part[(int64_t)unit * part_stride + 4 * (sb + qv) + kv] = tot;
+            else if (kv < 3)
+                xbt[3 * jj + kv] += tot;
             else
                 mbt[jj] = tot;
         }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The near field's pieces of split leaves, folded in piece order: `vals`
+// values per particle (3: xbar, sink side; 4: xbar and mbar, source side).
+// One wavefront per extra entry of the piece list; the one holding piece 1
+// of its leaf folds it.
+__global__ __launch_bounds__(256) void k_vjp_p2p_fold(
+    const int32_t *__restrict__ leaf_node, const int2 *__restrict__ list, int extra,
+    const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+    const int64_t *__restrict__ off, const double *__restrict__ part, int stride, int vals,
+    double *xbt, double *mbt)
+{
+    const int e = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (e >= extra || list[e].y != 1)
+        return;
+    const int lf = list[e].x;
+    const int v = leaf_node[lf];
+    const int64_t f = first[v];
+    const int c = count[v];
+    const int np = (int)(off[lf + 1] - off[lf]);
+    for (int iv = lane_id(); iv < vals * c; iv += 64) {
+        double tot = 0.0;
+        for (int q = 0; q < np; ++q)
+            tot += part[piece_pos(off, extra, lf, q) * stride + iv];
+        const int i = iv / vals, k = iv - vals * (iv / vals);
+        if (k < 3)
+            xbt[3 * (f + i) + k] += tot;
+        else
+            mbt[f + i] = tot;
     }
 }
 
@@ -1145,6 +1289,19 @@ __global__ __launch_bounds__(256) void k_cnt_write(const int32_t *cnt, int cap, 
     if (blockIdx.x == 0 && threadIdx.x == 0)
         off[nl] = *total;
 }
+
+hipError_t launch_count_scan(const int32_t *cnt, int cap, int n, int64_t *tsum, int64_t *off,
+                             hipStream_t s)
+{
+    const int ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t *total = tsum + ntiles;
+    k_cnt_tiles<<<ntiles, 256, 0, s>>>(cnt, cap, n, tsum);
+    k_cnt_tile_scan<<<1, 1024, 0, s>>>(tsum, ntiles, total);
+    k_cnt_write<<<ntiles, 256, 0, s>>>(cnt, cap, n, tsum, total, off);
+    return hipGetLastError();
+}
+
+int64_t count_scan_workspace(int n) { return n / SCAN_TILE + 2; }
 
 // (target, sink) pairs in sink-major order: key = target node, value = sink node
 __global__ void k_pairs_write(const int32_t *__restrict__ cnt, const int32_t *__restrict__ slots,
@@ -1347,6 +1504,68 @@ static hipError_t build_m2lt_pieces(Tree &t, hipStream_t s)
     return hipGetLastError();
 }
 
+// Pieces of the transposed near lists (the source side of P2P^T), cut as
+// the forward lists are: ceil(blocks / per) per leaf, at least one.
+__global__ void k_tpiece_count(const int32_t *__restrict__ leaf_node, int nleaves,
+                               const int64_t *__restrict__ toff, int nsub, int64_t per,
+                               int32_t *np)
+{
+    const int lf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lf >= nleaves)
+        return;
+    const int v = leaf_node[lf];
+    const int64_t wk = (toff[v + 1] - toff[v]) * nsub;
+    np[lf] = (int32_t)max<int64_t>(1, (wk + per - 1) / per);
+}
+
+static hipError_t build_p2pt_pieces(Tree &t, hipStream_t s)
+{
+    Tree::Pieces &P = t.pnearT;
+    const Topology &T = t.topo;
+    const int nl = T.nleaves;
+    const int nsub = (T.leaf_size + 7) / 8;
+    hipError_t e = hipSuccess;
+    if (!P.np) {
+        const int64_t lc = T.leaf_cap;
+        e = tree_malloc(t, (void **)&P.np, lc * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = tree_malloc(t, (void **)&P.off, (lc + 1) * sizeof(int64_t));
+        if (e == hipSuccess)
+            e = tree_malloc(t, (void **)&P.tsum, count_scan_workspace((int)lc) * sizeof(int64_t));
+        if (e != hipSuccess) {
+            vfree(t, {(void **)&P.np, (void **)&P.off, (void **)&P.tsum});
+            return e;
+        }
+    }
+    P.n = 0;
+    k_tpiece_count<<<(nl + 255) / 256, 256, 0, s>>>(t.leaf_node, nl, t.nearT.off, nsub,
+                                                     t.near_piece_blocks, P.np);
+    e = launch_count_scan(P.np, INT32_MAX, nl, P.tsum, P.off, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t.h_pairs + 2, P.off + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return e;
+    const int64_t np = t.h_pairs[2];
+    if (np > nl && np > P.cap) {
+        vfree(t, {(void **)&P.list, &P.part});
+        P.cap = 0;
+        const int64_t cp = np + np / 4 + 64;
+        e = tree_malloc(t, (void **)&P.list, cp * sizeof(int2));
+        if (e == hipSuccess)
+            e = tree_malloc(t, &P.part, cp * 4 * (size_t)T.leaf_size * sizeof(double));
+        if (e != hipSuccess) {
+            vfree(t, {(void **)&P.list, &P.part});
+            return e;
+        }
+        P.cap = cp;
+    }
+    P.part_stride = 4 * (size_t)T.leaf_size * sizeof(double);
+    P.n = np;
+    return np > nl ? launch_piece_table(P.off, P.np, nl, P.list, s) : hipSuccess;
+}
+
 // M2L^T, sink side per leaf and source side in pieces.
 template <int FORM>
 static void vjp_m2l(Tree &t, hipStream_t s)
@@ -1402,6 +1621,8 @@ hipError_t ensure_transposed(Tree &t, hipStream_t s)
     if (e == hipSuccess)
         e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, t.nearT, s);
     if (e == hipSuccess)
+        e = build_p2pt_pieces(t, s);
+    if (e == hipSuccess)
         t.has_transposed = true;
     return e;
 }
@@ -1441,12 +1662,35 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
                                                                   t.ppart, t.nadj);
     }
     const int nsub = (T.leaf_size + 7) / 8;
-    k_vjp_p2p_sink<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
-                                                nl, t.near_cnt, t.near_src, (int)t.cap_near,
-                                                nsub, t.recA, t.p.r_kern, n, t.xbt);
-    k_vjp_p2p_src<<<(nl + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node,
-                                               nl, t.nearT.off, t.nearT.src, nsub, t.recA,
-                                               t.p.r_kern, n, t.xbt, t.mbt);
+    const int per = (int)t.near_piece_blocks;
+    {
+        // sink side: the forward near lists, in their pieces when split
+        const bool pc = use_pieces(t);
+        const int nu = pc ? (int)t.pnear.n : nl;
+        const int stride = 3 * T.leaf_size;
+        k_vjp_p2p_sink<<<(nu + 3) / 4, 256, 0, s>>>(
+            t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node, nu, t.near_cnt, t.near_src,
+            (int)t.cap_near, nsub, n, t.xbt, pc ? t.pnear.list : nullptr, per,
+            (double *)t.pnear.part, stride);
+        if (pc && nu > nl)
+            k_vjp_p2p_fold<<<(nu - nl + 3) / 4, 256, 0, s>>>(
+                t.leaf_node, t.pnear.list, nu - nl, t.first, t.count, t.pnear.off,
+                (const double *)t.pnear.part, stride, 3, t.xbt, t.mbt);
+    }
+    {
+        // source side: the transposed near lists, in their own pieces
+        const bool pc = t.pnearT.n > nl;
+        const int nu = pc ? (int)t.pnearT.n : nl;
+        const int stride = 4 * T.leaf_size;
+        k_vjp_p2p_src<<<(nu + 3) / 4, 256, 0, s>>>(
+            t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node, nu, t.nearT.off, t.nearT.src, nsub,
+            n, t.xbt, t.mbt, pc ? t.pnearT.list : nullptr, per, (double *)t.pnearT.part,
+            stride);
+        if (pc)
+            k_vjp_p2p_fold<<<(nu - nl + 3) / 4, 256, 0, s>>>(
+                t.leaf_node, t.pnearT.list, nu - nl, t.first, t.count, t.pnearT.off,
+                (const double *)t.pnearT.part, stride, 4, t.xbt, t.mbt);
+    }
     if (fp32)
         k_vjp_moments<float><<<(int)((n + 255) / 256), 256, 0, s>>>(
             t.pm, n, t.recA, t.nadj, t.first, t.count, t.left, t.right, T.nnodes, t.xbt, t.mbt,
@@ -1467,7 +1711,9 @@ void release_vjp(Tree &t)
     t.vjp_owned.clear();
     vfree(t, {(void **)&t.vk0, (void **)&t.vk1, (void **)&t.vv0, (void **)&t.vv1,
               (void **)&t.vhist, (void **)&t.vtot, (void **)&t.farT.src, (void **)&t.nearT.src,
-              (void **)&t.pnode, (void **)&t.ppart});
+              (void **)&t.pnode, (void **)&t.ppart, (void **)&t.pnearT.np, (void **)&t.pnearT.off,
+              (void **)&t.pnearT.tsum, (void **)&t.pnearT.list, &t.pnearT.part});
+    t.pnearT.cap = t.pnearT.n = 0;
     if (t.h_pairs)
         (void)hipHostFree(t.h_pairs);
     t.h_pairs = nullptr;

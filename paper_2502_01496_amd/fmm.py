@@ -346,18 +346,22 @@ def fmm_debug_import(tree, x, m, h, ex: dict, stream=None):
                                   _ptr(h, torch.float64, (n,), "h"), *args, _stream(stream)))
 
 
-def fmm_debug_export(tree, lists: bool = True, local: bool = False) -> dict:
-    """Copy the tree, cell records and lists to host numpy arrays."""
+def fmm_debug_export(tree, lists=True, local: bool = False) -> dict:
+    """Copy the tree, cell records and lists to host numpy arrays.
+    lists: True (offsets and entries), "offsets" (the CSR offsets only, i.e.
+    the list lengths: cheap for trees too large to copy every entry), False."""
     info = fmm_tree_info(tree)
     n, nn = info["n"], info["nodes"]
     out = {"perm": np.empty(n, np.int32)}
     for k in ("first", "count", "left", "right", "axis"):
         out[k] = np.empty(nn, np.int32)
     out["rec"] = np.empty((nn, 12))
-    have_lists = lists and info["has_lists"]
+    have_lists = bool(lists) and info["has_lists"]
+    entries = have_lists and lists != "offsets"
     if have_lists:
         out["far_off"] = np.empty(nn + 1, np.int64)
         out["near_off"] = np.empty(nn + 1, np.int64)
+    if entries:
         out["far_src"] = np.empty(max(info["n_far"], 1), np.int32)
         out["near_src"] = np.empty(max(info["n_near"], 1), np.int32)
     if local:
@@ -370,7 +374,7 @@ def fmm_debug_export(tree, lists: bool = True, local: bool = False) -> dict:
     _check(lib().fmm_debug_export(C.c_void_p(tree), p("perm"), p("first"), p("count"),
                                   p("left"), p("right"), p("axis"), p("rec"), p("far_off"),
                                   p("far_src"), p("near_off"), p("near_src"), p("local")))
-    if have_lists:
+    if entries:
         out["far_src"] = out["far_src"][: info["n_far"]]
         out["near_src"] = out["near_src"][: info["n_near"]]
     return out

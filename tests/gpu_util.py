@@ -75,3 +75,25 @@ def gpu_vjp(x, m, h, abar, theta=0.5, leaf=8, G=1.0, precision=F.FMM_FP64, repea
     finally:
         F.fmm_tree_free(t)
     return A.cpu().numpy().astype(np.float64), out
+
+
+def oracle_fmm_threaded(orc, x, m, h, theta=0.5, leaf=8, threads=None):
+    """The oracle's serial FMM (leaf <- cell walk) for every particle, its
+    per-leaf evaluations spread over threads (the tree build stays serial).
+    Rows are identical to orc.fmm(...).a: same tree, lists and arithmetic."""
+    import concurrent.futures as cf
+    import os
+
+    if threads is None:
+        try:
+            threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        except Exception:
+            threads = 4
+    tree = orc.build_tree(x, leaf)
+    mom = orc.moments(x, m, h, tree)
+    leaves = np.flatnonzero(tree.left < 0)
+    a = np.zeros_like(np.asarray(x, dtype=np.float64))
+    parts = np.array_split(leaves, threads * 8)
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda p: orc.fmm_leaves(x, m, h, tree, mom, p, theta=theta, a=a), parts))
+    return a, tree, mom

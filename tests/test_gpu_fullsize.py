@@ -13,7 +13,13 @@ capacities, leaf size 8).
   their own system against the oracle's direct-sum adjoint;
 * binary 2 x 2^23: FP32 forward through 10 KDK steps and the checkpointed
   backward pass of |x_com(T) - x_com(0)|^2, against central finite
-  differences with every step's tree and lists held at the forward pass's."""
+  differences with every step's tree and lists held at the forward pass's;
+  its step-0 FP64 forward against the oracle: tree and cell records
+  bit-identical, list lengths and forces of 2048 sampled sink leaves from
+  the oracle's per-leaf evaluation on its own tree;
+* binary 2 x 2^18, the first 10 KDK steps (theta = 0.5) against the oracle:
+  every step's forces on every particle, the KDK update, and the oracle's own
+  trajectory (positions and total force per step)."""
 import time
 
 import numpy as np
@@ -23,7 +29,7 @@ import torch
 from paper_2502_01496_amd import fmm as F
 from paper_2502_01496_amd import leapfrog as LF
 from paper_2502_01496_amd import workloads as W
-from tests.gpu_util import eta, force_err, gpu_run, gpu_vjp, say, to_dev
+from tests.gpu_util import eta, force_err, gpu_run, gpu_vjp, oracle_fmm_threaded, say, to_dev
 from tests.test_gpu_parity import sorted_by_sink
 
 pytestmark = pytest.mark.gpu
@@ -110,16 +116,18 @@ def test_clumpy_2e22_precision_forms(orc):
     e32 = eta(a32, ref.a)
     sinks = np.random.default_rng(9).choice(n, 512, replace=False)
     d = orc.direct_sinks(x, m, h, sinks)
-    e64d, e32d = eta(a64[sinks], d), eta(a32[sinks], d)
+    e64d, e32d, eod = eta(a64[sinks], d), eta(a32[sinks], d), eta(ref.a[sinks], d)
     r64, r32, rref = (orc.stats(x, None, m, a)["ratio"] for a in (a64, a32, ref.a))
     say(f"    FP64 vs oracle FMM: max rel {err64:.3e}")
     say(f"    FP32 vs FP64 oracle FMM: eta {e32:.3e}, median {np.median(rel32):.3e}, "
         f"p99 {np.percentile(rel32, 99):.3e}, max {rel32.max():.3e}")
-    say(f"    vs direct (512 sinks): eta FP64 {e64d:.3e}, FP32 {e32d:.3e}")
+    say(f"    vs direct (512 sinks): eta FP64 {e64d:.3e}, FP32 {e32d:.3e}, oracle FMM {eod:.3e}")
     say(f"    |sumF|/sum|F|: FP64 {r64:.4e}, FP32 {r32:.4e}, oracle {rref:.4e}")
     assert err64 <= 1e-12
     assert e32 <= 1e-5 and np.percentile(rel32, 99) <= 1e-4
-    assert e64d <= 3e-3 and abs(e32d - e64d) <= 1e-4
+    # the error against the direct sum is the method's: the GPU's equals the
+    # oracle FMM's on the same sinks (FP64 to round-off, FP32 to its own error)
+    assert abs(e64d - eod) <= 1e-9 * eod and abs(e32d - eod) <= 1e-4 * eod + 1e-7
     assert abs(r64 - rref) <= 1e-10 and abs(r32 - rref) <= 1e-3 * rref + 1e-8
 
 
@@ -262,3 +270,104 @@ def test_binary_2x2e23_backward_through_10_steps():
     say(f"    loss |x_com(T)-x_com(0)|^2 = {L:.4e}; |dL/dx_0| = {float(torch.linalg.norm(grad_x0)):.3e}; "
         f"peak HBM (torch + library) {peak / 2**30:.2f} GiB; worst rel FD mismatch {worst:.3e}")
     assert worst <= 1e-5
+
+
+def _check_tree_records(ex, tree, mom):
+    np.testing.assert_array_equal(ex["perm"], tree.perm)
+    for k in ("first", "count", "left", "right", "axis"):
+        np.testing.assert_array_equal(ex[k], getattr(tree, k))
+    rec = ex["rec"]
+    np.testing.assert_array_equal(rec[:, 0], mom.M)
+    np.testing.assert_array_equal(rec[:, 1:4], mom.c)
+    np.testing.assert_array_equal(rec[:, 4], mom.s)
+    np.testing.assert_array_equal(rec[:, 5], mom.hmax)
+    scale = (mom.M * mom.s ** 2)[:, None]
+    assert (np.abs(rec[:, 6:12] - mom.Q) <= 1e-14 * scale + 1e-300).all()
+
+
+@pytest.mark.timeout(900)
+def test_binary_2x2e23_step0_against_oracle(orc):
+    x, m, h = W.polytrope_binary(1 << 23, 5)
+    n = len(m)
+    say(f"[gpu full] binary 2x2^23 step 0, FP64: tree bit-exact, 2048 sampled leaves vs oracle")
+    X, Mt, H = to_dev(x, m, h)
+    t = F.fmm_build_tree(X, F.default_params())
+    try:
+        F.fmm_moments(t, X, Mt, H)
+        A = torch.empty_like(X)
+        F.fmm_forces(t, A)
+        torch.cuda.synchronize()
+        ex = F.fmm_debug_export(t, lists="offsets")
+        a = A.cpu().numpy()
+    finally:
+        F.fmm_tree_free(t)
+    del X, Mt, H, A
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    tree = orc.build_tree(x, 8)
+    mom = orc.moments(x, m, h, tree)
+    say(f"    oracle tree and moments of {n} particles: {time.perf_counter() - t0:.1f} s")
+    _check_tree_records(ex, tree, mom)
+    leaves = np.flatnonzero(tree.left < 0)
+    sel = np.sort(np.random.default_rng(59).choice(leaves, 2048, replace=False))
+    ao, cnt = orc.fmm_leaves(x, m, h, tree, mom, sel, counts=True)
+    np.testing.assert_array_equal(np.diff(ex["far_off"])[sel], cnt[:, 0])
+    np.testing.assert_array_equal(np.diff(ex["near_off"])[sel], cnt[:, 1])
+    rows = np.concatenate([tree.perm[tree.first[v]:tree.first[v] + tree.count[v]] for v in sel])
+    err = force_err(a[rows], ao[rows])
+    say(f"    {len(rows)} particles of {len(sel)} leaves ({cnt[:, 0].mean():.0f} far, "
+        f"{cnt[:, 1].mean():.0f} near cells per leaf): max rel force error {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_binary_2x2e18_first_10_kdk_steps_against_oracle(orc):
+    x0, m, h = W.polytrope_binary(1 << 18, 2)
+    n, dt, steps = len(m), 1e-3, 10
+    say(f"[gpu full] binary 2x2^18: {steps} KDK steps, theta 0.5, every step against the oracle")
+    X, Mt, H = to_dev(x0, m, h)
+    V = torch.zeros_like(X)
+    A = torch.empty_like(X)
+    g = F.GravityFMM(theta=0.5)
+    xs, vs, as_ = [], [], []
+    try:
+        g.forces(X, Mt, H, out=A)
+        xs.append(X.cpu().numpy()), vs.append(V.cpu().numpy()), as_.append(A.cpu().numpy())
+        for _ in range(steps):
+            F.fmm_kick_drift(X, V, A, 0.5 * dt, dt)
+            g.forces(X, Mt, H, out=A)
+            F.fmm_kick_drift(X, V, A, 0.5 * dt, 0.0)
+            xs.append(X.cpu().numpy()), vs.append(V.cpu().numpy()), as_.append(A.cpu().numpy())
+    finally:
+        g.free()
+    # (1) every step: the oracle's forces at the GPU's positions, and the KDK
+    # update of the GPU's state repeated on the host (same two operations per
+    # component, so bit for bit)
+    worst = 0.0
+    for k in range(steps + 1):
+        ao, _, _ = oracle_fmm_threaded(orc, xs[k], m, h, theta=0.5)
+        err = force_err(as_[k], ao)
+        sg, so = orc.stats(xs[k], None, m, as_[k]), orc.stats(xs[k], None, m, ao)
+        worst = max(worst, err)
+        assert err <= 1e-12, (k, err)
+        assert np.abs(sg["sumF"] - so["sumF"]).max() <= 1e-12 * so["sumAbsF"], k
+        if k < steps:
+            vh = vs[k] + (0.5 * dt) * as_[k]
+            np.testing.assert_array_equal(xs[k + 1], xs[k] + dt * vh)
+            np.testing.assert_array_equal(vs[k + 1], vh + (0.5 * dt) * as_[k + 1])
+    # (2) the oracle's own trajectory from the same start
+    xo, vo = x0.copy(), np.zeros_like(x0)
+    ao, _, _ = oracle_fmm_threaded(orc, xo, m, h, theta=0.5)
+    dx_max = dF_max = 0.0
+    for k in range(steps):
+        vo = vo + (0.5 * dt) * ao
+        xo = xo + dt * vo
+        ao, _, _ = oracle_fmm_threaded(orc, xo, m, h, theta=0.5)
+        vo = vo + (0.5 * dt) * ao
+        dx = np.abs(xo - xs[k + 1]).max() / np.abs(xo).max()
+        so, sg = orc.stats(xo, vo, m, ao), orc.stats(xs[k + 1], vs[k + 1], m, as_[k + 1])
+        dF = np.abs(so["sumF"] - sg["sumF"]).max() / so["sumAbsF"]
+        dx_max, dF_max = max(dx_max, dx), max(dF_max, dF)
+        assert dx <= 1e-12 and dF <= 1e-12, (k, dx, dF)
+    say(f"    forces at the GPU's positions: worst max rel error {worst:.2e}; oracle's own "
+        f"trajectory: positions {dx_max:.2e}, sum F {dF_max:.2e} of sum |F|")
