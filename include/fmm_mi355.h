@@ -96,7 +96,16 @@ enum { FMM_EXPANSION_PHANTOM = 0, FMM_EXPANSION_DEHNEN = 1 };
 enum { FMM_TREE_MEDIAN = 0, FMM_TREE_COM = 1 };
 
 /* fmm_forces flags */
-enum { FMM_REWALK = 1 /* rebuild the interaction lists even if present */ };
+enum {
+    FMM_REWALK = 1,  /* rebuild the interaction lists even if present */
+    /* Prepare the tree for fmm_forces_vjp without evaluating the forces: the
+     * walk (when due) and, for an FP64 tree, the far-field expansions the
+     * reverse pass reads; the near field is not evaluated and a is neither
+     * read nor written (it may be NULL).  For callers that need the reverse
+     * pass at positions whose forces they already have, such as the
+     * backward sweep through checkpointed time steps. */
+    FMM_VJP_ONLY = 2
+};
 
 /* Device allocator hooks (fmm_params.dev_alloc / dev_free): every byte of
  * device memory a tree holds is taken with dev_alloc(bytes, alloc_ctx) and
@@ -201,7 +210,9 @@ fmm_status fmm_moments(fmm_tree *tree, const double *x, const double *m, const d
  * Walks the tree (building the interaction lists) when there are none or
  * flags & FMM_REWALK, then evaluates M2L (eq. (6)), L2L (mutual walk only),
  * L2P (eq. (8)) and the softened near field, and writes
- *   a  device, double[n][3] (FMM_FP64) or float[n][3] (FMM_FP32), caller order.
+ *   a  device, double[n][3] (FMM_FP64) or float[n][3] (FMM_FP32), caller order;
+ *      not used with FMM_VJP_ONLY (may then be NULL).
+ *   flags  FMM_REWALK and / or FMM_VJP_ONLY; other bits: FMM_ERR_INVALID.
  * Synchronises `stream` once: to size the interaction lists when it walks,
  * else to read the data checks of the last fmm_moments.
  * Errors: FMM_ERR_STATE (no moments), FMM_ERR_INVALID (bad input data found

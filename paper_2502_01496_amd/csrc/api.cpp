@@ -815,7 +815,7 @@ static fmm_status check_data_after(Tree &t, hipStream_t s)
 // fmm_forces for the mutual walk: walk (one readback of the pair counts,
 // buffers grown and the walk redone if they overflowed), sort into lists,
 // then M2L + L2L and the near field.
-static fmm_status forces_mutual(Tree &t, void *a, bool walk, hipStream_t s)
+static fmm_status forces_mutual(Tree &t, void *a, bool walk, bool vjp_only, hipStream_t s)
 {
     MutualLists &M = t.mw;
     const Topology &T = t.topo;
@@ -892,12 +892,12 @@ static fmm_status forces_mutual(Tree &t, void *a, bool walk, hipStream_t s)
         if (st != FMM_OK)
             return st;
     }
-    {
+    if (!vjp_only || t.p.precision == FMM_FP64) {
         StageTimer tm(t, s, 3);
         HIP_TRY(launch_far_mutual(t, s));
         tm.done();
     }
-    {
+    if (!vjp_only) {
         StageTimer tm(t, s, 4);
         HIP_TRY(launch_near(t, a, s));
         tm.done();
@@ -1063,15 +1063,22 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
 {
     if (!tree_ok(tree))
         return fail(FMM_ERR_STATE, "unknown or freed tree handle");
-    if (!a)
+    if (flags & ~(FMM_REWALK | FMM_VJP_ONLY))
+        return fail(FMM_ERR_INVALID, "unknown flags 0x%x", (unsigned)flags);
+    // FMM_VJP_ONLY: the state the reverse pass needs (lists; the far-field
+    // expansions of an FP64 tree, which the reverse pass reads -- an FP32
+    // tree's reverse pass forms its own FP64 ones), no forces
+    const bool vjp_only = (flags & FMM_VJP_ONLY) != 0;
+    if (!a && !vjp_only)
         return fail(FMM_ERR_INVALID, "a must not be NULL");
     Tree &t = *reinterpret_cast<Tree *>(tree);
+    const bool far_needed = !vjp_only || t.p.precision == FMM_FP64;
     if (!t.has_moments)
         return fail(FMM_ERR_STATE, "fmm_moments must run before fmm_forces");
     hipStream_t s = (hipStream_t)stream;
     const bool walk = !t.has_lists || (flags & FMM_REWALK) || t.lists_policy != t.p.walk;
     if (t.p.walk == FMM_WALK_MUTUAL) {
-        fmm_status st = forces_mutual(t, a, walk, s);
+        fmm_status st = forces_mutual(t, a, walk, vjp_only, s);
         if (st != FMM_OK || walk)
             return st;
         return check_data_after(t, s);
@@ -1098,12 +1105,12 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             if (st != FMM_OK)
                 return st;
         }
-        {
+        if (far_needed) {
             StageTimer tm(t, s, 3);
             HIP_TRY(launch_far(t, s));
             tm.done();
         }
-        {
+        if (!vjp_only) {
             StageTimer tm(t, s, 4);
             HIP_TRY(launch_near(t, a, s));
             tm.done();
@@ -1125,12 +1132,12 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             HIP_TRY(launch_piece_counts(t, s));
             HIP_TRY(read_piece_totals_async(t, s));
         } else {
-            {
+            if (far_needed) {
                 StageTimer tm(t, s, 3);
                 HIP_TRY(launch_far(t, s));
                 tm.done();
             }
-            {
+            if (!vjp_only) {
                 StageTimer tm(t, s, 4);
                 HIP_TRY(launch_near(t, a, s));
                 tm.done();
@@ -1179,12 +1186,12 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
                     if (st != FMM_OK)
                         return st;
                 }
-                {
+                if (far_needed) {
                     StageTimer tm(t, s, 3);
                     HIP_TRY(launch_far(t, s));
                     tm.done();
                 }
-                {
+                if (!vjp_only) {
                     StageTimer tm(t, s, 4);
                     HIP_TRY(launch_near(t, a, s));
                     tm.done();

@@ -26,6 +26,7 @@ FMM_WALK_PHANTOM, FMM_WALK_MUTUAL = 0, 1
 FMM_EXPANSION_PHANTOM, FMM_EXPANSION_DEHNEN = 0, 1
 FMM_TREE_MEDIAN, FMM_TREE_COM = 0, 1
 FMM_REWALK = 1
+FMM_VJP_ONLY = 2
 
 _STATUS = {0: "FMM_OK", -1: "FMM_ERR_INVALID", -2: "FMM_ERR_ALLOC", -3: "FMM_ERR_CAPACITY",
            -4: "FMM_ERR_HIP", -5: "FMM_ERR_STATE"}
@@ -215,8 +216,11 @@ def _tree_dtype_n(tree):
 
 
 def fmm_forces(tree, a, flags: int = 0, stream=None):
+    """a may be None with FMM_VJP_ONLY (the tree is prepared for the reverse
+    pass and no forces are written)."""
     dt, n = _tree_dtype_n(tree)
-    _check(lib().fmm_forces(C.c_void_p(tree), _ptr(a, dt, (n, 3), "a"), flags, _stream(stream)))
+    ap = None if (a is None and flags & FMM_VJP_ONLY) else _ptr(a, dt, (n, 3), "a")
+    _check(lib().fmm_forces(C.c_void_p(tree), ap, flags, _stream(stream)))
 
 
 def fmm_forces_vjp(tree, a_bar, x_bar, m_bar, stream=None):

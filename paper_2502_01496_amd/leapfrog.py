@@ -7,7 +7,8 @@ The adjoint of T steps needs a(x) and its VJP at every visited position
 x_0..x_T and nothing else (the forces depend on x only), so the forward keeps
 the positions as checkpoints and the reverse sweep rebuilds the tree at each
 checkpoint (the build is deterministic, so the tree and the interaction lists
-are those of the forward pass).  The two half kicks that act at x_k (the last
+are those of the forward pass) and walks it without evaluating the forces
+again.  The two half kicks that act at x_k (the last
 of step k-1 and the first of step k) carry the same cotangent, so one VJP per
 checkpoint suffices:
 
@@ -47,6 +48,15 @@ class ForceField:
             out = torch.empty((x.shape[0], 3), dtype=self.dtype, device=x.device)
         F.fmm_forces(self.g.tree, out, F.FMM_REWALK)
         return out
+
+    def prepare_vjp(self, x, m, h):
+        """Build the tree at x, then moments and walk: the state the reverse
+        pass needs, without evaluating the forces (they are known from the
+        forward sweep)."""
+        self.g.build(x, m=m)
+        self.generation += 1
+        F.fmm_moments(self.g.tree, x, m, h)
+        F.fmm_forces(self.g.tree, None, F.FMM_REWALK | F.FMM_VJP_ONLY)
 
     def vjp(self, abar):
         """VJP of the last forces() call: (xbar, mbar) in the force dtype."""
@@ -109,13 +119,13 @@ def kdk_backward(ckpt, m, h, dt, field: ForceField, xbar_T, vbar_T):
     xbar = xbar_T.to(torch.float64).clone()
     vbar = vbar_T.to(torch.float64).clone()
     mbar = torch.zeros_like(m, dtype=torch.float64)
-    field.forces(ckpt[T], m, h)
+    field.prepare_vjp(ckpt[T], m, h)
     xb, mb = field.vjp(0.5 * dt * vbar)
     xbar += xb.double()
     mbar += mb.double()
     for k in range(T - 1, -1, -1):
         vbar += dt * xbar
-        field.forces(ckpt[k], m, h)
+        field.prepare_vjp(ckpt[k], m, h)
         c = dt if k > 0 else 0.5 * dt
         xb, mb = field.vjp(c * vbar)
         xbar += xb.double()

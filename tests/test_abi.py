@@ -127,3 +127,16 @@ def test_binding_checks_dtype_and_shape_before_the_call():
         F._ptr(torch.zeros(3, 4, dtype=torch.float64).t(), torch.float64, (4, 3), "a")
     with pytest.raises(TypeError, match="GPU"):
         F._ptr(torch.zeros(4, 3, dtype=torch.float64), torch.float64, (4, 3), "a")
+
+
+def test_binding_constants_match_header():
+    # every FMM_* enumerator of the header has the same value in the binding
+    import os
+    import re
+
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "fmm_mi355.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    found = dict(re.findall(r"\b(FMM_[A-Z0-9_]+)\s*=\s*(-?\d+)", hdr))
+    assert "FMM_VJP_ONLY" in found and "FMM_REWALK" in found
+    for name, value in found.items():
+        assert getattr(F, name) == int(value), name

@@ -183,3 +183,41 @@ def test_mutual_vjp_deterministic_and_fp32(orc):
     _, [(x3, m3)] = gpu_vjp(x, m, h, abar, precision=F.FMM_FP32, walk=F.FMM_WALK_MUTUAL)
     assert np.linalg.norm(x3 - x1) <= 1e-5 * np.linalg.norm(x1)
     assert np.linalg.norm(m3 - m1) <= 1e-5 * np.linalg.norm(m1)
+
+
+@pytest.mark.parametrize("precision", [F.FMM_FP64, F.FMM_FP32])
+@pytest.mark.parametrize("walk", [F.FMM_WALK_PHANTOM, F.FMM_WALK_MUTUAL])
+def test_vjp_only_preparation_equals_full_forces(orc, precision, walk):
+    # FMM_VJP_ONLY walks the tree (and forms an FP64 tree's far-field
+    # expansions) without evaluating the forces: the reverse pass that follows
+    # is the one after a full forces call, bit for bit
+    import torch
+
+    x, m, h = W.polytrope_binary(3000, 6, cache=False)
+    abar = W.cotangent(len(m), 35)
+    say(f"[gpu vjp] FMM_VJP_ONLY preparation, precision {precision}, walk {walk}")
+    X = torch.from_numpy(x).cuda()
+    Mt = torch.from_numpy(m).cuda()
+    H = torch.from_numpy(h).cuda()
+    dt = torch.float32 if precision == F.FMM_FP32 else torch.float64
+    AB = torch.from_numpy(abar).cuda().to(dt)
+    outs = []
+    for flags in (F.FMM_REWALK, F.FMM_REWALK | F.FMM_VJP_ONLY):
+        t = F.fmm_build_tree(X, F.default_params(precision=precision, walk=walk))
+        try:
+            F.fmm_moments(t, X, Mt, H)
+            A = None if flags & F.FMM_VJP_ONLY else torch.empty((len(m), 3), dtype=dt,
+                                                                 device="cuda")
+            F.fmm_forces(t, A, flags)
+            XB = torch.empty((len(m), 3), dtype=dt, device="cuda")
+            MB = torch.empty(len(m), dtype=dt, device="cuda")
+            F.fmm_forces_vjp(t, AB, XB, MB)
+            torch.cuda.synchronize()
+            outs.append((XB.cpu().numpy(), MB.cpu().numpy()))
+            if flags & F.FMM_VJP_ONLY:
+                with pytest.raises(F.FmmError):
+                    F.fmm_forces(t, A, F.FMM_VJP_ONLY | 8)  # an unknown flag bit
+        finally:
+            F.fmm_tree_free(t)
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
