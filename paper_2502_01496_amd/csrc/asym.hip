@@ -115,10 +115,10 @@ __device__ __forceinline__ void asym_add(const double *__restrict__ recA,
 // (ascending: binary search).
 __global__ __launch_bounds__(256) void k_asym_pairs_leaf(
     const double *__restrict__ recA, const double *__restrict__ tun,
-    const int32_t *__restrict__ left, const int32_t *__restrict__ leaf_node, int nleaves,
-    const int32_t *__restrict__ far_cnt, const int32_t *__restrict__ far_src, int cap_far,
-    const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc, double m_leaf_in,
-    double *part)
+    const int32_t *__restrict__ left, const int32_t *__restrict__ leaf_node,
+    const int32_t *__restrict__ node_leaf, int nleaves, const int32_t *__restrict__ far_cnt,
+    const int32_t *__restrict__ far_src, int cap_far, const int64_t *__restrict__ toff,
+    const uint32_t *__restrict__ tsrc, double m_leaf_in, double *part)
 {
     const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (g >= nleaves)
@@ -134,15 +134,17 @@ __global__ __launch_bounds__(256) void k_asym_pairs_leaf(
         const int b = fl[k];
         bool rev = false;
         if (left[b] < 0) {
+            // the transposed far lists hold sink leaf indices, ascending
+            const int bl = node_leaf[b];
             int64_t lo = t0, hi = t1;
             while (lo < hi) {
                 const int64_t mid = (lo + hi) >> 1;
-                if ((int)tsrc[mid] < b)
+                if ((int)tsrc[mid] < bl)
                     lo = mid + 1;
                 else
                     hi = mid;
             }
-            rev = lo < t1 && (int)tsrc[lo] == b;
+            rev = lo < t1 && (int)tsrc[lo] == bl;
         }
         if (!rev)
             asym_add(recA, tun, a, b, m_leaf, acc);
@@ -255,9 +257,9 @@ hipError_t launch_asym(Tree &t, double m_leaf, double *out, hipStream_t s)
                                                          nl, m_leaf, part);
     } else {
         nsinks = nl;
-        k_asym_pairs_leaf<<<(nl + 3) / 4, 256, 0, s>>>(t.recA, tun, t.left, t.leaf_node, nl,
-                                                       t.far_cnt, t.far_src, (int)t.cap_far,
-                                                       t.farT.off, t.farT.src, m_leaf, part);
+        k_asym_pairs_leaf<<<(nl + 3) / 4, 256, 0, s>>>(
+            t.recA, tun, t.left, t.leaf_node, t.node_leaf, nl, t.far_cnt, t.far_src,
+            (int)t.cap_far, t.farT.off, t.farT.src, m_leaf, part);
     }
     k_asym_fold<<<1, ASYM_FOLD, 0, s>>>(part, nsinks, dout);
     e = hipGetLastError();

@@ -39,6 +39,7 @@ constexpr int NREC = 8;   // doubles per node record (geometry / quadrupole)
 // node), so that a walk reads one 64-byte record per visited cell.
 constexpr int REC_KIDS = 6, REC_LEAF = 7;
 constexpr int NLOC = 20;  // doubles per local expansion (19 used)
+constexpr int LLEAF = 24;  // doubles per leaf record of the reverse pass's M2L^T source side
 
 // ------------------------------------------------------------------ device
 __device__ __forceinline__ uint64_t ordbits(double v)
@@ -302,6 +303,7 @@ struct Tree {
     double *xbt = nullptr;         // xbar accumulator, tree order, 3 per particle
     double *mbt = nullptr;         // mbar accumulator, tree order
     double *Lbar = nullptr;        // NLOC per node
+    double *Lleaf = nullptr;       // LLEAF per leaf: Lbar[19], leaf centre[3], 0, 0
     double *nadj = nullptr;        // 16 per node: cbar_sink[3], cbar_src[3], Mbar, Qbar[6]
     int64_t *h_pairs = nullptr;    // pinned: pair totals, piece total
     // pieces of the transposed far lists (source side of M2L^T)

@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_vjp_l2p(const double4 *__restrict__ pm,
                                                  const int32_t *__restrict__ count,
                                                  const double *__restrict__ recA,
                                                  const double *__restrict__ Lloc, double *Lbar,
-                                                 double *xbt, double *nadj)
+                                                 double *Lleaf, double *xbt, double *nadj)
 {
     const int lf = blockIdx.x * blockDim.x + threadIdx.x;
     if (lf >= nleaves)
@@ -415,6 +415,18 @@ __global__ __launch_bounds__(256) void k_vjp_l2p(const double4 *__restrict__ pm,
 #pragma unroll
     for (int k = 0; k < 19; ++k)
         o[k] = Lb[k];
+    // the same by leaf index with the leaf's centre: the record the M2L^T
+    // source side reads once per far pair (consecutive sinks of a transposed
+    // list are adjacent records)
+    double *ol = Lleaf + (int64_t)LLEAF * lf;
+#pragma unroll
+    for (int k = 0; k < 19; ++k)
+        ol[k] = Lb[k];
+    ol[19] = rv[0];
+    ol[20] = rv[1];
+    ol[21] = rv[2];
+    ol[22] = 0.0;
+    ol[23] = 0.0;
     double *na = nadj + 16 * (int64_t)v;
     na[0] = cb0;
     na[1] = cb1;
@@ -428,7 +440,7 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_sink(
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
     const int32_t *__restrict__ far_src, int cap_far, const double *__restrict__ Lbar, double *nadj)
 {
-    const int g = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
     const int sub = threadIdx.x & 15;
     const bool valid = g < nleaves;
     const int v = valid ? leaf_node[g] : 0;
@@ -486,10 +498,12 @@ template <int FORM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_m2l_src_piece(
     const double *__restrict__ recA, const double *__restrict__ recQ,
     const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc,
-    const double *__restrict__ Lbar, const int32_t *__restrict__ pnode,
+    const double *__restrict__ Lleaf, const int32_t *__restrict__ pnode,
     const int64_t *__restrict__ poff, int64_t npieces, double *part)
 {
-    const int64_t pc = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // consecutive pieces (neighbouring source cells, which share most of
+    // their sinks) run behind the same L2
+    const int64_t pc = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (pc >= npieces)
         return;
     const int lane = lane_id();
@@ -504,13 +518,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     for (int k = 0; k < 10; ++k)
         acc[k] = 0.0;
     for (int64_t e = e0 + lane; e < e1; e += 64) {
-        const int sgm = (int)tsrc[e];
-        const double *rs = recA + (int64_t)NREC * sgm;
-        const double r[3] = {rs[0] - cb0, rs[1] - cb1, rs[2] - cb2};
-        double Lb[19];
+        // the sink leaf's L-bar and centre, one 192-byte record
+        const double2 *lr = (const double2 *)(Lleaf + (int64_t)LLEAF * (int)tsrc[e]);
+        double Lb[20];
 #pragma unroll
-        for (int k = 0; k < 19; ++k)
-            Lb[k] = Lbar[(int64_t)NLOC * sgm + k];
+        for (int k = 0; k < 10; ++k) {
+            const double2 q = lr[k];
+            Lb[2 * k] = q.x;
+            Lb[2 * k + 1] = q.y;
+        }
+        const double2 c12 = lr[10];
+        const double r[3] = {Lb[19] - cb0, c12.x - cb1, c12.y - cb2};
         double rb[3] = {0.0, 0.0, 0.0}, Mb = 0.0, Qb[6] = {0, 0, 0, 0, 0, 0};
         m2l_vjp<FORM>(r, M, Qs, Lb, rb, Mb, Qb);
         acc[0] += Mb;
@@ -802,7 +820,7 @@ __device__ __forceinline__ double reduce_scatter32(const double *v, int lane)
 // (abar_i is wave-uniform, so the G term needs no per-pair product).  The
 // queues that a step fills past a multiple of 64 are evaluated after the
 // step, when its source data are no longer held.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vjp_p2p_sink(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_sink(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nunits,
@@ -964,7 +982,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 // lanes the particles of the sink leaves of its transposed list.  Per source
 // q the lanes sum X = sum_i (G_ij abar_i + D_ij (d . abar_i) d) and
 // Y = sum_i G_ij (d . abar_i); a piece adds m_j X to xbar_j and -Y to mbar_j.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_vjp_p2p_src(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_src(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nunits,
@@ -1303,15 +1321,17 @@ hipError_t launch_count_scan(const int32_t *cnt, int cap, int n, int64_t *tsum, 
 
 int64_t count_scan_workspace(int n) { return n / SCAN_TILE + 2; }
 
-// (target, sink) pairs in sink-major order: key = target node, value = sink node
+// (target, sink) pairs in sink-major order: key = target node, value = the
+// sink leaf's node id (node_values) or its leaf index
 __global__ void k_pairs_write(const int32_t *__restrict__ cnt, const int32_t *__restrict__ slots,
                               int cap, int nl, const int32_t *__restrict__ leaf_node,
-                              const int64_t *__restrict__ off, uint32_t *keys, uint32_t *vals)
+                              int node_values, const int64_t *__restrict__ off, uint32_t *keys,
+                              uint32_t *vals)
 {
     const int lf = blockIdx.x;
     const int c = max(0, min(cnt[lf], cap));
     const int64_t o = off[lf];
-    const uint32_t sink = (uint32_t)leaf_node[lf];
+    const uint32_t sink = node_values ? (uint32_t)leaf_node[lf] : (uint32_t)lf;
     for (int k = threadIdx.x; k < c; k += blockDim.x) {
         keys[o + k] = (uint32_t)slots[(int64_t)lf * cap + k];
         vals[o + k] = sink;
@@ -1368,6 +1388,7 @@ static hipError_t ensure_vjp_base(Tree &t)
     if (e == hipSuccess) e = valloc(t, &t.xbt, 3 * n);
     if (e == hipSuccess) e = valloc(t, &t.mbt, n);
     if (e == hipSuccess) e = valloc(t, &t.Lbar, NLOC * nc);
+    if (e == hipSuccess) e = valloc(t, &t.Lleaf, LLEAF * (int64_t)T.leaf_cap);
     if (e == hipSuccess) e = valloc(t, &t.nadj, 16 * nc);
     if (e == hipSuccess) e = valloc(t, &t.pair_off, T.leaf_cap + 1);
     if (e == hipSuccess) e = valloc(t, &t.vscan, T.leaf_cap / SCAN_TILE + 2);
@@ -1383,7 +1404,7 @@ static hipError_t ensure_vjp_base(Tree &t)
         for (auto &b : t.vjp_owned)
             tree_free(t, b.p);
         t.vjp_owned.clear();
-        t.abt = t.xbt = t.mbt = t.Lbar = t.nadj = nullptr;
+        t.abt = t.xbt = t.mbt = t.Lbar = t.Lleaf = t.nadj = nullptr;
         t.pair_off = t.vscan = t.farT.off = t.poff = t.pscan = t.nearT.off = nullptr;
         t.pcnt = nullptr;
     }
@@ -1400,7 +1421,7 @@ static int key_passes(int nnodes)
 
 // Build one transposed list (sink-major pairs -> target-major CSR, stable).
 static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *slots, int64_t cap,
-                                  Tree::Transposed &out, hipStream_t s)
+                                  bool node_values, Tree::Transposed &out, hipStream_t s)
 {
     const Topology &T = t.topo;
     const int nl = T.nleaves;
@@ -1439,8 +1460,8 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
         t.vjp_pair_cap = cp;
     }
     if (nl > 0)
-        k_pairs_write<<<nl, 64, 0, s>>>(cnt, slots, (int)cap, nl, t.leaf_node, t.pair_off, t.vk0,
-                                        t.vv0);
+        k_pairs_write<<<nl, 64, 0, s>>>(cnt, slots, (int)cap, nl, t.leaf_node, node_values ? 1 : 0,
+                                        t.pair_off, t.vk0, t.vv0);
     const int passes = key_passes(T.nnodes);
     e = radix_sort_u32(t.vk0, t.vv0, t.vk1, t.vv1, np, 1, passes, t.vhist, t.vtot, s);
     if (e != hipSuccess)
@@ -1575,7 +1596,7 @@ static void vjp_m2l(Tree &t, hipStream_t s)
         t.recA, t.recQ, t.leaf_node, nl, t.far_cnt, t.far_src, (int)t.cap_far, t.Lbar, t.nadj);
     if (t.npieces > 0)
         k_vjp_m2l_src_piece<FORM><<<(int)((t.npieces + 3) / 4), 256, 0, s>>>(
-            t.recA, t.recQ, t.farT.off, t.farT.src, t.Lbar, t.pnode, t.poff, t.npieces, t.ppart);
+            t.recA, t.recQ, t.farT.off, t.farT.src, t.Lleaf, t.pnode, t.poff, t.npieces, t.ppart);
 }
 
 // Mutual walk: forward totals of the internal cells, L2L^T level by level
@@ -1614,12 +1635,12 @@ hipError_t ensure_transposed(Tree &t, hipStream_t s)
     if (e != hipSuccess || t.has_transposed)
         return e;
     if (t.lists_policy != FMM_WALK_MUTUAL) {
-        e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, t.farT, s);
+        e = transpose_lists(t, t.far_cnt, t.far_src, t.cap_far, false, t.farT, s);
         if (e == hipSuccess)
             e = build_m2lt_pieces(t, s);
     }
     if (e == hipSuccess)
-        e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, t.nearT, s);
+        e = transpose_lists(t, t.near_cnt, t.near_src, t.cap_near, true, t.nearT, s);
     if (e == hipSuccess)
         e = build_p2pt_pieces(t, s);
     if (e == hipSuccess)
@@ -1648,7 +1669,7 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
     else
         k_vjp_prep<double><<<gs, 256, 0, s>>>((const double *)abar, n, t.perm, t.p.G, t.abt);
     k_vjp_l2p<<<(nl + 255) / 256, 256, 0, s>>>(t.pm, t.abt, t.leaf_node, nl, t.first, t.count,
-                                               t.recA, t.L, t.Lbar, t.xbt, t.nadj);
+                                               t.recA, t.L, t.Lbar, t.Lleaf, t.xbt, t.nadj);
     if (t.lists_policy == FMM_WALK_MUTUAL) {
         e = vjp_mutual_far(t, s);
         if (e != hipSuccess)
