@@ -410,61 +410,86 @@ constexpr int RUN_SHORT = 64;
 
 __device__ __forceinline__ uint32_t hi32(uint64_t k) { return (uint32_t)(k >> 32); }
 
-__global__ __launch_bounds__(256) void k_run_fix(const uint64_t *__restrict__ kin,
-                                                 const uint32_t *__restrict__ vin, uint64_t *kout,
-                                                 uint32_t *vout, int64_t n, uint32_t *long_cnt,
-                                                 int64_t *long_list, int64_t long_cap,
-                                                 uint32_t *err)
+// A block stages its 256 entries with RUN_SHORT + 1 more on each side in
+// LDS (coalesced loads), so that finding a run's ends and ranking inside it
+// read LDS only.
+constexpr int RUN_BLOCK = 256;
+constexpr int RUN_HALO = RUN_SHORT + 1;
+
+__global__ __launch_bounds__(RUN_BLOCK) void k_run_fix(const uint64_t *__restrict__ kin,
+                                                       const uint32_t *__restrict__ vin,
+                                                       uint64_t *kout, uint32_t *vout, int64_t n,
+                                                       uint32_t *long_cnt, int64_t *long_list,
+                                                       int64_t long_cap, uint32_t *err)
 {
-    const int b = blockIdx.y;
+    __shared__ uint64_t sk[RUN_BLOCK + 2 * RUN_HALO];
+    __shared__ uint32_t sv[RUN_BLOCK + 2 * RUN_HALO];
+    const int b = blockIdx.y, t = threadIdx.x;
     const uint64_t *k = kin + (int64_t)b * n;
     const uint32_t *v = vin + (int64_t)b * n;
     uint64_t *ko = kout + (int64_t)b * n;
     uint32_t *vo = vout + (int64_t)b * n;
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * 256) {
-        // a run of one entry (nearly all of them) is decided by the two
-        // neighbours, loaded together with the entry
-        const uint64_t kp = k[p];
-        const uint64_t kprev = k[p > 0 ? p - 1 : 0], knext = k[p + 1 < n ? p + 1 : p];
-        const uint32_t vp = v[p];
-        const uint32_t hp = hi32(kp);
-        if ((p == 0 || hi32(kprev) != hp) && (p + 1 == n || hi32(knext) != hp)) {
-            ko[p] = kp;
-            vo[p] = vp;
-            continue;
-        }
-        int64_t a = p;
-        while (a > 0 && p - a < RUN_SHORT && hi32(k[a - 1]) == hp)
-            --a;
-        bool lng = a > 0 && hi32(k[a - 1]) == hp;
-        int64_t e = p + 1;
-        while (!lng && e < n && e - p <= RUN_SHORT && hi32(k[e]) == hp)
-            ++e;
-        lng = lng || (e < n && hi32(k[e]) == hp) || e - a > RUN_SHORT;
-        if (lng) {
-            if (a == p && (p == 0 || hi32(k[p - 1]) != hp)) {
-                const uint32_t slot = atomicAdd(long_cnt, 1u);
-                if ((int64_t)slot < long_cap)
-                    long_list[slot] = ((int64_t)b << 40) | p;
-                else
-                    atomicOr(err, 8u);
+    for (int64_t base = (int64_t)blockIdx.x * RUN_BLOCK; base < n;
+         base += (int64_t)gridDim.x * RUN_BLOCK) {
+        // window [base - RUN_HALO, base + RUN_BLOCK + RUN_HALO) of the array
+        for (int i = t; i < RUN_BLOCK + 2 * RUN_HALO; i += RUN_BLOCK) {
+            const int64_t g = base - RUN_HALO + i;
+            if (g >= 0 && g < n) {
+                sk[i] = k[g];
+                sv[i] = v[g];
             }
-            continue;
         }
-        if (e - a == 1) {
-            ko[p] = kp;
-            vo[p] = vp;
-            continue;
+        __syncthreads();
+        const int64_t p = base + t;
+        if (p < n) {
+            const int i = t + RUN_HALO;  // window index of p
+            const uint64_t kp = sk[i];
+            const uint32_t vp = sv[i];
+            const uint32_t hp = hi32(kp);
+            const bool prev_same = p > 0 && hi32(sk[i - 1]) == hp;
+            const bool next_same = p + 1 < n && hi32(sk[i + 1]) == hp;
+            if (!prev_same && !next_same) {
+                // a run of one entry (nearly all of them)
+                ko[p] = kp;
+                vo[p] = vp;
+            } else {
+                // window indices: ia - 1 >= i - RUN_SHORT - 1 >= 0 and
+                // ie <= i + RUN_SHORT + 1 < RUN_BLOCK + 2 RUN_HALO
+                int64_t a = p;
+                int ia = i;
+                while (a > 0 && p - a < RUN_SHORT && hi32(sk[ia - 1]) == hp) {
+                    --a;
+                    --ia;
+                }
+                bool lng = a > 0 && hi32(sk[ia - 1]) == hp;
+                int64_t e = p + 1;
+                int ie = i + 1;
+                while (!lng && e < n && e - p <= RUN_SHORT && hi32(sk[ie]) == hp) {
+                    ++e;
+                    ++ie;
+                }
+                lng = lng || (e < n && hi32(sk[ie]) == hp) || e - a > RUN_SHORT;
+                if (lng) {
+                    if (!prev_same) {
+                        const uint32_t slot = atomicAdd(long_cnt, 1u);
+                        if ((int64_t)slot < long_cap)
+                            long_list[slot] = ((int64_t)b << 40) | p;
+                        else
+                            atomicOr(err, 8u);
+                    }
+                } else {
+                    const uint32_t lp = (uint32_t)kp;
+                    int r = 0;
+                    for (int q = ia; q < ie; ++q) {
+                        const uint32_t lq = (uint32_t)sk[q], vq = sv[q];
+                        r += (lq < lp || (lq == lp && vq < vp)) ? 1 : 0;
+                    }
+                    ko[a + r] = kp;
+                    vo[a + r] = vp;
+                }
+            }
         }
-        const uint32_t lp = (uint32_t)kp;
-        int64_t r = 0;
-        for (int64_t q = a; q < e; ++q) {
-            const uint32_t lq = (uint32_t)k[q], vq = v[q];
-            r += (lq < lp || (lq == lp && vq < vp)) ? 1 : 0;
-        }
-        ko[a + r] = kp;
-        vo[a + r] = vp;
+        __syncthreads();
     }
 }
 

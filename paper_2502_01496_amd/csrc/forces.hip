@@ -382,6 +382,10 @@ __device__ __forceinline__ T reduce_scatter24(const T *v, int lane)
 // reproducible.
 // The per-lane sums are reduce-scattered so that the lane holding component
 // c of sink s adds L2P and writes G * a.
+// One wavefront per workgroup: the leaves' near lists differ in length, and a
+// workgroup's slots are only freed when its last wavefront ends.
+constexpr int P2P_WAVES = 1;
+constexpr int P2P_WG = 64 * P2P_WAVES;
 constexpr int P2P_NS = 8;        // sinks per pass
 constexpr int P2P_QCAP = 128;    // softened pairs a sink's queue holds (a step adds <= 64)
 constexpr int P2P_BLOCKS = 256;  // source blocks staged in LDS per chunk
@@ -445,7 +449,7 @@ __device__ __forceinline__ void p2p_drain_f64(const double4 *__restrict__ pm,
     az -= fm * dz;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_p2p_src_f64(
+__global__ __launch_bounds__(P2P_WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_p2p_src_f64(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const int32_t *__restrict__ first, const int32_t *__restrict__ count,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ near_cnt,
@@ -455,12 +459,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     int part_stride)
 {
     constexpr int NS = P2P_NS;
-    __shared__ int2 rng[4][P2P_BLOCKS + 8];
-    __shared__ int32_t que[4][NS][P2P_QCAP];
-    __shared__ double2 shh[4][NS];  // 1/h, 1/h^3 of the pass's sinks
+    __shared__ int2 rng[P2P_WAVES][P2P_BLOCKS + 8];
+    __shared__ int32_t que[P2P_WAVES][NS][P2P_QCAP];
+    __shared__ double2 shh[P2P_WAVES][NS];  // 1/h, 1/h^3 of the pass's sinks
     (void)r_kern;
     const int w = threadIdx.x >> 6;
-    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    const int unit =
+        __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * P2P_WAVES + w);
     if (unit >= nleaves)
         return;
     const int lane = lane_id();
@@ -642,7 +647,7 @@ __device__ __forceinline__ int skip_gap(int k, int front, int gap)
     return k < front ? k : k + gap;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_p2p_src_f32(
+__global__ __launch_bounds__(P2P_WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_p2p_src_f32(
     const float4 *__restrict__ pf, const float4 *__restrict__ pfh,
     const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nleaves,
@@ -653,10 +658,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 {
     constexpr int NS = P2P_NS;
     constexpr int NR = P2P_RANGES_F32;
-    __shared__ int2 rng[4][NR + 8];
-    __shared__ float4 dcs[4][NR + 8];
+    __shared__ int2 rng[P2P_WAVES][NR + 8];
+    __shared__ float4 dcs[P2P_WAVES][NR + 8];
     const int w = threadIdx.x >> 6;
-    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    const int unit =
+        __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * P2P_WAVES + w);
     if (unit >= nleaves)
         return;
     const int lane = lane_id();
@@ -1086,22 +1092,20 @@ hipError_t launch_near(Tree &t, void *a, hipStream_t s)
     const int stride = 3 * T.leaf_size;
     const int extra = pc ? nu - nl : 0;
     if (t.p.precision == FMM_FP64) {
-        k_p2p_src_f64<<<(nu + 3) / 4, 256, 0, s>>>(t.pm, t.ph, t.first, t.count, t.leaf_node, nu,
-                                                   t.near_cnt, t.near_src, (int)t.cap_near, nsub,
-                                                   t.L, t.recA, t.perm, t.p.G, t.p.r_kern,
-                                                   T.n, (double *)a, pl, per,
-                                                   (double *)t.pnear.part, stride);
+        k_p2p_src_f64<<<(nu + P2P_WAVES - 1) / P2P_WAVES, P2P_WG, 0, s>>>(
+            t.pm, t.ph, t.first, t.count, t.leaf_node, nu, t.near_cnt, t.near_src,
+            (int)t.cap_near, nsub, t.L, t.recA, t.perm, t.p.G, t.p.r_kern, T.n, (double *)a, pl,
+            per, (double *)t.pnear.part, stride);
         if (extra > 0)
             k_p2p_fold<double><<<(extra + 3) / 4, 256, 0, s>>>(
                 t.leaf_node, t.pnear.list, extra, t.first, t.count, t.pnear.off,
                 (const double *)t.pnear.part, stride, t.L, t.recA, t.pm, t.pf, t.perm, t.p.G,
                 (double *)a);
     } else {
-        k_p2p_src_f32<<<(nu + 3) / 4, 256, 0, s>>>(t.pf, t.pfh, t.first, t.count,
-                                                   t.leaf_node, nu, t.near_cnt, t.near_src,
-                                                   (int)t.cap_near, nsub, t.Lf, t.recA, t.perm,
-                                                   (float)t.p.G, t.p.r_kern, (float *)a, pl, per,
-                                                   (float *)t.pnear.part, stride);
+        k_p2p_src_f32<<<(nu + P2P_WAVES - 1) / P2P_WAVES, P2P_WG, 0, s>>>(
+            t.pf, t.pfh, t.first, t.count, t.leaf_node, nu, t.near_cnt, t.near_src,
+            (int)t.cap_near, nsub, t.Lf, t.recA, t.perm, (float)t.p.G, t.p.r_kern, (float *)a, pl,
+            per, (float *)t.pnear.part, stride);
         if (extra > 0)
             k_p2p_fold<float><<<(extra + 3) / 4, 256, 0, s>>>(
                 t.leaf_node, t.pnear.list, extra, t.first, t.count, t.pnear.off,

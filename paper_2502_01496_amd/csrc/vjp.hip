@@ -494,8 +494,11 @@ __global__ void k_piece_fill(const int64_t *__restrict__ poff, int nnodes, int32
             pnode[j] = b;
 }
 
+constexpr int VJPM_WAVES = 1;  // wavefronts (pieces) per workgroup
+
 template <int FORM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_m2l_src_piece(
+__global__ __launch_bounds__(64 * VJPM_WAVES)
+    __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_m2l_src_piece(
     const double *__restrict__ recA, const double *__restrict__ recQ,
     const int64_t *__restrict__ toff, const uint32_t *__restrict__ tsrc,
     const double *__restrict__ Lleaf, const int32_t *__restrict__ pnode,
@@ -503,7 +506,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 {
     // consecutive pieces (neighbouring source cells, which share most of
     // their sinks) run behind the same L2
-    const int64_t pc = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int64_t pc =
+        (int64_t)xcd_block(blockIdx.x, gridDim.x) * VJPM_WAVES + (threadIdx.x >> 6);
     if (pc >= npieces)
         return;
     const int lane = lane_id();
@@ -737,6 +741,11 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_mutual(
 // lists only.
 constexpr int VJP_NS = 8;        // uniform particles per pass
 constexpr int VJP_QCAP = 128;    // softened pairs a queue holds (a step adds <= 64)
+// One unit (leaf or piece) per wavefront and one wavefront per workgroup: the
+// units' lists differ in length, and a workgroup's slots are only freed when
+// its last wavefront ends.
+constexpr int VJP_WAVES = 1;
+constexpr int VJP_WG = 64 * VJP_WAVES;
 constexpr int VJP_BLOCKS = 256;  // blocks staged in LDS per chunk
 
 // Stage the non-empty blocks of list entries [c0, c0 + nc) (entry k: block
@@ -820,7 +829,7 @@ __device__ __forceinline__ double reduce_scatter32(const double *v, int lane)
 // (abar_i is wave-uniform, so the G term needs no per-pair product).  The
 // queues that a step fills past a multiple of 64 are evaluated after the
 // step, when its source data are no longer held.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_sink(
+__global__ __launch_bounds__(VJP_WG) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_sink(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nunits,
@@ -829,14 +838,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     int part_stride)
 {
     constexpr int NS = VJP_NS;
-    __shared__ int2 rng[4][VJP_BLOCKS + 8];
-    __shared__ int32_t que[4][NS][VJP_QCAP];
-    __shared__ double4 shx[4][NS];  // positions of the pass's sinks
-    __shared__ double4 sha[4][NS];  // abar of the pass's sinks
-    __shared__ double4 sh3[4][NS];  // -3 abar (the Newtonian D = -3 r^-5 folded in)
-    __shared__ double4 shh[4][NS];  // h data of the pass's sinks
+    __shared__ int2 rng[VJP_WAVES][VJP_BLOCKS + 8];
+    __shared__ int32_t que[VJP_WAVES][NS][VJP_QCAP];
+    __shared__ double4 shx[VJP_WAVES][NS];  // positions of the pass's sinks
+    __shared__ double4 sha[VJP_WAVES][NS];  // abar of the pass's sinks
+    __shared__ double4 sh3[VJP_WAVES][NS];  // -3 abar (the Newtonian D = -3 r^-5 folded in)
+    __shared__ double4 shh[VJP_WAVES][NS];  // h data of the pass's sinks
     const int w = threadIdx.x >> 6;
-    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    const int unit =
+        __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * VJP_WAVES + w);
     if (unit >= nunits)
         return;
     const int lane = lane_id();
@@ -982,7 +992,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 // lanes the particles of the sink leaves of its transposed list.  Per source
 // q the lanes sum X = sum_i (G_ij abar_i + D_ij (d . abar_i) d) and
 // Y = sum_i G_ij (d . abar_i); a piece adds m_j X to xbar_j and -Y to mbar_j.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_src(
+__global__ __launch_bounds__(VJP_WG) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_vjp_p2p_src(
     const double4 *__restrict__ pm, const double4 *__restrict__ ph,
     const double *__restrict__ abt, const int32_t *__restrict__ first,
     const int32_t *__restrict__ count, const int32_t *__restrict__ leaf_node, int nunits,
@@ -991,12 +1001,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     int part_stride)
 {
     constexpr int NS = VJP_NS;
-    __shared__ int2 rng[4][VJP_BLOCKS + 8];
-    __shared__ int32_t que[4][NS][VJP_QCAP];
-    __shared__ double4 shx[4][NS];  // positions of the pass's sources
-    __shared__ double4 shh[4][NS];  // h data of the pass's sources
+    __shared__ int2 rng[VJP_WAVES][VJP_BLOCKS + 8];
+    __shared__ int32_t que[VJP_WAVES][NS][VJP_QCAP];
+    __shared__ double4 shx[VJP_WAVES][NS];  // positions of the pass's sources
+    __shared__ double4 shh[VJP_WAVES][NS];  // h data of the pass's sources
     const int w = threadIdx.x >> 6;
-    const int unit = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + w);
+    const int unit =
+        __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * VJP_WAVES + w);
     if (unit >= nunits)
         return;
     const int lane = lane_id();
@@ -1595,7 +1606,8 @@ static void vjp_m2l(Tree &t, hipStream_t s)
     k_vjp_m2l_sink<FORM><<<(nl * 16 + 255) / 256, 256, 0, s>>>(
         t.recA, t.recQ, t.leaf_node, nl, t.far_cnt, t.far_src, (int)t.cap_far, t.Lbar, t.nadj);
     if (t.npieces > 0)
-        k_vjp_m2l_src_piece<FORM><<<(int)((t.npieces + 3) / 4), 256, 0, s>>>(
+        k_vjp_m2l_src_piece<FORM>
+            <<<(int)((t.npieces + VJPM_WAVES - 1) / VJPM_WAVES), 64 * VJPM_WAVES, 0, s>>>(
             t.recA, t.recQ, t.farT.off, t.farT.src, t.Lleaf, t.pnode, t.poff, t.npieces, t.ppart);
 }
 
@@ -1689,7 +1701,7 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
         const bool pc = use_pieces(t);
         const int nu = pc ? (int)t.pnear.n : nl;
         const int stride = 3 * T.leaf_size;
-        k_vjp_p2p_sink<<<(nu + 3) / 4, 256, 0, s>>>(
+        k_vjp_p2p_sink<<<(nu + VJP_WAVES - 1) / VJP_WAVES, VJP_WG, 0, s>>>(
             t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node, nu, t.near_cnt, t.near_src,
             (int)t.cap_near, nsub, n, t.xbt, pc ? t.pnear.list : nullptr, per,
             (double *)t.pnear.part, stride);
@@ -1703,7 +1715,7 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
         const bool pc = t.pnearT.n > nl;
         const int nu = pc ? (int)t.pnearT.n : nl;
         const int stride = 4 * T.leaf_size;
-        k_vjp_p2p_src<<<(nu + 3) / 4, 256, 0, s>>>(
+        k_vjp_p2p_src<<<(nu + VJP_WAVES - 1) / VJP_WAVES, VJP_WG, 0, s>>>(
             t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node, nu, t.nearT.off, t.nearT.src, nsub,
             n, t.xbt, t.mbt, pc ? t.pnearT.list : nullptr, per, (double *)t.pnearT.part,
             stride);

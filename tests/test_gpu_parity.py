@@ -21,9 +21,9 @@ def sorted_by_sink(off, src):
     return src[np.lexsort((src, seg))]
 
 
-def _grid_ties(n, seed):
+def _grid_ties(n, seed, grid=8):
     rng = np.random.default_rng(seed)
-    x = np.round(rng.random((n, 3)) * 8) / 8.0          # many tied coordinates
+    x = np.round(rng.random((n, 3)) * grid) / grid      # many tied coordinates
     x += 1e-9 * rng.standard_normal((n, 3)) * (rng.random((n, 1)) < 0.5)
     return x, np.full(n, 1.0 / n), np.full(n, 0.02)
 
@@ -62,6 +62,11 @@ def _case(name):
     if name == "ties_3000":
         x, m, h = _grid_ties(3000, 7)
         return x, m, h, 0.5, 8
+    if name == "ties_short_20000":
+        # about ten particles per grid value of each axis: runs of equal high
+        # key halves of a few entries, across the sort's block and tile edges
+        x, m, h = _grid_ties(20000, 13, grid=2048)
+        return x, m, h, 0.5, 8
     if name == "tiny_1":
         return np.array([[0.1, 0.2, 0.3]]), np.array([2.0]), np.array([0.1]), 0.5, 8
     if name == "tiny_7":
@@ -77,7 +82,8 @@ def _case(name):
 
 
 CASES = ["tiny_1", "tiny_7", "tiny_9", "plummer_4096", "plummer_5000_leaf3",
-         "plummer_3001_leaf10_theta1", "plummer_777_leaf1", "ties_3000", "theta0_2048",
+         "plummer_3001_leaf10_theta1", "plummer_777_leaf1", "ties_3000", "ties_short_20000",
+         "theta0_2048",
          "binary_2x4096_theta0.3", "binary_2x4096_theta0.7", "binary_2x8192",
          "clumpy_20000_lognormal", "plummer_65536", "plummer_100003_ragged"]
 
@@ -184,8 +190,8 @@ def test_narrow_stack_fallback(orc, monkeypatch):
     _check_lists_and_forces(orc, x, m, h, 0.5, 8)
 
 
-@pytest.mark.parametrize("name", ["plummer_4096", "ties_3000", "clumpy_20000_lognormal",
-                                  "plummer_100003_ragged"])
+@pytest.mark.parametrize("name", ["plummer_4096", "ties_3000", "ties_short_20000",
+                                  "clumpy_20000_lognormal", "plummer_100003_ragged"])
 def test_full_key_morton_sort(orc, monkeypatch, name):
     # the Morton order by all eight key digits (used once a tree has met
     # concentrated data) gives the same (key, position) order as the sort by
