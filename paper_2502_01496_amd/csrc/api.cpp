@@ -301,6 +301,10 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     // the exact narrow-stack walk.
     if (const char *e = std::getenv("FMM_MI355_WIDE_STACK"))
         t->wide_stack_limit = std::atoi(e);
+    // Test hook: a smaller step budget sends more leaf groups through the
+    // workgroup walk.
+    if (const char *e = std::getenv("FMM_MI355_WALK_BUDGET"))
+        t->walk_budget = std::max(1, std::atoi(e));
     // Test hook: small first capacities for the mutual walk's frontier and
     // pair buffers exercise their overflow-and-retry path.
     if (const char *e = std::getenv("FMM_MI355_MW_CAP"))
@@ -422,6 +426,7 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->far_cnt, nn));
     A(dalloc(*t, &t->near_cnt, nn));
     A(dalloc(*t, &t->walk_flags, 4));
+    A(dalloc(*t, &t->walk_heavy, (size_t)(n + 3) / 4 + 1));  // groups of four leaves
     A(dalloc(*t, &t->L, NLOC * nn));
     A(dalloc(*t, &t->Lf, NLOC * nn));
     A(dalloc(*t, &t->red, 16 + 16 * 512));

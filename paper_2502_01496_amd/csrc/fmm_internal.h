@@ -273,9 +273,11 @@ struct Tree {
     int64_t cap_far = 0, cap_near = 0;
     DevBuf far_buf, near_buf;
     int32_t *far_cnt = nullptr, *near_cnt = nullptr;
-    int32_t *walk_flags = nullptr;  // device: max far, max near, stack overflow, 0
+    int32_t *walk_flags = nullptr;  // device: max far, max near, stack overflow, queued groups
+    int32_t *walk_heavy = nullptr;  // groups of four leaves queued for the workgroup walk
     int32_t *h_flags = nullptr;     // pinned host mirror of walk_flags + error bits
     int wide_stack_limit = 1 << 30; // test hook: FMM_MI355_WIDE_STACK lowers it
+    int walk_budget = 256;          // steps of a group walk before it is queued (FMM_MI355_WALK_BUDGET)
     int nsinks = 0;
     int64_t n_far = 0, n_near = 0;
     double *L = nullptr;          // local expansions, NLOC per node

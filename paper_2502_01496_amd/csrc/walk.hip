@@ -62,17 +62,25 @@ __device__ __forceinline__ bool opened(double ca0, double ca1, double ca2, doubl
 // of the leaves that opened the cell.  Per leaf the decisions, and so the
 // lists, are those of the single-leaf walk.  A full stack marks the group's
 // leaves for the exact narrow-stack walk.
+//
+// A group still walking after `budget` steps stops and is queued for
+// k_walk_heavy (its counts read -2 until then): the few groups whose leaves
+// see most of the tree would otherwise hold one wavefront for thousands of
+// dependent steps.
 constexpr int WG = 4;
+constexpr int WALK_WAVES = 1;  // one wavefront per workgroup
 
-__global__ __launch_bounds__(256) void k_walk_group(
+__global__ __launch_bounds__(64 * WALK_WAVES) void k_walk_group(
     const double *__restrict__ recA, const int32_t *__restrict__ leaf_node, int nleaves,
     double theta2, double r_kern, int32_t *far_src, int cap_far, int32_t *near_src,
-    int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *stack_overflow, int stack_limit)
+    int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *stack_overflow, int stack_limit,
+    int budget, int32_t *nheavy, int32_t *heavy)
 {
-    __shared__ int32_t stk[4][WIDE_STACK];
-    __shared__ uint8_t msk[4][WIDE_STACK];
+    __shared__ int32_t stk[WALK_WAVES][WIDE_STACK];
+    __shared__ uint8_t msk[WALK_WAVES][WIDE_STACK];
     const int w = threadIdx.x >> 6, lane = lane_id();
-    const int g0 = __builtin_amdgcn_readfirstlane((xcd_block(blockIdx.x, gridDim.x) * 4 + w) * WG);
+    const int g0 = __builtin_amdgcn_readfirstlane(
+        (xcd_block(blockIdx.x, gridDim.x) * WALK_WAVES + w) * WG);
     if (g0 >= nleaves)
         return;
     const int ng = min(WG, nleaves - g0);
@@ -91,13 +99,17 @@ __global__ __launch_bounds__(256) void k_walk_group(
 #pragma unroll
     for (int g = 0; g < WG; ++g)
         nf[g] = nn[g] = 0;
-    int sp = 1;
-    bool ovf = false;
+    int sp = 1, steps = 0;
+    bool ovf = false, hvy = false;
     if (lane == 0) {
         stk[w][0] = 0;
         msk[w][0] = (uint8_t)((1u << ng) - 1u);
     }
     while (sp > 0) {
+        if (++steps > budget) {
+            hvy = true;
+            break;
+        }
         const int take = sp < 64 ? sp : 64;
         const int base = sp - take;
         const bool act = lane < take;
@@ -155,7 +167,10 @@ __global__ __launch_bounds__(256) void k_walk_group(
                 f = nf[g];
                 q = nn[g];
             }
-        if (ovf) {
+        if (hvy) {
+            far_cnt[g0 + lane] = -2;
+            near_cnt[g0 + lane] = 0;
+        } else if (ovf) {
             // marked for the narrow-stack walk; until then the leaf has no
             // list entries (the force kernels may run before that walk)
             far_cnt[g0 + lane] = -1;
@@ -167,6 +182,148 @@ __global__ __launch_bounds__(256) void k_walk_group(
     }
     if (ovf && lane == 0)
         atomicOr(stack_overflow, 1);
+    if (hvy && lane == 0)
+        heavy[atomicAdd(nheavy, 1)] = g0 / WG;
+}
+
+// The queued groups, one workgroup of HEAVY_WAVES wavefronts each: the same
+// walk with up to 64 HEAVY_WAVES stack entries per step, a shared LDS stack,
+// and each step's far / near entries and pushes placed in stack order (the
+// wavefronts' ballot counts scanned through LDS), so the lists come out in a
+// fixed order.  A full stack (at most HEAVY_STACK entries, stack_limit) marks
+// the group's leaves for the narrow walk.
+constexpr int HEAVY_WAVES = 16;
+constexpr int HEAVY_STACK = 1536 * HEAVY_WAVES;  // 120 KB of LDS with the masks
+
+__global__ __launch_bounds__(64 * HEAVY_WAVES) void k_walk_heavy(
+    const double *__restrict__ recA, const int32_t *__restrict__ leaf_node, int nleaves,
+    double theta2, double r_kern, int32_t *far_src, int cap_far, int32_t *near_src,
+    int cap_near, int32_t *far_cnt, int32_t *near_cnt, int32_t *stack_overflow,
+    int stack_limit, const int32_t *nheavy, const int32_t *__restrict__ heavy)
+{
+    constexpr int NT = 64 * HEAVY_WAVES;
+    __shared__ int32_t stk[HEAVY_STACK];
+    __shared__ uint8_t msk[HEAVY_STACK];
+    __shared__ int32_t wc[HEAVY_WAVES][2 * WG + 1];  // per wavefront: far, near per leaf; pushes
+    __shared__ int32_t wpre[HEAVY_WAVES][2 * WG + 1];  // the same, summed over earlier wavefronts
+    __shared__ int32_t wtot[2 * WG + 1];               // and over all of them
+    const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const int nh = *nheavy;
+    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int g0 = heavy[h] * WG;
+        const int ng = min(WG, nleaves - g0);
+        double ca0[WG], ca1[WG], ca2[WG], sa[WG], ha[WG];
+#pragma unroll
+        for (int g = 0; g < WG; ++g) {
+            const double *ra = recA + (int64_t)NREC * leaf_node[g0 + min(g, ng - 1)];
+            ca0[g] = ra[0];
+            ca1[g] = ra[1];
+            ca2[g] = ra[2];
+            sa[g] = ra[4];
+            ha[g] = ra[5];
+        }
+        int nf[WG], nn[WG];  // the same in every thread
+#pragma unroll
+        for (int g = 0; g < WG; ++g)
+            nf[g] = nn[g] = 0;
+        int sp = 1;
+        bool ovf = false;
+        if (t == 0) {
+            stk[0] = 0;
+            msk[0] = (uint8_t)((1u << ng) - 1u);
+        }
+        __syncthreads();
+        while (sp > 0) {
+            const int take = sp < NT ? sp : NT;
+            const int base = sp - take;
+            const bool act = t < take;
+            const int b = act ? stk[base + t] : 0;
+            const uint32_t m = act ? msk[base + t] : 0u;
+            sp = base;
+            const CellRec cb = load_cell(recA, b);
+            const int lb = cb.left, rgt = cb.right;
+            uint32_t open = 0;
+            uint64_t mf[WG], mn[WG];
+            bool far[WG], nea[WG];
+#pragma unroll
+            for (int g = 0; g < WG; ++g) {
+                const bool live = (m >> g) & 1u;
+                const bool op =
+                    opened(ca0[g], ca1[g], ca2[g], sa[g], ha[g], cb, theta2, r_kern) && live;
+                far[g] = live && !op;
+                nea[g] = op && lb < 0;
+                open |= (op ? 1u : 0u) << g;
+                mf[g] = __ballot(far[g]);
+                mn[g] = __ballot(nea[g]);
+            }
+            const bool desc = open != 0u && lb >= 0;
+            const uint64_t md = __ballot(desc);
+            if (lane == 0) {
+#pragma unroll
+                for (int g = 0; g < WG; ++g) {
+                    wc[w][g] = __popcll(mf[g]);
+                    wc[w][WG + g] = __popcll(mn[g]);
+                }
+                wc[w][2 * WG] = __popcll(md);
+            }
+            __syncthreads();  // the pops are read and the counts published
+            if (t < 2 * WG + 1) {
+                // column t: exclusive scan over the wavefronts, then the total
+                int run = 0;
+                for (int v = 0; v < HEAVY_WAVES; ++v) {
+                    const int c = wc[v][t];
+                    wpre[v][t] = run;
+                    run += c;
+                }
+                wtot[t] = run;
+            }
+            __syncthreads();
+            const int td = wtot[2 * WG], bd = wpre[w][2 * WG];
+#pragma unroll
+            for (int g = 0; g < WG; ++g) {
+                if (far[g]) {
+                    const int k = nf[g] + wpre[w][g] + __popcll(mf[g] & lt);
+                    if (k < cap_far)
+                        far_src[(int64_t)(g0 + g) * cap_far + k] = b;
+                }
+                if (nea[g]) {
+                    const int k = nn[g] + wpre[w][WG + g] + __popcll(mn[g] & lt);
+                    if (k < cap_near)
+                        near_src[(int64_t)(g0 + g) * cap_near + k] = b;
+                }
+                nf[g] += wtot[g];
+                nn[g] += wtot[WG + g];
+            }
+            if (sp + 2 * td > stack_limit) {
+                ovf = true;
+                break;
+            }
+            if (desc) {
+                const int k = sp + 2 * (bd + __popcll(md & lt));
+                stk[k] = rgt;
+                msk[k] = (uint8_t)open;
+                stk[k + 1] = lb;
+                msk[k + 1] = (uint8_t)open;
+            }
+            sp += 2 * td;
+            __syncthreads();  // the pushes are visible and wc may be reused
+        }
+        if (t < ng) {
+            int f = 0, q = 0;
+#pragma unroll
+            for (int g = 0; g < WG; ++g)
+                if (g == t) {
+                    f = nf[g];
+                    q = nn[g];
+                }
+            far_cnt[g0 + t] = ovf ? -1 : f;
+            near_cnt[g0 + t] = ovf ? 0 : q;
+        }
+        if (ovf && t == 0)
+            atomicOr(stack_overflow, 1);
+        __syncthreads();  // the stack is reused by the next group
+    }
 }
 
 // Fallback for leaves whose wide walk overflowed its stack (far_cnt == -1):
@@ -282,10 +439,15 @@ hipError_t launch_walk(Tree &t, hipStream_t s)
     const int nl = T.nleaves;
     k_walk_init<<<1, 64, 0, s>>>(t.walk_flags);
     const int groups = (nl + WG - 1) / WG;
-    k_walk_group<<<(groups + 3) / 4, 256, 0, s>>>(
+    k_walk_group<<<(groups + WALK_WAVES - 1) / WALK_WAVES, 64 * WALK_WAVES, 0, s>>>(
         t.recA, t.leaf_node, nl, theta2, t.p.r_kern, t.far_src, (int)t.cap_far,
         t.near_src, (int)t.cap_near, t.far_cnt, t.near_cnt, t.walk_flags + 2,
-        std::min(std::max(t.wide_stack_limit, 2), WIDE_STACK));
+        std::min(std::max(t.wide_stack_limit, 2), WIDE_STACK), std::max(t.walk_budget, 1),
+        t.walk_flags + 3, t.walk_heavy);
+    k_walk_heavy<<<std::min(groups, 4096 / HEAVY_WAVES), 64 * HEAVY_WAVES, 0, s>>>(
+        t.recA, t.leaf_node, nl, theta2, t.p.r_kern, t.far_src, (int)t.cap_far, t.near_src,
+        (int)t.cap_near, t.far_cnt, t.near_cnt, t.walk_flags + 2,
+        std::min(std::max(t.wide_stack_limit, 2), HEAVY_STACK), t.walk_flags + 3, t.walk_heavy);
     k_list_max<<<std::min(LIST_MAX_BLOCKS, (nl + 1023) / 1024), 1024, 0, s>>>(t.far_cnt, t.near_cnt,
                                                                            nl, t.walk_flags);
     return hipGetLastError();

@@ -190,6 +190,35 @@ def test_narrow_stack_fallback(orc, monkeypatch):
     _check_lists_and_forces(orc, x, m, h, 0.5, 8)
 
 
+@pytest.mark.parametrize("budget", [1, 3])
+@pytest.mark.parametrize("name", ["plummer_4096", "plummer_777_leaf1", "theta0_2048",
+                                  "plummer_3001_leaf10_theta1", "plummer_100003_ragged"])
+def test_workgroup_walk(orc, monkeypatch, name, budget):
+    # a step budget of 1 sends every leaf group to the workgroup walk, 3 only
+    # some of them: the lists are the oracle's, and the forces too
+    monkeypatch.setenv("FMM_MI355_WALK_BUDGET", str(budget))
+    test_fp64_parity(orc, name)
+
+
+def test_workgroup_walk_deterministic(monkeypatch):
+    monkeypatch.setenv("FMM_MI355_WALK_BUDGET", "2")
+    x, m, h = W.plummer(50000, 14)
+    say("[gpu parity] workgroup walk determinism, plummer_50000, two runs")
+    a1, _, _ = gpu_run(x, m, h, export=False)
+    a2, _, _ = gpu_run(x, m, h, export=False)
+    assert np.array_equal(a1, a2)
+
+
+def test_workgroup_walk_stack_fallback(orc, monkeypatch):
+    # the workgroup walk's own stack overflow sends its leaves to the narrow
+    # walk (a wide stack of 8 entries overflows on the first pushes)
+    monkeypatch.setenv("FMM_MI355_WALK_BUDGET", "1")
+    monkeypatch.setenv("FMM_MI355_WIDE_STACK", "8")
+    x, m, h = W.plummer(20000, 13)
+    say("[gpu parity] workgroup walk + narrow-stack fallback, plummer_20000")
+    _check_lists_and_forces(orc, x, m, h, 0.5, 8)
+
+
 @pytest.mark.parametrize("name", ["plummer_4096", "ties_3000", "ties_short_20000",
                                   "clumpy_20000_lognormal", "plummer_100003_ragged"])
 def test_full_key_morton_sort(orc, monkeypatch, name):
