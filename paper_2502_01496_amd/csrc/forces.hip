@@ -233,13 +233,17 @@ __device__ __forceinline__ void m2l_leaf_src(const double *__restrict__ recA, co
     m2l_acc<float, FORM>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
 }
 
-// M2L of eq. (6) at the sink leaves.  16 lanes per unit, 4 units per wave;
-// lanes stride the far list, and a butterfly sum over the 16 lanes ends each
+// M2L of eq. (6) at the sink leaves.  8 lanes per unit, 8 units per wave
+// (consecutive leaves, whose far lists largely coincide, so the wave's loads
+// of a source record often share an address); lanes stride the far list,
+// and a butterfly sum over the unit's lanes ends each
 // piece of `per` list entries; piece sums add up in piece order, starting
 // from zero (fixed order: deterministic).  A unit is a leaf (pieces == nullptr: all its pieces in
 // turn, total to Lout) or one entry of the piece list: the only piece of its
 // leaf (total to Lout) or one piece of a split list (its sum to part, added
 // by k_m2l_fold), with bit-identical totals either way.
+constexpr int M2L_LANES = 8;  // lanes per unit
+
 template <typename T, int FORM>
 __global__ __launch_bounds__(256) void k_m2l_leaf(
     const double *__restrict__ recA, const double *__restrict__ recQ,
@@ -247,8 +251,8 @@ __global__ __launch_bounds__(256) void k_m2l_leaf(
     const int32_t *__restrict__ far_cnt, const int32_t *__restrict__ far_src, int cap_far,
     T *Lout, const int2 *__restrict__ pieces, int per, T *part)
 {
-    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
-    const int sub = threadIdx.x & 15;
+    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) / M2L_LANES;
+    const int sub = threadIdx.x & (M2L_LANES - 1);
     const bool valid = g < nunits;
     const int2 pc = pieces && valid ? pieces[g] : make_int2(valid ? g : 0, 0);
     const int lf = pc.x;
@@ -274,14 +278,14 @@ __global__ __launch_bounds__(256) void k_m2l_leaf(
             L[k] = T(0);
         // the next source's index is loaded one interaction ahead
         int bn = p0 + sub < p1 ? fl[p0 + sub] : 0;
-        for (int k = p0 + sub; k < p1; k += 16) {
+        for (int k = p0 + sub; k < p1; k += M2L_LANES) {
             const int b = bn;
-            if (k + 16 < p1)
-                bn = fl[k + 16];
+            if (k + M2L_LANES < p1)
+                bn = fl[k + M2L_LANES];
             m2l_leaf_src<FORM>(recA, recQ, recF, b, c0, c1, c2, L);
         }
 #pragma unroll
-        for (int off = 8; off >= 1; off >>= 1)
+        for (int off = M2L_LANES / 2; off >= 1; off >>= 1)
 #pragma unroll
             for (int k = 0; k < 19; ++k)
                 L[k] += __shfl_xor(L[k], off);
@@ -994,7 +998,7 @@ static void far_leaf(Tree &t, bool fp64, hipStream_t s)
     const int nl = t.topo.nleaves;
     const bool pc = use_pieces(t);
     const int nu = pc ? (int)t.pfar.n : nl;
-    const int g = (nu * 16 + 255) / 256;
+    const int g = (int)(((int64_t)nu * M2L_LANES + 255) / 256);
     const int2 *pl = pc ? t.pfar.list : nullptr;
     const int per = (int)t.far_piece_entries;
     const int extra = pc ? nu - nl : 0;

@@ -434,14 +434,16 @@ __global__ __launch_bounds__(256) void k_vjp_l2p(const double4 *__restrict__ pm,
 }
 
 // 2a. M2L^T, sink side: 16 lanes per leaf over its far list, cbar_sink += rbar.
+constexpr int M2LT_LANES = 16;  // lanes per sink leaf (8 and 4 measured no different)
+
 template <int FORM>
 __global__ __launch_bounds__(256) void k_vjp_m2l_sink(
     const double *__restrict__ recA, const double *__restrict__ recQ,
     const int32_t *__restrict__ leaf_node, int nleaves, const int32_t *__restrict__ far_cnt,
     const int32_t *__restrict__ far_src, int cap_far, const double *__restrict__ Lbar, double *nadj)
 {
-    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
-    const int sub = threadIdx.x & 15;
+    const int g = (xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x) / M2LT_LANES;
+    const int sub = threadIdx.x & (M2LT_LANES - 1);
     const bool valid = g < nleaves;
     const int v = valid ? leaf_node[g] : 0;
     const double *rv = recA + (int64_t)NREC * v;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_sink(
     double rb[3] = {0.0, 0.0, 0.0};
     const int nk = valid ? max(0, min(far_cnt[g], cap_far)) : 0;
     const int32_t *fl = far_src + (int64_t)(valid ? g : 0) * cap_far;
-    for (int k = sub; k < nk; k += 16) {
+    for (int k = sub; k < nk; k += M2LT_LANES) {
         const int b = fl[k];
         const double *rbp = recA + (int64_t)NREC * b;
         const double r[3] = {rv[0] - rbp[0], rv[1] - rbp[1], rv[2] - rbp[2]};
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(256) void k_vjp_m2l_sink(
         m2l_vjp<FORM>(r, rbp[3], recQ + (int64_t)NREC * b, Lb, rb, Mb, Qb);
     }
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1)
+    for (int off = M2LT_LANES / 2; off >= 1; off >>= 1)
 #pragma unroll
         for (int d = 0; d < 3; ++d)
             rb[d] += __shfl_xor(rb[d], off);
@@ -1603,7 +1605,7 @@ template <int FORM>
 static void vjp_m2l(Tree &t, hipStream_t s)
 {
     const int nl = t.topo.nleaves;
-    k_vjp_m2l_sink<FORM><<<(nl * 16 + 255) / 256, 256, 0, s>>>(
+    k_vjp_m2l_sink<FORM><<<(int)(((int64_t)nl * M2LT_LANES + 255) / 256), 256, 0, s>>>(
         t.recA, t.recQ, t.leaf_node, nl, t.far_cnt, t.far_src, (int)t.cap_far, t.Lbar, t.nadj);
     if (t.npieces > 0)
         k_vjp_m2l_src_piece<FORM>
