@@ -371,6 +371,106 @@ __global__ __launch_bounds__(256) void k_node_s2(const double4 *__restrict__ pm,
     }
 }
 
+// Leaves of a count-median cell of c particles: cells are halved (the left
+// half takes ceil) while they hold more than L particles.  At depth k the
+// sizes are floor(c / 2^k) or one more (c mod 2^k of them); every cell above
+// the first depth K at which ceil(c / 2^K) <= L splits, and at depth K - 1
+// those holding more than L particles split once more.
+__device__ __forceinline__ int med_leaves(int c, int L)
+{
+    if (c <= L)
+        return 1;
+    const int a = 31 - __clz(c), b = 31 - __clz(L);
+    const int k = ((uint64_t)L << (a - b)) >= (uint64_t)c ? a - b : a - b + 1;  // K >= 1
+    const int km = k - 1;
+    const int q = c >> km, r = c & ((1 << km) - 1);
+    return (1 << km) + (q + 1 > L ? r : 0) + (q > L ? (1 << km) - r : 0);
+}
+
+// k_node_s2 for the count-median tree: its pre-order ids follow from the
+// split rule (the right child of v is v + 2 leaves(left child)), so a
+// particle's path needs no memory reads, and the centres of S2_BATCH levels
+// are loaded together.  Same reductions and outputs as k_node_s2.
+constexpr int S2_BATCH = 4;
+
+__global__ __launch_bounds__(256) void k_node_s2_med(const double4 *__restrict__ pm, int64_t n,
+                                                     const double *__restrict__ recA, int leaf_size,
+                                                     uint64_t *s2bits, uint64_t *part,
+                                                     int64_t nwaves)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t wave = p >> 6;
+    const int lane = lane_id();
+    bool alive = p < n;
+    const double4 xp = alive ? pm[p] : make_double4(0, 0, 0, 0);
+    int v = 0, f = 0, c = (int)n;
+    for (int lvl = 0; __ballot(alive) != 0ull; lvl += S2_BATCH) {
+        int vb[S2_BATCH];
+        bool ab[S2_BATCH];
+#pragma unroll
+        for (int j = 0; j < S2_BATCH; ++j) {
+            ab[j] = alive;
+            vb[j] = v;
+            if (alive) {
+                if (c > leaf_size) {
+                    const int nl = (c + 1) >> 1;
+                    if (p < f + nl) {
+                        v += 1;
+                        c = nl;
+                    } else {
+                        v += 2 * med_leaves(nl, leaf_size);
+                        f += nl;
+                        c -= nl;
+                    }
+                } else {
+                    alive = false;
+                }
+            }
+        }
+        double cx[S2_BATCH], cy[S2_BATCH], cz[S2_BATCH];
+#pragma unroll
+        for (int j = 0; j < S2_BATCH; ++j) {
+            const double *ra = recA + (int64_t)NREC * (ab[j] ? vb[j] : 0);
+            cx[j] = ra[0];
+            cy[j] = ra[1];
+            cz[j] = ra[2];
+        }
+#pragma unroll
+        for (int j = 0; j < S2_BATCH; ++j) {
+            const int key = ab[j] ? vb[j] : -1;
+            uint64_t val = 0ull;
+            if (ab[j]) {
+                const double dx = xp.x - cx[j], dy = xp.y - cy[j], dz = xp.z - cz[j];
+                const double d2 = (dx * dx + dy * dy) + dz * dz;
+                val = (uint64_t)__double_as_longlong(d2);
+            }
+            const int k0 = __shfl(key, 0);
+            const bool uniform = __ballot(key == k0 && key >= 0) == ~0ull;
+            if (uniform) {
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const uint64_t ov = __shfl_xor(val, off);
+                    val = ov > val ? ov : val;
+                }
+                if (lane == 63)
+                    part[(int64_t)(lvl + j) * nwaves + wave] = val;
+            } else if (__ballot(key >= 0) != 0ull) {
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint64_t ov = __shfl_up(val, off);
+                    const int ok = __shfl_up(key, off);
+                    if (lane >= off && ok == key)
+                        val = ov > val ? ov : val;
+                }
+                const int nk = __shfl_down(key, 1);
+                const bool tail = (lane == 63) || (nk != key);
+                if (key >= 0 && tail)
+                    atomicMax((unsigned long long *)&s2bits[key], (unsigned long long)val);
+            }
+        }
+    }
+}
+
 // Phase 2: one wavefront per node of at least 64 particles folds the partial
 // maxima of the wavefronts lying entirely inside it.
 __global__ __launch_bounds__(256) void k_node_s2_fold(const int32_t *__restrict__ big,
@@ -551,9 +651,13 @@ hipError_t launch_moments(Tree &t, const double *x, const double *m, const doubl
         }
     }
     const int64_t nwaves = (n + 63) / 64;
-    k_node_s2<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, t.first, t.count, t.left,
-                                                     t.right, T.nnodes, t.s2bits, t.s2part,
-                                                     nwaves);
+    if (T.com)
+        k_node_s2<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, t.first, t.count,
+                                                         t.left, t.right, T.nnodes, t.s2bits,
+                                                         t.s2part, nwaves);
+    else
+        k_node_s2_med<<<(int)((n + 255) / 256), 256, 0, s>>>(t.pm, n, t.recA, T.leaf_size,
+                                                             t.s2bits, t.s2part, nwaves);
     const int nbig = T.nbig;
     if (nbig > 0)
         k_node_s2_fold<<<(nbig + 3) / 4, 256, 0, s>>>(t.big_nodes, nbig, t.first, t.count,
