@@ -167,13 +167,14 @@ __global__ void k_rs_zero(uint32_t *p, int64_t cnt)
         p[i] = 0u;
 }
 
-template <typename K>
+template <typename K, int BITS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const K *__restrict__ keys, int64_t n,
                                                         int shift, uint32_t *hist, int nblk)
 {
-    __shared__ uint32_t h[256];
+    constexpr int NB = 1 << BITS;  // digits (at most RS_THREADS)
+    __shared__ uint32_t h[NB];
     int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
-    if (t < 256)
+    if (t < NB)
         h[t] = 0u;
     __syncthreads();
     const K *k = keys + (int64_t)b * n;
@@ -186,10 +187,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const K *__restrict__ ke
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r)
         if (base + r * RS_THREADS + t < n)
-            atomicAdd(&h[(uint32_t)(kr[r] >> shift) & 255u], 1u);
+            atomicAdd(&h[(uint32_t)(kr[r] >> shift) & (NB - 1u)], 1u);
     __syncthreads();
-    if (t < 256)
-        hist[((int64_t)b * 256 + t) * nblk + blk] = h[t];
+    if (t < NB)
+        hist[((int64_t)b * NB + t) * nblk + blk] = h[t];
 }
 
 // Exclusive scan across one block of up to 256 threads (values <= 2^32).
@@ -223,8 +224,9 @@ __global__ __launch_bounds__(RS_SCAN_THREADS) void k_rs_scan(uint32_t *hist, uin
                                                              int nblk)
 {
     __shared__ uint32_t sh[8];
+    const int nb = gridDim.x;  // digits
     int d = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
-    uint32_t *row = hist + ((int64_t)b * 256 + d) * nblk;
+    uint32_t *row = hist + ((int64_t)b * nb + d) * nblk;
     uint32_t run = 0;
     for (int c0 = 0; c0 < nblk; c0 += RS_SCAN_THREADS) {
         int i = c0 + t;
@@ -236,14 +238,15 @@ __global__ __launch_bounds__(RS_SCAN_THREADS) void k_rs_scan(uint32_t *hist, uin
         run += total;
     }
     if (t == 0)
-        tot[b * 256 + d] = run;
+        tot[b * nb + d] = run;
 }
 
-__device__ __forceinline__ uint64_t match_u8(uint32_t d, bool valid)
+template <int BITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
 {
     uint64_t m = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < BITS; ++bit) {
         bool on = (d >> bit) & 1u;
         uint64_t bb = __ballot(valid && on);
         m &= on ? bb : ~bb;
@@ -255,20 +258,22 @@ __device__ __forceinline__ uint64_t match_u8(uint32_t d, bool valid)
 // matching; waves in order), place the tile digit-sorted in LDS, then write
 // each digit's run to its global position with consecutive threads on
 // consecutive addresses.
-template <typename K>
+template <typename K, int BITS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *kout, uint32_t *vout,
     int64_t n, int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
     int nblk)
 {
+    constexpr int NB = 1 << BITS;  // digits, one per thread of the first NB threads
+    constexpr uint32_t DM = NB - 1u;
     __shared__ K skey[RS_TILE];
     __shared__ uint32_t sval[RS_TILE];
-    __shared__ uint16_t wrun[RS_WAVES][256];
-    __shared__ uint32_t loff[256];
-    __shared__ uint32_t gofs[256];
-    __shared__ uint32_t wtot[4], wtot2[4];
+    __shared__ uint16_t wrun[RS_WAVES][NB];
+    __shared__ uint32_t loff[NB];
+    __shared__ uint32_t gofs[NB];
+    __shared__ uint32_t wtot[NB / 64], wtot2[NB / 64];
     const int b = blockIdx.y, blk = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = lane_id();
-    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS)
+    for (int i = t; i < RS_WAVES * NB; i += RS_THREADS)
         (&wrun[0][0])[i] = 0;
     __syncthreads();
     const K *k = kin + (int64_t)b * n;
@@ -288,13 +293,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     }
     // this tile's offsets within the digit runs and the digit totals, loaded
     // while the keys are in flight
-    const uint32_t gofs_t = t < 256 ? hist[((int64_t)b * 256 + t) * nblk + blk] : 0u;
-    const uint32_t dtot = t < 256 ? tot[b * 256 + t] : 0u;
+    const uint32_t gofs_t = t < NB ? hist[((int64_t)b * NB + t) * nblk + blk] : 0u;
+    const uint32_t dtot = t < NB ? tot[b * NB + t] : 0u;
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const bool valid = wbase + r * 64 + lane < nv;
-        const uint32_t d = valid ? (uint32_t)(key[r] >> shift) & 255u : 0u;
-        const uint64_t peers = match_u8(d, valid);
+        const uint32_t d = valid ? (uint32_t)(key[r] >> shift) & DM : 0u;
+        const uint64_t peers = match_digit<BITS>(d, valid);
         const uint32_t cur = wrun[w][d];
         rank[r] = cur + (uint32_t)__popcll(peers & lt);
         if (valid && (peers & lt) == 0ull)
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     __syncthreads();
     // per digit: offsets of the waves, then the tile-local digit offsets
     uint32_t cnt = 0;
-    if (t < 256) {
+    if (t < NB) {
 #pragma unroll
         for (int i = 0; i < RS_WAVES; ++i) {
             const uint32_t c = wrun[i][t];
@@ -329,7 +334,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         gofs[t] = gofs_t + (inc2 - dtot);
     }
     __syncthreads();
-    if (t < 256) {
+    if (t < NB) {
         uint32_t add = 0, add2 = 0;
         for (int i = 0; i < w; ++i) {
             add += wtot[i];
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         if (wbase + r * 64 + lane < nv) {
-            const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+            const uint32_t d = (uint32_t)(key[r] >> shift) & DM;
             const uint32_t lp = loff[d] + wrun[w][d] + rank[r];
             skey[lp] = key[r];
             sval[lp] = val[r];
@@ -353,7 +358,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     uint32_t *vo = vin ? vout + (int64_t)b * n : nullptr;
     for (int j = t; j < nv; j += RS_THREADS) {
         const K kk = skey[j];
-        const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+        const uint32_t d = (uint32_t)(kk >> shift) & DM;
         const int64_t gp = (int64_t)gofs[d] + (j - (int)loff[d]);
         ko[gp] = kk;
         if (vo)
@@ -361,41 +366,58 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     }
 }
 
-// Sort B arrays of n (key, value) pairs by the low 8 * passes key bits
-// (v0 == v1 == nullptr: keys only).  The result ends in (k0, v0) after an
-// even number of passes, in (k1, v1) after an odd one.  hist needs
-// B * 256 * ceil(n / RS_TILE) words, tot passes * B * 256.
-template <typename K>
+// Sort B arrays of n (key, value) pairs by the low BITS * passes key bits
+// (v0 == v1 == nullptr: keys only), BITS = 8 or 10 bits per pass.  The result
+// ends in (k0, v0) after an even number of passes, in (k1, v1) after an odd
+// one.  hist needs B * 2^BITS * ceil(n / RS_TILE) words, tot
+// passes * B * 2^BITS.
+template <typename K, int BITS>
 static hipError_t radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int B,
                              int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
 {
+    constexpr int NB = 1 << BITS;
     int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
     if (nblk == 0)
         return hipSuccess;
     for (int pass = 0; pass < passes; ++pass) {
-        int shift = 8 * pass;
+        int shift = BITS * pass;
         K *ki = (pass & 1) ? k1 : k0, *ko = (pass & 1) ? k0 : k1;
         uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
-        uint32_t *tp = tot + (int64_t)pass * B * 256;
+        uint32_t *tp = tot + (int64_t)pass * B * NB;
         dim3 g(nblk, B);
-        k_rs_hist<K><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
-        k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<K><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp, nblk);
+        k_rs_hist<K, BITS><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
+        k_rs_scan<<<dim3(NB, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
+        k_rs_scatter<K, BITS><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp, nblk);
     }
     return hipGetLastError();
 }
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
-                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s,
+                          int digit_bits)
 {
-    return radix_sort<uint64_t>(k0, v0, k1, v1, n, B, passes, hist, tot, s);
+    return digit_bits == 10
+               ? radix_sort<uint64_t, 10>(k0, v0, k1, v1, n, B, passes, hist, tot, s)
+               : radix_sort<uint64_t, 8>(k0, v0, k1, v1, n, B, passes, hist, tot, s);
 }
 
-// 32-bit keys (at most four passes): half the key traffic of the 64-bit sort.
+// 32-bit keys: half the key traffic of the 64-bit sort.
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
-                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s)
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s,
+                          int digit_bits)
 {
-    return radix_sort<uint32_t>(k0, v0, k1, v1, n, B, passes, hist, tot, s);
+    return digit_bits == 10
+               ? radix_sort<uint32_t, 10>(k0, v0, k1, v1, n, B, passes, hist, tot, s)
+               : radix_sort<uint32_t, 8>(k0, v0, k1, v1, n, B, passes, hist, tot, s);
+}
+
+// Passes and digit width for keys of `bits` bits: 10-bit digits where they
+// take fewer passes than 8-bit ones.
+void radix_plan(int bits, int &passes, int &digit_bits)
+{
+    const int p8 = (bits + 7) / 8, p10 = (bits + 9) / 10;
+    digit_bits = p10 < p8 ? 10 : 8;
+    passes = p10 < p8 ? p10 : p8;
 }
 
 // ---------------------------------------------------------------- (key, value) by halves
@@ -565,7 +587,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t
                 for (int j = t; j < RS_WAVES * 256; j += RS_THREADS)
                     (&wcnt[0][0])[j] = 0u;
                 __syncthreads();
-                const uint64_t peers = match_u8(d, valid);
+                const uint64_t peers = match_digit<8>(d, valid);
                 const uint32_t rk = (uint32_t)__popcll(peers & lt);
                 if (valid && (peers & lt) == 0ull)
                     wcnt[w][d] = (uint32_t)__popcll(peers);
@@ -618,9 +640,9 @@ hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
         uint32_t *vi = (pass & 1) ? v1 : v0, *vo = (pass & 1) ? v0 : v1;
         uint32_t *tp = tot + (int64_t)pass * B * 256;
         dim3 g(nblk, B);
-        k_rs_hist<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
+        k_rs_hist<uint64_t, 8><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
         k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<uint64_t><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp,
+        k_rs_scatter<uint64_t, 8><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp,
                                                          nblk);
     }
     const int gf = (int)std::min<int64_t>((n + 255) / 256, 4096);
@@ -1057,7 +1079,7 @@ hipError_t launch_morton_order(Tree &t, const double *x, hipStream_t s)
         // half, so the run fix would sort long runs one workgroup each; all
         // eight digits device-wide give the same (key, position) order
         hipError_t e = radix_sort_u64(t.keys1, t.vals1, t.keys0, t.vals0, n, 1, 8, t.rs_hist,
-                                      t.rs_tot, s);
+                                      t.rs_tot, s, 8);
         if (e == hipSuccess)
             e = hipMemcpyAsync(t.keys0, t.keys1, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess)

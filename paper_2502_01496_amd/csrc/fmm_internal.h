@@ -378,10 +378,16 @@ struct Tree {
     int64_t acc_n[8] = {};
 };
 
+// Stable LSD radix sorts, digit_bits = 8 or 10 bits per pass (hist: B 2^digit_bits
+// words per 4096-key tile; tot: passes B 2^digit_bits words).
+constexpr int RS_MAX_DIGITS = 1024;
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
-                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s);
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s,
+                          int digit_bits);
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
-                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s);
+                          int B, int passes, uint32_t *hist, uint32_t *tot, hipStream_t s,
+                          int digit_bits);
+void radix_plan(int bits, int &passes, int &digit_bits);
 
 
 // launchers (return hipError_t of the last launch / runtime call)

@@ -387,15 +387,18 @@ hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream
     const Topology &T = t.topo;
     MutualLists &M = t.mw;
     const int bits = mutual_key_bits(t);
-    const int pf = (2 * bits + 7) / 8;
     const int lbits = bit_width(T.nleaves);
+    // 8-bit digits: the 64-bit keys' 10-bit passes need more LDS per tile
+    // than two tiles per CU allow, and measured slower despite fewer passes
+    const int pf = (2 * bits + 7) / 8;
     const int pn = (2 * lbits + 7) / 8;  // near keys: (sink leaf, source leaf)
     hipError_t e = radix_sort_u64(M.fkeys[0], nullptr, M.fkeys[1], nullptr, n_far, 1, pf,
-                                  M.hist, M.tot, s);
+                                  M.hist, M.tot, s, 8);
     if (e != hipSuccess)
         return e;
     M.far_sorted = (pf & 1) ? M.fkeys[1] : M.fkeys[0];
-    e = radix_sort_u64(M.nkeys[0], nullptr, M.nkeys[1], nullptr, n_near, 1, pn, M.hist, M.tot, s);
+    e = radix_sort_u64(M.nkeys[0], nullptr, M.nkeys[1], nullptr, n_near, 1, pn, M.hist, M.tot, s,
+                       8);
     if (e != hipSuccess)
         return e;
     const uint64_t *ns = (pn & 1) ? M.nkeys[1] : M.nkeys[0];

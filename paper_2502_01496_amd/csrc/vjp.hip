@@ -1424,12 +1424,13 @@ static hipError_t ensure_vjp_base(Tree &t)
     return e;
 }
 
-static int key_passes(int nnodes)
+// Bits of a node index (the keys of the transposition sort).
+static int key_bits(int nnodes)
 {
     int bits = 1;
     while ((1ll << bits) <= nnodes)
         ++bits;
-    return (bits + 7) / 8;
+    return bits;
 }
 
 // Build one transposed list (sink-major pairs -> target-major CSR, stable).
@@ -1463,8 +1464,10 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
         if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vk1, cp * sizeof(uint32_t));
         if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vv0, cp * sizeof(uint32_t));
         if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vv1, cp * sizeof(uint32_t));
-        if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vhist, 256 * nblk * sizeof(uint32_t));
-        if (e == hipSuccess) e = tree_malloc(t, (void **)&t.vtot, 8 * 256 * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = tree_malloc(t, (void **)&t.vhist, RS_MAX_DIGITS * nblk * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = tree_malloc(t, (void **)&t.vtot, 8 * RS_MAX_DIGITS * sizeof(uint32_t));
         if (e != hipSuccess) {
             vfree(t, {(void **)&t.vk0, (void **)&t.vk1, (void **)&t.vv0, (void **)&t.vv1,
                       (void **)&t.vhist, (void **)&t.vtot});
@@ -1475,8 +1478,9 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     if (nl > 0)
         k_pairs_write<<<nl, 64, 0, s>>>(cnt, slots, (int)cap, nl, t.leaf_node, node_values ? 1 : 0,
                                         t.pair_off, t.vk0, t.vv0);
-    const int passes = key_passes(T.nnodes);
-    e = radix_sort_u32(t.vk0, t.vv0, t.vk1, t.vv1, np, 1, passes, t.vhist, t.vtot, s);
+    int passes, dbits;
+    radix_plan(key_bits(T.nnodes), passes, dbits);
+    e = radix_sort_u32(t.vk0, t.vv0, t.vk1, t.vv1, np, 1, passes, t.vhist, t.vtot, s, dbits);
     if (e != hipSuccess)
         return e;
     uint32_t *ks = (passes & 1) ? t.vk1 : t.vk0;
