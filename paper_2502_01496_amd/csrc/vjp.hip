@@ -1450,7 +1450,7 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     if (e != hipSuccess)
         return e;
     const int64_t np = t.h_pairs[0];
-    if (np > t.vjp_pair_cap) {
+    if (np > t.vjp_pair_cap || !t.vv0) {
         // (re)allocate the pair sort buffers
         e = hipStreamSynchronize(s);
         if (e != hipSuccess)
@@ -1484,23 +1484,26 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     if (e != hipSuccess)
         return e;
     uint32_t *ks = (passes & 1) ? t.vk1 : t.vk0;
-    uint32_t *vs = (passes & 1) ? t.vv1 : t.vv0;
+    uint32_t *&vs = (passes & 1) ? t.vv1 : t.vv0;
     k_lower_bound<<<(T.nnodes + 256) / 256, 256, 0, s>>>(ks, np, T.nnodes, out.off);
-    // keep the sorted values
-    if (out.src && out.src_cap < np) {
-        (void)hipStreamSynchronize(s);
-        vfree(t, {(void **)&out.src});
-        out.src_cap = 0;
-    }
-    if (!out.src) {
-        e = tree_malloc(t, (void **)&out.src, std::max<int64_t>(np, 1) * sizeof(uint32_t));
-        if (e != hipSuccess)
-            return e;
-        out.src_cap = std::max<int64_t>(np, 1);
-    }
+    // the sorted values become the transposed list without a copy: out takes
+    // the sort's value buffer, which takes out's previous buffer in exchange
+    // (or a new one when that is too small for the next sort)
+    uint32_t *prev = out.src;
+    const int64_t prev_cap = out.src_cap;
+    out.src = vs;
+    out.src_cap = t.vjp_pair_cap;
     out.npairs = np;
-    if (np > 0)
-        e = hipMemcpyAsync(out.src, vs, np * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (prev && prev_cap >= t.vjp_pair_cap) {
+        vs = prev;
+    } else {
+        vs = nullptr;
+        if (prev) {
+            (void)hipStreamSynchronize(s);
+            vfree(t, {(void **)&prev});
+        }
+        e = tree_malloc(t, (void **)&vs, t.vjp_pair_cap * sizeof(uint32_t));
+    }
     return e;
 }
 
@@ -1753,6 +1756,7 @@ void release_vjp(Tree &t)
               (void **)&t.pnode, (void **)&t.ppart, (void **)&t.pnearT.np, (void **)&t.pnearT.off,
               (void **)&t.pnearT.tsum, (void **)&t.pnearT.list, &t.pnearT.part});
     t.pnearT.cap = t.pnearT.n = 0;
+    t.vjp_pair_cap = t.farT.src_cap = t.nearT.src_cap = 0;
     if (t.h_pairs)
         (void)hipHostFree(t.h_pairs);
     t.h_pairs = nullptr;
