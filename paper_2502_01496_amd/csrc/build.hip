@@ -257,8 +257,9 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
 // Stable scatter of one tile: rank the keys by digit (per wave, ballot
 // matching; waves in order), place the tile digit-sorted in LDS, then write
 // each digit's run to its global position with consecutive threads on
-// consecutive addresses.
-template <typename K, int BITS>
+// consecutive addresses.  VALS = false: keys only (no LDS for values, so a
+// tile of 64-bit keys with 10-bit digits still fits two to a CU).
+template <typename K, int BITS, bool VALS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *kout, uint32_t *vout,
     int64_t n, int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     constexpr int NB = 1 << BITS;  // digits, one per thread of the first NB threads
     constexpr uint32_t DM = NB - 1u;
     __shared__ K skey[RS_TILE];
-    __shared__ uint32_t sval[RS_TILE];
+    __shared__ uint32_t sval[VALS ? RS_TILE : 1];
     __shared__ uint16_t wrun[RS_WAVES][NB];
     __shared__ uint32_t loff[NB];
     __shared__ uint32_t gofs[NB];
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         (&wrun[0][0])[i] = 0;
     __syncthreads();
     const K *k = kin + (int64_t)b * n;
-    const uint32_t *v = vin ? vin + (int64_t)b * n : nullptr;
+    const uint32_t *v = VALS ? vin + (int64_t)b * n : nullptr;
     const int64_t tile0 = (int64_t)blk * RS_TILE;
     const int nv = (int)min((int64_t)RS_TILE, n - tile0);
     const int wbase = w * (RS_TILE / RS_WAVES);
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const int i = wbase + r * 64 + lane;
         key[r] = i < nv ? k[tile0 + i] : K(0);
-        val[r] = (v && i < nv) ? v[tile0 + i] : 0u;
+        val[r] = (VALS && i < nv) ? v[tile0 + i] : 0u;
     }
     // this tile's offsets within the digit runs and the digit totals, loaded
     // while the keys are in flight
@@ -350,18 +351,19 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
             const uint32_t d = (uint32_t)(key[r] >> shift) & DM;
             const uint32_t lp = loff[d] + wrun[w][d] + rank[r];
             skey[lp] = key[r];
-            sval[lp] = val[r];
+            if constexpr (VALS)
+                sval[lp] = val[r];
         }
     }
     __syncthreads();
     K *ko = kout + (int64_t)b * n;
-    uint32_t *vo = vin ? vout + (int64_t)b * n : nullptr;
+    uint32_t *vo = VALS ? vout + (int64_t)b * n : nullptr;
     for (int j = t; j < nv; j += RS_THREADS) {
         const K kk = skey[j];
         const uint32_t d = (uint32_t)(kk >> shift) & DM;
         const int64_t gp = (int64_t)gofs[d] + (j - (int)loff[d]);
         ko[gp] = kk;
-        if (vo)
+        if constexpr (VALS)
             vo[gp] = sval[j];
     }
 }
@@ -387,7 +389,12 @@ static hipError_t radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n
         dim3 g(nblk, B);
         k_rs_hist<K, BITS><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
         k_rs_scan<<<dim3(NB, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<K, BITS><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp, nblk);
+        if (vi)
+            k_rs_scatter<K, BITS, true><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist,
+                                                                 tp, nblk);
+        else
+            k_rs_scatter<K, BITS, false><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist,
+                                                                  tp, nblk);
     }
     return hipGetLastError();
 }
@@ -516,8 +523,11 @@ __global__ __launch_bounds__(RUN_BLOCK) void k_run_fix(const uint64_t *__restric
 }
 
 // One workgroup per long run: find its end, then a stable LSD radix sort of
-// the composite (low key half, value) in eight 8-bit passes, ping-ponging
-// between the run's segments of the input and output arrays.
+// the low key half in four 8-bit passes, ping-ponging between the run's
+// segments of the input and output arrays.  The values of a run are already
+// ascending (the high-half passes are stable and the values are the input
+// positions), so the stable sort by the low half leaves it in (low half,
+// value) order.
 __global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t *vin,
                                                          uint64_t *kout, uint32_t *vout, int64_t n,
                                                          uint32_t *long_cnt,
@@ -556,16 +566,14 @@ __global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t
         const int64_t L = end_sh - a;
         if (t == 0)
             atomicAdd(&long_cnt[1], (uint32_t)L);  // entries in long runs, for the host
-        for (int pass = 0; pass < 8; ++pass) {
+        for (int pass = 0; pass < 4; ++pass) {
             const int src = pass & 1, dst = src ^ 1;
             const uint64_t *ks = K[src] + a;
             const uint32_t *vs = V[src] + a;
             uint64_t *kd = K[dst] + a;
             uint32_t *vd = V[dst] + a;
-            const int sh = 8 * (pass & 3);
-            auto digit = [&](int64_t i) -> uint32_t {
-                return pass < 4 ? (vs[i] >> sh) & 255u : ((uint32_t)ks[i] >> sh) & 255u;
-            };
+            const int sh = 8 * pass;
+            auto digit = [&](int64_t i) -> uint32_t { return ((uint32_t)ks[i] >> sh) & 255u; };
             if (t < 256)
                 hist[t] = 0u;
             __syncthreads();
@@ -613,7 +621,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_run_long(uint64_t *kin, uint32_t
                 __syncthreads();
             }
         }
-        // eight passes end in the input arrays: copy the run to the output
+        // four passes end in the input arrays: copy the run to the output
         for (int64_t i = t; i < L; i += RS_THREADS) {
             K[1][a + i] = K[0][a + i];
             V[1][a + i] = V[0][a + i];
@@ -642,8 +650,8 @@ hipError_t sort_by_halves(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1
         dim3 g(nblk, B);
         k_rs_hist<uint64_t, 8><<<g, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
         k_rs_scan<<<dim3(256, B), RS_SCAN_THREADS, 0, s>>>(hist, tp, nblk);
-        k_rs_scatter<uint64_t, 8><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, tp,
-                                                         nblk);
+        k_rs_scatter<uint64_t, 8, true><<<g, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist,
+                                                               tp, nblk);
     }
     const int gf = (int)std::min<int64_t>((n + 255) / 256, 4096);
     k_run_fix<<<dim3(gf, B), 256, 0, s>>>(k0, v0, k1, v1, n, long_cnt, long_list, long_cap, err);

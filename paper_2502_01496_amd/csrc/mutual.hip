@@ -388,8 +388,8 @@ hipError_t launch_mutual_lists(Tree &t, int64_t n_far, int64_t n_near, hipStream
     MutualLists &M = t.mw;
     const int bits = mutual_key_bits(t);
     const int lbits = bit_width(T.nleaves);
-    // 8-bit digits: the 64-bit keys' 10-bit passes need more LDS per tile
-    // than two tiles per CU allow, and measured slower despite fewer passes
+    // 8-bit digits: 10-bit ones take a pass less for these 64-bit keys but
+    // measured slower, with or without value staging in LDS
     const int pf = (2 * bits + 7) / 8;
     const int pn = (2 * lbits + 7) / 8;  // near keys: (sink leaf, source leaf)
     hipError_t e = radix_sort_u64(M.fkeys[0], nullptr, M.fkeys[1], nullptr, n_far, 1, pf,
