@@ -27,6 +27,8 @@
 //
 // Storage: symmetric rank-2 (xx,xy,xz,yy,yz,zz); rank-3
 // (xxx,xxy,xxz,xyy,xyz,xzz,yyy,yyz,yzz,zzz).
+#include <type_traits>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -233,6 +235,29 @@ __device__ __forceinline__ void m2l_leaf_src(const double *__restrict__ recA, co
     m2l_acc<float, FORM>((float)(c0 - cb.x), (float)(c1 - cb.y), (float)(c2 - cb.z), f0.x, Q, L);
 }
 
+// The FP32 form with the load of the source record apart from the
+// arithmetic, so that the next source's record can be in flight while the
+// current one is evaluated.
+struct M2lSrc32 {
+    double4 cb;
+    float4 f0, f1;
+};
+__device__ __forceinline__ void m2l_src_load(const double *__restrict__ recA,
+                                             const float *__restrict__ recF, int b, M2lSrc32 &S)
+{
+    S.cb = *(const double4 *)(recA + (int64_t)NREC * b);
+    S.f0 = *(const float4 *)(recF + (int64_t)NREC * b);
+    S.f1 = *(const float4 *)(recF + (int64_t)NREC * b + 4);
+}
+template <int FORM>
+__device__ __forceinline__ void m2l_src_eval(const M2lSrc32 &S, double c0, double c1, double c2,
+                                             float *L)
+{
+    const float Q[6] = {S.f0.y, S.f0.z, S.f0.w, S.f1.x, S.f1.y, S.f1.z};
+    m2l_acc<float, FORM>((float)(c0 - S.cb.x), (float)(c1 - S.cb.y), (float)(c2 - S.cb.z), S.f0.x,
+                         Q, L);
+}
+
 // M2L of eq. (6) at the sink leaves.  8 lanes per unit, 8 units per wave
 // (consecutive leaves, whose far lists largely coincide, so the wave's loads
 // of a source record often share an address); lanes stride the far list,
@@ -276,13 +301,36 @@ __global__ __launch_bounds__(256) void k_m2l_leaf(
 #pragma unroll
         for (int k = 0; k < 19; ++k)
             L[k] = T(0);
-        // the next source's index is loaded one interaction ahead
-        int bn = p0 + sub < p1 ? fl[p0 + sub] : 0;
-        for (int k = p0 + sub; k < p1; k += M2L_LANES) {
-            const int b = bn;
-            if (k + M2L_LANES < p1)
-                bn = fl[k + M2L_LANES];
-            m2l_leaf_src<FORM>(recA, recQ, recF, b, c0, c1, c2, L);
+        if constexpr (std::is_same<T, float>::value) {
+            // FP32: the next source's record and the index after it are in
+            // flight while the current source is evaluated (the FP64 form
+            // keeps one wavefront more per SIMD without them, which pays more)
+            M2lSrc32 cur;
+            int bn = 0;
+            if (p0 + sub < p1) {
+                m2l_src_load(recA, recF, fl[p0 + sub], cur);
+                if (p0 + sub + M2L_LANES < p1)
+                    bn = fl[p0 + sub + M2L_LANES];
+            }
+            for (int k = p0 + sub; k < p1; k += M2L_LANES) {
+                M2lSrc32 nxt;
+                if (k + M2L_LANES < p1) {
+                    m2l_src_load(recA, recF, bn, nxt);
+                    if (k + 2 * M2L_LANES < p1)
+                        bn = fl[k + 2 * M2L_LANES];
+                }
+                m2l_src_eval<FORM>(cur, c0, c1, c2, L);
+                cur = nxt;
+            }
+        } else {
+            // the next source's index is loaded one interaction ahead
+            int bn = p0 + sub < p1 ? fl[p0 + sub] : 0;
+            for (int k = p0 + sub; k < p1; k += M2L_LANES) {
+                const int b = bn;
+                if (k + M2L_LANES < p1)
+                    bn = fl[k + M2L_LANES];
+                m2l_leaf_src<FORM>(recA, recQ, recF, b, c0, c1, c2, L);
+            }
         }
 #pragma unroll
         for (int off = M2L_LANES / 2; off >= 1; off >>= 1)
