@@ -404,7 +404,7 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     A(dalloc(*t, &t->r2o, n));
     A(dalloc(*t, &t->xr, 3 * n));
     A(dalloc(*t, &t->lists, 8 * n));
-    A(dalloc(*t, &t->side, 4 * n));
+    A(dalloc(*t, &t->side, 5 * n));  // 4 lists by position, then one byte per rank
     A(dalloc(*t, &t->lvl_cnt, 4 * (size_t)std::max(1, T.max_lvl_blocks)));
     A(dalloc(*t, &t->bbox, 8));
     A(dalloc(*t, &t->err, 4));

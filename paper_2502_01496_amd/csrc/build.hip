@@ -767,6 +767,85 @@ __global__ __launch_bounds__(LVL_THREADS) void k_lvl_count(
         cnt[d * stride + b] = (int32_t)total;
 }
 
+// Sides by Morton rank at one level: each cell's longest-axis list gives
+// them by position (its first ceil(c/2) entries go left), and the other
+// lists of the cell then look their entries' sides up by rank (one byte per
+// particle instead of a gathered coordinate).  For trees of LVL_BYRANK_MIN
+// particles or more, whose coordinate arrays miss in L2; smaller ones gather
+// the coordinates and save the extra launch per level.
+constexpr int64_t LVL_BYRANK_MIN = int64_t(1) << 20;
+__global__ __launch_bounds__(LVL_THREADS) void k_lvl_side(
+    const uint32_t *__restrict__ L, int64_t n, const double *__restrict__ xr,
+    const int32_t *blk_node, const int32_t *blk_start, const int32_t *blk_end,
+    const int32_t *first, const int32_t *count, int32_t *axis_out, uint8_t *byrank)
+{
+    constexpr int PER = LVL_CHUNK / LVL_THREADS;
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int v = blk_node[b];
+    const int64_t s0 = blk_start[b], e0 = blk_end[b];
+    const int64_t f = first[v], c = count[v], nl = (c + 1) / 2;
+    const int ax = node_axis(L, n, xr, f, c);
+    if (t == 0 && s0 == f)
+        axis_out[v] = ax;
+    const uint32_t *La = L + ax * n;
+    uint32_t r[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        r[k] = La[min(s0 + t + k * LVL_THREADS, e0 - 1)];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t p = s0 + t + k * LVL_THREADS;
+        if (p < e0)
+            byrank[r[k]] = p - f < nl ? 1 : 0;
+    }
+}
+
+// Sides of a chunk of one list from the sides by rank (stored per position
+// for the scatter) and the chunk's left count.
+__global__ __launch_bounds__(LVL_THREADS) void k_lvl_count_byrank(
+    const uint32_t *__restrict__ L, int64_t n, const int32_t *blk_node,
+    const int32_t *blk_start, const int32_t *blk_end, const int32_t *first,
+    const int32_t *count, const int32_t *__restrict__ axis, const uint8_t *__restrict__ byrank,
+    uint8_t *side, int32_t *cnt, int stride)
+{
+    constexpr int PER = LVL_CHUNK / LVL_THREADS;
+    __shared__ uint32_t sh[8];
+    const int b = blockIdx.x, d = blockIdx.y, t = threadIdx.x;
+    const int v = blk_node[b];
+    const int64_t s0 = blk_start[b], e0 = blk_end[b];
+    const int64_t f = first[v], nl = (count[v] + 1) / 2;
+    const int ax = axis[v];
+    uint32_t g[PER];
+    if (d == ax) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            g[k] = s0 + t + k * LVL_THREADS - f < nl ? 1u : 0u;
+    } else {
+        const uint32_t *Ld = L + d * n;
+        uint32_t r[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            r[k] = Ld[min(s0 + t + k * LVL_THREADS, e0 - 1)];
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            g[k] = byrank[r[k]];
+    }
+    uint8_t *sd = side + d * n;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t p = s0 + t + k * LVL_THREADS;
+        if (p < e0) {
+            sd[p] = (uint8_t)g[k];
+            c += g[k];
+        }
+    }
+    uint32_t total;
+    block_excl_scan_u32(c, sh, total);
+    if (t == 0)
+        cnt[d * stride + b] = (int32_t)total;
+}
+
 // Stable partition of one chunk of one list: the chunk is staged in LDS,
 // each thread ranks PER consecutive entries, the chunk's left and right runs
 // are assembled in LDS and written out as two contiguous runs.
@@ -1122,9 +1201,19 @@ hipError_t launch_build(Tree &t, const double *x, hipStream_t s)
         int b0 = T.lvl_blk_off[l], nb = T.lvl_blk_off[l + 1] - b0;
         const uint32_t *Ls = (l & 1) ? L1 : L0;
         uint32_t *Ld = (l & 1) ? L0 : L1;
-        k_lvl_count<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
-            Ls, n, t.xr, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.first, t.count,
-            t.axis, t.side, t.lvl_cnt, T.max_lvl_blocks);
+        if (n >= LVL_BYRANK_MIN) {
+            uint8_t *byrank = t.side + 4 * n;
+            k_lvl_side<<<nb, LVL_THREADS, 0, s>>>(Ls, n, t.xr, t.blk_node + b0,
+                                                  t.blk_start + b0, t.blk_end + b0, t.first,
+                                                  t.count, t.axis, byrank);
+            k_lvl_count_byrank<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
+                Ls, n, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.first, t.count,
+                t.axis, byrank, t.side, t.lvl_cnt, T.max_lvl_blocks);
+        } else {
+            k_lvl_count<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
+                Ls, n, t.xr, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0, t.first,
+                t.count, t.axis, t.side, t.lvl_cnt, T.max_lvl_blocks);
+        }
         k_lvl_scatter<<<dim3(nb, 4), LVL_THREADS, 0, s>>>(
             Ls, Ld, n, t.side, t.blk_node + b0, t.blk_start + b0, t.blk_end + b0,
             t.blk_first + b0, t.first, t.count, t.lvl_cnt, T.max_lvl_blocks);

@@ -241,7 +241,8 @@ struct Tree {
     int32_t *r2o = nullptr;       // Morton rank -> caller index
     double *xr = nullptr;         // coordinates by Morton rank, 3 x n SoA
     uint32_t *lists = nullptr;    // 2 buffers x 4 lists x n
-    uint8_t *side = nullptr;      // 4 x n: side of each list entry at the current level
+    uint8_t *side = nullptr;      // 4 x n: side of each list entry at the current level,
+                                  // then n: the sides by Morton rank
     int32_t *lvl_cnt = nullptr;
     uint64_t *bbox = nullptr;     // ordered bits: min xyz, max xyz
     // device error flags: err[0] from the build (bit 0 non-finite x, bit 3

@@ -1486,6 +1486,25 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     uint32_t *ks = (passes & 1) ? t.vk1 : t.vk0;
     uint32_t *&vs = (passes & 1) ? t.vv1 : t.vv0;
     k_lower_bound<<<(T.nnodes + 256) / 256, 256, 0, s>>>(ks, np, T.nnodes, out.off);
+    out.npairs = np;
+    if (t.vjp_pair_cap - np > np / 2 + 1024) {
+        // the sort buffers were sized for the other (longer) transposition:
+        // keep a list-sized buffer and copy the sorted values into it
+        if (out.src && out.src_cap < np) {
+            (void)hipStreamSynchronize(s);
+            vfree(t, {(void **)&out.src});
+            out.src_cap = 0;
+        }
+        if (!out.src) {
+            e = tree_malloc(t, (void **)&out.src, std::max<int64_t>(np, 1) * sizeof(uint32_t));
+            if (e != hipSuccess)
+                return e;
+            out.src_cap = std::max<int64_t>(np, 1);
+        }
+        if (np > 0)
+            e = hipMemcpyAsync(out.src, vs, np * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        return e;
+    }
     // the sorted values become the transposed list without a copy: out takes
     // the sort's value buffer, which takes out's previous buffer in exchange
     // (or a new one when that is too small for the next sort)
@@ -1493,7 +1512,6 @@ static hipError_t transpose_lists(Tree &t, const int32_t *cnt, const int32_t *sl
     const int64_t prev_cap = out.src_cap;
     out.src = vs;
     out.src_cap = t.vjp_pair_cap;
-    out.npairs = np;
     if (prev && prev_cap >= t.vjp_pair_cap) {
         vs = prev;
     } else {

@@ -285,6 +285,29 @@ def _check_tree_records(ex, tree, mom):
     assert (np.abs(rec[:, 6:12] - mom.Q) <= 1e-14 * scale + 1e-300).all()
 
 
+def test_tied_grid_2e20_tree_against_oracle(orc):
+    # 2^20 particles on a 64^3 grid, half of them moved by 1e-9: cells of this
+    # size take their sides by rank at every level, and ties of the split
+    # coordinate are decided by Morton rank exactly as the oracle decides them
+    rng = np.random.default_rng(61)
+    n = 1 << 20
+    x = np.round(rng.random((n, 3)) * 64) / 64
+    x += 1e-9 * rng.standard_normal((n, 3)) * (rng.random((n, 1)) < 0.5)
+    m, h = np.full(n, 1.0 / n), np.full(n, 0.02)
+    say(f"[gpu full] tied grid 2^20: tree and records bit-exact against the oracle")
+    X, Mt, H = to_dev(x, m, h)
+    t = F.fmm_build_tree(X, F.default_params())
+    try:
+        F.fmm_moments(t, X, Mt, H)
+        torch.cuda.synchronize()
+        ex = F.fmm_debug_export(t, lists=False)
+    finally:
+        F.fmm_tree_free(t)
+    tree = orc.build_tree(x, 8)
+    mom = orc.moments(x, m, h, tree)
+    _check_tree_records(ex, tree, mom)
+
+
 @pytest.mark.timeout(900)
 def test_binary_2x2e23_step0_against_oracle(orc):
     x, m, h = W.polytrope_binary(1 << 23, 5)
