@@ -310,9 +310,14 @@ static fmm_status create_tree(int64_t n, const fmm_params &p, Tree **out)
     if (const char *e = std::getenv("FMM_MI355_MW_CAP"))
         t->mw_init_cap = std::max<int64_t>(1, std::atoll(e));
     // Test hook: small list pieces (near-field blocks and far-field entries
-    // per piece) put the split evaluation to work on ordinary trees.
-    if (const char *e = std::getenv("FMM_MI355_PIECE"))
-        t->near_piece_blocks = t->far_piece_entries = std::max<int64_t>(1, std::atoll(e));
+    // per piece) put the split evaluation to work on ordinary trees; "a,b"
+    // sets the near and far piece sizes apart.
+    if (const char *e = std::getenv("FMM_MI355_PIECE")) {
+        t->near_piece_blocks = t->far_piece_entries = t->vjp_src_piece_blocks =
+            std::max<int64_t>(1, std::atoll(e));
+        if (const char *c = std::strchr(e, ','))
+            t->far_piece_entries = std::max<int64_t>(1, std::atoll(c + 1));
+    }
     // Test hook: the full-key Morton sort from the first build on.
     if (const char *e = std::getenv("FMM_MI355_MORTON_FULL"))
         t->morton_full = std::atoi(e) != 0;

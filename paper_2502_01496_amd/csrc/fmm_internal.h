@@ -365,6 +365,10 @@ struct Tree {
     bool split_lists = false;     // the last walk's lists are split (predicted for the next)
     bool pieces_valid = false;    // pnear / pfar describe the current lists
     int64_t near_piece_blocks = 512, far_piece_entries = 1024;  // test hook: FMM_MI355_PIECE
+    // pieces of the transposed near lists (reverse pass, source side): the
+    // source-side P2P^T has more work per block than the forward kernel and
+    // balances better with shorter pieces
+    int64_t vjp_src_piece_blocks = 256;
     int32_t max_far = 0, max_near = 0;  // longest lists of the last walk
     int64_t *h_piece = nullptr;         // pinned: piece totals (near, far)
 

@@ -1598,7 +1598,7 @@ static hipError_t build_p2pt_pieces(Tree &t, hipStream_t s)
     }
     P.n = 0;
     k_tpiece_count<<<(nl + 255) / 256, 256, 0, s>>>(t.leaf_node, nl, t.nearT.off, nsub,
-                                                     t.near_piece_blocks, P.np);
+                                                     t.vjp_src_piece_blocks, P.np);
     e = launch_count_scan(P.np, INT32_MAX, nl, P.tsum, P.off, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(t.h_pairs + 2, P.off + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s);
@@ -1744,8 +1744,8 @@ hipError_t launch_vjp(Tree &t, const void *abar, void *xbar, void *mbar, hipStre
         const int stride = 4 * T.leaf_size;
         k_vjp_p2p_src<<<(nu + VJP_WAVES - 1) / VJP_WAVES, VJP_WG, 0, s>>>(
             t.pm, t.ph, t.abt, t.first, t.count, t.leaf_node, nu, t.nearT.off, t.nearT.src, nsub,
-            n, t.xbt, t.mbt, pc ? t.pnearT.list : nullptr, per, (double *)t.pnearT.part,
-            stride);
+            n, t.xbt, t.mbt, pc ? t.pnearT.list : nullptr, (int)t.vjp_src_piece_blocks,
+            (double *)t.pnearT.part, stride);
         if (pc)
             k_vjp_p2p_fold<<<(nu - nl + 3) / 4, 256, 0, s>>>(
                 t.leaf_node, t.pnearT.list, nu - nl, t.first, t.count, t.pnearT.off,
