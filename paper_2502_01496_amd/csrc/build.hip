@@ -257,8 +257,8 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
 // Stable scatter of one tile: rank the keys by digit (per wave, ballot
 // matching; waves in order), place the tile digit-sorted in LDS, then write
 // each digit's run to its global position with consecutive threads on
-// consecutive addresses.  VALS = false: keys only (no LDS for values, so a
-// tile of 64-bit keys with 10-bit digits still fits two to a CU).
+// consecutive addresses.  VALS = false: keys only (no values loaded, staged
+// in LDS or written).
 template <typename K, int BITS, bool VALS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *kout, uint32_t *vout,
