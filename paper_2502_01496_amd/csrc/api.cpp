@@ -1104,8 +1104,9 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
         }
     }
     // Lists are evaluated whole, or split into pieces when the last walk
-    // found lists longer than one piece (the sums are bit-identical either
-    // way; pieces only balance the work).  Whole lists: walk, M2L, P2P, then
+    // found lists longer than one piece, or, on a tree's first walk, when
+    // that walk does (the sums are bit-identical either way; pieces only
+    // balance the work).  Whole lists: walk, M2L, P2P, then
     // one readback of the list maxima.  Split lists: the list lengths are read
     // back first, then the pieces are laid out and evaluated.  If a slot
     // overflowed, the slots grow and it is done again.
@@ -1134,7 +1135,9 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             HIP_TRY(launch_walk(t, s));
             tm.done();
         }
-        const bool split = t.split_lists;
+        // the first walk of a tree has no earlier maxima to predict from: it
+        // reads its own before evaluating, as a split walk does
+        const bool split = t.split_lists || !t.lists_seen;
         if (split) {
             fmm_status st = ensure_piece_base(t);
             if (st != FMM_OK)
@@ -1187,6 +1190,7 @@ fmm_status fmm_forces(fmm_tree *tree, void *a, int32_t flags, void *stream)
             t.max_near = (int32_t)mn;
             const int nsub = (t.topo.leaf_size + 7) / 8;
             t.split_lists = mf > t.far_piece_entries || mn * nsub > t.near_piece_blocks;
+            t.lists_seen = true;
             if (split || fallback) {
                 // evaluate now: on the pieces of these lists (their totals were
                 // read with the maxima unless the fallback changed the lists),

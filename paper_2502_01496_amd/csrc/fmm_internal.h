@@ -363,6 +363,8 @@ struct Tree {
         size_t part_stride = 0;   // bytes of partial sums per piece
     } pnear, pfar, pnearT;  // forward near and far lists; transposed near lists
     bool split_lists = false;     // the last walk's lists are split (predicted for the next)
+    bool lists_seen = false;      // a walk's list maxima were read back (until then a walk
+                                  // reads them before the lists are evaluated)
     bool pieces_valid = false;    // pnear / pfar describe the current lists
     int64_t near_piece_blocks = 512, far_piece_entries = 1024;  // test hook: FMM_MI355_PIECE
     // pieces of the transposed near lists (reverse pass, source side): the
